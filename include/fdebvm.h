@@ -1,0 +1,163 @@
+/*
+ * fdebvm — Strang block-circulant preconditioned GMRES for the all-at-once
+ * boundary-value-method (BVM) discretisation of the 1-D two-sided space-fractional
+ * diffusion equation, on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2, eq. (1.1)):
+ *   u_t = d+(x) D+^a u + d-(x) D-^a u + f(x,t),  x in (xL,xR), t in (t0,T],
+ *   u(xL,t) = u(xR,t) = 0,  u(x,t0) = u0(x),  1 < a < 2,  d+- >= 0, d+ + d- > 0.
+ * Space: shifted Grunwald formula on x_i = xL + i dx, dx = (xR-xL)/(m+1), i = 1..m,
+ *   J = dx^{-a} (D+ G_a + D- G_a^T)  (eq. (1.2)-(1.5)).
+ * Time: a mu-step BVM with (nu1, nu2) = (nu, mu-nu) on t_n = t0 + n tau, tau = (T-t0)/s
+ *   (eq. (1.7)-(1.9)).  u_0 is moved to the right-hand side, so the unknowns are
+ *   u_1..u_s and the all-at-once system (eq. (1.10)) is
+ *     M u = (A (x) I_m - tau B (x) J) u = b,
+ *     b   = tau (Bhat[1:,:] (x) I) f - a0 (x) u0 + tau b0 (x) (J u0),
+ *   with Ahat, Bhat the (s+1)x(s+1) BVM matrices, A = Ahat[1:,1:], a0 = Ahat[1:,0], etc.
+ * Preconditioner (Section 3.1, eq. (1.11)):  S = s(A) (x) I - tau s(B) (x) J, applied
+ *   through the time-axis DFT as s independent blocks K_k = lambda_k I - tau mu_k J
+ *   (Section 3.2), K_{s-k} = conj(K_k).
+ *
+ * Layouts.  All space-time vectors are FP64, time-major: element (n, i) at n*m + i.
+ *   f is [s+1][m] (f_0..f_s); u and b are [s][m] (rows 1..s); u0 is [m].
+ * Memory spaces.  Calls that take a `mem_space` argument accept host pointers
+ *   (FDE_MEM_HOST; copied through the handle's staging buffers) or device pointers
+ *   (FDE_MEM_DEVICE; used in place, must stay valid until the call returns).
+ * Ownership.  Every input array is copied or consumed during the call; the caller may
+ *   free it on return.  The handle owns all device memory until fde_bvm_destroy().
+ * Errors.  Status codes only (no exceptions, no abort across the ABI); the message of
+ *   the last failure on the calling thread is returned by fde_last_error().
+ * Streams.  Work is enqueued on the handle's stream (fde_set_stream, default: a stream
+ *   the library creates) and every call returns after that stream is synchronised.
+ *   A handle is not thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef FDEBVM_H
+#define FDEBVM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fde_bvm fde_bvm; /* opaque handle */
+
+typedef enum {
+  FDE_OK = 0,
+  FDE_EINVAL = -1,       /* invalid argument or call order                          */
+  FDE_ENOMEM = -2,       /* device allocation failed                                 */
+  FDE_ESINGULAR = -3,    /* zero/non-finite pivot in a preconditioner block          */
+  FDE_ENOCONV = -4,      /* maxit reached; u holds the last iterate, info is filled  */
+  FDE_EDEVICE = -5,      /* HIP runtime error                                        */
+  FDE_EUNSUPPORTED = -6  /* valid input this build does not handle (e.g. s not 2^k)  */
+} fde_status;
+
+typedef enum { FDE_BVM_TRAPEZOIDAL = 0, FDE_BVM_GBDF3 = 1, FDE_BVM_CUSTOM = 2 } fde_bvm_kind;
+
+/* A mu-step BVM, mu = nu1 + nu2 (eq. (1.7)-(1.9)).  Coefficient i of the main formula
+ * multiplies u_{n-nu1+i}; of initial formula j (1 <= j < nu1, row j-1 of the *_init
+ * arrays) multiplies u_i; of final formula r (0 <= r < nu2) multiplies u_{s-mu+i}.
+ * Arrays are row-major with mu+1 columns.  The main formula must be consistent:
+ * rho(1) = 0 and rho'(1) = sigma(1) (Section 3.1). */
+typedef struct {
+  int nu1, nu2;
+  const double *alpha, *beta;           /* [mu+1]          */
+  const double *alpha_init, *beta_init; /* [nu1-1][mu+1]   */
+  const double *alpha_fin, *beta_fin;   /* [nu2][mu+1]     */
+} fde_bvm_formula;
+
+/* The problem statement of eq. (1.1) on the grid of Section 2.1.  d_plus, d_minus are
+ * sampled at the interior nodes x_1..x_m (time-independent).  `custom` is read only
+ * when kind == FDE_BVM_CUSTOM. */
+typedef struct {
+  double alpha, xL, xR, t0, T;
+  int m, s;
+  const double *d_plus, *d_minus; /* host pointers, [m] */
+  fde_bvm_kind kind;
+  const fde_bvm_formula *custom;
+} fde_problem;
+
+typedef enum { FDE_FP64 = 0, FDE_MIXED_C32 = 1 } fde_precision;
+typedef enum { FDE_MEM_HOST = 0, FDE_MEM_DEVICE = 1 } fde_mem_space;
+
+/* rtol: stop when ||b - M u||_2 <= rtol ||b||_2 (true residual, recomputed in FP64).
+ * restart: GMRES restart length (1..64).  maxit: total iteration cap.
+ * x0: initial guess [s][m] in mem_space, or NULL for zero. */
+typedef struct {
+  double rtol;
+  int restart, maxit;
+  const double *x0;
+  int mem_space;
+} fde_solve_opts;
+
+typedef struct {
+  int iters, restarts, converged, precision;
+  double true_relres; /* ||b - M u|| / ||b|| of the returned u, FP64 */
+  double est_relres;  /* GMRES least-squares estimate at exit        */
+  double t_factor_ms, t_solve_ms;
+} fde_solve_info;
+
+/* Validates the problem (1 < alpha < 2; d+- >= 0 and d+ + d- > 0 at every node; m >= 1;
+ * s >= mu+1 and a power of two (else FDE_EUNSUPPORTED); xR > xL; T > t0; consistent
+ * custom formula), builds the Grunwald weights (eq. (1.2)), the BVM tables and the Strang
+ * eigenvalues (closed form after eq. (1.13)), allocates the device workspace and computes
+ * the Toeplitz symbol FFT of G_a on the device.  On success *out owns a new handle. */
+fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out);
+
+/* Assembles the floor(s/2)+1 distinct blocks K_k = lambda_k I - tau mu_k J and factors them
+ * by pivot-free blocked LU on the GPU (Section 3.2), in complex FP64 (FDE_FP64) or complex
+ * FP32 (FDE_MIXED_C32).  Pivot-free elimination is safe because every K_k is strictly row
+ * diagonally dominant for an A_{nu,mu-nu}-stable formula (Prop 2.2, Definition 3.1); a zero
+ * or non-finite pivot returns FDE_ESINGULAR.  May be called again to switch precision. */
+fde_status fde_precond_factor(fde_bvm *h, fde_precision prec);
+
+/* Solves M u = b (b built on the GPU from u0 [m] and f [s+1][m]) by right-preconditioned
+ * restarted GMRES (flexible form; FP64 Arnoldi with modified Gram-Schmidt, Givens rotations
+ * and true residual).  u0, f, u are in o->mem_space.  Requires fde_precond_factor first. */
+fde_status fde_bvm_solve(fde_bvm *h, const double *u0, const double *f, double *u,
+                         const fde_solve_opts *o, fde_solve_info *info);
+
+/* Solves `count` independent, already factored handles.  Iterations of all unconverged
+ * instances advance together; each instance stops on its own residual.  Arrays of
+ * pointers are host arrays; the pointed-to data is in o->mem_space.  info is [count]. */
+fde_status fde_bvm_solve_batch(fde_bvm *const *h, int count, const double *const *u0,
+                               const double *const *f, double *const *u,
+                               const fde_solve_opts *o, fde_solve_info *info);
+
+void fde_bvm_destroy(fde_bvm *h);
+const char *fde_last_error(void);
+
+/* ---- stream and sizes ------------------------------------------------------------ */
+/* Use `stream` (a hipStream_t, or NULL for the library's own stream) for all later work. */
+fde_status fde_set_stream(fde_bvm *h, void *stream);
+/* dims[0..5] = m, s, mu, nu1, nb = s/2+1, padded block order mp. */
+fde_status fde_get_dims(const fde_bvm *h, int *dims);
+
+/* ---- the individual steps of the path, for per-kernel checks ----------------------- */
+/* b = right-hand side of eq. (1.10) in s-form, [s][m]. */
+fde_status fde_build_rhs(fde_bvm *h, const double *u0, const double *f, double *b, int mem_space);
+/* w = M z (Toeplitz FFT product with J at every time level, then the banded A, B
+ * coupling), z and w [s][m]. */
+fde_status fde_apply_matvec(fde_bvm *h, const double *z, double *w, int mem_space);
+/* y = J x for `count` vectors, x and y [count][m] (LDS radix-2 FFT, circulant embedding). */
+fde_status fde_toeplitz_apply(fde_bvm *h, const double *x, double *y, int count, int mem_space);
+/* vhat[k][i] = sum_n v[n][i] e^{-2 pi i nk/s}, k = 0..s/2; v [s][m] real, vhat
+ * [s/2+1][m] complex interleaved (re, im). */
+fde_status fde_time_rfft(fde_bvm *h, const double *v, double *vhat, int mem_space);
+/* z = S^{-1} v (time DFT, block solves with the stored factors, inverse DFT), [s][m]. */
+fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, int mem_space);
+/* Copies the stored LU factors of block k (unit-lower L below the diagonal, U on and above
+ * it, complex interleaved, [m][m] row-major, widened to FP64) to the host array out. */
+fde_status fde_get_factor_block(fde_bvm *h, int k, double *out);
+
+/* ---- per-kernel timing ------------------------------------------------------------- */
+/* When enabled, every kernel launch is bracketed by HIP events on the handle's stream and
+ * its duration is added to a per-kernel-name total.  Enabling clears the totals. */
+fde_status fde_profile_enable(fde_bvm *h, int enable);
+/* Total milliseconds, launch count and algorithmic work (flops or bytes, per the kernel:
+ * FLOP for the LU kernels, bytes for the others) recorded for the kernel named `name`. */
+fde_status fde_profile_query(const fde_bvm *h, const char *name, double *total_ms, int *count,
+                             double *work);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDEBVM_H */

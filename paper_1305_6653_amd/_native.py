@@ -1,0 +1,126 @@
+"""ctypes binding of libfdebvm.so (include/fdebvm.h): argument marshalling only.
+
+The library is loaded from this package directory; there is no fallback.  A missing or
+unloadable library raises ``NativeLibraryMissing`` on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdebvm.so")
+
+FDE_OK, FDE_EINVAL, FDE_ENOMEM, FDE_ESINGULAR, FDE_ENOCONV, FDE_EDEVICE, FDE_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "FDE_OK", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -3: "FDE_ESINGULAR",
+                -4: "FDE_ENOCONV", -5: "FDE_EDEVICE", -6: "FDE_EUNSUPPORTED"}
+FDE_BVM_TRAPEZOIDAL, FDE_BVM_GBDF3, FDE_BVM_CUSTOM = 0, 1, 2
+FDE_FP64, FDE_MIXED_C32 = 0, 1
+FDE_MEM_HOST, FDE_MEM_DEVICE = 0, 1
+
+_dp = C.POINTER(C.c_double)
+
+
+class FdeBvmFormula(C.Structure):
+    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int),
+                ("alpha", _dp), ("beta", _dp),
+                ("alpha_init", _dp), ("beta_init", _dp),
+                ("alpha_fin", _dp), ("beta_fin", _dp)]
+
+
+class FdeProblem(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("xL", C.c_double), ("xR", C.c_double),
+                ("t0", C.c_double), ("T", C.c_double), ("m", C.c_int), ("s", C.c_int),
+                ("d_plus", _dp), ("d_minus", _dp), ("kind", C.c_int),
+                ("custom", C.POINTER(FdeBvmFormula))]
+
+
+class FdeSolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
+                ("x0", C.c_void_p), ("mem_space", C.c_int)]
+
+
+class FdeSolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("precision", C.c_int), ("true_relres", C.c_double), ("est_relres", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class NativeLibraryMissing(ImportError):
+    pass
+
+
+class FdeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+# (name, restype, argtypes) for every symbol declared in include/fdebvm.h
+_VP = C.c_void_p
+SIGNATURES = [
+    ("fde_bvm_setup", C.c_int, [C.POINTER(FdeProblem), C.POINTER(_VP)]),
+    ("fde_precond_factor", C.c_int, [_VP, C.c_int]),
+    ("fde_bvm_solve", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(FdeSolveOpts), C.POINTER(FdeSolveInfo)]),
+    ("fde_bvm_solve_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
+                                      C.POINTER(_VP), C.POINTER(FdeSolveOpts), C.POINTER(FdeSolveInfo)]),
+    ("fde_bvm_destroy", None, [_VP]),
+    ("fde_last_error", C.c_char_p, []),
+    ("fde_set_stream", C.c_int, [_VP, _VP]),
+    ("fde_get_dims", C.c_int, [_VP, C.POINTER(C.c_int)]),
+    ("fde_build_rhs", C.c_int, [_VP, _VP, _VP, _VP, C.c_int]),
+    ("fde_apply_matvec", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_toeplitz_apply", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_int]),
+    ("fde_time_rfft", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_apply_precond", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_get_factor_block", C.c_int, [_VP, C.c_int, _VP]),
+    ("fde_profile_enable", C.c_int, [_VP, C.c_int]),
+    ("fde_profile_query", C.c_int, [_VP, C.c_char_p, _dp, C.POINTER(C.c_int), _dp]),
+]
+
+_lib = None
+
+
+def _preload_torch_hip_runtime():
+    """Bind the process to ONE HIP runtime.  torch ships its own libamdhip64.so with the same
+    SONAME as ROCm's; if ours were loaded first, torch would later map a second runtime that
+    sees no GPU.  Loading torch's copy first (by path, RTLD_GLOBAL) makes libfdebvm.so bind to
+    it, so torch tensors, streams and this library share a runtime."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        C.CDLL(path, mode=C.RTLD_GLOBAL)
+
+
+def lib():
+    """Load libfdebvm.so once; raise NativeLibraryMissing if it is absent or broken."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    _preload_torch_hip_runtime()
+    if not os.path.exists(LIB_PATH):
+        raise NativeLibraryMissing(
+            f"{LIB_PATH} is not built; run `python -m paper_1305_6653_amd.build` (hipcc, gfx950)")
+    try:
+        L = C.CDLL(LIB_PATH)
+    except OSError as e:
+        raise NativeLibraryMissing(f"cannot load {LIB_PATH}: {e}") from e
+    for name, res, args in SIGNATURES:
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int) -> int:
+    if status != FDE_OK:
+        raise FdeError(status, lib().fde_last_error().decode(errors="replace"))
+    return status

@@ -1,0 +1,215 @@
+"""Python face of the C ABI: a thin wrapper that marshals arrays into ``libfdebvm.so``.
+
+Host arrays are numpy FP64 arrays; device arrays are torch CUDA (ROCm/HIP) FP64 tensors,
+passed by pointer (torch is only the allocator and stream owner).  Every computation
+happens in the HIP library; nothing here does arithmetic on the data.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _native as N
+
+_KINDS = {"trapezoidal": N.FDE_BVM_TRAPEZOIDAL, "gbdf3": N.FDE_BVM_GBDF3}
+_PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
+
+
+def _is_torch_cuda(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _arg(x, count: int, name: str, writable: bool = False):
+    """Return (pointer, mem_space, keepalive) for a host numpy or device torch FP64 array."""
+    if _is_torch_cuda(x):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise TypeError(f"{name}: device tensor must be contiguous float64")
+        if x.numel() != count:
+            raise ValueError(f"{name}: expected {count} elements, got {x.numel()}")
+        return C.c_void_p(x.data_ptr()), N.FDE_MEM_DEVICE, x
+    a = np.asarray(x)
+    if writable:
+        if a.dtype != np.float64 or not a.flags.c_contiguous or not a.flags.writeable:
+            raise TypeError(f"{name}: host output must be a writable C-contiguous float64 array")
+    else:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != count:
+        raise ValueError(f"{name}: expected {count} elements, got {a.size}")
+    return C.c_void_p(a.ctypes.data), N.FDE_MEM_HOST, a
+
+
+def _same_space(*spaces):
+    sp = {s for s in spaces if s is not None}
+    if len(sp) > 1:
+        raise ValueError("all arrays of one call must be either host arrays or device tensors")
+    return sp.pop() if sp else N.FDE_MEM_HOST
+
+
+class BvmSolver:
+    """One all-at-once BVM system: ``setup`` on construction, then ``factor`` and ``solve``.
+
+    problem: any object with alpha, m, s, d_plus, d_minus, bvm ('trapezoidal'|'gbdf3')
+    and optional xL, xR, t0, T (a ``workloads.Problem`` works).
+    """
+
+    def __init__(self, problem, stream=None):
+        L = N.lib()
+        self.m = int(problem.m)
+        self.s = int(problem.s)
+        self._dp = np.ascontiguousarray(problem.d_plus, dtype=np.float64)
+        self._dm = np.ascontiguousarray(problem.d_minus, dtype=np.float64)
+        if self._dp.size != self.m or self._dm.size != self.m:
+            raise ValueError("d_plus and d_minus must have m entries")
+        kind = getattr(problem, "bvm", "gbdf3")
+        if kind not in _KINDS:
+            raise ValueError(f"unknown BVM {kind!r}")
+        p = N.FdeProblem(float(problem.alpha), float(getattr(problem, "xL", 0.0)),
+                         float(getattr(problem, "xR", 2.0)), float(getattr(problem, "t0", 0.0)),
+                         float(getattr(problem, "T", 1.0)), self.m, self.s,
+                         self._dp.ctypes.data_as(N._dp), self._dm.ctypes.data_as(N._dp),
+                         _KINDS[kind], None)
+        h = C.c_void_p()
+        N.check(L.fde_bvm_setup(C.byref(p), C.byref(h)))
+        self._h = h
+        dims = (C.c_int * 6)()
+        N.check(L.fde_get_dims(h, dims))
+        self.mu, self.nu, self.nb, self.mp = dims[2], dims[3], dims[4], dims[5]
+        self.n = self.m * self.s
+        if stream is not None:
+            self.set_stream(stream)
+
+    # ---- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().fde_bvm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        ptr = getattr(stream, "cuda_stream", stream)
+        N.check(N.lib().fde_set_stream(self._h, C.c_void_p(ptr or 0)))
+
+    # ---- the three calls
+    def factor(self, precision: str = "fp64"):
+        N.check(N.lib().fde_precond_factor(self._h, _PREC[precision]))
+
+    def solve(self, u0, f, x0=None, out=None, rtol: float = 1e-10, restart: int = 20,
+              maxit: int = 1000, raise_on_noconv: bool = True):
+        """Returns (u [s][m], info dict).  u0 [m], f [s+1][m], x0 [s][m] or None."""
+        pu0, s1, k1 = _arg(u0, self.m, "u0")
+        pf, s2, k2 = _arg(f, (self.s + 1) * self.m, "f")
+        sx = None
+        px0 = None
+        if x0 is not None:
+            px0, sx, k3 = _arg(x0, self.n, "x0")
+        space = _same_space(s1, s2, sx)
+        if out is None:
+            out = self._alloc_like(space, (self.s, self.m), u0)
+        pu, so, k4 = _arg(out, self.n, "out", writable=True)
+        _same_space(space, so)
+        opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), px0, space)
+        info = N.FdeSolveInfo()
+        st = N.lib().fde_bvm_solve(self._h, pu0, pf, pu, C.byref(opts), C.byref(info))
+        if st != N.FDE_OK and (st != N.FDE_ENOCONV or raise_on_noconv):
+            N.check(st)
+        return out, info.as_dict()
+
+    # ---- single steps
+    def rhs(self, u0, f, out=None):
+        pu0, s1, _a = _arg(u0, self.m, "u0")
+        pf, s2, _b = _arg(f, (self.s + 1) * self.m, "f")
+        space = _same_space(s1, s2)
+        out = self._alloc_like(space, (self.s, self.m), u0) if out is None else out
+        pb, _, _c = _arg(out, self.n, "out", writable=True)
+        N.check(N.lib().fde_build_rhs(self._h, pu0, pf, pb, space))
+        return out
+
+    def matvec(self, z, out=None):
+        pz, space, _a = _arg(z, self.n, "z")
+        out = self._alloc_like(space, (self.s, self.m), z) if out is None else out
+        pw, _, _b = _arg(out, self.n, "out", writable=True)
+        N.check(N.lib().fde_apply_matvec(self._h, pz, pw, space))
+        return out
+
+    def precond(self, v, out=None):
+        pv, space, _a = _arg(v, self.n, "v")
+        out = self._alloc_like(space, (self.s, self.m), v) if out is None else out
+        pz, _, _b = _arg(out, self.n, "out", writable=True)
+        N.check(N.lib().fde_apply_precond(self._h, pv, pz, space))
+        return out
+
+    def toeplitz(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        count = x.size // self.m
+        y = np.empty_like(x)
+        N.check(N.lib().fde_toeplitz_apply(self._h, C.c_void_p(x.ctypes.data),
+                                            C.c_void_p(y.ctypes.data), count, N.FDE_MEM_HOST))
+        return y
+
+    def time_rfft(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty((self.s // 2 + 1, self.m), dtype=np.complex128)
+        N.check(N.lib().fde_time_rfft(self._h, C.c_void_p(v.ctypes.data),
+                                       C.c_void_p(out.ctypes.data), N.FDE_MEM_HOST))
+        return out
+
+    def factor_block(self, k: int) -> np.ndarray:
+        out = np.empty((self.m, self.m), dtype=np.complex128)
+        N.check(N.lib().fde_get_factor_block(self._h, int(k), C.c_void_p(out.ctypes.data)))
+        return out
+
+    # ---- timing
+    def profile(self, enable: bool = True):
+        N.check(N.lib().fde_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_query(self, name: str):
+        ms, cnt, work = C.c_double(), C.c_int(), C.c_double()
+        N.check(N.lib().fde_profile_query(self._h, name.encode(), C.byref(ms), C.byref(cnt),
+                                           C.byref(work)))
+        return {"total_ms": ms.value, "count": cnt.value, "work": work.value}
+
+    @staticmethod
+    def _alloc_like(space, shape, like):
+        if space == N.FDE_MEM_DEVICE:
+            import torch
+            return torch.empty(shape, dtype=torch.float64, device=like.device)
+        return np.empty(shape, dtype=np.float64)
+
+
+def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit: int = 1000,
+                outs=None):
+    """fde_bvm_solve_batch over already factored solvers; returns (outs, infos)."""
+    count = len(solvers)
+    if outs is None:
+        outs = [BvmSolver._alloc_like(_arg(u, s.m, "u0")[1], (s.s, s.m), u)
+                for s, u in zip(solvers, u0s)]
+    keep = []
+    hs = (C.c_void_p * count)(*[s.handle for s in solvers])
+    pu0 = (C.c_void_p * count)()
+    pf = (C.c_void_p * count)()
+    pu = (C.c_void_p * count)()
+    spaces = []
+    for i, s in enumerate(solvers):
+        a, sa, ka = _arg(u0s[i], s.m, "u0")
+        b, sb, kb = _arg(fs[i], (s.s + 1) * s.m, "f")
+        c, sc, kc = _arg(outs[i], s.n, "out", writable=True)
+        keep += [ka, kb, kc]
+        spaces += [sa, sb, sc]
+        pu0[i], pf[i], pu[i] = a, b, c
+    space = _same_space(*spaces)
+    opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), None, space)
+    infos = (N.FdeSolveInfo * count)()
+    N.check(N.lib().fde_bvm_solve_batch(hs, count, pu0, pf, pu, C.byref(opts), infos))
+    return outs, [i.as_dict() for i in infos]

@@ -1,0 +1,174 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, step by step and
+end to end.  Sizes span several 64-wide tiles with ragged tails; the full-size cases
+use the workloads' seeded generators."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_1305_6653_amd import BvmSolver, FdeError
+from paper_1305_6653_amd import _native as N
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "trap_m1_s2": lambda: W.tiny(1, 2, 1.5, 1, "trapezoidal"),
+    "gbdf3_m1_s4": lambda: W.tiny(1, 4, 1.3, 2, "gbdf3"),
+    "gbdf3_m7_s8": lambda: W.tiny(7, 8, 1.9, 3, "gbdf3"),
+    "trap_m63_s64_manufactured": W.manufactured_c1,
+    "gbdf3_m200_s32": lambda: W.tiny(200, 32, 1.7, 4, "gbdf3"),
+    "trap_m130_s16": lambda: W.tiny(130, 16, 1.2, 5, "trapezoidal"),
+    "gbdf3_m255_s128_random": lambda: W.warmstart_instance(7),
+}
+SMALL = ["trap_m1_s2", "gbdf3_m1_s4", "gbdf3_m7_s8", "trap_m63_s64_manufactured",
+         "gbdf3_m200_s32", "trap_m130_s16"]
+
+
+def _setup(name):
+    p = CASES[name]()
+    return p, BvmSolver(p)
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_toeplitz_matvec_vs_dense(name):
+    p, S = _setup(name)
+    J, _, _, _ = O.problem_matrices(p)
+    x = np.random.default_rng(1).standard_normal((3, p.m))
+    y = S.toeplitz(x)
+    ref = x @ J.T
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(J).max() * np.abs(x).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_time_rfft_vs_dft(name):
+    p, S = _setup(name)
+    V = np.random.default_rng(2).standard_normal((p.s, p.m))
+    Vh = S.time_rfft(V)
+    # plain DFT definition, e^{-2 pi i n k / s}
+    n = np.arange(p.s)
+    k = np.arange(p.s // 2 + 1)
+    ref = np.exp(-2j * np.pi * np.outer(k, n) / p.s) @ V
+    assert np.abs(Vh - ref).max() <= 1e-13 * np.abs(V).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_rhs_and_matvec_vs_oracle(name):
+    p, S = _setup(name)
+    J, F, tau, _ = O.problem_matrices(p)
+    A, B, a0, b0, Bfull = O.s_form(F, p.s)
+    b_ref = tau * (Bfull @ p.f) - np.outer(a0, p.u0) + tau * np.outer(b0, J @ p.u0)
+    b = S.rhs(p.u0, p.f)
+    assert _rel(b, b_ref) <= 1e-13
+    Z = np.random.default_rng(3).standard_normal((p.s, p.m))
+    w = S.matvec(Z)
+    assert _rel(w, O.apply_M(J, A, B, tau, Z)) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+@pytest.mark.parametrize("name", ["gbdf3_m7_s8", "trap_m63_s64_manufactured", "gbdf3_m200_s32",
+                                  "trap_m130_s16"])
+def test_block_lu_factors(name, prec, tol):
+    """||L U - K_k|| / ||K_k|| for the pivot-free MFMA factorization."""
+    p, S = _setup(name)
+    S.factor(prec)
+    J, F, tau, _ = O.problem_matrices(p)
+    P = O.StrangPreconditioner(J, F, p.s, tau)
+    nb = p.s // 2 + 1
+    for k in sorted({0, 1, nb // 2, nb - 1}):
+        Fk = S.factor_block(k)
+        L = np.tril(Fk, -1) + np.eye(p.m)
+        U = np.triu(Fk)
+        K = P.block(k, J, tau)
+        assert _rel(L @ U, K) <= tol, (k, _rel(L @ U, K))
+
+
+@pytest.mark.parametrize("prec,eps", [("fp64", 2.0 ** -53), ("mixed", 2.0 ** -24)])
+@pytest.mark.parametrize("name", SMALL)
+def test_preconditioner_apply(name, prec, eps):
+    """Forward error of S^{-1} v within 30 * eps * max_k cond(K_k) (backward-stable solves)."""
+    p, S = _setup(name)
+    S.factor(prec)
+    J, F, tau, _ = O.problem_matrices(p)
+    P = O.StrangPreconditioner(J, F, p.s, tau)
+    kappa = max(np.linalg.cond(P.block(k, J, tau)) for k in range(p.s // 2 + 1))
+    v = np.random.default_rng(4).standard_normal((p.s, p.m))
+    assert _rel(S.precond(v), P.apply(v)) <= 30 * eps * max(kappa, 10.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-8)])
+@pytest.mark.parametrize("name", SMALL + ["gbdf3_m255_s128_random"])
+def test_solve_vs_oracle(name, prec, tol):
+    p, S = _setup(name)
+    S.factor(prec)
+    u, info = S.solve(p.u0, p.f, rtol=1e-10)
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+    ref = O.solve_gmres(p, tol=1e-12)   # 1e-13 is below the FP64 floor of some cases
+    assert ref.converged
+    assert _rel(u, ref.x) <= tol, _rel(u, ref.x)
+    assert O.true_relres(p, u) <= 1.5e-10
+    if prec == "fp64":
+        ref10 = O.solve_gmres(p, tol=1e-10)
+        assert abs(info["iters"] - ref10.iters) <= 1, (info["iters"], ref10.iters)
+
+
+def test_manufactured_solution_accuracy():
+    p, S = _setup("trap_m63_s64_manufactured")
+    S.factor("fp64")
+    u, info = S.solve(p.u0, p.f)
+    Ue = p.exact(W.grid_x(p.m), W.grid_t(p.s)[1:])
+    assert 0.005 < _rel(u, Ue) < 0.02
+
+
+def test_deterministic_and_warm_start():
+    p, S = _setup("gbdf3_m200_s32")
+    S.factor("fp64")
+    u1, i1 = S.solve(p.u0, p.f)
+    u2, i2 = S.solve(p.u0, p.f)
+    assert np.array_equal(u1, u2) and i1["iters"] == i2["iters"]
+    u3, i3 = S.solve(p.u0, p.f, x0=u1)
+    assert i3["iters"] == 0 and np.array_equal(u3, u1)
+
+
+def test_errors_and_noconv():
+    p, S = _setup("gbdf3_m7_s8")
+    with pytest.raises(FdeError) as e:
+        S.solve(p.u0, p.f)
+    assert e.value.status == N.FDE_EINVAL
+    S.factor("fp64")
+    u, info = S.solve(p.u0, p.f, maxit=1, rtol=1e-14, raise_on_noconv=False)
+    assert info["converged"] == 0 and info["iters"] == 1
+    with pytest.raises(FdeError) as e:
+        S.solve(p.u0, p.f, maxit=1, rtol=1e-14)
+    assert e.value.status == N.FDE_ENOCONV
+
+
+def test_device_pointers_match_host():
+    import torch
+    p, S = _setup("gbdf3_m200_s32")
+    S.factor("fp64")
+    uh, _ = S.solve(p.u0, p.f)
+    dev = torch.device("cuda:0")
+    u0 = torch.from_numpy(p.u0).to(dev)
+    f = torch.from_numpy(np.ascontiguousarray(p.f)).to(dev)
+    ud, info = S.solve(u0, f)
+    torch.cuda.synchronize()
+    assert np.array_equal(ud.cpu().numpy(), uh)
+
+
+def test_batch_equals_single():
+    from paper_1305_6653_amd import solve_batch
+    names = ["gbdf3_m7_s8", "trap_m130_s16", "gbdf3_m200_s32"]
+    ps, Ss = zip(*[_setup(n) for n in names])
+    for S in Ss:
+        S.factor("fp64")
+    singles = [S.solve(p.u0, p.f)[0] for p, S in zip(ps, Ss)]
+    outs, infos = solve_batch(list(Ss), [p.u0 for p in ps], [p.f for p in ps])
+    for a, b, i in zip(outs, singles, infos):
+        assert i["converged"] == 1
+        assert _rel(a, b) <= 1e-12

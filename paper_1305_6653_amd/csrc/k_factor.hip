@@ -56,94 +56,135 @@ __global__ __launch_bounds__(256) void k_assemble(c_t<T> *__restrict__ K, int m,
 }
 
 // ------------------------------------------------------------------------------------
-// Diagonal tile: LU without pivoting, then the two triangular inverses.  256 threads;
-// thread t owns row t/4 and columns (t%4) + 4j, j = 0..15.
+// Diagonal tile: LU without pivoting, then the inverses of its unit-lower and upper
+// triangles.  512 threads; thread t owns row r = t/8 and columns c = (t%8) + 8j, j < 8, in
+// registers.  Each elimination step needs only the pivot row and the pivot column, which
+// their owners publish into double-buffered LDS vectors at the end of the previous step, so
+// every step costs one barrier.  The triangular inverses read the factors from LDS and
+// publish the rows of the inverse the same way.
+static constexpr int DG_NT = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_diag(c_t<T> *__restrict__ K, int mp, int p,
-                                                 c_t<T> *__restrict__ dinv, int *__restrict__ flag) {
+__global__ __launch_bounds__(DG_NT) void k_lu_diag(c_t<T> *__restrict__ K, int mp, int p,
+                                                   c_t<T> *__restrict__ dinv, int *__restrict__ flag) {
   typedef c_t<T> C;
   __shared__ C a[PB][PB + 1];
-  __shared__ C x[PB][PB + 1];
+  __shared__ C prow[2][PB];
+  __shared__ C pcol[2][PB];
   const int blk = blockIdx.x, tid = threadIdx.x;
   const int npan = mp / PB;
+  const int r = tid >> 3, cq = tid & 7;
   C *A = K + (size_t)blk * mp * mp + (size_t)p * PB * mp + (size_t)p * PB;
-  for (int e = tid; e < PB * PB; e += 256) a[e >> 6][e & 63] = A[(size_t)(e >> 6) * mp + (e & 63)];
+  C x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = A[(size_t)r * mp + cq + 8 * j];
+  // publish row 0 and column 0
+  if (r == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = x[j];
+  }
+  if (cq == 0) pcol[0][r] = x[0];
   __syncthreads();
-  const int r = tid >> 2, cq = tid & 3;
   int bad = 0;
   for (int k = 0; k < PB; ++k) {
-    const C piv = a[k][k];
+    const int b = k & 1, nbuf = b ^ 1;
+    const C piv = prow[b][k];
     const T pm = piv.x * piv.x + piv.y * piv.y;
-    if (!(pm > (T)0) || !isfinite(pm)) bad = 1;
-    const C ip = trecip<T>(piv);
-    C l = mk<T>(0, 0);
-    C nv[16];
+    if (tid == 0 && (!(pm > (T)0) || !isfinite(pm))) bad = 1;
     if (r > k) {
-      l = tmul<T>(a[r][k], ip);
+      const C l = tmul<T>(pcol[b][r], trecip<T>(piv));
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = cq + 4 * j;
-        nv[j] = (c > k) ? tsub<T>(a[r][c], tmul<T>(l, a[k][c])) : a[r][c];
+      for (int j = 0; j < 8; ++j) {
+        const int c = cq + 8 * j;
+        if (c > k) x[j] = tsub<T>(x[j], tmul<T>(l, prow[b][c]));
+        else if (c == k) x[j] = l;
       }
     }
-    __syncthreads();
-    if (r > k) {
+    if (k + 1 < PB) {
+      if (r == k + 1) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = cq + 4 * j;
-        if (c > k) a[r][c] = nv[j];
-        else if (c == k) a[r][c] = l;
+        for (int j = 0; j < 8; ++j) prow[nbuf][cq + 8 * j] = x[j];
+      }
+      if (cq == ((k + 1) & 7)) {
+        C xc = x[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j)
+          if (j == ((k + 1) >> 3)) xc = x[j];  // select, not a dynamic register index
+        pcol[nbuf][r] = xc;
       }
     }
     __syncthreads();
   }
-  if (bad && tid == 0) atomicOr(flag, 1);
-  for (int e = tid; e < PB * PB; e += 256) A[(size_t)(e >> 6) * mp + (e & 63)] = a[e >> 6][e & 63];
-
+  if (bad) atomicOr(flag, 1);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    A[(size_t)r * mp + cq + 8 * j] = x[j];
+    a[r][cq + 8 * j] = x[j];
+  }
   C *Dl = dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   C *Du = Dl + PB * PB;
-  // X = L11^{-1}: rows r > k receive -L[r][k] X[k][:], row k is final at step k.
-  for (int e = tid; e < PB * PB; e += 256)
-    x[e >> 6][e & 63] = mk<T>((e >> 6) == (e & 63) ? (T)1 : (T)0, (T)0);
+  // X = L^{-1} (unit lower): row r receives -L[r][k] X[k][:] at step k < r; X row k+1 is final
+  // after step k and is published then.
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
+  if (r == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = x[j];
+  }
   __syncthreads();
   for (int k = 0; k < PB - 1; ++k) {
+    const int b = k & 1, nbuf = b ^ 1;
     if (r > k) {
       const C lrk = a[r][k];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = cq + 4 * j;
-        if (c <= k) x[r][c] = tsub<T>(x[r][c], tmul<T>(lrk, x[k][c]));
+      for (int j = 0; j < 8; ++j) {
+        const int c = cq + 8 * j;
+        if (c <= k) x[j] = tsub<T>(x[j], tmul<T>(lrk, prow[b][c]));
       }
+    }
+    if (r == k + 1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) prow[nbuf][cq + 8 * j] = x[j];
     }
     __syncthreads();
   }
-  for (int e = tid; e < PB * PB; e += 256) Dl[e] = x[e >> 6][e & 63];
-  __syncthreads();
-  // X = U11^{-1}: for k = 63..0, scale row k by 1/U[k][k], then rows r < k receive -U[r][k] X[k][:].
-  for (int e = tid; e < PB * PB; e += 256)
-    x[e >> 6][e & 63] = mk<T>((e >> 6) == (e & 63) ? (T)1 : (T)0, (T)0);
-  __syncthreads();
-  for (int k = PB - 1; k >= 0; --k) {
-    if (r == k) {
-      const C iu = trecip<T>(a[k][k]);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = cq + 4 * j;
-        if (c >= k) x[k][c] = tmul<T>(x[k][c], iu);
-      }
+  for (int j = 0; j < 8; ++j) Dl[r * PB + cq + 8 * j] = x[j];
+  // X = U^{-1}: for k = 63..0 row k is scaled by 1/U[k][k] (its last update came at step k+1),
+  // published, and rows r < k receive -U[r][k] X[k][:].
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
+  if (r == PB - 1) {
+    const C iu = trecip<T>(a[PB - 1][PB - 1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] = tmul<T>(x[j], iu);
+      prow[1][cq + 8 * j] = x[j];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int k = PB - 1; k >= 1; --k) {
+    const int b = k & 1, nbuf = b ^ 1;
     if (r < k) {
       const C u = a[r][k];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = cq + 4 * j;
-        if (c >= k) x[r][c] = tsub<T>(x[r][c], tmul<T>(u, x[k][c]));
+      for (int j = 0; j < 8; ++j) {
+        const int c = cq + 8 * j;
+        if (c >= k) x[j] = tsub<T>(x[j], tmul<T>(u, prow[b][c]));
+      }
+    }
+    if (r == k - 1) {
+      const C iu = trecip<T>(a[k - 1][k - 1]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        x[j] = tmul<T>(x[j], iu);
+        prow[nbuf][cq + 8 * j] = x[j];
       }
     }
     __syncthreads();
   }
-  for (int e = tid; e < PB * PB; e += 256) Du[e] = x[e >> 6][e & 63];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = x[j];
 }
 
 // ------------------------------------------------------------------------------------
@@ -323,6 +364,147 @@ __global__ __launch_bounds__(TS_NT) void k_trsv(const c_t<T> *__restrict__ K,
 }
 
 // ------------------------------------------------------------------------------------
+// Block solves with several workgroups per block (cooperative launch, all workgroups
+// co-resident).  Item (k, w), w < W, owns the 64-row panels P = w, w+W, ... of block k in
+// both sweeps.  Panel P of the forward sweep needs y_Q for every Q < P: the owner streams
+// L[P][Q] as soon as y_Q is published (flag[k][Q][0] == epoch), so the bulk of the bytes
+// is read in parallel and only the last 64x64 chunk plus the diagonal inverse sit on the
+// dependency chain.  The backward sweep mirrors it with U and flag[k][Q][1].
+//
+// Coherence across the XCDs' separate L2 caches: the published pieces y_Q and the flags
+// are written and read with relaxed agent-scope atomics (sc1: write-through / re-fetch
+// at the coherence point); the producer waits for its stores before raising the flag.
+// This avoids agent-scope fences, which write back or invalidate a whole L2.
+// Every wait is bounded: after TS_SPIN_MAX polls, or once any workgroup has raised the
+// error flag, the workgroup sets the flag and returns, so the grid always drains.
+static constexpr int TS_SPIN_MAX = 1 << 18;
+
+__device__ __forceinline__ void st_coh(double2 *p, double2 v) {
+  unsigned long long *q = reinterpret_cast<unsigned long long *>(p);
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 ld_coh(const double2 *p) {
+  const unsigned long long *q = reinterpret_cast<const unsigned long long *>(p);
+  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
+}
+
+// Returns false (uniformly across the workgroup) if the wait was abandoned.
+__device__ __forceinline__ bool ts_wait(const int *flag, int epoch, int *err) {
+  int ok = 1;
+  if (threadIdx.x == 0) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      for (int it = 0;; ++it) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (it > TS_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicOr(err, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+  }
+  return __syncthreads_and(ok) != 0;
+}
+
+__device__ __forceinline__ void ts_publish(int *flag, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over the 16 lanes that share lane/16 (xor 1, 2, 4, 8 stay inside the group).
+__device__ __forceinline__ double2 sum16(double2 v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
+// acc[g] += M[rows][cols] * x, for this wave's 16 rows (4 groups of 4, row = base + 4g + lane/16)
+// over 64 columns (4 groups of 16, col = 16j + lane%16); x[j] is the column value of group j.
+template <typename T>
+__device__ __forceinline__ void chunk_gemv(const c_t<T> *__restrict__ M, size_t ld,
+                                           const double2 (&x)[4], double2 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
+  c_t<T> a[4][4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[g][j] = M[(size_t)(4 * g + rs) * ld + 16 * j + cs];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g] = cfma(widen(a[g][j]), x[j], acc[g]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_coop(const c_t<T> *__restrict__ K,
+                                                   const c_t<T> *__restrict__ dinv,
+                                                   double2 *__restrict__ Vh, int *__restrict__ flags,
+                                                   int mp, int nb, int W, int epoch,
+                                                   int *__restrict__ err) {
+  __shared__ double2 tmp[PB];
+  const int npan = mp / PB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
+  const int r16 = wave * 16;  // this wave's first row inside the panel
+  const int items = nb * W;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int k = item / W, w = item % W;
+    const c_t<T> *A = K + (size_t)k * mp * mp;
+    double2 *v = Vh + (size_t)k * mp;
+    int *fl = flags + (size_t)k * npan * 2;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
+      for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
+        const int p0 = P * PB;
+        double2 acc[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
+        const int nq = sweep == 0 ? P : npan - 1 - P;
+        for (int t = 0; t < nq; ++t) {
+          const int Q = sweep == 0 ? t : npan - 1 - t;
+          if (!ts_wait(&fl[Q * 2 + sweep], epoch, err)) return;
+          double2 x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = ld_coh(&v[Q * PB + 16 * j + cs]);
+          chunk_gemv<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, x, acc);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          acc[g] = sum16(acc[g]);
+          if (cs == 0) {
+            const int rr = r16 + 4 * g + rs;
+            tmp[rr] = csub(ld_coh(&v[p0 + rr]), acc[g]);
+          }
+        }
+        __syncthreads();
+        const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
+        double2 x[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = tmp[16 * j + cs];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
+        chunk_gemv<T>(Di + (size_t)r16 * PB, PB, x, b);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          b[g] = sum16(b[g]);
+          if (cs == 0) st_coh(&v[p0 + r16 + 4 * g + rs], b[g]);
+        }
+        ts_publish(&fl[P * 2 + sweep], epoch);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_assemble(void *K, int m, int mp, int nb, const double2 *lam, const double2 *mu,
                            double tau, double scale, const double *g, const double *dp,
@@ -335,7 +517,7 @@ hipError_t launch_assemble(void *K, int m, int mp, int nb, const double2 *lam, c
 
 template <typename T>
 hipError_t launch_lu_diag(void *K, int mp, int nb, int p, void *dinv, int *flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_lu_diag<T>, dim3(nb), dim3(256), 0, st, (c_t<T> *)K, mp, p,
+  hipLaunchKernelGGL(k_lu_diag<T>, dim3(nb), dim3(DG_NT), 0, st, (c_t<T> *)K, mp, p,
                      (c_t<T> *)dinv, flag);
   return hipGetLastError();
 }
@@ -355,6 +537,41 @@ hipError_t launch_lu_update(void *K, int mp, int nb, int p, hipStream_t st) {
   if (nrem <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lu_update<T>, dim3(nrem * nrem, nb), dim3(256), 0, st, (c_t<T> *)K, mp, p);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trsv_coop_grid(int mp, int nb, int *grid, int *W) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  int per = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv_coop<T>, 256, 0);
+  if (e != hipSuccess) return e;
+  const int npan = mp / PB;
+  const int maxg = per * cus;
+  int w = maxg / nb;
+  if (w > npan) w = npan;
+  if (w < 1) w = 1;
+  *W = w;
+  *grid = nb * w < maxg ? nb * w : maxg;
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_trsv_coop(const void *K, const void *dinv, double2 *Vh, int *flags, int mp,
+                            int nb, int epoch, int *err, hipStream_t st) {
+  int grid = 0, W = 0;
+  hipError_t e = trsv_coop_grid<T>(mp, nb, &grid, &W);
+  if (e != hipSuccess) return e;
+  const c_t<T> *Kp = (const c_t<T> *)K;
+  const c_t<T> *Dp = (const c_t<T> *)dinv;
+  void *args[] = {(void *)&Kp, (void *)&Dp, (void *)&Vh, (void *)&flags, (void *)&mp,
+                  (void *)&nb, (void *)&W, (void *)&epoch, (void *)&err};
+  return hipLaunchCooperativeKernel((const void *)k_trsv_coop<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
 template <typename T>
@@ -378,7 +595,9 @@ hipError_t launch_trsv(const void *K, const void *dinv, double2 *Vh, int mp, int
   template hipError_t launch_lu_diag<T>(void *, int, int, int, void *, int *, hipStream_t);      \
   template hipError_t launch_lu_panel<T>(void *, int, int, int, const void *, hipStream_t);      \
   template hipError_t launch_lu_update<T>(void *, int, int, int, hipStream_t);                   \
-  template hipError_t launch_trsv<T>(const void *, const void *, double2 *, int, int, hipStream_t);
+  template hipError_t launch_trsv<T>(const void *, const void *, double2 *, int, int, hipStream_t); \
+  template hipError_t launch_trsv_coop<T>(const void *, const void *, double2 *, int *, int, int,   \
+                                          int, int *, hipStream_t);
 FDE_INST(double)
 FDE_INST(float)
 #undef FDE_INST

@@ -11,7 +11,7 @@ namespace fde {
 static constexpr int KR_NT = 256;
 
 int krylov_blocks(size_t n) {
-  size_t b = (n + 2047) / 2048;
+  size_t b = (n + 1023) / 1024;
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return (int)b;

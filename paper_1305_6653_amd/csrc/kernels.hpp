@@ -52,6 +52,11 @@ template <typename T>
 hipError_t launch_lu_update(void *K, int mp, int nb, int p, hipStream_t st);
 template <typename T>
 hipError_t launch_trsv(const void *K, const void *dinv, double2 *Vh, int mp, int nb, hipStream_t st);
+// Several workgroups per block, cooperative launch; flags [nb][mp/64][2] hold the epoch of
+// the last published panel; *err is raised if a dependency wait had to be abandoned.
+template <typename T>
+hipError_t launch_trsv_coop(const void *K, const void *dinv, double2 *Vh, int *flags, int mp,
+                            int nb, int epoch, int *err, hipStream_t st);
 
 // ---- Krylov BLAS-1 (FP64, deterministic reductions) ----
 int krylov_blocks(size_t n);

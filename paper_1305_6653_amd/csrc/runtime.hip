@@ -114,6 +114,9 @@ struct fde_bvm {
   // ---- factors
   void *d_K = nullptr, *d_dinv = nullptr;
   size_t K_bytes = 0, dinv_bytes = 0;
+  int *d_tsflags = nullptr, *d_tserr = nullptr;  // block-solve dependency flags, error flag
+  int ts_epoch = 0;
+  bool ts_coop = true;
   int prec = -1;
   double t_factor_ms = 0.0;
   // ---- Krylov workspace
@@ -421,6 +424,8 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
   ALLOC(h->d_lam, nb);
   ALLOC(h->d_mu, nb);
   ALLOC(h->d_flag, 1);
+  ALLOC(h->d_tserr, 1);
+  ALLOC(h->d_tsflags, (size_t)h->nb * h->npan * 2);
   ALLOC(h->d_w, n);
   ALLOC(h->d_x, n);
   ALLOC(h->d_b, n);
@@ -471,6 +476,9 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
   h->sp = DevSpace{m, h->log2L, h->d_dp, h->d_dm, h->d_chat, h->d_twL, h->scale};
   h->bd = DevBand{s, mu1, h->d_band_c, h->d_band_a, h->d_band_b};
   h->bdJ = DevBand{1, 1, h->d_bandJ_c, h->d_bandJ_a, h->d_bandJ_b};
+  if (hipMemsetAsync(h->d_tsflags, 0, sizeof(int) * h->nb * h->npan * 2, q) != hipSuccess ||
+      hipMemsetAsync(h->d_tserr, 0, sizeof(int), q) != hipSuccess)
+    return bail(fail(FDE_EDEVICE, "flag initialisation failed"));
   if (launch_symbol(h->d_cG, h->d_chat, h->log2L, h->d_twL, q) != hipSuccess)
     return bail(fail(FDE_EDEVICE, "symbol FFT launch failed: %s", hipGetErrorString(hipGetLastError())));
   if (hipStreamSynchronize(q) != hipSuccess) return bail(fail(FDE_EDEVICE, "setup synchronisation failed"));
@@ -584,10 +592,27 @@ static fde_status op_precond(fde_bvm *h, const double *v, double *z) {
     return launch_time_rfft(v, h->d_Vh, m, h->mp, h->log2s, h->d_tws, h->stream);
   }));
   const double esz = h->prec == FDE_FP64 ? 16.0 : 8.0;
+  if (h->ts_epoch >= 0x7ffffff0) {  // epochs are compared for equality; restart the count
+    HIPCHK(hipMemsetAsync(h->d_tsflags, 0, sizeof(int) * h->nb * h->npan * 2, h->stream));
+    h->ts_epoch = 0;
+  }
+  const int epoch = ++h->ts_epoch;
   HIPCHK(run(h, "trsv", (double)nb * m * m * esz + 32.0 * nb * m, [&] {
-    return h->prec == FDE_FP64
-               ? launch_trsv<double>(h->d_K, h->d_dinv, h->d_Vh, h->mp, nb, h->stream)
-               : launch_trsv<float>(h->d_K, h->d_dinv, h->d_Vh, h->mp, nb, h->stream);
+    hipError_t e = hipErrorNotSupported;
+    if (h->ts_coop) {
+      e = h->prec == FDE_FP64 ? launch_trsv_coop<double>(h->d_K, h->d_dinv, h->d_Vh, h->d_tsflags,
+                                                         h->mp, nb, epoch, h->d_tserr, h->stream)
+                              : launch_trsv_coop<float>(h->d_K, h->d_dinv, h->d_Vh, h->d_tsflags,
+                                                        h->mp, nb, epoch, h->d_tserr, h->stream);
+      if (e != hipSuccess) {  // cooperative launch refused: one workgroup per block instead
+        (void)hipGetLastError();
+        h->ts_coop = false;
+      }
+    }
+    if (!h->ts_coop)
+      e = h->prec == FDE_FP64 ? launch_trsv<double>(h->d_K, h->d_dinv, h->d_Vh, h->mp, nb, h->stream)
+                              : launch_trsv<float>(h->d_K, h->d_dinv, h->d_Vh, h->mp, nb, h->stream);
+    return e;
   }));
   HIPCHK(run(h, "time_irfft", vbytes, [&] {
     return launch_time_irfft(h->d_Vh, z, m, h->mp, h->log2s, h->d_tws, h->stream);
@@ -606,6 +631,18 @@ static fde_status op_rhs(fde_bvm *h, const double *u0, const double *f, double *
   HIPCHK(run(h, "rhs", 8.0 * (2.0 * h->s + 1.0) * h->m, [&] {
     return launch_rhs(f, u0, Ju0, b, h->m, h->bd, h->tau, h->stream);
   }));
+  return FDE_OK;
+}
+
+// The block solve raises d_tserr if it had to abandon a dependency wait (never expected).
+static fde_status check_trsv_err(fde_bvm *h) {
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, h->d_tserr, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (err) {
+    (void)hipMemsetAsync(h->d_tserr, 0, sizeof(int), h->stream);
+    return fail(FDE_EDEVICE, "block solve abandoned a dependency wait");
+  }
   return FDE_OK;
 }
 
@@ -746,6 +783,7 @@ static fde_status gmres(fde_bvm *h, const fde_solve_opts &o, fde_solve_info *inf
                [&] { return launch_update_x(h->d_x, h->d_Z, h->d_y, k, n, h->stream); }));
     ++restarts;
   }
+  STCHK(check_trsv_err(h));
   if (info) {
     info->iters = its;
     info->restarts = restarts;
@@ -868,7 +906,8 @@ extern "C" fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, 
   STCHK(stage_in(h, v, h->n(), mem_space, h->d_sio, &dv));
   STCHK(op_precond(h, dv, h->d_tmp));
   STCHK(copy_out(h, z, h->d_tmp, h->n(), mem_space));
-  return sync_and_flush(h);
+  STCHK(sync_and_flush(h));
+  return check_trsv_err(h);
 }
 
 extern "C" fde_status fde_time_rfft(fde_bvm *h, const double *v, double *vhat, int mem_space) {

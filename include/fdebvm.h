@@ -115,12 +115,24 @@ fde_status fde_precond_factor(fde_bvm *h, fde_precision prec);
 fde_status fde_bvm_solve(fde_bvm *h, const double *u0, const double *f, double *u,
                          const fde_solve_opts *o, fde_solve_info *info);
 
-/* Solves `count` independent, already factored handles.  Iterations of all unconverged
- * instances advance together; each instance stops on its own residual.  Arrays of
- * pointers are host arrays; the pointed-to data is in o->mem_space.  info is [count]. */
+/* Factors the blocks of `count` handles together: every phase of the blocked LU is one
+ * launch covering the blocks of all instances (uneven m and s allowed).  Same numerics
+ * and errors as fde_precond_factor; the handles must be distinct. */
+fde_status fde_precond_factor_batch(fde_bvm *const *h, int count, fde_precision prec);
+
+/* Solves `count` independent handles factored with the same precision.  Every phase is
+ * one launch over all instances that take part in it (a device table of per-instance
+ * descriptors drives the kernels); restart cycles run in lockstep and each instance stops
+ * on its own true residual.  Arrays of pointers are host arrays; the pointed-to data is in
+ * o->mem_space; o->x0 must be NULL (use fde_bvm_solve_batch_x0).  info is [count].
+ * Returns FDE_ENOCONV if any instance hit maxit (its info says which). */
 fde_status fde_bvm_solve_batch(fde_bvm *const *h, int count, const double *const *u0,
                                const double *const *f, double *const *u,
                                const fde_solve_opts *o, fde_solve_info *info);
+/* As fde_bvm_solve_batch with per-instance initial guesses x0[i] (NULL entries: zero). */
+fde_status fde_bvm_solve_batch_x0(fde_bvm *const *h, int count, const double *const *u0,
+                                  const double *const *f, const double *const *x0,
+                                  double *const *u, const fde_solve_opts *o, fde_solve_info *info);
 
 void fde_bvm_destroy(fde_bvm *h);
 const char *fde_last_error(void);

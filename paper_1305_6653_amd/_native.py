@@ -66,8 +66,12 @@ SIGNATURES = [
     ("fde_bvm_setup", C.c_int, [C.POINTER(FdeProblem), C.POINTER(_VP)]),
     ("fde_precond_factor", C.c_int, [_VP, C.c_int]),
     ("fde_bvm_solve", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(FdeSolveOpts), C.POINTER(FdeSolveInfo)]),
+    ("fde_precond_factor_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.c_int]),
     ("fde_bvm_solve_batch", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
                                       C.POINTER(_VP), C.POINTER(FdeSolveOpts), C.POINTER(FdeSolveInfo)]),
+    ("fde_bvm_solve_batch_x0", C.c_int, [C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP),
+                                         C.POINTER(_VP), C.POINTER(_VP), C.POINTER(FdeSolveOpts),
+                                         C.POINTER(FdeSolveInfo)]),
     ("fde_bvm_destroy", None, [_VP]),
     ("fde_last_error", C.c_char_p, []),
     ("fde_set_stream", C.c_int, [_VP, _VP]),

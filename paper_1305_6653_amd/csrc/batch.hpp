@@ -1,0 +1,70 @@
+// Per-instance descriptors shared by every kernel.  A launch covers a set of instances: the
+// host passes, per launch, the prefix sums of the number of work items each instance
+// contributes (`pre[0] = 0, pre[i+1] = pre[i] + items_i`) and the instance ids; a workgroup
+// finds its instance by binary search and decodes its local item from that instance's sizes.
+// A single solve is a batch of one.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fde {
+
+struct InstDesc {
+  // sizes
+  int m, s, mp, nb, npan, log2L, log2s, mu1;
+  int W;     // workgroups per block in the cooperative block solve
+  int nblk;  // Krylov reduction blocks
+  int need_ju0;  // the right-hand side uses J u_0 (a u_0 coefficient in B)
+  double tau, scale;
+  // operator tables
+  const double *dp, *dm, *g;
+  const double2 *chat, *twL, *tws, *lam, *mu;
+  const int *band_c;
+  const double *band_a, *band_b;
+  // factors (complex FP64 or FP32 per the plan), block-solve flags
+  void *K, *dinv;
+  int *tsflags;
+  // vectors (FP64, [s][m] unless noted)
+  double *V, *Z;              // (R+1) and R vectors
+  double *w, *x, *b, *tmp, *sio;
+  double *u0, *f, *Ju0;       // [m], [s+1][m], [m]
+  double2 *Vh;                // [nb][mp]
+  double *part0, *part1;      // [nblk] reduction partials
+  double *H, *y, *nrm;        // Hessenberg column [R+2], LSQ solution [R], norms [2]
+};
+
+// vector selectors resolved on the device
+enum VSel : int { VS_V = 0, VS_Z, VS_W, VS_X, VS_B, VS_TMP, VS_SIO, VS_U0, VS_JU0 };
+
+__device__ __forceinline__ double *vsel(const InstDesc &d, int sel, int j) {
+  const size_t n = (size_t)d.s * d.m;
+  switch (sel) {
+    case VS_V: return d.V + (size_t)j * n;
+    case VS_Z: return d.Z + (size_t)j * n;
+    case VS_W: return d.w;
+    case VS_X: return d.x;
+    case VS_B: return d.b;
+    case VS_TMP: return d.tmp;
+    case VS_SIO: return d.sio;
+    case VS_U0: return d.u0;
+    default: return d.Ju0;
+  }
+}
+
+// Launch-wide item map: instance ids[count], prefix pre[count+1].
+struct ItemMap {
+  const int *ids;
+  const int *pre;
+  int count;
+};
+
+// Returns the position q in the map with pre[q] <= item < pre[q+1].
+__device__ __forceinline__ int item_slot(const ItemMap &mp, int item) {
+  int lo = 0, hi = mp.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mp.pre[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace fde

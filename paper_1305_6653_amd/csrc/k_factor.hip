@@ -11,6 +11,7 @@
 //   L21 = A21 U11^{-1},  U12 = L11^{-1} A12   (k_lu_panel, 64x64x64 complex GEMMs)
 //   A22 -= L21 U12                             (k_lu_update, 64x64 tiles, K = 64)
 // Complex products use four real MFMAs on the re/im parts (gfx950 has no complex MFMA).
+#include "batch.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -19,32 +20,35 @@ namespace fde {
 static constexpr int PB = 64;  // panel width / tile size
 
 // ------------------------------------------------------------------------------------
-// Assembly: one workgroup per row i, covering blocks [k0, k0+kchunk).
+// Assembly.  Item = (instance, row i, chunk of kchunk blocks).
 // J[i][j] = dx^{-a} (d+_i g_{i-j+1} + d-_i g_{j-i+1}), g_k = 0 outside 0..m.
 template <typename T>
-__global__ __launch_bounds__(256) void k_assemble(c_t<T> *__restrict__ K, int m, int mp, int nb,
-                                                  int kchunk, const double2 *__restrict__ lam,
-                                                  const double2 *__restrict__ mu, double tau,
-                                                  double scale, const double *__restrict__ g,
-                                                  const double *__restrict__ dp,
-                                                  const double *__restrict__ dm) {
-  const int i = blockIdx.x;
-  const int k0 = blockIdx.y * kchunk;
+__global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D, ItemMap map,
+                                                  int kchunk) {
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = D[map.ids[q]];
+  const int local = blockIdx.x - map.pre[q];
+  const int m = d.m, mp = d.mp, nb = d.nb;
+  const int nkc = (nb + kchunk - 1) / kchunk;
+  const int i = local / nkc;
+  const int k0 = (local % nkc) * kchunk;
   const int k1 = min(nb, k0 + kchunk);
+  c_t<T> *K = (c_t<T> *)d.K;
+  const double tau = d.tau, scale = d.scale;
   for (int j = threadIdx.x; j < mp; j += 256) {
     double Jij = 0.0;
     if (i < m && j < m) {
-      const int d = i - j;
-      const double gp = (d >= -1 && d + 1 <= m) ? g[d + 1] : 0.0;
-      const double gm = (d <= 1 && 1 - d <= m) ? g[1 - d] : 0.0;
-      Jij = scale * fma(dp[i], gp, dm[i] * gm);
+      const int dd = i - j;
+      const double gp = (dd >= -1 && dd + 1 <= m) ? d.g[dd + 1] : 0.0;
+      const double gm = (dd <= 1 && 1 - dd <= m) ? d.g[1 - dd] : 0.0;
+      Jij = scale * fma(d.dp[i], gp, d.dm[i] * gm);
     }
     for (int k = k0; k < k1; ++k) {
-      double re = -tau * mu[k].x * Jij, im = -tau * mu[k].y * Jij;
+      double re = -tau * d.mu[k].x * Jij, im = -tau * d.mu[k].y * Jij;
       if (i == j) {
         if (i < m) {
-          re += lam[k].x;
-          im += lam[k].y;
+          re += d.lam[k].x;
+          im += d.lam[k].y;
         } else {
           re = 1.0;
           im = 0.0;
@@ -65,14 +69,18 @@ __global__ __launch_bounds__(256) void k_assemble(c_t<T> *__restrict__ K, int m,
 static constexpr int DG_NT = 512;
 
 template <typename T>
-__global__ __launch_bounds__(DG_NT) void k_lu_diag(c_t<T> *__restrict__ K, int mp, int p,
-                                                   c_t<T> *__restrict__ dinv, int *__restrict__ flag) {
+__global__ __launch_bounds__(DG_NT) void k_lu_diag(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                   int p, int *__restrict__ flag) {
   typedef c_t<T> C;
   __shared__ C a[PB][PB + 1];
   __shared__ C prow[2][PB];
   __shared__ C pcol[2][PB];
-  const int blk = blockIdx.x, tid = threadIdx.x;
-  const int npan = mp / PB;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = Dd[map.ids[q]];
+  const int blk = blockIdx.x - map.pre[q], tid = threadIdx.x;
+  const int mp = d.mp, npan = d.npan;
+  C *K = (C *)d.K;
+  C *dinv = (C *)d.dinv;
   const int r = tid >> 3, cq = tid & 7;
   C *A = K + (size_t)blk * mp * mp + (size_t)p * PB * mp + (size_t)p * PB;
   C x[8];
@@ -258,19 +266,23 @@ __device__ __forceinline__ void tile_zero(acc_t<T> (&cre)[2][2], acc_t<T> (&cim)
       }
 }
 
-// Panel: blockIdx.x < nrem -> L21 tile t = A21_t U11^{-1}; else U12 tile = L11^{-1} A12_t.
+// Panel.  Item = (instance, block, t): t < nrem -> L21 tile t = A21_t U11^{-1};
+// else U12 tile t-nrem = L11^{-1} A12_t.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_panel(c_t<T> *__restrict__ K, int mp, int p,
-                                                  const c_t<T> *__restrict__ dinv) {
+__global__ __launch_bounds__(256) void k_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                  int p) {
   typedef c_t<T> C;
-  const int npan = mp / PB, nrem = npan - p - 1;
-  const int t = blockIdx.x, blk = blockIdx.y;
-  C *Kb = K + (size_t)blk * mp * mp;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = Dd[map.ids[q]];
+  const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
+  const int local = blockIdx.x - map.pre[q];
+  const int blk = local / (2 * nrem), t = local % (2 * nrem);
+  C *Kb = (C *)d.K + (size_t)blk * mp * mp;
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   acc_t<T> cre[2][2], cim[2][2];
   tile_zero<T>(cre, cim);
-  const C *Dl = dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
+  const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   const C *Du = Dl + PB * PB;
   C *Ct;
   if (t < nrem) {
@@ -284,13 +296,18 @@ __global__ __launch_bounds__(256) void k_lu_panel(c_t<T> *__restrict__ K, int mp
   tile_store<T>(Ct + (size_t)wr * mp + wc, mp, cre, cim);
 }
 
-// Trailing update: tile (ti, tj) of A22 -= L21_ti U12_tj.
+// Trailing update.  Item = (instance, block, tile (ti, tj)):  A22[ti][tj] -= L21_ti U12_tj.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_update(c_t<T> *__restrict__ K, int mp, int p) {
+__global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                   int p) {
   typedef c_t<T> C;
-  const int npan = mp / PB, nrem = npan - p - 1;
-  const int ti = blockIdx.x / nrem, tj = blockIdx.x % nrem, blk = blockIdx.y;
-  C *Kb = K + (size_t)blk * mp * mp;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = Dd[map.ids[q]];
+  const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
+  const int local = blockIdx.x - map.pre[q];
+  const int blk = local / (nrem * nrem), t = local % (nrem * nrem);
+  const int ti = t / nrem, tj = t % nrem;
+  C *Kb = (C *)d.K + (size_t)blk * mp * mp;
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   C *Ct = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
@@ -309,15 +326,20 @@ __global__ __launch_bounds__(256) void k_lu_update(c_t<T> *__restrict__ K, int m
 static constexpr int TS_NT = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(TS_NT) void k_trsv(const c_t<T> *__restrict__ K,
-                                                const c_t<T> *__restrict__ dinv,
-                                                double2 *__restrict__ Vh, int mp) {
+__global__ __launch_bounds__(TS_NT) void k_trsv(const InstDesc *__restrict__ Dd, ItemMap map) {
   extern __shared__ double2 sh[];
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = Dd[map.ids[q]];
+  const int mp = d.mp, npan = d.npan;
+  // the item map counts nb * W items per instance; one workgroup per block does the solve
+  const int local = blockIdx.x - map.pre[q];
+  if (local % d.W != 0) return;
+  const int blk = local / d.W;
   double2 *y = sh;
   double2 *tmp = sh + mp;
-  const int blk = blockIdx.x, npan = mp / PB;
-  const c_t<T> *A = K + (size_t)blk * mp * mp;
-  double2 *v = Vh + (size_t)blk * mp;
+  const c_t<T> *dinv = (const c_t<T> *)d.dinv;
+  const c_t<T> *A = (const c_t<T> *)d.K + (size_t)blk * mp * mp;
+  double2 *v = d.Vh + (size_t)blk * mp;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int NW = TS_NT / 64;
   for (int i = threadIdx.x; i < mp; i += TS_NT) y[i] = v[i];
@@ -446,21 +468,21 @@ __device__ __forceinline__ void chunk_gemv(const c_t<T> *__restrict__ M, size_t 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_coop(const c_t<T> *__restrict__ K,
-                                                   const c_t<T> *__restrict__ dinv,
-                                                   double2 *__restrict__ Vh, int *__restrict__ flags,
-                                                   int mp, int nb, int W, int epoch,
-                                                   int *__restrict__ err) {
+__global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                   int items, int epoch, int *__restrict__ err) {
   __shared__ double2 tmp[PB];
-  const int npan = mp / PB;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
   const int r16 = wave * 16;  // this wave's first row inside the panel
-  const int items = nb * W;
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
-    const int k = item / W, w = item % W;
-    const c_t<T> *A = K + (size_t)k * mp * mp;
-    double2 *v = Vh + (size_t)k * mp;
-    int *fl = flags + (size_t)k * npan * 2;
+    const int q = item_slot(map, item);
+    const InstDesc &d = Dd[map.ids[q]];
+    const int local = item - map.pre[q];
+    const int mp = d.mp, npan = d.npan, W = d.W;
+    const int k = local / W, w = local % W;
+    const c_t<T> *dinv = (const c_t<T> *)d.dinv;
+    const c_t<T> *A = (const c_t<T> *)d.K + (size_t)k * mp * mp;
+    double2 *v = d.Vh + (size_t)k * mp;
+    int *fl = d.tsflags + (size_t)k * npan * 2;
     for (int sweep = 0; sweep < 2; ++sweep) {
       const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
       for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
@@ -505,99 +527,94 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const c_t<T> *__restrict__ K,
 }
 
 // ------------------------------------------------------------------------------------
+static constexpr int ASM_KCHUNK = 8;
+int assemble_items(int mp, int nb) { return mp * ((nb + ASM_KCHUNK - 1) / ASM_KCHUNK); }
+
 template <typename T>
-hipError_t launch_assemble(void *K, int m, int mp, int nb, const double2 *lam, const double2 *mu,
-                           double tau, double scale, const double *g, const double *dp,
-                           const double *dm, hipStream_t st) {
-  const int kchunk = 8;
-  hipLaunchKernelGGL(k_assemble<T>, dim3(mp, (nb + kchunk - 1) / kchunk), dim3(256), 0, st,
-                     (c_t<T> *)K, m, mp, nb, kchunk, lam, mu, tau, scale, g, dp, dm);
+hipError_t launch_assemble(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble<T>, dim3(items), dim3(256), 0, st, D, map, ASM_KCHUNK);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_lu_diag(void *K, int mp, int nb, int p, void *dinv, int *flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_lu_diag<T>, dim3(nb), dim3(DG_NT), 0, st, (c_t<T> *)K, mp, p,
-                     (c_t<T> *)dinv, flag);
+hipError_t launch_lu_diag(const InstDesc *D, const ItemMap &map, int items, int p, int *flag,
+                          hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lu_diag<T>, dim3(items), dim3(DG_NT), 0, st, D, map, p, flag);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_lu_panel(void *K, int mp, int nb, int p, const void *dinv, hipStream_t st) {
-  const int nrem = mp / PB - p - 1;
-  if (nrem <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lu_panel<T>, dim3(2 * nrem, nb), dim3(256), 0, st, (c_t<T> *)K, mp, p,
-                     (const c_t<T> *)dinv);
+hipError_t launch_lu_panel(const InstDesc *D, const ItemMap &map, int items, int p,
+                           hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lu_panel<T>, dim3(items), dim3(256), 0, st, D, map, p);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_lu_update(void *K, int mp, int nb, int p, hipStream_t st) {
-  const int nrem = mp / PB - p - 1;
-  if (nrem <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lu_update<T>, dim3(nrem * nrem, nb), dim3(256), 0, st, (c_t<T> *)K, mp, p);
+hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p,
+                            hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lu_update<T>, dim3(items), dim3(256), 0, st, D, map, p);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t trsv_coop_grid(int mp, int nb, int *grid, int *W) {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-  }
-  int per = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv_coop<T>, 256, 0);
-  if (e != hipSuccess) return e;
-  const int npan = mp / PB;
-  const int maxg = per * cus;
-  int w = maxg / nb;
-  if (w > npan) w = npan;
-  if (w < 1) w = 1;
-  *W = w;
-  *grid = nb * w < maxg ? nb * w : maxg;
-  return hipSuccess;
-}
-
-template <typename T>
-hipError_t launch_trsv_coop(const void *K, const void *dinv, double2 *Vh, int *flags, int mp,
-                            int nb, int epoch, int *err, hipStream_t st) {
-  int grid = 0, W = 0;
-  hipError_t e = trsv_coop_grid<T>(mp, nb, &grid, &W);
-  if (e != hipSuccess) return e;
-  const c_t<T> *Kp = (const c_t<T> *)K;
-  const c_t<T> *Dp = (const c_t<T> *)dinv;
-  void *args[] = {(void *)&Kp, (void *)&Dp, (void *)&Vh, (void *)&flags, (void *)&mp,
-                  (void *)&nb, (void *)&W, (void *)&epoch, (void *)&err};
-  return hipLaunchCooperativeKernel((const void *)k_trsv_coop<T>, dim3(grid), dim3(256), args, 0, st);
-}
-
-template <typename T>
-hipError_t launch_trsv(const void *K, const void *dinv, double2 *Vh, int mp, int nb,
+hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max_mp,
                        hipStream_t st) {
-  const size_t lds = sizeof(double2) * (mp + PB);
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double2) * (max_mp + PB);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)k_trsv<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_trsv<T>, dim3(nb), dim3(TS_NT), lds, st, (const c_t<T> *)K,
-                     (const c_t<T> *)dinv, Vh, mp);
+  hipLaunchKernelGGL(k_trsv<T>, dim3(items), dim3(TS_NT), lds, st, D, map);
   return hipGetLastError();
 }
 
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+  }
+  return cus;
+}
+
+template <typename T>
+int trsv_coop_capacity() {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv_coop<T>, 256, 0) != hipSuccess)
+    return 0;
+  return per * device_cus();
+}
+
+template <typename T>
+hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items, int epoch, int *err,
+                            hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const int cap = trsv_coop_capacity<T>();
+  if (cap <= 0) return hipErrorNotSupported;
+  const int grid = items < cap ? items : cap;
+  void *args[] = {(void *)&D, (void *)&map, (void *)&items, (void *)&epoch, (void *)&err};
+  return hipLaunchCooperativeKernel((const void *)k_trsv_coop<T>, dim3(grid), dim3(256), args, 0, st);
+}
+
 #define FDE_INST(T)                                                                              \
-  template hipError_t launch_assemble<T>(void *, int, int, int, const double2 *, const double2 *, \
-                                         double, double, const double *, const double *,         \
-                                         const double *, hipStream_t);                           \
-  template hipError_t launch_lu_diag<T>(void *, int, int, int, void *, int *, hipStream_t);      \
-  template hipError_t launch_lu_panel<T>(void *, int, int, int, const void *, hipStream_t);      \
-  template hipError_t launch_lu_update<T>(void *, int, int, int, hipStream_t);                   \
-  template hipError_t launch_trsv<T>(const void *, const void *, double2 *, int, int, hipStream_t); \
-  template hipError_t launch_trsv_coop<T>(const void *, const void *, double2 *, int *, int, int,   \
-                                          int, int *, hipStream_t);
+  template hipError_t launch_assemble<T>(const InstDesc *, const ItemMap &, int, hipStream_t);    \
+  template hipError_t launch_lu_diag<T>(const InstDesc *, const ItemMap &, int, int, int *,        \
+                                        hipStream_t);                                           \
+  template hipError_t launch_lu_panel<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
+  template hipError_t launch_lu_update<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
+  template hipError_t launch_trsv<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t);    \
+  template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int, int, int *,      \
+                                          hipStream_t);                                         \
+  template int trsv_coop_capacity<T>();
 FDE_INST(double)
 FDE_INST(float)
 #undef FDE_INST

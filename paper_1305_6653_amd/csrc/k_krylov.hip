@@ -1,8 +1,9 @@
-// FP64 Krylov vector kernels for GMRES: modified Gram-Schmidt as a chain of launches
-// (launch i subtracts the projection on v_{i-1} and accumulates the dot with v_i, so the
-// MGS order is kept exactly), normalisation, residual, solution update.  Every
-// reduction has a fixed order (block partials summed in index order), so results are
-// bitwise reproducible run to run.
+// FP64 Krylov vector kernels for GMRES, batched over instances (item = (instance, chunk)):
+// modified Gram-Schmidt as a chain of launches (launch i subtracts the projection on v_{i-1}
+// and accumulates the dot with v_i, so the MGS order is kept exactly), normalisation,
+// residual, solution update.  Every reduction has a fixed order (chunk partials summed in
+// index order), so results are bitwise reproducible run to run.
+#include "batch.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -23,26 +24,44 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return block_sum<KR_NT>(t, red);
 }
 
-// i = 0..j+1.  i > 0: h_{i-1} = <v_{i-1}, w> from part_in; w -= h_{i-1} v_{i-1}.
-// i <= j: partial <v_i, w>;  i == j+1: partial <w, w>.
-__global__ __launch_bounds__(KR_NT) void k_mgs_step(int i, int j, const double *__restrict__ V,
-                                                    double *__restrict__ w, size_t n,
-                                                    const double *__restrict__ part_in,
-                                                    double *__restrict__ part_out, int nblk,
-                                                    double *__restrict__ Hcol) {
+struct Chunk {
+  const InstDesc *d;
+  int b;
+  size_t begin, end, n;
+};
+
+__device__ __forceinline__ Chunk chunk_of(const InstDesc *__restrict__ D, const ItemMap &map) {
+  const int q = item_slot(map, blockIdx.x);
+  Chunk c;
+  c.d = &D[map.ids[q]];
+  c.b = blockIdx.x - map.pre[q];
+  c.n = (size_t)c.d->s * c.d->m;
+  const size_t len = (c.n + c.d->nblk - 1) / c.d->nblk;
+  c.begin = (size_t)c.b * len;
+  c.end = c.begin + len < c.n ? c.begin + len : c.n;
+  return c;
+}
+
+// i = 0..j+1.  i > 0: h_{i-1} = <v_{i-1}, w> from the partials of launch i-1; w -= h v_{i-1}.
+// i <= j: partial <v_i, w>;  i == j+1: partial <w, w>.  Launch i reads part[(i+1)&1] and
+// writes part[i&1].
+__global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__ D, ItemMap map,
+                                                    int i, int j) {
   __shared__ double red[KR_NT / 64];
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  const double *pin = (i & 1) ? d.part0 : d.part1;
+  double *pout = (i & 1) ? d.part1 : d.part0;
   double h = 0.0;
   if (i > 0) {
-    h = sum_partials(part_in, nblk, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) Hcol[i - 1] = h;
+    h = sum_partials(pin, d.nblk, red);
+    if (c.b == 0 && threadIdx.x == 0) d.H[i - 1] = h;
   }
-  const size_t chunk = (n + nblk - 1) / nblk;
-  const size_t begin = (size_t)blockIdx.x * chunk;
-  const size_t end = begin + chunk < n ? begin + chunk : n;
-  const double *vp = (i > 0) ? V + (size_t)(i - 1) * n : V;
-  const double *vc = (i <= j) ? V + (size_t)i * n : V;
+  const double *vp = d.V + (size_t)(i > 0 ? i - 1 : 0) * c.n;
+  const double *vc = d.V + (size_t)(i <= j ? i : 0) * c.n;
+  double *w = d.w;
   double acc = 0.0;
-  for (size_t e = begin + threadIdx.x; e < end; e += KR_NT) {
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
     double we = w[e];
     if (i > 0) {
       we = fma(-h, vp[e], we);
@@ -51,99 +70,98 @@ __global__ __launch_bounds__(KR_NT) void k_mgs_step(int i, int j, const double *
     acc = (i <= j) ? fma(vc[e], we, acc) : fma(we, we, acc);
   }
   acc = block_sum<KR_NT>(acc, red);
-  if (threadIdx.x == 0) part_out[blockIdx.x] = acc;
+  if (threadIdx.x == 0) pout[c.b] = acc;
 }
 
-// nrm = sqrt(sum part); dst = src / nrm (0 if nrm == 0); *out_norm = nrm.
-__global__ __launch_bounds__(KR_NT) void k_normalize(const double *__restrict__ src,
-                                                     double *__restrict__ dst, size_t n,
-                                                     const double *__restrict__ part, int nblk,
-                                                     double *__restrict__ out_norm) {
+// nrm = sqrt(sum of part[psel]); dst = src / nrm (0 if nrm == 0).  The norm is stored in
+// H[hidx] if hidx >= 0, else in nrm[0].
+__global__ __launch_bounds__(KR_NT) void k_normalize(const InstDesc *__restrict__ D, ItemMap map,
+                                                     int src_sel, int src_j, int dst_sel, int dst_j,
+                                                     int psel, int hidx) {
   __shared__ double red[KR_NT / 64];
-  const double nrm = sqrt(sum_partials(part, nblk, red));
-  if (blockIdx.x == 0 && threadIdx.x == 0) *out_norm = nrm;
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  const double nrm = sqrt(sum_partials(psel ? d.part1 : d.part0, d.nblk, red));
+  if (c.b == 0 && threadIdx.x == 0) {
+    if (hidx >= 0) d.H[hidx] = nrm;
+    else d.nrm[0] = nrm;
+  }
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (size_t e = (size_t)blockIdx.x * KR_NT + threadIdx.x; e < n; e += (size_t)gridDim.x * KR_NT)
-    dst[e] = src[e] * inv;
+  const double *src = vsel(d, src_sel, src_j);
+  double *dst = vsel(d, dst_sel, dst_j);
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) dst[e] = src[e] * inv;
 }
 
-__global__ __launch_bounds__(KR_NT) void k_residual(const double *__restrict__ b,
-                                                    const double *__restrict__ Mx,
-                                                    double *__restrict__ r, size_t n,
-                                                    double *__restrict__ part, int nblk) {
+// v_0 = b - tmp (tmp = M x), partial <v_0, v_0> into part0.
+__global__ __launch_bounds__(KR_NT) void k_residual(const InstDesc *__restrict__ D, ItemMap map) {
   __shared__ double red[KR_NT / 64];
-  const size_t chunk = (n + nblk - 1) / nblk;
-  const size_t begin = (size_t)blockIdx.x * chunk;
-  const size_t end = begin + chunk < n ? begin + chunk : n;
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
   double acc = 0.0;
-  for (size_t e = begin + threadIdx.x; e < end; e += KR_NT) {
-    const double re = b[e] - Mx[e];
-    r[e] = re;
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
+    const double re = d.b[e] - d.tmp[e];
+    d.V[e] = re;
     acc = fma(re, re, acc);
   }
   acc = block_sum<KR_NT>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (threadIdx.x == 0) d.part0[c.b] = acc;
 }
 
-__global__ __launch_bounds__(KR_NT) void k_dot_partial(const double *__restrict__ x,
-                                                       const double *__restrict__ y, size_t n,
-                                                       double *__restrict__ part, int nblk) {
+__global__ __launch_bounds__(KR_NT) void k_dot_partial(const InstDesc *__restrict__ D, ItemMap map,
+                                                       int xsel, int ysel) {
   __shared__ double red[KR_NT / 64];
-  const size_t chunk = (n + nblk - 1) / nblk;
-  const size_t begin = (size_t)blockIdx.x * chunk;
-  const size_t end = begin + chunk < n ? begin + chunk : n;
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  const double *x = vsel(d, xsel, 0), *y = vsel(d, ysel, 0);
   double acc = 0.0;
-  for (size_t e = begin + threadIdx.x; e < end; e += KR_NT) acc = fma(x[e], y[e], acc);
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) acc = fma(x[e], y[e], acc);
   acc = block_sum<KR_NT>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (threadIdx.x == 0) d.part0[c.b] = acc;
 }
 
-__global__ __launch_bounds__(KR_NT) void k_update_x(double *__restrict__ x,
-                                                    const double *__restrict__ Z,
-                                                    const double *__restrict__ y, int k, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * KR_NT + threadIdx.x; e < n; e += (size_t)gridDim.x * KR_NT) {
-    double acc = x[e];
-    for (int j = 0; j < k; ++j) acc = fma(y[j], Z[(size_t)j * n + e], acc);
-    x[e] = acc;
+// x += sum_{j<k} y[1+j] Z_j with k = (int) y[0].
+__global__ __launch_bounds__(KR_NT) void k_update_x(const InstDesc *__restrict__ D, ItemMap map) {
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  const int k = (int)d.y[0];
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
+    double acc = d.x[e];
+    for (int j = 0; j < k; ++j) acc = fma(d.y[1 + j], d.Z[(size_t)j * c.n + e], acc);
+    d.x[e] = acc;
   }
 }
 
-static int grid_for(size_t n) {
-  size_t g = (n + KR_NT - 1) / KR_NT;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  return (int)g;
-}
-
-hipError_t launch_mgs_step(int i, int j, double *V, double *w, size_t n, const double *part_in,
-                           double *part_out, int nblk, double *Hcol, hipStream_t st) {
-  hipLaunchKernelGGL(k_mgs_step, dim3(nblk), dim3(KR_NT), 0, st, i, j, V, w, n, part_in, part_out,
-                     nblk, Hcol);
-  return hipGetLastError();
-}
-
-hipError_t launch_normalize(const double *src, double *dst, size_t n, const double *part, int nblk,
-                            double *out_norm, hipStream_t st) {
-  hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(KR_NT), 0, st, src, dst, n, part, nblk,
-                     out_norm);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual(const double *b, const double *Mx, double *r, size_t n, double *part,
-                           int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(KR_NT), 0, st, b, Mx, r, n, part, nblk);
-  return hipGetLastError();
-}
-
-hipError_t launch_dot_partial(const double *x, const double *y, size_t n, double *part, int nblk,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(KR_NT), 0, st, x, y, n, part, nblk);
-  return hipGetLastError();
-}
-
-hipError_t launch_update_x(double *x, const double *Z, const double *y, int k, size_t n,
+hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_update_x, dim3(grid_for(n)), dim3(KR_NT), 0, st, x, Z, y, k, n);
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mgs_step, dim3(items), dim3(KR_NT), 0, st, D, map, i, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const InstDesc *D, const ItemMap &map, int items, int src_sel,
+                            int src_j, int dst_sel, int dst_j, int psel, int hidx, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize, dim3(items), dim3(KR_NT), 0, st, D, map, src_sel, src_j, dst_sel,
+                     dst_j, psel, hidx);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3(items), dim3(KR_NT), 0, st, D, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_partial(const InstDesc *D, const ItemMap &map, int items, int xsel, int ysel,
+                              hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dot_partial, dim3(items), dim3(KR_NT), 0, st, D, map, xsel, ysel);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_x, dim3(items), dim3(KR_NT), 0, st, D, map);
   return hipGetLastError();
 }
 

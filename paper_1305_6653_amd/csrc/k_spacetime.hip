@@ -1,4 +1,4 @@
-// Space-time kernels of the all-at-once operator (gfx950):
+// Space-time kernels of the all-at-once operator (gfx950), batched over instances:
 //  * Toeplitz symbol of G_a (eq. (1.5)) by an LDS FFT of its circulant embedding,
 //  * the fused product M z = (A (x) I) z - tau (B (x) J) z of eq. (1.10): for every time
 //    level the banded BVM rows are combined first, then J is applied once through the
@@ -6,6 +6,7 @@
 //  * the right-hand side of the s-form system,
 //  * the real DFT along time that diagonalises s(A), s(B) (Section 3.2), two spatial
 //    columns packed per complex FFT.
+#include "batch.hpp"
 #include "common.hpp"
 #include "fft_lds.hpp"
 #include "kernels.hpp"
@@ -26,80 +27,94 @@ __global__ __launch_bounds__(ST_NT) void k_symbol(const double *__restrict__ cG,
   for (int i = threadIdx.x; i < L; i += ST_NT) chat_br[i] = buf[i];
 }
 
-// One workgroup per time level n.
-//   v = sum_q b[n][q] Z[col_q],  u = sum_q a[n][q] Z[col_q]   (col_q = c[n]+q-1, skip < 0)
-//   FFT(v);  X = chat*V + i conj(chat)*V;  IFFT(X) = L (G v + i G^T v)
-//   W[n][i] = u_i + coefJ * scale/L * (d+_i Re + d-_i Im)
-__global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const double *__restrict__ Z,
-                                                      double *__restrict__ W, DevSpace sp,
-                                                      DevBand bd, double coef) {
+// Item = (instance, row n).
+// mode 0 (M z):  v = sum_q b[n][q] Z[col_q], u = sum_q a[n][q] Z[col_q]  (col_q = c[n]+q-1 >= 0)
+//                W[n] = u - tau J v
+// mode 1 (J x):  W[n] = J Z[n]
+// J v = scale/L * (d+ Re + d- Im) of IFFT(chat*V + i conj(chat)*V) = L (G v + i G^T v).
+__global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict__ D, ItemMap map,
+                                                      int src_sel, int src_j, int dst_sel,
+                                                      int dst_j, int mode) {
   extern __shared__ double2 buf[];
-  const int n = blockIdx.x;
-  const int m = sp.m, L = 1 << sp.log2L;
-  const int c0 = bd.c[n] - 1;
-  const double *ra = bd.a + (size_t)n * bd.mu1;
-  const double *rb = bd.b + (size_t)n * bd.mu1;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = D[map.ids[q]];
+  const int n = blockIdx.x - map.pre[q];
+  const int m = d.m, L = 1 << d.log2L;
+  const double *Z = vsel(d, src_sel, src_j);
+  double *W = vsel(d, dst_sel, dst_j);
+  const int c0 = mode == 0 ? d.band_c[n] - 1 : n;
+  const int nq = mode == 0 ? d.mu1 : 1;
+  const double *ra = d.band_a + (size_t)n * d.mu1;
+  const double *rb = d.band_b + (size_t)n * d.mu1;
   for (int i = threadIdx.x; i < L; i += ST_NT) {
     double v = 0.0;
     if (i < m) {
-      for (int q = 0; q < bd.mu1; ++q) {
-        const int col = c0 + q;
-        if (col >= 0 && col < bd.s) v = fma(rb[q], Z[(size_t)col * m + i], v);
+      for (int t = 0; t < nq; ++t) {
+        const int col = c0 + t;
+        const double bq = mode == 0 ? rb[t] : 1.0;
+        if (col >= 0 && (mode != 0 || col < d.s)) v = fma(bq, Z[(size_t)col * m + i], v);
       }
     }
     buf[i] = make_double2(v, 0.0);
   }
   __syncthreads();
-  fft_dif<ST_NT>(buf, sp.log2L, 1, sp.twL);
+  fft_dif<ST_NT>(buf, d.log2L, 1, d.twL);
   for (int k = threadIdx.x; k < L; k += ST_NT) {
-    const double2 x = buf[k], c = sp.chat_br[k];
+    const double2 x = buf[k], c = d.chat[k];
     const double2 P = cmul(c, x);
-    const double2 Q = cmulc(x, c);
-    buf[k] = make_double2(P.x - Q.y, P.y + Q.x);
+    const double2 Qv = cmulc(x, c);
+    buf[k] = make_double2(P.x - Qv.y, P.y + Qv.x);
   }
   __syncthreads();
-  fft_dit_inv<ST_NT>(buf, sp.log2L, 1, sp.twL);
+  fft_dit_inv<ST_NT>(buf, d.log2L, 1, d.twL);
+  const double coef = (mode == 0 ? -d.tau : 1.0) * d.scale / (double)L;
   for (int i = threadIdx.x; i < m; i += ST_NT) {
     double u = 0.0;
-    for (int q = 0; q < bd.mu1; ++q) {
-      const int col = c0 + q;
-      if (col >= 0 && col < bd.s) u = fma(ra[q], Z[(size_t)col * m + i], u);
+    if (mode == 0) {
+      for (int t = 0; t < d.mu1; ++t) {
+        const int col = c0 + t;
+        if (col >= 0 && col < d.s) u = fma(ra[t], Z[(size_t)col * m + i], u);
+      }
     }
     const double2 y = buf[i];
-    W[(size_t)n * m + i] = fma(coef, fma(sp.dplus[i], y.x, sp.dminus[i] * y.y), u);
+    W[(size_t)n * m + i] = fma(coef, fma(d.dp[i], y.x, d.dm[i] * y.y), u);
   }
 }
 
-__global__ __launch_bounds__(ST_NT) void k_rhs(const double *__restrict__ f,
-                                               const double *__restrict__ u0,
-                                               const double *__restrict__ Ju0,
-                                               double *__restrict__ b, int m, DevBand bd,
-                                               double tau) {
-  const int n = blockIdx.y;
-  const int i = blockIdx.x * ST_NT + threadIdx.x;
-  if (i >= m) return;
-  const int c = bd.c[n];
-  const double *ra = bd.a + (size_t)n * bd.mu1;
-  const double *rb = bd.b + (size_t)n * bd.mu1;
-  double acc = 0.0;
-  for (int q = 0; q < bd.mu1; ++q) acc = fma(rb[q], f[(size_t)(c + q) * m + i], acc);
-  acc *= tau;
-  if (c == 0) {
-    acc = fma(-ra[0], u0[i], acc);
-    if (Ju0 != nullptr) acc = fma(tau * rb[0], Ju0[i], acc);
+// Item = (instance, row n):  b[n] = tau sum_q bhat[n][q] f[c+q] - a0[n] u0 + tau b0[n] Ju0,
+// where a0[n], b0[n] are the coefficients on u_0 (nonzero only when the band starts at u_0).
+__global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, ItemMap map,
+                                               int use_ju0) {
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = D[map.ids[q]];
+  const int n = blockIdx.x - map.pre[q];
+  const int m = d.m, c = d.band_c[n];
+  const double *ra = d.band_a + (size_t)n * d.mu1;
+  const double *rb = d.band_b + (size_t)n * d.mu1;
+  for (int i = threadIdx.x; i < m; i += ST_NT) {
+    double acc = 0.0;
+    for (int t = 0; t < d.mu1; ++t) acc = fma(rb[t], d.f[(size_t)(c + t) * m + i], acc);
+    acc *= d.tau;
+    if (c == 0) {
+      acc = fma(-ra[0], d.u0[i], acc);
+      if (use_ju0 && d.need_ju0) acc = fma(d.tau * rb[0], d.Ju0[i], acc);
+    }
+    d.b[(size_t)n * m + i] = acc;
   }
-  b[(size_t)n * m + i] = acc;
 }
 
-// Time-axis real DFT.  Workgroup = 2*TP spatial columns, TP complex FFTs of length s.
+// Time-axis real DFT.  Item = (instance, group of 2*TP spatial columns); TP complex FFTs of
+// length s per workgroup.
 static constexpr int TP = 8;
 
-__global__ __launch_bounds__(ST_NT) void k_time_rfft(const double *__restrict__ V,
-                                                     double2 *__restrict__ Vh, int m, int mp,
-                                                     int log2s, const double2 *__restrict__ tw) {
+__global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict__ D, ItemMap map,
+                                                     int src_sel, int src_j) {
   extern __shared__ double2 buf[];
-  const int s = 1 << log2s;
-  const int col0 = blockIdx.x * 2 * TP;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = D[map.ids[q]];
+  const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
+  const double *V = vsel(d, src_sel, src_j);
+  const int col0 = (blockIdx.x - map.pre[q]) * 2 * TP;
   for (int e = threadIdx.x; e < s * 2 * TP; e += ST_NT) {
     const int n = e / (2 * TP), c = e % (2 * TP);
     const int col = col0 + c;
@@ -107,7 +122,7 @@ __global__ __launch_bounds__(ST_NT) void k_time_rfft(const double *__restrict__ 
     reinterpret_cast<double *>(&buf[(c >> 1) * s + n])[c & 1] = v;
   }
   __syncthreads();
-  fft_dif<ST_NT>(buf, log2s, TP, tw);
+  fft_dif<ST_NT>(buf, log2s, TP, d.tws);
   const int nbk = s / 2 + 1;
   for (int e = threadIdx.x; e < nbk * 2 * TP; e += ST_NT) {
     const int k = e / (2 * TP), c = e % (2 * TP), f = c >> 1;
@@ -123,16 +138,19 @@ __global__ __launch_bounds__(ST_NT) void k_time_rfft(const double *__restrict__ 
       o = make_double2(0.5 * (Zk.y - Zn.y), -0.5 * (Zk.x - Zn.x));
     }
     if (col >= m) o = make_double2(0.0, 0.0);
-    Vh[(size_t)k * mp + col] = o;
+    d.Vh[(size_t)k * mp + col] = o;
   }
 }
 
-__global__ __launch_bounds__(ST_NT) void k_time_irfft(const double2 *__restrict__ Wh,
-                                                      double *__restrict__ W, int m, int mp,
-                                                      int log2s, const double2 *__restrict__ tw) {
+__global__ __launch_bounds__(ST_NT) void k_time_irfft(const InstDesc *__restrict__ D, ItemMap map,
+                                                      int dst_sel, int dst_j) {
   extern __shared__ double2 buf[];
-  const int s = 1 << log2s;
-  const int col0 = blockIdx.x * 2 * TP;
+  const int q = item_slot(map, blockIdx.x);
+  const InstDesc &d = D[map.ids[q]];
+  const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
+  double *W = vsel(d, dst_sel, dst_j);
+  const double2 *Wh = d.Vh;
+  const int col0 = (blockIdx.x - map.pre[q]) * 2 * TP;
   // position p of the bit-reversed input holds Z[k], k = bitrev(p); Z = What_a + i What_b
   for (int e = threadIdx.x; e < s * TP; e += ST_NT) {
     const int p = e / TP, f = e % TP;
@@ -142,7 +160,10 @@ __global__ __launch_bounds__(ST_NT) void k_time_irfft(const double2 *__restrict_
     if (k <= s / 2) {
       a = Wh[(size_t)k * mp + ca];
       b = Wh[(size_t)k * mp + ca + 1];
-      if (k == 0 || k == s / 2) { a.y = 0.0; b.y = 0.0; }
+      if (k == 0 || k == s / 2) {
+        a.y = 0.0;
+        b.y = 0.0;
+      }
     } else {
       a = cconj(Wh[(size_t)(s - k) * mp + ca]);
       b = cconj(Wh[(size_t)(s - k) * mp + ca + 1]);
@@ -150,7 +171,7 @@ __global__ __launch_bounds__(ST_NT) void k_time_irfft(const double2 *__restrict_
     buf[f * s + p] = make_double2(a.x - b.y, a.y + b.x);
   }
   __syncthreads();
-  fft_dit_inv<ST_NT>(buf, log2s, TP, tw);
+  fft_dit_inv<ST_NT>(buf, log2s, TP, d.tws);
   const double inv_s = 1.0 / (double)s;
   for (int e = threadIdx.x; e < s * 2 * TP; e += ST_NT) {
     const int n = e / (2 * TP), c = e % (2 * TP);
@@ -176,41 +197,45 @@ hipError_t launch_symbol(const double *cG, double2 *chat_br, int log2L, const do
   return hipGetLastError();
 }
 
-hipError_t launch_bvm_matvec(const double *Z, double *W, const DevSpace &sp, const DevBand &bd,
-                             double coefJ, hipStream_t st) {
-  const size_t lds = sizeof(double2) << sp.log2L;
+hipError_t launch_bvm_matvec(const InstDesc *D, const ItemMap &map, int items, int max_log2L,
+                             int src_sel, int src_j, int dst_sel, int dst_j, int mode,
+                             hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double2) << max_log2L;
   hipError_t e = set_lds((const void *)k_bvm_matvec, lds);
   if (e != hipSuccess) return e;
-  const double coef = coefJ * sp.scale / (double)(1 << sp.log2L);
-  hipLaunchKernelGGL(k_bvm_matvec, dim3(bd.s), dim3(ST_NT), lds, st, Z, W, sp, bd, coef);
+  hipLaunchKernelGGL(k_bvm_matvec, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j,
+                     dst_sel, dst_j, mode);
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(const double *f, const double *u0, const double *Ju0, double *b, int m,
-                      const DevBand &bd, double tau, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs, dim3((m + ST_NT - 1) / ST_NT, bd.s), dim3(ST_NT), 0, st, f, u0, Ju0,
-                     b, m, bd, tau);
+hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_ju0,
+                      hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rhs, dim3(items), dim3(ST_NT), 0, st, D, map, use_ju0);
   return hipGetLastError();
 }
 
-hipError_t launch_time_rfft(const double *V, double2 *Vh, int m, int mp, int log2s,
-                            const double2 *tws, hipStream_t st) {
-  const size_t lds = (sizeof(double2) * TP) << log2s;
+hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                            int src_sel, int src_j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = (sizeof(double2) * TP) << max_log2s;
   hipError_t e = set_lds((const void *)k_time_rfft, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_time_rfft, dim3(mp / (2 * TP)), dim3(ST_NT), lds, st, V, Vh, m, mp, log2s,
-                     tws);
+  hipLaunchKernelGGL(k_time_rfft, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j);
   return hipGetLastError();
 }
 
-hipError_t launch_time_irfft(const double2 *Wh, double *W, int m, int mp, int log2s,
-                             const double2 *tws, hipStream_t st) {
-  const size_t lds = (sizeof(double2) * TP) << log2s;
+hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                             int dst_sel, int dst_j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = (sizeof(double2) * TP) << max_log2s;
   hipError_t e = set_lds((const void *)k_time_irfft, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_time_irfft, dim3(mp / (2 * TP)), dim3(ST_NT), lds, st, Wh, W, m, mp,
-                     log2s, tws);
+  hipLaunchKernelGGL(k_time_irfft, dim3(items), dim3(ST_NT), lds, st, D, map, dst_sel, dst_j);
   return hipGetLastError();
 }
+
+int time_fft_cols_per_item() { return 2 * TP; }
 
 }  // namespace fde

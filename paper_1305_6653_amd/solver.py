@@ -188,9 +188,16 @@ class BvmSolver:
         return np.empty(shape, dtype=np.float64)
 
 
+def factor_batch(solvers, precision: str = "fp64"):
+    """fde_precond_factor_batch: one launch per LU phase over the blocks of all solvers."""
+    count = len(solvers)
+    hs = (C.c_void_p * count)(*[s.handle for s in solvers])
+    N.check(N.lib().fde_precond_factor_batch(hs, count, _PREC[precision]))
+
+
 def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit: int = 1000,
-                outs=None):
-    """fde_bvm_solve_batch over already factored solvers; returns (outs, infos)."""
+                outs=None, x0s=None, raise_on_noconv: bool = True):
+    """fde_bvm_solve_batch (or _x0 when x0s is given) over factored solvers; returns (outs, infos)."""
     count = len(solvers)
     if outs is None:
         outs = [BvmSolver._alloc_like(_arg(u, s.m, "u0")[1], (s.s, s.m), u)
@@ -200,6 +207,7 @@ def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit:
     pu0 = (C.c_void_p * count)()
     pf = (C.c_void_p * count)()
     pu = (C.c_void_p * count)()
+    px0 = (C.c_void_p * count)()
     spaces = []
     for i, s in enumerate(solvers):
         a, sa, ka = _arg(u0s[i], s.m, "u0")
@@ -208,8 +216,18 @@ def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit:
         keep += [ka, kb, kc]
         spaces += [sa, sb, sc]
         pu0[i], pf[i], pu[i] = a, b, c
+        if x0s is not None and x0s[i] is not None:
+            d, sd, kd = _arg(x0s[i], s.n, "x0")
+            keep.append(kd)
+            spaces.append(sd)
+            px0[i] = d
     space = _same_space(*spaces)
     opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), None, space)
     infos = (N.FdeSolveInfo * count)()
-    N.check(N.lib().fde_bvm_solve_batch(hs, count, pu0, pf, pu, C.byref(opts), infos))
+    if x0s is None:
+        st = N.lib().fde_bvm_solve_batch(hs, count, pu0, pf, pu, C.byref(opts), infos)
+    else:
+        st = N.lib().fde_bvm_solve_batch_x0(hs, count, pu0, pf, px0, pu, C.byref(opts), infos)
+    if st != N.FDE_OK and (st != N.FDE_ENOCONV or raise_on_noconv):
+        N.check(st)
     return outs, [i.as_dict() for i in infos]

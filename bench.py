@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=30.0,
@@ -115,8 +115,71 @@ def cpu_baseline(p, budget_s):
             "sample": sample, "seconds": round(dt, 3), "iters": res.iters}, res.x
 
 
+def bench_batch(args):
+    """64 uneven instances (seeds 4000..4063), mixed precision; one step = fde_precond_factor_batch
+    + fde_bvm_solve_batch over all of them with inputs resident in HBM."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1305_6653_amd import BvmSolver, factor_batch, solve_batch
+    ps = W.batch_c4(64)
+    dev = torch.device("cuda:0")
+    u0s = [torch.from_numpy(np.ascontiguousarray(p.u0)).to(dev) for p in ps]
+    fs = [torch.from_numpy(np.ascontiguousarray(p.f)).to(dev) for p in ps]
+    outs = [torch.empty((p.s, p.m), dtype=torch.float64, device=dev) for p in ps]
+    Ss = [BvmSolver(p) for p in ps]
+    stream = torch.cuda.current_stream()
+    for S in Ss:
+        S.set_stream(stream)
+    for _ in range(args.warmup):
+        factor_batch(Ss, "mixed")
+        solve_batch(Ss, u0s, fs, outs=outs)
+    torch.cuda.synchronize()
+    lead = Ss[0]
+    lead.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        factor_batch(Ss, "mixed")
+        _, infos = solve_batch(Ss, u0s, fs, outs=outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = {}
+    for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "time_rfft", "time_irfft",
+              "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
+        q = lead.profile_query(k)
+        if q["count"]:
+            prof[k] = q
+    lead.profile(False)
+    flops = sum((p.s // 2 + 1) * 8.0 * p.m ** 3 / 3.0 for p in ps)
+    result = {
+        "metric": METRIC, "value": round(64 * 1000.0 / ms, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c32+f64",
+        "data": "synthetic (seeded random instances, workloads.batch_c4)",
+        "config": {"workload": "batch of 64 uneven instances (seeds 4000..4063), GBDF3, mixed",
+                   "instances": 64, "m_range": [min(p.m for p in ps), max(p.m for p in ps)],
+                   "s_range": [min(p.s for p in ps), max(p.s for p in ps)],
+                   "unknowns_total": sum(p.m * p.s for p in ps), "precision": "mixed", "rtol": 1e-10,
+                   "step": "fde_precond_factor_batch + fde_bvm_solve_batch"},
+        "iters_max": max(i["iters"] for i in infos), "iters_mean": float(np.mean([i["iters"] for i in infos])),
+        "max_true_relres": max(i["true_relres"] for i in infos), "lu_flops": flops,
+        "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4), "count": v["count"] // args.steps}
+                    for k, v in prof.items()},
+        "roofline": roofline(prof, "mixed"), "cpu_baseline": None,
+    }
+    for S in Ss:
+        S.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "c4":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_batch(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards across "
               "GPUs by frequency block, which this build does not run", file=sys.stderr)

@@ -80,12 +80,20 @@ typedef enum { FDE_MEM_HOST = 0, FDE_MEM_DEVICE = 1 } fde_mem_space;
 
 /* rtol: stop when ||b - M u||_2 <= rtol ||b||_2 (true residual, recomputed in FP64).
  * restart: GMRES restart length (1..64).  maxit: total iteration cap.
- * x0: initial guess [s][m] in mem_space, or NULL for zero. */
+ * x0: initial guess [s][m] in mem_space, or NULL for zero.  A guess is first scaled by the
+ *     gamma that minimises ||b - gamma M x0|| (so ||r_0|| <= ||b||: a poor guess never
+ *     starts worse than the zero start).
+ * x0_kind: FDE_X0_SOLUTION (the guess approximates u) or FDE_X0_LOWRANK (the guess
+ *     approximates c = (S - M) u, the part of S u that differs from b; the start is then
+ *     S^{-1}(b + c), which equals u when c is exact).  By Theorem 3.3 S^{-1} M = I + L with
+ *     L supported on the nu + (mu - nu) boundary block rows, so c has only those rows. */
+typedef enum { FDE_X0_SOLUTION = 0, FDE_X0_LOWRANK = 1 } fde_x0_kind;
 typedef struct {
   double rtol;
   int restart, maxit;
   const double *x0;
   int mem_space;
+  int x0_kind;
 } fde_solve_opts;
 
 typedef struct {
@@ -168,6 +176,69 @@ fde_status fde_profile_enable(fde_bvm *h, int enable);
  * FLOP for the LU kernels, bytes for the others) recorded for the kernel named `name`. */
 fde_status fde_profile_query(const fde_bvm *h, const char *name, double *total_ms, int *count,
                              double *work);
+
+/* ---- learned warm start ------------------------------------------------------------
+ * A small network predicts an initial guess x0 of the all-at-once solution from one
+ * instance's data (alpha, d+, d-, f on the grid, u0 = 0); GMRES started from it converges
+ * to the same solution (the true FP64 residual decides), so a poor guess costs iterations,
+ * never accuracy.  Network: three stride-2 width-5 convolutions over the 256 padded
+ * spatial positions (channels = the s+1 time levels of f normalised by its RMS, d+, d-,
+ * alpha-1.5), three fully connected layers, and a fixed synthesis basis
+ * cos(q pi t) sin(p pi x/2) (q < nt, p < nx) that maps the nx*nt coefficients to [s][m].
+ * Convolutions are im2col + GEMM; every GEMM runs on bf16 MFMA with FP32 accumulation;
+ * weights are FP32 masters with bf16 copies; Adam updates the masters.
+ * Parameter layout (FP32 vector): per layer l = conv1..3, fc1..3, W_l [kin][kout] row-major
+ * then b_l [kout]; conv kin = 5*Cin with element (t, c) at t*Cin + c (tap t reads position
+ * 2o + t - 2).  Device arrays: X [N][256][s+4] features, rms [N], T [N][s*m] FP64 targets. */
+typedef struct fde_nn fde_nn;
+typedef struct {
+  int m, s;          /* grid of the instances the network serves (m <= 256)        */
+  int max_batch;     /* largest batch passed to the calls below                     */
+  int conv_ch[3];    /* output channels of the three convolutions                   */
+  int fc[2];         /* widths of the two hidden fully connected layers            */
+  int nx, nt;        /* synthesis basis: nx sine modes in x, nt cosine modes in t  */
+  int seed;          /* initialisation seed                                         */
+} fde_nn_config;
+
+fde_status fde_nn_create(const fde_nn_config *c, fde_nn **out);
+void fde_nn_destroy(fde_nn *n);
+const char *fde_nn_last_error(void);
+fde_status fde_nn_num_params(const fde_nn *n, long long *count);
+/* host FP32 parameter vector in, refreshes the bf16 copies */
+fde_status fde_nn_set_params(fde_nn *n, const float *host);
+/* Replaces the fixed synthesis matrix: host FP32 [nx*nt][s*m] (output = coefficients x basis). */
+fde_status fde_nn_set_basis(fde_nn *n, const float *host);
+/* which = 0 parameters, 1 gradients of the last fde_nn_loss_grad, 2/3 Adam moments */
+fde_status fde_nn_get_params(const fde_nn *n, float *host, int which);
+/* restores Adam moments and step count (checkpoint resume) */
+fde_status fde_nn_set_state(fde_nn *n, const float *m1, const float *m2, int step);
+fde_status fde_nn_get_step(const fde_nn *n, int *step);
+/* Features of B instances: f[b], dp[b], dm[b] are device FP64 arrays ([s+1][m], [m], [m]),
+ * the pointer arrays and alpha[B] are host arrays; X [B][256][s+4] and rms [B] are device. */
+fde_status fde_nn_features(fde_nn *n, int B, const double *const *f, const double *const *dp,
+                           const double *const *dm, const double *alpha, float *X, float *rms);
+/* Forward, relative-MSE loss against T/rms and backward for the rows idx[0..B) (host array,
+ * NULL = rows 0..B-1); gradients are averaged over the batch; *loss (nullable) is the mean. */
+fde_status fde_nn_loss_grad(fde_nn *n, const float *X, const double *T, const float *rms,
+                            const int *idx, int B, float *loss);
+/* One Adam step with the gradients of the last fde_nn_loss_grad. */
+fde_status fde_nn_adam(fde_nn *n, float lr, float beta1, float beta2, float eps);
+/* x0[b] (device FP64 [s][m], host array of pointers) = prediction for row idx[b] times rms. */
+fde_status fde_nn_predict(fde_nn *n, const float *X, const float *rms, const int *idx, int B,
+                          double *const *x0);
+/* host copy of the last forward output (normalised), [B][s*m] FP32 */
+fde_status fde_nn_output(const fde_nn *n, float *host, int B);
+fde_status fde_nn_sync(fde_nn *n);
+
+/* w = S z (the Strang block-circulant of eq. (1.11) applied forward), z and w [s][m]. */
+fde_status fde_bvm_strang_apply(fde_bvm *h, const double *z, double *w, int mem_space);
+/* c = (S - M) z, nonzero only on the nu + (mu - nu) boundary time rows (Theorem 3.3). */
+fde_status fde_bvm_lowrank_correction(fde_bvm *h, const double *z, double *c, int mem_space);
+
+/* Replaces alpha and d+- of a set-up handle (same m, s, grid and formula), recomputing the
+ * weights, the symbol and the eigen-free tables; the stored factorization is discarded. */
+fde_status fde_bvm_set_coefficients(fde_bvm *h, double alpha, const double *d_plus,
+                                    const double *d_minus);
 
 #ifdef __cplusplus
 }

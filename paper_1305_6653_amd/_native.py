@@ -36,9 +36,12 @@ class FdeProblem(C.Structure):
                 ("custom", C.POINTER(FdeBvmFormula))]
 
 
+FDE_X0_SOLUTION, FDE_X0_LOWRANK = 0, 1
+
+
 class FdeSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
-                ("x0", C.c_void_p), ("mem_space", C.c_int)]
+                ("x0", C.c_void_p), ("mem_space", C.c_int), ("x0_kind", C.c_int)]
 
 
 class FdeSolveInfo(C.Structure):
@@ -48,6 +51,12 @@ class FdeSolveInfo(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FdeNnConfig(C.Structure):
+    _fields_ = [("m", C.c_int), ("s", C.c_int), ("max_batch", C.c_int),
+                ("conv_ch", C.c_int * 3), ("fc", C.c_int * 2), ("nx", C.c_int), ("nt", C.c_int),
+                ("seed", C.c_int)]
 
 
 class NativeLibraryMissing(ImportError):
@@ -84,6 +93,26 @@ SIGNATURES = [
     ("fde_get_factor_block", C.c_int, [_VP, C.c_int, _VP]),
     ("fde_profile_enable", C.c_int, [_VP, C.c_int]),
     ("fde_profile_query", C.c_int, [_VP, C.c_char_p, _dp, C.POINTER(C.c_int), _dp]),
+    ("fde_bvm_set_coefficients", C.c_int, [_VP, C.c_double, _dp, _dp]),
+    ("fde_bvm_strang_apply", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_bvm_lowrank_correction", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_nn_set_basis", C.c_int, [_VP, _VP]),
+    ("fde_nn_create", C.c_int, [C.POINTER(FdeNnConfig), C.POINTER(_VP)]),
+    ("fde_nn_destroy", None, [_VP]),
+    ("fde_nn_last_error", C.c_char_p, []),
+    ("fde_nn_num_params", C.c_int, [_VP, C.POINTER(C.c_longlong)]),
+    ("fde_nn_set_params", C.c_int, [_VP, _VP]),
+    ("fde_nn_get_params", C.c_int, [_VP, _VP, C.c_int]),
+    ("fde_nn_set_state", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_nn_get_step", C.c_int, [_VP, C.POINTER(C.c_int)]),
+    ("fde_nn_features", C.c_int, [_VP, C.c_int, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP),
+                                  _dp, _VP, _VP]),
+    ("fde_nn_loss_grad", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(C.c_int), C.c_int,
+                                   C.POINTER(C.c_float)]),
+    ("fde_nn_adam", C.c_int, [_VP, C.c_float, C.c_float, C.c_float, C.c_float]),
+    ("fde_nn_predict", C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_int), C.c_int, C.POINTER(_VP)]),
+    ("fde_nn_output", C.c_int, [_VP, _VP, C.c_int]),
+    ("fde_nn_sync", C.c_int, [_VP]),
 ]
 
 _lib = None
@@ -127,4 +156,10 @@ def lib():
 def check(status: int) -> int:
     if status != FDE_OK:
         raise FdeError(status, lib().fde_last_error().decode(errors="replace"))
+    return status
+
+
+def check_nn(status: int) -> int:
+    if status != FDE_OK:
+        raise FdeError(status, lib().fde_nn_last_error().decode(errors="replace"))
     return status

@@ -10,7 +10,7 @@ namespace fde {
 
 struct InstDesc {
   // sizes
-  int m, s, mp, nb, npan, log2L, log2s, mu1;
+  int m, s, mp, nb, npan, log2L, log2s, mu1, nu;
   int W;     // workgroups per block in the cooperative block solve
   int nblk;  // Krylov reduction blocks
   int need_ju0;  // the right-hand side uses J u_0 (a u_0 coefficient in B)

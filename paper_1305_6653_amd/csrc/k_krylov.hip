@@ -108,7 +108,7 @@ __global__ __launch_bounds__(KR_NT) void k_residual(const InstDesc *__restrict__
 }
 
 __global__ __launch_bounds__(KR_NT) void k_dot_partial(const InstDesc *__restrict__ D, ItemMap map,
-                                                       int xsel, int ysel) {
+                                                       int xsel, int ysel, int psel) {
   __shared__ double red[KR_NT / 64];
   const Chunk c = chunk_of(D, map);
   const InstDesc &d = *c.d;
@@ -116,7 +116,32 @@ __global__ __launch_bounds__(KR_NT) void k_dot_partial(const InstDesc *__restric
   double acc = 0.0;
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) acc = fma(x[e], y[e], acc);
   acc = block_sum<KR_NT>(acc, red);
-  if (threadIdx.x == 0) d.part0[c.b] = acc;
+  if (threadIdx.x == 0) (psel ? d.part1 : d.part0)[c.b] = acc;
+}
+
+// dst += a * src (vector selectors)
+__global__ __launch_bounds__(KR_NT) void k_axpy(const InstDesc *__restrict__ D, ItemMap map,
+                                                int dst_sel, int src_sel, double a) {
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  double *dst = vsel(d, dst_sel, 0);
+  const double *src = vsel(d, src_sel, 0);
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) dst[e] = fma(a, src[e], dst[e]);
+}
+
+hipError_t launch_axpy(const InstDesc *D, const ItemMap &map, int items, int dst_sel, int src_sel,
+                       double a, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(items), dim3(KR_NT), 0, st, D, map, dst_sel, src_sel, a);
+  return hipGetLastError();
+}
+
+// x *= y[0]  (per-instance factor)
+__global__ __launch_bounds__(KR_NT) void k_scale_x(const InstDesc *__restrict__ D, ItemMap map) {
+  const Chunk c = chunk_of(D, map);
+  const InstDesc &d = *c.d;
+  const double g = d.y[0];
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) d.x[e] *= g;
 }
 
 // x += sum_{j<k} y[1+j] Z_j with k = (int) y[0].
@@ -153,9 +178,15 @@ hipError_t launch_residual(const InstDesc *D, const ItemMap &map, int items, hip
 }
 
 hipError_t launch_dot_partial(const InstDesc *D, const ItemMap &map, int items, int xsel, int ysel,
-                              hipStream_t st) {
+                              int psel, hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dot_partial, dim3(items), dim3(KR_NT), 0, st, D, map, xsel, ysel);
+  hipLaunchKernelGGL(k_dot_partial, dim3(items), dim3(KR_NT), 0, st, D, map, xsel, ysel, psel);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_x, dim3(items), dim3(KR_NT), 0, st, D, map);
   return hipGetLastError();
 }
 

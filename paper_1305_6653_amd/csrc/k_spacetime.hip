@@ -31,7 +31,50 @@ __global__ __launch_bounds__(ST_NT) void k_symbol(const double *__restrict__ cG,
 // mode 0 (M z):  v = sum_q b[n][q] Z[col_q], u = sum_q a[n][q] Z[col_q]  (col_q = c[n]+q-1 >= 0)
 //                W[n] = u - tau J v
 // mode 1 (J x):  W[n] = J Z[n]
+// mode 2 (S z):  the Strang circulant rows: every row carries the main formula on the
+//                wrapped columns (n - nu + q) mod s:  W[n] = u_S - tau J v_S
+// mode 3 ((S - M) z): W[n] = (u_S - u) - tau J (v_S - v); nonzero only on the nu + (mu-nu)
+//                boundary rows where the circulant and the BVM matrices differ.
 // J v = scale/L * (d+ Re + d- Im) of IFFT(chat*V + i conj(chat)*V) = L (G v + i G^T v).
+__device__ __forceinline__ void band_combo(const InstDesc &d, const double *Z, int n, int mode, int i,
+                                           double &u, double &v) {
+  const int m = d.m, s = d.s, mu1 = d.mu1;
+  u = 0.0;
+  v = 0.0;
+  if (mode == 1) {
+    v = Z[(size_t)n * m + i];
+    return;
+  }
+  if (mode != 2) {  // BVM rows (subtracted in mode 3)
+    const int c0 = d.band_c[n] - 1;
+    const double *ra = d.band_a + (size_t)n * mu1;
+    const double *rb = d.band_b + (size_t)n * mu1;
+    for (int t = 0; t < mu1; ++t) {
+      const int col = c0 + t;
+      if (col >= 0 && col < s) {
+        const double z = Z[(size_t)col * m + i];
+        u = fma(ra[t], z, u);
+        v = fma(rb[t], z, v);
+      }
+    }
+    if (mode == 3) {
+      u = -u;
+      v = -v;
+    }
+  }
+  if (mode >= 2) {  // circulant rows: main formula (stored in s-form row nu-1) wrapped mod s
+    const double *ra = d.band_a + (size_t)(d.nu - 1) * mu1;
+    const double *rb = d.band_b + (size_t)(d.nu - 1) * mu1;
+    for (int t = 0; t < mu1; ++t) {
+      int col = (n - d.nu + t) % s;
+      if (col < 0) col += s;
+      const double z = Z[(size_t)col * m + i];
+      u = fma(ra[t], z, u);
+      v = fma(rb[t], z, v);
+    }
+  }
+}
+
 __global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict__ D, ItemMap map,
                                                       int src_sel, int src_j, int dst_sel,
                                                       int dst_j, int mode) {
@@ -42,19 +85,15 @@ __global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict
   const int m = d.m, L = 1 << d.log2L;
   const double *Z = vsel(d, src_sel, src_j);
   double *W = vsel(d, dst_sel, dst_j);
-  const int c0 = mode == 0 ? d.band_c[n] - 1 : n;
-  const int nq = mode == 0 ? d.mu1 : 1;
-  const double *ra = d.band_a + (size_t)n * d.mu1;
-  const double *rb = d.band_b + (size_t)n * d.mu1;
+  if (mode == 3 && n >= d.nu && n < d.s - (d.mu1 - 1 - d.nu)) {
+    // interior row: S and M apply the same main formula without wrap-around, so the
+    // difference is exactly zero (uniform per workgroup, before any barrier)
+    for (int i = threadIdx.x; i < m; i += ST_NT) W[(size_t)n * m + i] = 0.0;
+    return;
+  }
   for (int i = threadIdx.x; i < L; i += ST_NT) {
-    double v = 0.0;
-    if (i < m) {
-      for (int t = 0; t < nq; ++t) {
-        const int col = c0 + t;
-        const double bq = mode == 0 ? rb[t] : 1.0;
-        if (col >= 0 && (mode != 0 || col < d.s)) v = fma(bq, Z[(size_t)col * m + i], v);
-      }
-    }
+    double u, v = 0.0;
+    if (i < m) band_combo(d, Z, n, mode, i, u, v);
     buf[i] = make_double2(v, 0.0);
   }
   __syncthreads();
@@ -67,15 +106,10 @@ __global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict
   }
   __syncthreads();
   fft_dit_inv<ST_NT>(buf, d.log2L, 1, d.twL);
-  const double coef = (mode == 0 ? -d.tau : 1.0) * d.scale / (double)L;
+  const double coef = (mode == 1 ? 1.0 : -d.tau) * d.scale / (double)L;
   for (int i = threadIdx.x; i < m; i += ST_NT) {
-    double u = 0.0;
-    if (mode == 0) {
-      for (int t = 0; t < d.mu1; ++t) {
-        const int col = c0 + t;
-        if (col >= 0 && col < d.s) u = fma(ra[t], Z[(size_t)col * m + i], u);
-      }
-    }
+    double u, v;
+    band_combo(d, Z, n, mode, i, u, v);
     const double2 y = buf[i];
     W[(size_t)n * m + i] = fma(coef, fma(d.dp[i], y.x, d.dm[i] * y.y), u);
   }

@@ -59,7 +59,12 @@ hipError_t launch_normalize(const InstDesc *D, const ItemMap &map, int items, in
                             int src_j, int dst_sel, int dst_j, int psel, int hidx, hipStream_t st);
 hipError_t launch_residual(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 hipError_t launch_dot_partial(const InstDesc *D, const ItemMap &map, int items, int xsel, int ysel,
-                              hipStream_t st);
+                              int psel, hipStream_t st);
+// dst += a src (vector selectors)
+hipError_t launch_axpy(const InstDesc *D, const ItemMap &map, int items, int dst_sel, int src_sel,
+                       double a, hipStream_t st);
+// x *= y[0] per instance
+hipError_t launch_scale_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 
 }  // namespace fde

@@ -319,6 +319,7 @@ static InstDesc make_desc(fde_bvm *h) {
   d.log2L = h->log2L;
   d.log2s = h->log2s;
   d.mu1 = h->mu + 1;
+  d.nu = h->nu;
   d.W = 1;
   d.nblk = h->nblk;
   d.need_ju0 = h->need_Ju0 ? 1 : 0;
@@ -711,6 +712,37 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
   return FDE_OK;
 }
 
+extern "C" fde_status fde_bvm_set_coefficients(fde_bvm *h, double alpha, const double *d_plus,
+                                               const double *d_minus) {
+  if (!h || !d_plus || !d_minus) return fail(FDE_EINVAL, "NULL argument");
+  if (!(alpha > 1.0 && alpha < 2.0)) return fail(FDE_EINVAL, "alpha must lie in (1,2), got %g", alpha);
+  if (!finite_all(d_plus, h->m) || !finite_all(d_minus, h->m))
+    return fail(FDE_EINVAL, "non-finite diffusion coefficient");
+  for (int i = 0; i < h->m; ++i)
+    if (d_plus[i] < 0.0 || d_minus[i] < 0.0 || !(d_plus[i] + d_minus[i] > 0.0))
+      return fail(FDE_EINVAL, "d+- must be nonnegative with a positive sum (node %d)", i + 1);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->alpha = alpha;
+  h->scale = std::pow(h->dx, -alpha);
+  h->dp.assign(d_plus, d_plus + h->m);
+  h->dm.assign(d_minus, d_minus + h->m);
+  h->g.assign(h->m + 1, 0.0);
+  h->g[0] = 1.0;
+  for (int k = 0; k < h->m; ++k) h->g[k + 1] = (1.0 - (alpha + 1.0) / (k + 1.0)) * h->g[k];
+  std::vector<double> cG(h->L, 0.0);
+  for (int i = 0; i < h->m; ++i) cG[i] = h->g[i + 1];
+  cG[h->L - 1] = h->g[0];
+  HIPCHK(hipMemcpy(h->d_g, h->g.data(), sizeof(double) * (h->m + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_dp, h->dp.data(), sizeof(double) * h->m, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_dm, h->dm.data(), sizeof(double) * h->m, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_cG, cG.data(), sizeof(double) * h->L, hipMemcpyHostToDevice));
+  HIPCHK(launch_symbol(h->d_cG, h->d_chat, h->log2L, h->d_twL, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->prec = -1;
+  h->self->desc_dirty = true;
+  return FDE_OK;
+}
+
 extern "C" void fde_bvm_destroy(fde_bvm *h) { destroy_handle(h); }
 extern "C" const char *fde_last_error(void) { return g_err.c_str(); }
 
@@ -981,7 +1013,16 @@ struct InstState {
   std::vector<double> H, cs, sn, g, y;
 };
 
-static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, std::vector<InstState> &st) {
+// Sum of an instance's chunk partials (part0 or part1) in index order.
+static double part_sum(const Plan *P, const std::vector<double> &parts, int i, int psel) {
+  double t = 0.0;
+  const size_t base = P->part_off[i] + (psel ? P->hs[i]->nblk : 0);
+  for (int q = 0; q < P->hs[i]->nblk; ++q) t += parts[base + q];
+  return t;
+}
+
+static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector<char> &has_x0,
+                             std::vector<InstState> &st) {
   fde_bvm *L = P->lead;
   const int count = (int)P->hs.size();
   const int R = o.restart;
@@ -993,16 +1034,42 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, std::vector<InstS
   STCHK(build_solve_maps(P, all, S));
   // right-hand sides and their norms
   STCHK(op_rhs(P, S));
-  HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_B, stream); }));
+  HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_B, 0, stream); }));
   size_t nparts = 0;
   for (fde_bvm *h : P->hs) nparts += 2 * (size_t)h->nblk;
   std::vector<double> parts(nparts), hbuf((size_t)count * (R + 2)), nrm((size_t)count * 2);
   HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
   STCHK(sync_and_flush(L));
+  std::vector<double> bsq(count);
+  for (int i = 0; i < count; ++i) bsq[i] = part_sum(P, parts, i, 0);
+  // An initial guess is first scaled by the gamma minimising ||b - gamma M x0|| (one step of
+  // minimal residual along x0), so that ||r_0|| <= ||b||: a poor guess never starts worse
+  // than the zero start.
+  std::vector<int> with_x0;
+  for (int i = 0; i < count; ++i)
+    if (has_x0[i]) with_x0.push_back(i);
+  if (!with_x0.empty()) {
+    STCHK(build_solve_maps(P, with_x0, S));
+    if (o.x0_kind == FDE_X0_LOWRANK) {  // x holds c: start from S^{-1}(b + c)
+      HIPCHK(run(L, "axpy", 3.0 * S.vec_bytes, [&] { return launch_axpy(P->d_desc, S.kry, S.n_kry, VS_X, VS_B, 1.0, stream); }));
+      STCHK(op_precond(P, S, VS_X, 0, VS_X, 0));
+    }
+    STCHK(op_matvec(P, S, VS_X, 0, VS_TMP, 0));
+    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_TMP, 0, stream); }));
+    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_TMP, VS_TMP, 1, stream); }));
+    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
+    STCHK(sync_and_flush(L));
+    std::vector<double> ybuf((size_t)count * (R + 1), 0.0);
+    for (int i : with_x0) {
+      const double bm = part_sum(P, parts, i, 0), mm = part_sum(P, parts, i, 1);
+      ybuf[(size_t)i * (R + 1)] = (mm > 0.0 && std::isfinite(bm / mm)) ? bm / mm : 0.0;
+    }
+    HIPCHK(hipMemcpy(P->d_y, ybuf.data(), ybuf.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(run(L, "scale_x", 2.0 * S.vec_bytes, [&] { return launch_scale_x(P->d_desc, S.kry, S.n_kry, stream); }));
+    STCHK(build_solve_maps(P, all, S));
+  }
   for (int i = 0; i < count; ++i) {
-    double t = 0;
-    for (int q = 0; q < P->hs[i]->nblk; ++q) t += parts[P->part_off[i] + q];
-    st[i].bnorm = std::sqrt(t);
+    st[i].bnorm = std::sqrt(bsq[i]);
     st[i].H.assign((size_t)(R + 1) * R, 0.0);
     st[i].cs.assign(R, 0.0);
     st[i].sn.assign(R, 0.0);
@@ -1133,8 +1200,10 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, std::vector<InstS
 }
 
 static fde_status check_opts(const fde_solve_opts *o, fde_solve_opts *out) {
-  fde_solve_opts d{1e-10, 20, 1000, nullptr, FDE_MEM_HOST};
+  fde_solve_opts d{1e-10, 20, 1000, nullptr, FDE_MEM_HOST, FDE_X0_SOLUTION};
   if (o) d = *o;
+  if (d.x0_kind != FDE_X0_SOLUTION && d.x0_kind != FDE_X0_LOWRANK)
+    return fail(FDE_EINVAL, "unknown x0_kind %d", d.x0_kind);
   if (!(d.rtol > 0.0) || !std::isfinite(d.rtol)) return fail(FDE_EINVAL, "rtol must be positive");
   if (d.restart < 1 || d.restart > 64) return fail(FDE_EINVAL, "restart must be in 1..64");
   if (d.maxit < 0) return fail(FDE_EINVAL, "maxit must be >= 0");
@@ -1183,7 +1252,9 @@ static fde_status solve_plan(Plan *P, const double *const *u0, const double *con
     else HIPCHK(hipMemsetAsync(h->d_x, 0, h->n() * sizeof(double), L->stream));
   }
   std::vector<InstState> st(count);
-  fde_status gs = gmres_plan(P, o, st);
+  std::vector<char> has_x0(count, 0);
+  for (int i = 0; i < count; ++i) has_x0[i] = (x0 && x0[i]) ? 1 : 0;
+  fde_status gs = gmres_plan(P, o, has_x0, st);
   if (gs != FDE_OK && gs != FDE_ENOCONV) return gs;
   const std::string msg = g_err;
   for (int i = 0; i < count; ++i) STCHK(copy_out(L, u[i], P->hs[i]->d_x, P->hs[i]->n(), o.mem_space));
@@ -1309,6 +1380,29 @@ extern "C" fde_status fde_apply_matvec(fde_bvm *h, const double *z, double *w, i
   STCHK(op_matvec(h->self, S, VS_SIO, 0, VS_TMP, 0));
   STCHK(copy_out(h, w, h->d_tmp, h->n(), mem_space));
   return sync_and_flush(h);
+}
+
+static fde_status self_band_op(fde_bvm *h, const double *z, double *w, int mem_space, int mode,
+                               const char *name) {
+  if (!h || !z || !w) return fail(FDE_EINVAL, "NULL argument");
+  if (mem_space != FDE_MEM_HOST && mem_space != FDE_MEM_DEVICE) return fail(FDE_EINVAL, "bad mem_space");
+  SolveMaps S;
+  STCHK(self_maps(h, S));
+  STCHK(copy_in(h, h->d_sio, z, h->n(), mem_space));
+  HIPCHK(run(h, name, 16.0 * h->n(), [&] {
+    return launch_bvm_matvec(h->self->d_desc, S.mv, S.n_mv, S.max_log2L, VS_SIO, 0, VS_TMP, 0, mode,
+                             h->stream);
+  }));
+  STCHK(copy_out(h, w, h->d_tmp, h->n(), mem_space));
+  return sync_and_flush(h);
+}
+
+extern "C" fde_status fde_bvm_strang_apply(fde_bvm *h, const double *z, double *w, int mem_space) {
+  return self_band_op(h, z, w, mem_space, 2, "strang_apply");
+}
+
+extern "C" fde_status fde_bvm_lowrank_correction(fde_bvm *h, const double *z, double *c, int mem_space) {
+  return self_band_op(h, z, c, mem_space, 3, "lowrank_correction");
 }
 
 extern "C" fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, int mem_space) {

@@ -106,8 +106,9 @@ class BvmSolver:
         N.check(N.lib().fde_precond_factor(self._h, _PREC[precision]))
 
     def solve(self, u0, f, x0=None, out=None, rtol: float = 1e-10, restart: int = 20,
-              maxit: int = 1000, raise_on_noconv: bool = True):
-        """Returns (u [s][m], info dict).  u0 [m], f [s+1][m], x0 [s][m] or None."""
+              maxit: int = 1000, raise_on_noconv: bool = True, x0_kind: int = N.FDE_X0_SOLUTION):
+        """Returns (u [s][m], info dict).  u0 [m], f [s+1][m], x0 [s][m] or None
+        (x0_kind: FDE_X0_SOLUTION, or FDE_X0_LOWRANK for a guess of (S - M) u)."""
         pu0, s1, k1 = _arg(u0, self.m, "u0")
         pf, s2, k2 = _arg(f, (self.s + 1) * self.m, "f")
         sx = None
@@ -119,7 +120,7 @@ class BvmSolver:
             out = self._alloc_like(space, (self.s, self.m), u0)
         pu, so, k4 = _arg(out, self.n, "out", writable=True)
         _same_space(space, so)
-        opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), px0, space)
+        opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), px0, space, int(x0_kind))
         info = N.FdeSolveInfo()
         st = N.lib().fde_bvm_solve(self._h, pu0, pf, pu, C.byref(opts), C.byref(info))
         if st != N.FDE_OK and (st != N.FDE_ENOCONV or raise_on_noconv):
@@ -142,6 +143,27 @@ class BvmSolver:
         pw, _, _b = _arg(out, self.n, "out", writable=True)
         N.check(N.lib().fde_apply_matvec(self._h, pz, pw, space))
         return out
+
+    def strang_apply(self, z, out=None):
+        """w = S z (forward Strang block-circulant)."""
+        return self._band_op(N.lib().fde_bvm_strang_apply, z, out)
+
+    def lowrank_correction(self, z, out=None):
+        """c = (S - M) z, supported on the boundary time rows."""
+        return self._band_op(N.lib().fde_bvm_lowrank_correction, z, out)
+
+    def _band_op(self, fn, z, out):
+        pz, space, _a = _arg(z, self.n, "z")
+        out = self._alloc_like(space, (self.s, self.m), z) if out is None else out
+        pw, _, _b = _arg(out, self.n, "out", writable=True)
+        N.check(fn(self._h, pz, pw, space))
+        return out
+
+    def set_coefficients(self, alpha: float, d_plus, d_minus):
+        dp = np.ascontiguousarray(d_plus, dtype=np.float64)
+        dm = np.ascontiguousarray(d_minus, dtype=np.float64)
+        N.check(N.lib().fde_bvm_set_coefficients(self._h, float(alpha), dp.ctypes.data_as(N._dp),
+                                                  dm.ctypes.data_as(N._dp)))
 
     def precond(self, v, out=None):
         pv, space, _a = _arg(v, self.n, "v")
@@ -196,7 +218,7 @@ def factor_batch(solvers, precision: str = "fp64"):
 
 
 def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit: int = 1000,
-                outs=None, x0s=None, raise_on_noconv: bool = True):
+                outs=None, x0s=None, raise_on_noconv: bool = True, x0_kind: int = N.FDE_X0_SOLUTION):
     """fde_bvm_solve_batch (or _x0 when x0s is given) over factored solvers; returns (outs, infos)."""
     count = len(solvers)
     if outs is None:
@@ -222,7 +244,7 @@ def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit:
             spaces.append(sd)
             px0[i] = d
     space = _same_space(*spaces)
-    opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), None, space)
+    opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), None, space, int(x0_kind))
     infos = (N.FdeSolveInfo * count)()
     if x0s is None:
         st = N.lib().fde_bvm_solve_batch(hs, count, pu0, pf, pu, C.byref(opts), infos)

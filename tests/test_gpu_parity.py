@@ -70,6 +70,24 @@ def test_rhs_and_matvec_vs_oracle(name):
     assert _rel(w, O.apply_M(J, A, B, tau, Z)) <= 1e-13
 
 
+@pytest.mark.parametrize("name", ["gbdf3_m7_s8", "trap_m130_s16", "gbdf3_m200_s32"])
+def test_strang_forward_and_lowrank_correction(name):
+    """S z (eq. (1.11) applied forward) and (S - M) z, whose support is the nu + (mu - nu)
+    boundary block rows of Theorem 3.3."""
+    p, S = _setup(name)
+    J, F, tau, _ = O.problem_matrices(p)
+    Sd = O.strang_dense(J, F, p.s, tau)
+    M, _ = O.problem_system(p)
+    z = np.random.default_rng(6).standard_normal((p.s, p.m))
+    assert _rel(S.strang_apply(z).reshape(-1), Sd @ z.reshape(-1)) <= 1e-13
+    c = S.lowrank_correction(z)
+    assert _rel(c.reshape(-1), (Sd - M) @ z.reshape(-1)) <= 1e-13
+    rows = sorted(set(range(F.nu)) | set(range(p.s - (F.mu - F.nu), p.s)))
+    mask = np.ones(p.s, bool)
+    mask[rows] = False
+    assert np.all(c[mask] == 0.0)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
 @pytest.mark.parametrize("name", ["gbdf3_m7_s8", "trap_m63_s64_manufactured", "gbdf3_m200_s32",
                                   "trap_m130_s16"])
@@ -131,8 +149,18 @@ def test_deterministic_and_warm_start():
     u1, i1 = S.solve(p.u0, p.f)
     u2, i2 = S.solve(p.u0, p.f)
     assert np.array_equal(u1, u2) and i1["iters"] == i2["iters"]
-    u3, i3 = S.solve(p.u0, p.f, x0=u1)
-    assert i3["iters"] == 0 and np.array_equal(u3, u1)
+    u3, i3 = S.solve(p.u0, p.f, x0=u1)    # the guess is projected (gamma ~ 1), no iteration
+    assert i3["iters"] == 0 and _rel(u3, u1) <= 1e-12 and i3["true_relres"] <= 1e-10
+
+
+def test_lowrank_start_with_exact_correction_needs_no_iteration():
+    """x0_kind = LOWRANK: with the exact c = (S - M) u the start S^{-1}(b + c) is u itself."""
+    p, S = _setup("gbdf3_m200_s32")
+    S.factor("fp64")
+    u, _ = S.solve(p.u0, p.f, rtol=1e-12)
+    c = S.lowrank_correction(u)
+    u2, info = S.solve(p.u0, p.f, x0=c, x0_kind=N.FDE_X0_LOWRANK)
+    assert info["iters"] == 0 and _rel(u2, u) <= 1e-10
 
 
 def test_errors_and_noconv():

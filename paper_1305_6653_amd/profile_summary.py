@@ -1,9 +1,21 @@
-"""Summarise a rocprofv3 kernel-trace database (rocpd SQLite) as a short text table.
+"""Summaries of rocprofv3 output as short text tables.
 
-    python -m paper_1305_6653_amd.profile_summary <results.db> [--title T] [--command C]
+Kernel trace (rocpd SQLite database written by ``rocprofv3 --kernel-trace --stats``):
+
+    python -m paper_1305_6653_amd.profile_summary trace <results.db> [--title T] [--command C]
+
+Hardware counters (CSV written by ``rocprofv3 --pmc FETCH_SIZE -f csv`` and, in a second run,
+``--pmc WRITE_SIZE``): average KiB per dispatch per kernel, and the same figures scaled to bytes
+by a reference copy dispatch of known size (the largest dispatch whose name matches
+``--copy-kernel``, which read and wrote ``--copy-bytes`` bytes):
+
+    python -m paper_1305_6653_amd.profile_summary pmc <fetch.csv> <write.csv> --copy-bytes N
 """
 import argparse
+import csv
+import re
 import sqlite3
+from collections import defaultdict
 
 
 def summarise(db: str, top: int = 25):
@@ -17,12 +29,11 @@ def summarise(db: str, top: int = 25):
     return rows[:top], total
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("--title", default="")
-    ap.add_argument("--command", default="")
-    a = ap.parse_args()
+def short_name(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def trace_main(a):
     rows, total = summarise(a.db)
     if a.title:
         print(a.title)
@@ -31,9 +42,96 @@ def main():
     print(f"{'kernel':58s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'min_us':>9s} "
           f"{'max_us':>9s} {'pct':>6s} {'vgpr':>5s} {'agpr':>5s} {'lds':>7s} {'grid':>10s} {'wg':>5s}")
     for name, n, tot, avg, mn, mx, vg, ag, lds, grid, wg in rows:
-        short = name.split("(")[0].replace("void ", "")[:58]
+        short = short_name(name)[:58]
         print(f"{short:58s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:10.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f} "
               f"{100 * tot / total:6.2f} {vg:5d} {ag:5d} {lds:7d} {grid:10d} {wg:5d}")
+
+
+def _col(header, *keys):
+    for k in keys:
+        for i, h in enumerate(header):
+            if h.strip().lower() == k.lower():
+                return i
+    raise KeyError(f"none of {keys} in CSV header {header}")
+
+
+def read_counter(path: str, counter: str):
+    """{dispatch id: (kernel name, value)} for one counter of a counter-collection CSV."""
+    out = {}
+    with open(path, newline="") as fh:
+        rd = csv.reader(fh)
+        header = next(rd)
+        ik = _col(header, "Kernel_Name", "Kernel-Name", "KernelName")
+        ic = _col(header, "Counter_Name", "Counter-Name")
+        iv = _col(header, "Counter_Value", "Counter-Value")
+        idd = _col(header, "Dispatch_Id", "Dispatch-Id", "Correlation_Id")
+        for row in rd:
+            if row[ic].strip() != counter:
+                continue
+            d = row[idd]
+            name, v = row[ik], float(row[iv])
+            prev = out.get(d)
+            out[d] = (name, v + (prev[1] if prev else 0.0))
+    return out
+
+
+def pmc_main(a):
+    fetch = read_counter(a.fetch_csv, "FETCH_SIZE")
+    write = read_counter(a.write_csv, "WRITE_SIZE")
+    pat = re.compile(a.copy_kernel)
+
+    def largest_copy(tab):
+        cands = [v for (n, v) in tab.values() if pat.search(n)]
+        if not cands:
+            raise SystemExit(f"no dispatch matches {a.copy_kernel!r}")
+        return max(cands)
+
+    kib = a.copy_bytes / 1024.0
+    f_scale = kib / largest_copy(fetch)
+    w_scale = kib / largest_copy(write)
+    agg = defaultdict(lambda: [0, 0.0, 0, 0.0])
+    for n, v in fetch.values():
+        e = agg[short_name(n)]
+        e[0] += 1
+        e[1] += v
+    for n, v in write.values():
+        e = agg[short_name(n)]
+        e[2] += 1
+        e[3] += v
+    if a.title:
+        print(a.title)
+    for c in a.command or []:
+        print(f"command: {c}")
+    print(f"reference copy: {a.copy_bytes} bytes read and written; FETCH_SIZE scale {f_scale:.4f}, "
+          f"WRITE_SIZE scale {w_scale:.4f} (bytes = KiB counter x 1024 x scale)")
+    print(f"{'kernel':44s} {'disp':>6s} {'FETCH_KiB/disp':>15s} {'WRITE_KiB/disp':>15s} "
+          f"{'read_MB/disp':>13s} {'write_MB/disp':>13s} {'HBM_MB/disp':>12s}")
+    rows = sorted(agg.items(), key=lambda kv: -(kv[1][1] + kv[1][3]))
+    for name, (nf, sf, nw, sw) in rows[:a.top]:
+        fa = sf / nf if nf else 0.0
+        wa = sw / nw if nw else 0.0
+        rb = fa * 1024 * f_scale / 1e6
+        wb = wa * 1024 * w_scale / 1e6
+        print(f"{name[:44]:44s} {max(nf, nw):6d} {fa:15.1f} {wa:15.1f} {rb:13.3f} {wb:13.3f} {rb + wb:12.3f}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--title", default="")
+    t.add_argument("--command", default="")
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("--copy-bytes", type=float, required=True)
+    p.add_argument("--copy-kernel", default="copyBuffer")
+    p.add_argument("--title", default="")
+    p.add_argument("--command", action="append")
+    p.add_argument("--top", type=int, default=25)
+    a = ap.parse_args()
+    trace_main(a) if a.mode == "trace" else pmc_main(a)
 
 
 if __name__ == "__main__":

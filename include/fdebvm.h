@@ -151,6 +151,36 @@ fde_status fde_set_stream(fde_bvm *h, void *stream);
 /* dims[0..5] = m, s, mu, nu1, nb = s/2+1, padded block order mp. */
 fde_status fde_get_dims(const fde_bvm *h, int *dims);
 
+/* ---- execution options -------------------------------------------------------------
+ * A solve runs its restart steps and restart cycles as fixed launch sequences driven by
+ * per-instance control records on the device (Givens rotations, convergence tests and the
+ * least-squares update happen there; finished instances are gated off), so the host reads
+ * the state once per cycle.  The sequences are recorded once per plan as hipGraphs and
+ * replayed; if recording fails they are launched directly, with identical results.
+ *   FDE_OPT_GRAPHS        1 (default): replay recorded sequences; 0: launch directly.
+ *   FDE_OPT_AUTOTUNE      1 (default): on the first solve of a shape (the sizes of all
+ *                         instances of the call and the precision), time the cooperative
+ *                         block solve for every candidate number of workgroups per block and
+ *                         keep the fastest for the life of the process.
+ *   FDE_OPT_TRSV_W        0 (default): autotuned or the largest co-resident value;
+ *                         k > 0: at most k workgroups per block (clamped to what fits).
+ *   FDE_OPT_TRSV_W_IN_USE read-only: workgroups per block of the handle's last plan.
+ *   FDE_OPT_GRAPHS_IN_USE read-only: 1 if the handle's solves replay recorded sequences.
+ * Options of the first handle of a batch call apply to the call.  Setting an option
+ * synchronises the handle's stream.  Unknown options return FDE_EINVAL. */
+typedef enum {
+  FDE_OPT_GRAPHS = 0,
+  FDE_OPT_AUTOTUNE = 1,
+  FDE_OPT_TRSV_W = 2,
+  FDE_OPT_TRSV_W_IN_USE = 3,
+  FDE_OPT_GRAPHS_IN_USE = 4
+} fde_option;
+fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
+fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
+/* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);
+ * FDE_EINVAL if len is too small. */
+fde_status fde_autotune_report(char *buf, int len);
+
 /* ---- the individual steps of the path, for per-kernel checks ----------------------- */
 /* b = right-hand side of eq. (1.10) in s-form, [s][m]. */
 fde_status fde_build_rhs(fde_bvm *h, const double *u0, const double *f, double *b, int mem_space);

@@ -37,6 +37,7 @@ class FdeProblem(C.Structure):
 
 
 FDE_X0_SOLUTION, FDE_X0_LOWRANK = 0, 1
+FDE_OPT_GRAPHS, FDE_OPT_AUTOTUNE, FDE_OPT_TRSV_W, FDE_OPT_TRSV_W_IN_USE, FDE_OPT_GRAPHS_IN_USE = 0, 1, 2, 3, 4
 
 
 class FdeSolveOpts(C.Structure):
@@ -85,6 +86,9 @@ SIGNATURES = [
     ("fde_last_error", C.c_char_p, []),
     ("fde_set_stream", C.c_int, [_VP, _VP]),
     ("fde_get_dims", C.c_int, [_VP, C.POINTER(C.c_int)]),
+    ("fde_bvm_set_option", C.c_int, [_VP, C.c_int, C.c_int]),
+    ("fde_bvm_get_option", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
+    ("fde_autotune_report", C.c_int, [C.c_char_p, C.c_int]),
     ("fde_build_rhs", C.c_int, [_VP, _VP, _VP, _VP, C.c_int]),
     ("fde_apply_matvec", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("fde_toeplitz_apply", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_int]),

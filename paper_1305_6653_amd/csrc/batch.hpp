@@ -20,9 +20,10 @@ struct InstDesc {
   const double2 *chat, *twL, *tws, *lam, *mu;
   const int *band_c;
   const double *band_a, *band_b;
-  // factors (complex FP64 or FP32 per the plan), block-solve flags
+  // factors (complex FP64 or FP32 per the plan), block-solve flags (epoch of the last
+  // published panel, [nb][npan][2])
   void *K, *dinv;
-  int *tsflags;
+  unsigned long long *tsflags;
   // vectors (FP64, [s][m] unless noted)
   double *V, *Z;              // (R+1) and R vectors
   double *w, *x, *b, *tmp, *sio;
@@ -50,12 +51,40 @@ __device__ __forceinline__ double *vsel(const InstDesc &d, int sel, int j) {
   }
 }
 
-// Launch-wide item map: instance ids[count], prefix pre[count+1].
+// Launch-wide item map: instance ids[count], prefix pre[count+1].  If gate is set, the
+// items of instance i are skipped unless gate[i] != 0 (a device array written by earlier
+// launches, so a fixed launch sequence can follow the instances' progress).
 struct ItemMap {
   const int *ids;
   const int *pre;
   int count;
+  const int *gate;
 };
+
+__device__ __forceinline__ bool item_gated(const ItemMap &mp, int q) {
+  return mp.gate != nullptr && mp.gate[mp.ids[q]] == 0;
+}
+
+// Restarted GMRES control, one record per instance of a plan, advanced on the device between
+// launches.  Restart lengths up to GM_RMAX.
+static constexpr int GM_RMAX = 64;
+
+struct GmresCtl {
+  double bnorm;     // ||b||
+  double tol;       // relative tolerance on ||b - M x|| / ||b||
+  double truer;     // last true relative residual
+  double est;       // Givens estimate of the relative residual
+  int maxit, its, k, restarts;
+  int conv, done, fail, active;  // active: taking part in the current cycle (mirrors the gate)
+};
+
+struct GmresWork {
+  double H[GM_RMAX + 1][GM_RMAX];  // rotated Hessenberg matrix of the current cycle
+  double cs[GM_RMAX], sn[GM_RMAX], g[GM_RMAX + 1];
+};
+
+// gate arrays of a plan, [GATE_COUNT][count]
+enum GateSel : int { GATE_LIVE = 0, GATE_ACTIVE, GATE_X0, GATE_COUNT };
 
 // Returns the position q in the map with pre[q] <= item < pre[q+1].
 __device__ __forceinline__ int item_slot(const ItemMap &mp, int item) {

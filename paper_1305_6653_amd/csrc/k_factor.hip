@@ -26,6 +26,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D, ItemMap map,
                                                   int kchunk) {
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int local = blockIdx.x - map.pre[q];
   const int m = d.m, mp = d.mp, nb = d.nb;
@@ -61,138 +62,227 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D
 
 // ------------------------------------------------------------------------------------
 // Diagonal tile: LU without pivoting, then the inverses of its unit-lower and upper
-// triangles.  512 threads; thread t owns row r = t/8 and columns c = (t%8) + 8j, j < 8, in
-// registers.  Each elimination step needs only the pivot row and the pivot column, which
-// their owners publish into double-buffered LDS vectors at the end of the previous step, so
-// every step costs one barrier.  The triangular inverses read the factors from LDS and
-// publish the rows of the inverse the same way.
-static constexpr int DG_NT = 512;
+// triangles.  NT threads: 1024 for FP32 factors, 512 for FP64 (whose registers would
+// otherwise allow only one workgroup per CU).
+//
+// LU: thread t owns row r = t / (NT/64) and columns c = t % (NT/64) + (NT/64) j in registers.
+// Step k needs the pivot row, the pivot column and the pivot's reciprocal; their owners
+// publish them into double-buffered LDS vectors at the end of step k-1 (the reciprocal is
+// computed once, by the pivot's owner), so a step costs one barrier, one batch of LDS reads
+// and at most 64^2/NT complex multiply-adds per thread.
+//
+// Inverses (eight threads per row, eight columns each): forward substitution for L^{-1} and
+// backward substitution for U^{-1}, 63 barrier-separated steps each, the row of the inverse
+// that became final being published every step.  With 1024 threads the two run at once on
+// the two halves of the workgroup; with 512 they run one after the other.
+template <typename T> struct DiagThreads { static constexpr int value = 1024; };
+template <> struct DiagThreads<double> { static constexpr int value = 512; };
+
+// cond ? a : b, component-wise (a select of the vector struct would be lowered through
+// private memory)
+template <typename T>
+__device__ __forceinline__ c_t<T> csel(bool cond, c_t<T> a, c_t<T> b) {
+  return mk<T>(cond ? a.x : b.x, cond ? a.y : b.y);
+}
+
+// 1/z = conj(z) / |z|^2 (one real division); `ok` is false for a zero or non-finite |z|^2.
+template <typename T>
+__device__ __forceinline__ c_t<T> recip_checked(c_t<T> z, bool &ok) {
+  const T m2 = z.x * z.x + z.y * z.y;
+  ok = (m2 > (T)0) && isfinite(m2);
+  const T inv = (T)1 / m2;
+  return mk<T>(z.x * inv, -z.y * inv);
+}
+
+// One step of L^{-1} (unit lower) by rows: rows r > k receive -L[r][k] X[k][:] on the columns
+// c <= k; row k + 1 is then final and is published into pub.
+template <typename T>
+__device__ __forceinline__ void inv_lower_step(c_t<T> (&y)[8], const c_t<T> (*a)[PB + 1], int r,
+                                               int cq, int k, const c_t<T> *pr, c_t<T> *pub) {
+  if (r > k) {
+    const c_t<T> f = a[r][k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = cq + 8 * j;
+      y[j] = csel<T>(c <= k, tsub<T>(y[j], tmul<T>(f, pr[c])), y[j]);
+    }
+  }
+  if (r == k + 1) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pub[cq + 8 * j] = y[j];
+  }
+}
+
+// One step of U^{-1} by rows: rows r < k receive -U[r][k] X[k][:] on the columns c >= k;
+// row k - 1 is then final, is scaled by 1/U[k-1][k-1] and is published into pub.
+template <typename T>
+__device__ __forceinline__ void inv_upper_step(c_t<T> (&y)[8], const c_t<T> (*a)[PB + 1],
+                                               const c_t<T> *dgi, int r, int cq, int k,
+                                               const c_t<T> *pr, c_t<T> *pub) {
+  if (r < k) {
+    const c_t<T> f = a[r][k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = cq + 8 * j;
+      y[j] = csel<T>(c >= k, tsub<T>(y[j], tmul<T>(f, pr[c])), y[j]);
+    }
+  }
+  if (r == k - 1) {
+    const c_t<T> iu = dgi[k - 1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      y[j] = tmul<T>(y[j], iu);
+      pub[cq + 8 * j] = y[j];
+    }
+  }
+}
 
 template <typename T>
-__global__ __launch_bounds__(DG_NT) void k_lu_diag(const InstDesc *__restrict__ Dd, ItemMap map,
-                                                   int p, int *__restrict__ flag) {
+__device__ __forceinline__ void unit_rows(c_t<T> (&y)[8], int r, int cq) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) y[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_lu_diag(const InstDesc *__restrict__ Dd, ItemMap map, int p,
+                                                int *__restrict__ flag) {
   typedef c_t<T> C;
+  constexpr int TPR = NT / PB, NC = PB / TPR;  // LU: threads per row, columns per thread
   __shared__ C a[PB][PB + 1];
   __shared__ C prow[2][PB];
   __shared__ C pcol[2][PB];
+  __shared__ C prowU[2][PB];
+  __shared__ C dgi[PB];  // reciprocals of U's diagonal
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int blk = blockIdx.x - map.pre[q], tid = threadIdx.x;
   const int mp = d.mp, npan = d.npan;
   C *K = (C *)d.K;
   C *dinv = (C *)d.dinv;
-  const int r = tid >> 3, cq = tid & 7;
   C *A = K + (size_t)blk * mp * mp + (size_t)p * PB * mp + (size_t)p * PB;
-  C x[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) x[j] = A[(size_t)r * mp + cq + 8 * j];
-  // publish row 0 and column 0
-  if (r == 0) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = x[j];
-  }
-  if (cq == 0) pcol[0][r] = x[0];
-  __syncthreads();
   int bad = 0;
-  for (int k = 0; k < PB; ++k) {
-    const int b = k & 1, nbuf = b ^ 1;
-    const C piv = prow[b][k];
-    const T pm = piv.x * piv.x + piv.y * piv.y;
-    if (tid == 0 && (!(pm > (T)0) || !isfinite(pm))) bad = 1;
-    if (r > k) {
-      const C l = tmul<T>(pcol[b][r], trecip<T>(piv));
+  {
+    const int r = tid / TPR, cl = tid % TPR;
+    C x[NC];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int c = cq + 8 * j;
-        if (c > k) x[j] = tsub<T>(x[j], tmul<T>(l, prow[b][c]));
-        else if (c == k) x[j] = l;
-      }
+    for (int j = 0; j < NC; ++j) x[j] = A[(size_t)r * mp + cl + TPR * j];
+    if (r == 0) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) prow[0][cl + TPR * j] = x[j];
     }
-    if (k + 1 < PB) {
-      if (r == k + 1) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) prow[nbuf][cq + 8 * j] = x[j];
-      }
-      if (cq == ((k + 1) & 7)) {
-        C xc = x[0];
-#pragma unroll
-        for (int j = 1; j < 8; ++j)
-          if (j == ((k + 1) >> 3)) xc = x[j];  // select, not a dynamic register index
-        pcol[nbuf][r] = xc;
-      }
+    if (cl == 0) pcol[0][r] = x[0];
+    if (tid == 0) {
+      bool ok;
+      dgi[0] = recip_checked<T>(x[0], ok);
+      bad |= ok ? 0 : 1;
     }
     __syncthreads();
+    // k = TPR kk + ki; kk is unrolled so that every register index below is a constant
+#pragma unroll
+    for (int kk = 0; kk < NC; ++kk) {
+#pragma unroll 1
+      for (int ki = 0; ki < TPR; ++ki) {
+        const int k = TPR * kk + ki, b = k & 1, nbuf = b ^ 1;
+        if (r > k) {
+          const C l = tmul<T>(pcol[b][r], dgi[k]);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const int c = cl + TPR * j;
+            const C upd = tsub<T>(x[j], tmul<T>(l, prow[b][c]));
+            x[j] = csel<T>(c > k, upd, csel<T>(c == k, l, x[j]));
+          }
+        }
+        const int kc = k + 1;
+        if (kc < PB) {
+          if (r == kc) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) prow[nbuf][cl + TPR * j] = x[j];
+          }
+          if (cl == kc % TPR) {
+            // column kc lives in register x[kc / TPR]: x[kk], or x[kk + 1] after the last ki
+            const C xc = csel<T>(ki == TPR - 1, x[kk + 1 < NC ? kk + 1 : NC - 1], x[kk]);
+            pcol[nbuf][r] = xc;
+            if (r == kc) {
+              bool ok;
+              dgi[kc] = recip_checked<T>(xc, ok);
+              bad |= ok ? 0 : 1;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      A[(size_t)r * mp + cl + TPR * j] = x[j];
+      a[r][cl + TPR * j] = x[j];
+    }
   }
   if (bad) atomicOr(flag, 1);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    A[(size_t)r * mp + cq + 8 * j] = x[j];
-    a[r][cq + 8 * j] = x[j];
-  }
   C *Dl = dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   C *Du = Dl + PB * PB;
-  // X = L^{-1} (unit lower): row r receives -L[r][k] X[k][:] at step k < r; X row k+1 is final
-  // after step k and is published then.
+  C y[8];
+  if (NT == 1024) {
+    const bool lower = tid < 512;  // uniform per wavefront
+    const int tt = tid & 511, r = tt >> 3, cq = tt & 7;
+    unit_rows<T>(y, r, cq);
+    __syncthreads();  // a[][] complete
+    if (lower) {
+      if (r == 0) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) x[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
-  if (r == 0) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = x[j];
-  }
-  __syncthreads();
-  for (int k = 0; k < PB - 1; ++k) {
-    const int b = k & 1, nbuf = b ^ 1;
-    if (r > k) {
-      const C lrk = a[r][k];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int c = cq + 8 * j;
-        if (c <= k) x[j] = tsub<T>(x[j], tmul<T>(lrk, prow[b][c]));
+        for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = y[j];
       }
-    }
-    if (r == k + 1) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) prow[nbuf][cq + 8 * j] = x[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) Dl[r * PB + cq + 8 * j] = x[j];
-  // X = U^{-1}: for k = 63..0 row k is scaled by 1/U[k][k] (its last update came at step k+1),
-  // published, and rows r < k receive -U[r][k] X[k][:].
-#pragma unroll
-  for (int j = 0; j < 8; ++j) x[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
-  if (r == PB - 1) {
-    const C iu = trecip<T>(a[PB - 1][PB - 1]);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      x[j] = tmul<T>(x[j], iu);
-      prow[1][cq + 8 * j] = x[j];
-    }
-  }
-  __syncthreads();
-  for (int k = PB - 1; k >= 1; --k) {
-    const int b = k & 1, nbuf = b ^ 1;
-    if (r < k) {
-      const C u = a[r][k];
+    } else if (r == PB - 1) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int c = cq + 8 * j;
-        if (c >= k) x[j] = tsub<T>(x[j], tmul<T>(u, prow[b][c]));
-      }
-    }
-    if (r == k - 1) {
-      const C iu = trecip<T>(a[k - 1][k - 1]);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        x[j] = tmul<T>(x[j], iu);
-        prow[nbuf][cq + 8 * j] = x[j];
+        y[j] = tmul<T>(y[j], dgi[PB - 1]);
+        prowU[1][cq + 8 * j] = y[j];
       }
     }
     __syncthreads();
-  }
+#pragma unroll 1
+    for (int t = 0; t < PB - 1; ++t) {
+      if (lower) inv_lower_step<T>(y, a, r, cq, t, prow[t & 1], prow[(t & 1) ^ 1]);
+      else inv_upper_step<T>(y, a, dgi, r, cq, PB - 1 - t, prowU[(PB - 1 - t) & 1], prowU[(PB - t) & 1]);
+      __syncthreads();
+    }
+    C *Dx = lower ? Dl : Du;  // pointer select
 #pragma unroll
-  for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = x[j];
+    for (int j = 0; j < 8; ++j) Dx[r * PB + cq + 8 * j] = y[j];
+  } else {
+    const int r = tid >> 3, cq = tid & 7;
+    unit_rows<T>(y, r, cq);
+    __syncthreads();  // a[][] complete
+    if (r == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = y[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < PB - 1; ++k) {
+      inv_lower_step<T>(y, a, r, cq, k, prow[k & 1], prow[(k & 1) ^ 1]);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Dl[r * PB + cq + 8 * j] = y[j];
+    unit_rows<T>(y, r, cq);
+    if (r == PB - 1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        y[j] = tmul<T>(y[j], dgi[PB - 1]);
+        prowU[1][cq + 8 * j] = y[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = PB - 1; k >= 1; --k) {
+      inv_upper_step<T>(y, a, dgi, r, cq, k, prowU[k & 1], prowU[(k & 1) ^ 1]);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = y[j];
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -273,6 +363,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(const InstDesc *__restrict__ D
                                                   int p) {
   typedef c_t<T> C;
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
   const int local = blockIdx.x - map.pre[q];
@@ -302,6 +393,7 @@ __global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ 
                                                    int p) {
   typedef c_t<T> C;
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
   const int local = blockIdx.x - map.pre[q];
@@ -329,6 +421,7 @@ template <typename T>
 __global__ __launch_bounds__(TS_NT) void k_trsv(const InstDesc *__restrict__ Dd, ItemMap map) {
   extern __shared__ double2 sh[];
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan;
   // the item map counts nb * W items per instance; one workgroup per block does the solve
@@ -416,7 +509,8 @@ __device__ __forceinline__ double2 ld_coh(const double2 *p) {
 }
 
 // Returns false (uniformly across the workgroup) if the wait was abandoned.
-__device__ __forceinline__ bool ts_wait(const int *flag, int epoch, int *err) {
+__device__ __forceinline__ bool ts_wait(const unsigned long long *flag, unsigned long long epoch,
+                                        int *err) {
   int ok = 1;
   if (threadIdx.x == 0) {
     if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -434,7 +528,7 @@ __device__ __forceinline__ bool ts_wait(const int *flag, int epoch, int *err) {
   return __syncthreads_and(ok) != 0;
 }
 
-__device__ __forceinline__ void ts_publish(int *flag, int epoch) {
+__device__ __forceinline__ void ts_publish(unsigned long long *flag, unsigned long long epoch) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -469,12 +563,17 @@ __device__ __forceinline__ void chunk_gemv(const c_t<T> *__restrict__ M, size_t 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
-                                                   int items, int epoch, int *__restrict__ err) {
+                                                   int items,
+                                                   const unsigned long long *__restrict__ epoch_p,
+                                                   int *__restrict__ err) {
   __shared__ double2 tmp[PB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
   const int r16 = wave * 16;  // this wave's first row inside the panel
+  const unsigned long long epoch =
+      __hip_atomic_load(epoch_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int q = item_slot(map, item);
+    if (item_gated(map, q)) continue;
     const InstDesc &d = Dd[map.ids[q]];
     const int local = item - map.pre[q];
     const int mp = d.mp, npan = d.npan, W = d.W;
@@ -482,7 +581,7 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
     const c_t<T> *dinv = (const c_t<T> *)d.dinv;
     const c_t<T> *A = (const c_t<T> *)d.K + (size_t)k * mp * mp;
     double2 *v = d.Vh + (size_t)k * mp;
-    int *fl = d.tsflags + (size_t)k * npan * 2;
+    unsigned long long *fl = d.tsflags + (size_t)k * npan * 2;
     for (int sweep = 0; sweep < 2; ++sweep) {
       const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
       for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
@@ -541,7 +640,8 @@ template <typename T>
 hipError_t launch_lu_diag(const InstDesc *D, const ItemMap &map, int items, int p, int *flag,
                           hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lu_diag<T>, dim3(items), dim3(DG_NT), 0, st, D, map, p, flag);
+  constexpr int NT = DiagThreads<T>::value;
+  hipLaunchKernelGGL((k_lu_diag<T, NT>), dim3(items), dim3(NT), 0, st, D, map, p, flag);
   return hipGetLastError();
 }
 
@@ -595,8 +695,8 @@ int trsv_coop_capacity() {
 }
 
 template <typename T>
-hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items, int epoch, int *err,
-                            hipStream_t st) {
+hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
+                            const unsigned long long *epoch, int *err, hipStream_t st) {
   if (items <= 0) return hipSuccess;
   const int cap = trsv_coop_capacity<T>();
   if (cap <= 0) return hipErrorNotSupported;
@@ -612,8 +712,8 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items, in
   template hipError_t launch_lu_panel<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
   template hipError_t launch_lu_update<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
   template hipError_t launch_trsv<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t);    \
-  template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int, int, int *,      \
-                                          hipStream_t);                                         \
+  template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int,                 \
+                                          const unsigned long long *, int *, hipStream_t);       \
   template int trsv_coop_capacity<T>();
 FDE_INST(double)
 FDE_INST(float)

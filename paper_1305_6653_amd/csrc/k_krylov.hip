@@ -30,9 +30,14 @@ struct Chunk {
   size_t begin, end, n;
 };
 
+// c.d is null if the item's instance is gated off (uniform per workgroup).
 __device__ __forceinline__ Chunk chunk_of(const InstDesc *__restrict__ D, const ItemMap &map) {
   const int q = item_slot(map, blockIdx.x);
   Chunk c;
+  if (item_gated(map, q)) {
+    c.d = nullptr;
+    return c;
+  }
   c.d = &D[map.ids[q]];
   c.b = blockIdx.x - map.pre[q];
   c.n = (size_t)c.d->s * c.d->m;
@@ -49,6 +54,7 @@ __global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__
                                                     int i, int j) {
   __shared__ double red[KR_NT / 64];
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   const double *pin = (i & 1) ? d.part0 : d.part1;
   double *pout = (i & 1) ? d.part1 : d.part0;
@@ -80,6 +86,7 @@ __global__ __launch_bounds__(KR_NT) void k_normalize(const InstDesc *__restrict_
                                                      int psel, int hidx) {
   __shared__ double red[KR_NT / 64];
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   const double nrm = sqrt(sum_partials(psel ? d.part1 : d.part0, d.nblk, red));
   if (c.b == 0 && threadIdx.x == 0) {
@@ -96,6 +103,7 @@ __global__ __launch_bounds__(KR_NT) void k_normalize(const InstDesc *__restrict_
 __global__ __launch_bounds__(KR_NT) void k_residual(const InstDesc *__restrict__ D, ItemMap map) {
   __shared__ double red[KR_NT / 64];
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   double acc = 0.0;
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
@@ -111,6 +119,7 @@ __global__ __launch_bounds__(KR_NT) void k_dot_partial(const InstDesc *__restric
                                                        int xsel, int ysel, int psel) {
   __shared__ double red[KR_NT / 64];
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   const double *x = vsel(d, xsel, 0), *y = vsel(d, ysel, 0);
   double acc = 0.0;
@@ -123,6 +132,7 @@ __global__ __launch_bounds__(KR_NT) void k_dot_partial(const InstDesc *__restric
 __global__ __launch_bounds__(KR_NT) void k_axpy(const InstDesc *__restrict__ D, ItemMap map,
                                                 int dst_sel, int src_sel, double a) {
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   double *dst = vsel(d, dst_sel, 0);
   const double *src = vsel(d, src_sel, 0);
@@ -139,6 +149,7 @@ hipError_t launch_axpy(const InstDesc *D, const ItemMap &map, int items, int dst
 // x *= y[0]  (per-instance factor)
 __global__ __launch_bounds__(KR_NT) void k_scale_x(const InstDesc *__restrict__ D, ItemMap map) {
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   const double g = d.y[0];
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) d.x[e] *= g;
@@ -147,6 +158,7 @@ __global__ __launch_bounds__(KR_NT) void k_scale_x(const InstDesc *__restrict__ 
 // x += sum_{j<k} y[1+j] Z_j with k = (int) y[0].
 __global__ __launch_bounds__(KR_NT) void k_update_x(const InstDesc *__restrict__ D, ItemMap map) {
   const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
   const InstDesc &d = *c.d;
   const int k = (int)d.y[0];
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {

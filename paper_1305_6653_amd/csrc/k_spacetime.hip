@@ -80,6 +80,7 @@ __global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict
                                                       int dst_j, int mode) {
   extern __shared__ double2 buf[];
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int n = blockIdx.x - map.pre[q];
   const int m = d.m, L = 1 << d.log2L;
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict
 __global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, ItemMap map,
                                                int use_ju0) {
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int n = blockIdx.x - map.pre[q];
   const int m = d.m, c = d.band_c[n];
@@ -141,10 +143,17 @@ __global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, I
 // length s per workgroup.
 static constexpr int TP = 8;
 
+// If epoch_ctr is set, the first workgroup also draws the next block-solve epoch from the
+// device-wide counter into *epoch_slot (read by the block solve that follows on the stream),
+// so a recorded launch sequence gets a fresh epoch on every replay.
 __global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict__ D, ItemMap map,
-                                                     int src_sel, int src_j) {
+                                                     int src_sel, int src_j,
+                                                     unsigned long long *epoch_ctr,
+                                                     unsigned long long *epoch_slot) {
   extern __shared__ double2 buf[];
+  if (epoch_ctr && blockIdx.x == 0 && threadIdx.x == 0) *epoch_slot = atomicAdd(epoch_ctr, 1ull) + 1ull;
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
   const double *V = vsel(d, src_sel, src_j);
@@ -180,6 +189,7 @@ __global__ __launch_bounds__(ST_NT) void k_time_irfft(const InstDesc *__restrict
                                                       int dst_sel, int dst_j) {
   extern __shared__ double2 buf[];
   const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
   double *W = vsel(d, dst_sel, dst_j);
@@ -251,12 +261,14 @@ hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_
 }
 
 hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                            int src_sel, int src_j, hipStream_t st) {
+                            int src_sel, int src_j, hipStream_t st, unsigned long long *epoch_ctr,
+                            unsigned long long *epoch_slot) {
   if (items <= 0) return hipSuccess;
   const size_t lds = (sizeof(double2) * TP) << max_log2s;
   hipError_t e = set_lds((const void *)k_time_rfft, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_time_rfft, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j);
+  hipLaunchKernelGGL(k_time_rfft, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j,
+                     epoch_ctr, epoch_slot);
   return hipGetLastError();
 }
 

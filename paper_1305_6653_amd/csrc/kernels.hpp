@@ -19,9 +19,12 @@ hipError_t launch_bvm_matvec(const InstDesc *D, const ItemMap &map, int items, i
                              hipStream_t st);
 // b = tau Bhat f - a0 u0 (+ tau b0 J u0), items = s per instance
 hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_ju0, hipStream_t st);
-// items = mp / time_fft_cols_per_item() per instance
+// items = mp / time_fft_cols_per_item() per instance.  With epoch_ctr set, the launch also
+// draws the next block-solve epoch into *epoch_slot (see launch_trsv_coop).
 hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                            int src_sel, int src_j, hipStream_t st);
+                            int src_sel, int src_j, hipStream_t st,
+                            unsigned long long *epoch_ctr = nullptr,
+                            unsigned long long *epoch_slot = nullptr);
 hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
                              int dst_sel, int dst_j, hipStream_t st);
 int time_fft_cols_per_item();
@@ -42,11 +45,12 @@ hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, in
 template <typename T>
 hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max_mp, hipStream_t st);
 // several workgroups per block (descriptor field W), cooperative launch: items = nb W per
-// instance; flags in the descriptors hold the epoch of the last published panel; *err is
+// instance; flags in the descriptors hold the epoch of the last published panel; the epoch of
+// this launch is read from *epoch (device memory, written by the preceding time FFT); *err is
 // raised if a dependency wait had to be abandoned.
 template <typename T>
-hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items, int epoch, int *err,
-                            hipStream_t st);
+hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
+                            const unsigned long long *epoch, int *err, hipStream_t st);
 // co-resident workgroups of the cooperative block solve on this device (0 if unknown)
 template <typename T>
 int trsv_coop_capacity();
@@ -66,5 +70,18 @@ hipError_t launch_axpy(const InstDesc *D, const ItemMap &map, int items, int dst
 // x *= y[0] per instance
 hipError_t launch_scale_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
+
+// ---- restarted GMRES control on the device (one thread per instance of the plan) ----
+// restart: beta = nrm[0] of every live instance -> converged / out of iterations / new cycle;
+// sets gate[GATE_LIVE] and gate[GATE_ACTIVE].
+hipError_t launch_gm_restart(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int *gates,
+                             int count, hipStream_t st);
+// Arnoldi step j done: rotate the new Hessenberg column, update the residual estimate and
+// retire instances that converged, ran out of iterations or reached the end of the cycle.
+hipError_t launch_gm_givens(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int *gates,
+                            int count, int j, int R, hipStream_t st);
+// end of cycle: y = H^{-1} g into the descriptors' y (y[0] = k, 0 if the instance did not run)
+hipError_t launch_gm_backsolve(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int count,
+                               hipStream_t st);
 
 }  // namespace fde

@@ -16,7 +16,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -96,13 +98,20 @@ struct Pending {
   std::string name;
   double work;
   hipEvent_t a, b;
+  bool owned;  // false: the events belong to a recorded graph and are reused by its replays
+  int step;    // Arnoldi step of a restart cycle (-1 outside the cycle)
 };
 
-// Process-wide epoch of the cooperative block solve.  Flags hold the epoch of the last
-// published panel; every launch uses a new value.  On wrap-around the generation changes
-// and every handle clears its flags before its next solve.
-int g_epoch = 0;
-int g_epoch_gen = 0;
+// A recorded launch sequence (hipGraph) and the timing events recorded inside it.
+struct GraphSeg {
+  hipGraphExec_t exec = nullptr;
+  std::vector<Pending> prof;
+};
+
+// Set while a launch sequence is being recorded on this thread.
+thread_local GraphSeg *g_capture = nullptr;
+// Arnoldi step whose launches are being issued (-1 outside a restart cycle).
+thread_local int g_step = -1;
 
 }  // namespace
 
@@ -128,8 +137,7 @@ struct fde_bvm {
   // ---- factors
   void *d_K = nullptr, *d_dinv = nullptr;
   size_t K_bytes = 0;
-  int *d_tsflags = nullptr;
-  int flag_gen = -1;
+  unsigned long long *d_tsflags = nullptr;
   int prec = -1;
   double t_factor_ms = 0.0;
   // ---- vectors
@@ -140,8 +148,11 @@ struct fde_bvm {
   double2 *d_Vh = nullptr;
   // ---- the plan of this handle alone
   Plan *self = nullptr;
+  // ---- options (fde_bvm_set_option)
+  int opt_graphs = 1, opt_autotune = 1, opt_trsv_w = 0;
   // ---- profiling
   bool prof = false;
+  int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<Pending> pend;
   std::vector<hipEvent_t> evpool;
@@ -199,14 +210,26 @@ static hipEvent_t get_event(fde_bvm *h) {
   return e;
 }
 
+// Launch with optional timing: HIP events around the launch on the handle's stream.  While a
+// launch sequence is recorded, the events are recorded into the graph as event nodes and
+// are read after every replay.
 template <typename Fn>
-static hipError_t run(fde_bvm *h, const char *name, double work, Fn &&launch) {
+static hipError_t run(fde_bvm *h, const char *name, double work, Fn &&launch,
+                      hipStream_t on = nullptr) {
   if (!h->prof) return launch();
+  const hipStream_t st = on ? on : h->stream;
   hipEvent_t a = get_event(h), b = get_event(h);
-  (void)hipEventRecord(a, h->stream);
+  if (g_capture) {
+    hipError_t e = hipEventRecordWithFlags(a, st, hipEventRecordExternal);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecordWithFlags(b, st, hipEventRecordExternal);
+    g_capture->prof.push_back({name, work, a, b, false, g_step});
+    return e;
+  }
+  (void)hipEventRecord(a, st);
   hipError_t e = launch();
-  (void)hipEventRecord(b, h->stream);
-  h->pend.push_back({name, work, a, b});
+  (void)hipEventRecord(b, st);
+  h->pend.push_back({name, work, a, b, true, g_step});
   return e;
 }
 
@@ -214,16 +237,42 @@ static fde_status sync_and_flush(fde_bvm *h) {
   HIPCHK(hipStreamSynchronize(h->stream));
   for (auto &p : h->pend) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    if (p.step < h->prof_step_limit && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ProfEntry &e = h->prof_tab[p.name];
       e.ms += ms;
       e.count += 1;
       e.work += p.work;
     }
-    h->evpool.push_back(p.a);
-    h->evpool.push_back(p.b);
+    if (p.owned) {
+      h->evpool.push_back(p.a);
+      h->evpool.push_back(p.b);
+    }
   }
   h->pend.clear();
+  return FDE_OK;
+}
+
+// Device-wide counter of block-solve epochs, one per GPU (64-bit: never wraps in practice).
+// Every preconditioner apply draws a new value on the device, so flags left by earlier
+// applies (of any plan, eager or replayed) never match.
+static std::mutex g_epoch_mu;
+static unsigned long long *g_epoch_ctr[64] = {};
+
+static fde_status epoch_counter(unsigned long long **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(FDE_EUNSUPPORTED, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_epoch_mu);
+  if (!g_epoch_ctr[dev]) {
+    void *p = nullptr;
+    STCHK(dalloc_raw(&p, sizeof(unsigned long long)));
+    if (hipMemset(p, 0, sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipFree(p);
+      return fail(FDE_EDEVICE, "epoch counter initialisation failed");
+    }
+    g_epoch_ctr[dev] = (unsigned long long *)p;  // kept for the life of the process
+  }
+  *out = g_epoch_ctr[dev];
   return FDE_OK;
 }
 
@@ -234,6 +283,22 @@ struct HostMap {
   std::vector<int> ids, pre;
   int items = 0;
 };
+
+// Item maps of the solve-phase launches over every instance of a plan.
+struct SolveMaps {
+  ItemMap mv, tfft, trsv, kry, rhs, ju0;
+  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0;
+  int max_log2L = 1, max_log2s = 1, max_mp = 64;
+  int prec = -1;
+  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0;
+};
+
+// The same maps with their items skipped for instances whose gate entry is zero.
+static SolveMaps gated(const SolveMaps &S, const int *gate) {
+  SolveMaps G = S;
+  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0}) m->gate = gate;
+  return G;
+}
 
 struct Plan {
   std::vector<fde_bvm *> hs;
@@ -249,10 +314,57 @@ struct Plan {
   std::vector<size_t> part_off;
   std::vector<void *> allocs;
   bool desc_dirty = true;
+  // device GMRES control
+  GmresCtl *d_ctl = nullptr;
+  GmresWork *d_work = nullptr;
+  int *d_gates = nullptr;             // [GATE_COUNT][count]
+  unsigned long long *d_epoch = nullptr;  // epoch of this plan's current block solve
+  std::vector<GmresCtl> ctl_host;
+  std::vector<int> gates_host;
+  // solve maps over all instances, in their own allocation (recorded graphs refer to them)
+  SolveMaps full;
+  bool full_ok = false;
+  int *d_fullmaps = nullptr;
+  size_t fullmaps_ints = 0;
+  std::vector<int> fullmaps_host;
+  // recorded launch sequences: the first restart step, Arnoldi steps [j0, j1) of a cycle,
+  // and the end of a cycle (least-squares update) followed by the next restart step
+  GraphSeg seg_restart, seg_finish;
+  std::map<std::pair<int, int>, GraphSeg> seg_steps;
+  int graph_R = -1, graph_prec = -1;
+  bool graph_off = false;
+  std::vector<int> pred_steps;  // Arnoldi steps of each cycle of the previous solve
 };
+
+static void graph_release(Plan *P, GraphSeg &g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+  for (Pending &p : g.prof) {
+    P->lead->evpool.push_back(p.a);
+    P->lead->evpool.push_back(p.b);
+  }
+  g.prof.clear();
+}
+
+static bool graphs_recorded(const Plan *P) {
+  if (P->seg_restart.exec || P->seg_finish.exec) return true;
+  for (auto &kv : P->seg_steps)
+    if (kv.second.exec) return true;
+  return false;
+}
+
+static void graphs_invalidate(Plan *P) {
+  graph_release(P, P->seg_restart);
+  graph_release(P, P->seg_finish);
+  for (auto &kv : P->seg_steps) graph_release(P, kv.second);
+  P->seg_steps.clear();
+  P->graph_R = P->graph_prec = -1;
+}
 
 static void plan_free(Plan *P) {
   if (!P) return;
+  if (graphs_recorded(P)) (void)hipStreamSynchronize(P->lead->stream);
+  graphs_invalidate(P);
   for (void *p : P->allocs) (void)hipFree(p);
   delete P;
 }
@@ -301,7 +413,7 @@ static fde_status upload_maps(Plan *P, const std::vector<HostMap> &maps, std::ve
     P->arena_host.insert(P->arena_host.end(), m.ids.begin(), m.ids.end());
     const size_t op = P->arena_host.size();
     P->arena_host.insert(P->arena_host.end(), m.pre.begin(), m.pre.end());
-    out.push_back(ItemMap{P->d_arena + oi, P->d_arena + op, (int)m.ids.size()});
+    out.push_back(ItemMap{P->d_arena + oi, P->d_arena + op, (int)m.ids.size(), nullptr});
   }
   HIPCHK(hipMemcpy(P->d_arena, P->arena_host.data(), P->arena_host.size() * sizeof(int),
                    hipMemcpyHostToDevice));
@@ -369,7 +481,61 @@ static fde_status ensure_krylov(fde_bvm *h, int R) {
 }
 
 // (Re)builds descriptors and plan-level buffers for restart length R; uploads descriptors.
-static fde_status plan_prepare(Plan *P, int R, int trsv_cap) {
+// ---- workgroups per block of the cooperative block solve --------------------------------
+// All items of a launch must be co-resident (W * sum(nb) <= capacity), so that a block's
+// workgroups never wait on a workgroup that has not started.  Within that limit the value
+// comes from, in order: the lead handle's option, the autotuner's table for the plan's shape
+// (sizes of all instances and the precision), or the largest value that fits.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tuned_w;
+
+static std::string plan_shape_key(const Plan *P, int prec) {
+  std::string k = prec == FDE_FP64 ? "f64" : "c32";
+  char buf[32];
+  for (const fde_bvm *h : P->hs) {
+    snprintf(buf, sizeof buf, ":%dx%d", h->m, h->s);
+    k += buf;
+  }
+  return k;
+}
+
+// Autotuned choices so far, "shape=W" separated by ';' (for reports).
+static std::string tuned_summary() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::string out;
+  for (auto &kv : g_tuned_w) {
+    if (!out.empty()) out += ";";
+    out += kv.first + "=" + std::to_string(kv.second);
+  }
+  return out;
+}
+
+static int trsv_capacity(int prec) {
+  return prec == FDE_MIXED_C32 ? trsv_coop_capacity<float>() : trsv_coop_capacity<double>();
+}
+
+static int trsv_wmax(const Plan *P, const fde_bvm *h, int prec) {
+  long total_nb = 0;
+  for (const fde_bvm *q : P->hs) total_nb += q->nb;
+  const int cap = trsv_capacity(prec);
+  const long w = (cap > 0 && total_nb <= cap) ? cap / total_nb : 1;
+  return (int)std::max(1L, std::min<long>(h->npan, w));
+}
+
+static int trsv_workgroups(const Plan *P, const fde_bvm *h, int prec) {
+  const int wmax = trsv_wmax(P, h, prec);
+  int w = wmax;
+  if (P->lead->opt_trsv_w > 0) {
+    w = P->lead->opt_trsv_w;
+  } else {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned_w.find(plan_shape_key(P, prec));
+    if (it != g_tuned_w.end()) w = it->second;
+  }
+  return std::max(1, std::min(wmax, w));
+}
+
+static fde_status plan_prepare(Plan *P, int R, int prec) {
   const int count = (int)P->hs.size();
   for (fde_bvm *h : P->hs) STCHK(ensure_krylov(h, R));
   if (P->R < R || !P->d_H) {
@@ -397,15 +563,12 @@ static fde_status plan_prepare(Plan *P, int R, int trsv_cap) {
     P->R = R;
     P->desc_dirty = true;
   }
-  // workgroups per block of the cooperative solve: all items co-resident when they fit
-  long total_nb = 0;
-  for (fde_bvm *h : P->hs) total_nb += h->nb;
-  const int Wu = (trsv_cap > 0 && total_nb <= trsv_cap) ? (int)(trsv_cap / total_nb) : 1;
   P->desc.resize(count);
   for (int i = 0; i < count; ++i) {
     fde_bvm *h = P->hs[i];
     InstDesc d = make_desc(h);
-    d.W = std::max(1, std::min(h->npan, Wu));
+    d.W = trsv_workgroups(P, h, prec);
+    if (d.W != P->desc[i].W) P->full_ok = false;  // item counts change: new maps, new graphs
     d.part0 = P->d_part + P->part_off[i];
     d.part1 = d.part0 + h->nblk;
     d.H = P->d_H + (size_t)i * (R + 2);
@@ -443,6 +606,24 @@ static fde_status plan_create(const std::vector<fde_bvm *> &hs, Plan **out) {
     plan_free(P);
     return fail(FDE_EDEVICE, "plan flag initialisation failed");
   }
+  const size_t count = hs.size();
+  const size_t ctl_bytes = (sizeof(GmresCtl) * count + 255) / 256 * 256;
+  const size_t gate_bytes = (sizeof(int) * GATE_COUNT * count + 255) / 256 * 256;
+  if ((st = plan_alloc(P, &p, ctl_bytes + gate_bytes + 256 + sizeof(GmresWork) * count)) != FDE_OK) {
+    plan_free(P);
+    return st;
+  }
+  char *base = (char *)p;
+  P->d_ctl = (GmresCtl *)base;
+  P->d_gates = (int *)(base + ctl_bytes);
+  P->d_epoch = (unsigned long long *)(base + ctl_bytes + gate_bytes);
+  P->d_work = (GmresWork *)(base + ctl_bytes + gate_bytes + 256);
+  if (hipMemset(base, 0, ctl_bytes + gate_bytes + 256) != hipSuccess) {
+    plan_free(P);
+    return fail(FDE_EDEVICE, "plan control initialisation failed");
+  }
+  P->ctl_host.assign(count, GmresCtl{});
+  P->gates_host.assign(GATE_COUNT * count, 0);
   P->desc.resize(hs.size());
   std::memset(P->desc.data(), 0, sizeof(InstDesc) * hs.size());
   *out = P;
@@ -548,10 +729,11 @@ static void destroy_handle(fde_bvm *h) {
   plan_free(h->self);
   h->self = nullptr;
   for (void *p : h->allocs) (void)hipFree(p);
-  for (auto &p : h->pend) {
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
-  }
+  for (auto &p : h->pend)
+    if (p.owned) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
   for (auto e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
@@ -662,7 +844,7 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
   ALLOC(h->d_band_b, (size_t)s * mu1);
   ALLOC(h->d_lam, nb);
   ALLOC(h->d_mu, nb);
-  ALLOC(h->d_tsflags, (size_t)nb * h->npan * 2);
+  ALLOC(h->d_tsflags, (size_t)nb * h->npan * 2);  // 0: no epoch drawn yet (epochs start at 1)
   ALLOC(h->d_w, n);
   ALLOC(h->d_x, n);
   ALLOC(h->d_b, n);
@@ -700,10 +882,9 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
   H2D(h->d_lam, lam.data(), sizeof(double2) * nb);
   H2D(h->d_mu, muk.data(), sizeof(double2) * nb);
 #undef H2D
-  if (hipMemsetAsync(h->d_tsflags, 0, sizeof(int) * nb * h->npan * 2, q) != hipSuccess ||
+  if (hipMemsetAsync(h->d_tsflags, 0, sizeof(unsigned long long) * nb * h->npan * 2, q) != hipSuccess ||
       hipMemsetAsync(h->d_Ju0, 0, sizeof(double) * m, q) != hipSuccess)
     return bail(fail(FDE_EDEVICE, "initialisation failed"));
-  h->flag_gen = g_epoch_gen;
   if (launch_symbol(h->d_cG, h->d_chat, h->log2L, h->d_twL, q) != hipSuccess)
     return bail(fail(FDE_EDEVICE, "symbol FFT launch failed: %s", hipGetErrorString(hipGetLastError())));
   if (hipStreamSynchronize(q) != hipSuccess) return bail(fail(FDE_EDEVICE, "setup synchronisation failed"));
@@ -753,6 +934,46 @@ extern "C" fde_status fde_set_stream(fde_bvm *h, void *stream) {
   return FDE_OK;
 }
 
+extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
+  if (!h) return fail(FDE_EINVAL, "handle is NULL");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  switch (option) {
+    case FDE_OPT_GRAPHS:
+      h->opt_graphs = value ? 1 : 0;
+      graphs_invalidate(h->self);
+      h->self->graph_off = false;
+      return FDE_OK;
+    case FDE_OPT_AUTOTUNE:
+      h->opt_autotune = value ? 1 : 0;
+      return FDE_OK;
+    case FDE_OPT_TRSV_W:
+      if (value < 0 || value > 1024) return fail(FDE_EINVAL, "FDE_OPT_TRSV_W must be in 0..1024");
+      h->opt_trsv_w = value;
+      return FDE_OK;
+    default:
+      return fail(FDE_EINVAL, "unknown or read-only option %d", option);
+  }
+}
+
+extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
+  if (!h || !value) return fail(FDE_EINVAL, "NULL argument");
+  switch (option) {
+    case FDE_OPT_GRAPHS: *value = h->opt_graphs; return FDE_OK;
+    case FDE_OPT_AUTOTUNE: *value = h->opt_autotune; return FDE_OK;
+    case FDE_OPT_TRSV_W: *value = h->opt_trsv_w; return FDE_OK;
+    case FDE_OPT_TRSV_W_IN_USE: *value = h->self->desc.empty() ? 0 : h->self->desc[0].W; return FDE_OK;
+    case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
+    default: return fail(FDE_EINVAL, "unknown option %d", option);
+  }
+}
+
+extern "C" fde_status fde_autotune_report(char *buf, int len) {
+  if (!buf || len < 1) return fail(FDE_EINVAL, "invalid buffer");
+  const std::string r = tuned_summary();
+  std::snprintf(buf, (size_t)len, "%s", r.c_str());
+  return (int)r.size() < len ? FDE_OK : fail(FDE_EINVAL, "buffer too small (%zu bytes needed)", r.size() + 1);
+}
+
 extern "C" fde_status fde_get_dims(const fde_bvm *h, int *dims) {
   if (!h || !dims) return fail(FDE_EINVAL, "NULL argument");
   dims[0] = h->m;
@@ -767,6 +988,8 @@ extern "C" fde_status fde_get_dims(const fde_bvm *h, int *dims) {
 // ====================================================================================
 // factorization
 // ====================================================================================
+// Blocked right-looking LU of every block of every instance, panel step by panel step:
+// diagonal tile, panel, trailing update (one launch each, over all blocks of all instances).
 template <typename T>
 static fde_status factor_plan_impl(Plan *P) {
   fde_bvm *L = P->lead;
@@ -844,7 +1067,7 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
     }
   }
   P->desc_dirty = true;
-  STCHK(plan_prepare(P, std::max(P->R, 1), 0));
+  STCHK(plan_prepare(P, std::max(P->R, 1), prec));
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipMemsetAsync(P->d_flag, 0, sizeof(int), L->stream));
   HIPCHK(hipEventRecord(e0, L->stream));
@@ -873,26 +1096,21 @@ extern "C" fde_status fde_precond_factor(fde_bvm *h, fde_precision prec) {
 // ====================================================================================
 // solve-phase maps and operators over a plan
 // ====================================================================================
-struct SolveMaps {
-  ItemMap mv, tfft, trsv, kry, rhs, ju0;
-  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0;
-  int max_log2L = 1, max_log2s = 1, max_mp = 64;
-  int prec = -1;
-  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0;
-};
-
-static fde_status build_solve_maps(Plan *P, const std::vector<int> &active, SolveMaps &S) {
-  const int count = (int)active.size();
-  std::vector<int> a(count), b(count), c(count), d(count), e(count), f(count);
-  S.max_log2L = S.max_log2s = 1;
-  S.max_mp = 64;
-  S.trsv_bytes = S.vec_bytes = S.tfft_bytes = 0;
+// Maps over every instance of the plan (gates select the instances of a launch), uploaded
+// into the plan's own buffer.  Rebuilt only when the item counts change (block-solve W or
+// precision); recorded graphs refer to this buffer, so a rebuild drops them.
+static fde_status ensure_full_maps(Plan *P) {
+  const int count = (int)P->hs.size();
+  const int prec = P->hs[0]->prec;
+  if (P->full_ok && P->full.prec == prec) return FDE_OK;
+  std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count);
+  SolveMaps S;
   for (int q = 0; q < count; ++q) {
-    fde_bvm *h = P->hs[active[q]];
-    const InstDesc &ds = P->desc[active[q]];
+    fde_bvm *h = P->hs[q];
+    slots[q] = q;
     a[q] = h->s;
     b[q] = h->mp / time_fft_cols_per_item();
-    c[q] = h->nb * ds.W;
+    c[q] = h->nb * P->desc[q].W;
     d[q] = h->nblk;
     e[q] = h->s;
     f[q] = h->need_Ju0 ? 1 : 0;
@@ -904,10 +1122,36 @@ static fde_status build_solve_maps(Plan *P, const std::vector<int> &active, Solv
     S.vec_bytes += 8.0 * h->n();
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
   }
-  std::vector<HostMap> hm = {make_map(active, a), make_map(active, b), make_map(active, c),
-                             make_map(active, d), make_map(active, e), make_map(active, f)};
+  const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
+                                   make_map(slots, d), make_map(slots, e), make_map(slots, f)};
+  size_t need = 0;
+  for (const HostMap &m : hm) need += m.ids.size() + m.pre.size();
+  HIPCHK(hipStreamSynchronize(P->lead->stream));
+  graphs_invalidate(P);
+  if (need > P->fullmaps_ints) {
+    if (P->d_fullmaps) {
+      auto it = std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_fullmaps);
+      if (it != P->allocs.end()) P->allocs.erase(it);
+      (void)hipFree(P->d_fullmaps);
+      P->d_fullmaps = nullptr;
+      P->fullmaps_ints = 0;
+    }
+    void *p = nullptr;
+    STCHK(plan_alloc(P, &p, need * sizeof(int)));
+    P->d_fullmaps = (int *)p;
+    P->fullmaps_ints = need;
+  }
+  P->fullmaps_host.clear();
   std::vector<ItemMap> dm;
-  STCHK(upload_maps(P, hm, dm));
+  for (const HostMap &m : hm) {
+    const size_t oi = P->fullmaps_host.size();
+    P->fullmaps_host.insert(P->fullmaps_host.end(), m.ids.begin(), m.ids.end());
+    const size_t op = P->fullmaps_host.size();
+    P->fullmaps_host.insert(P->fullmaps_host.end(), m.pre.begin(), m.pre.end());
+    dm.push_back(ItemMap{P->d_fullmaps + oi, P->d_fullmaps + op, (int)m.ids.size(), nullptr});
+  }
+  HIPCHK(hipMemcpy(P->d_fullmaps, P->fullmaps_host.data(), P->fullmaps_host.size() * sizeof(int),
+                   hipMemcpyHostToDevice));
   S.mv = dm[0];
   S.tfft = dm[1];
   S.trsv = dm[2];
@@ -920,7 +1164,9 @@ static fde_status build_solve_maps(Plan *P, const std::vector<int> &active, Solv
   S.n_kry = hm[3].items;
   S.n_rhs = hm[4].items;
   S.n_ju0 = hm[5].items;
-  S.prec = P->hs[active[0]]->prec;
+  S.prec = prec;
+  P->full = S;
+  P->full_ok = true;
   return FDE_OK;
 }
 
@@ -932,44 +1178,31 @@ static fde_status op_matvec(Plan *P, const SolveMaps &S, int src, int sj, int ds
   return FDE_OK;
 }
 
+// The cooperative block solve is used unless the device refuses cooperative launches
+// (then one workgroup per block, k_trsv); decided once per process, never while recording.
+static bool g_coop_ok = true;
+
 static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int dst, int dj) {
   fde_bvm *L = P->lead;
   hipStream_t st = L->stream;
+  unsigned long long *ctr = nullptr;
+  STCHK(epoch_counter(&ctr));
   HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
-    return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st);
+    return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st, ctr, P->d_epoch);
   }));
-  for (fde_bvm *h : P->hs)
-    if (h->flag_gen != g_epoch_gen) {
-      HIPCHK(hipMemsetAsync(h->d_tsflags, 0, sizeof(int) * h->nb * h->npan * 2, st));
-      h->flag_gen = g_epoch_gen;
-    }
-  if (g_epoch >= 0x7ffffff0) {
-    g_epoch = 0;
-    ++g_epoch_gen;
-    for (fde_bvm *h : P->hs) {
-      HIPCHK(hipMemsetAsync(h->d_tsflags, 0, sizeof(int) * h->nb * h->npan * 2, st));
-      h->flag_gen = g_epoch_gen;
-    }
-  }
-  const int epoch = ++g_epoch;
-  static bool coop_ok = true;
   HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
     hipError_t e = hipErrorNotSupported;
-    if (coop_ok) {
+    if (g_coop_ok) {
       e = S.prec == FDE_FP64
-              ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, epoch, P->d_err, st)
-              : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, epoch, P->d_err, st);
-      if (e != hipSuccess) {  // cooperative launch refused: one workgroup per block instead
-        (void)hipGetLastError();
-        coop_ok = false;
-      }
+              ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st)
+              : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st);
+      if (e == hipSuccess || g_capture) return e;  // a refusal while recording ends the recording
+      (void)hipGetLastError();
+      g_coop_ok = false;
     }
-    if (!coop_ok) {
-      // one workgroup per block: W = 1 items; the trsv map counts nb W, so rebuild counts
-      e = S.prec == FDE_FP64 ? launch_trsv<double>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st)
-                             : launch_trsv<float>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st);
-    }
-    return e;
+    // one workgroup per block; the map counts nb W items per instance, the extra ones return
+    return S.prec == FDE_FP64 ? launch_trsv<double>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st)
+                              : launch_trsv<float>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st);
   }));
   HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
     return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
@@ -1003,14 +1236,23 @@ static fde_status check_trsv_err(Plan *P) {
 }
 
 // ====================================================================================
-// GMRES over a plan: lockstep restart cycles (right preconditioning, flexible form, MGS
-// Arnoldi, Givens rotations; convergence only on the recomputed true residual)
+// GMRES over a plan: restart cycles in lockstep (right preconditioning, flexible form, MGS
+// Arnoldi, Givens rotations; convergence only on the recomputed true residual).
+//
+// The host sets up (right-hand sides, norms, the projected initial guess), then alternates
+// two fixed launch sequences until every instance has finished:
+//   restart step: r = b - M x, beta = ||r||, v_0 = r / beta, and the device decides per
+//                 instance: converged, out of iterations, or a new cycle;
+//   cycle:        R Arnoldi steps (S^{-1}, M, MGS, normalisation, Givens on the device),
+//                 then y = H^{-1} g and x += Z y.
+// Instances that finish stop contributing items through the gate arrays, so the sequences
+// never change and are recorded once as hipGraphs and replayed (unless recording fails,
+// then they are launched directly).  The host reads the control records once per cycle.
 // ====================================================================================
 struct InstState {
-  double bnorm = 0, truer = 0, est = 0;
-  int its = 0, restarts = 0, k = 0;
-  bool done = false, conv = false, in_cycle = false;
-  std::vector<double> H, cs, sn, g, y;
+  double truer = 0, est = 0;
+  int its = 0, restarts = 0;
+  bool conv = false, fail = false;
 };
 
 // Sum of an instance's chunk partials (part0 or part1) in index order.
@@ -1021,182 +1263,228 @@ static double part_sum(const Plan *P, const std::vector<double> &parts, int i, i
   return t;
 }
 
+// Records emit()'s launches on the lead stream into g.  On any failure nothing has run and g
+// stays empty.
+static fde_status record_segment(Plan *P, GraphSeg &g, const std::function<fde_status()> &emit) {
+  hipStream_t st = P->lead->stream;
+  graph_release(P, g);
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return FDE_EUNSUPPORTED;
+  }
+  g_capture = &g;
+  const std::string saved = g_err;
+  const fde_status s = emit();
+  g_capture = nullptr;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  hipError_t ei = hipErrorUnknown;
+  if (s == FDE_OK && e == hipSuccess && graph) ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    (void)hipGetLastError();
+    g.exec = nullptr;
+    graph_release(P, g);
+    g_err = saved;
+    return FDE_EUNSUPPORTED;
+  }
+  return FDE_OK;
+}
+
+// Runs a segment: replays its graph (recording it first if needed) or launches it directly.
+static fde_status run_segment(Plan *P, GraphSeg &g, bool use_graph,
+                              const std::function<fde_status()> &emit) {
+  fde_bvm *L = P->lead;
+  if (use_graph && !g.exec && record_segment(P, g, emit) != FDE_OK) P->graph_off = true;
+  if (use_graph && g.exec) {
+    HIPCHK(hipGraphLaunch(g.exec, L->stream));
+    for (const Pending &p : g.prof) L->pend.push_back(p);
+    return FDE_OK;
+  }
+  return emit();
+}
+
 static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector<char> &has_x0,
                              std::vector<InstState> &st) {
   fde_bvm *L = P->lead;
   const int count = (int)P->hs.size();
   const int R = o.restart;
-  const double tol = o.rtol;
   hipStream_t stream = L->stream;
-  std::vector<int> all(count);
-  for (int i = 0; i < count; ++i) all[i] = i;
-  SolveMaps S;
-  STCHK(build_solve_maps(P, all, S));
+  STCHK(ensure_full_maps(P));
+  unsigned long long *ctr = nullptr;
+  STCHK(epoch_counter(&ctr));  // allocated (once) before anything is recorded
+  const SolveMaps &S = P->full;
+  int *g_live = P->d_gates + GATE_LIVE * count;
+  int *g_act = P->d_gates + GATE_ACTIVE * count;
+  int *g_x0 = P->d_gates + GATE_X0 * count;
+  const SolveMaps Slive = gated(S, g_live), Sact = gated(S, g_act), Sx0 = gated(S, g_x0);
+
   // right-hand sides and their norms
   STCHK(op_rhs(P, S));
   HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_B, 0, stream); }));
   size_t nparts = 0;
   for (fde_bvm *h : P->hs) nparts += 2 * (size_t)h->nblk;
-  std::vector<double> parts(nparts), hbuf((size_t)count * (R + 2)), nrm((size_t)count * 2);
+  std::vector<double> parts(nparts);
   HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
   STCHK(sync_and_flush(L));
-  std::vector<double> bsq(count);
-  for (int i = 0; i < count; ++i) bsq[i] = part_sum(P, parts, i, 0);
+  std::vector<double> bnorm(count);
+  for (int i = 0; i < count; ++i) {
+    bnorm[i] = std::sqrt(part_sum(P, parts, i, 0));
+    if (!std::isfinite(bnorm[i])) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
+  }
   // An initial guess is first scaled by the gamma minimising ||b - gamma M x0|| (one step of
   // minimal residual along x0), so that ||r_0|| <= ||b||: a poor guess never starts worse
   // than the zero start.
-  std::vector<int> with_x0;
-  for (int i = 0; i < count; ++i)
-    if (has_x0[i]) with_x0.push_back(i);
-  if (!with_x0.empty()) {
-    STCHK(build_solve_maps(P, with_x0, S));
+  bool any_x0 = false;
+  std::vector<int> &gh = P->gates_host;
+  gh.assign(GATE_COUNT * count, 0);
+  for (int i = 0; i < count; ++i) {
+    gh[GATE_X0 * count + i] = has_x0[i] ? 1 : 0;
+    any_x0 = any_x0 || has_x0[i];
+  }
+  if (any_x0) {
+    HIPCHK(hipMemcpyAsync(P->d_gates, gh.data(), gh.size() * sizeof(int), hipMemcpyHostToDevice, stream));
     if (o.x0_kind == FDE_X0_LOWRANK) {  // x holds c: start from S^{-1}(b + c)
-      HIPCHK(run(L, "axpy", 3.0 * S.vec_bytes, [&] { return launch_axpy(P->d_desc, S.kry, S.n_kry, VS_X, VS_B, 1.0, stream); }));
-      STCHK(op_precond(P, S, VS_X, 0, VS_X, 0));
+      HIPCHK(run(L, "axpy", 3.0 * S.vec_bytes, [&] { return launch_axpy(P->d_desc, Sx0.kry, S.n_kry, VS_X, VS_B, 1.0, stream); }));
+      STCHK(op_precond(P, Sx0, VS_X, 0, VS_X, 0));
     }
-    STCHK(op_matvec(P, S, VS_X, 0, VS_TMP, 0));
-    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_TMP, 0, stream); }));
-    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_TMP, VS_TMP, 1, stream); }));
+    STCHK(op_matvec(P, Sx0, VS_X, 0, VS_TMP, 0));
+    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, Sx0.kry, S.n_kry, VS_B, VS_TMP, 0, stream); }));
+    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, Sx0.kry, S.n_kry, VS_TMP, VS_TMP, 1, stream); }));
     HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
     STCHK(sync_and_flush(L));
     std::vector<double> ybuf((size_t)count * (R + 1), 0.0);
-    for (int i : with_x0) {
+    for (int i = 0; i < count; ++i) {
+      if (!has_x0[i]) continue;
       const double bm = part_sum(P, parts, i, 0), mm = part_sum(P, parts, i, 1);
       ybuf[(size_t)i * (R + 1)] = (mm > 0.0 && std::isfinite(bm / mm)) ? bm / mm : 0.0;
     }
     HIPCHK(hipMemcpy(P->d_y, ybuf.data(), ybuf.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(run(L, "scale_x", 2.0 * S.vec_bytes, [&] { return launch_scale_x(P->d_desc, S.kry, S.n_kry, stream); }));
-    STCHK(build_solve_maps(P, all, S));
+    HIPCHK(run(L, "scale_x", 2.0 * S.vec_bytes, [&] { return launch_scale_x(P->d_desc, Sx0.kry, S.n_kry, stream); }));
   }
+  // control records and gates
+  std::vector<GmresCtl> &ctl = P->ctl_host;
+  ctl.assign(count, GmresCtl{});
   for (int i = 0; i < count; ++i) {
-    st[i].bnorm = std::sqrt(bsq[i]);
-    st[i].H.assign((size_t)(R + 1) * R, 0.0);
-    st[i].cs.assign(R, 0.0);
-    st[i].sn.assign(R, 0.0);
-    st[i].g.assign(R + 1, 0.0);
-    st[i].y.assign(R + 1, 0.0);
-    if (!std::isfinite(st[i].bnorm)) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
-    if (st[i].bnorm == 0.0) {
+    GmresCtl &c = ctl[i];
+    c.bnorm = bnorm[i];
+    c.tol = o.rtol;
+    c.maxit = o.maxit;
+    if (bnorm[i] == 0.0) {  // u = 0 exactly
       HIPCHK(hipMemsetAsync(P->hs[i]->d_x, 0, P->hs[i]->n() * sizeof(double), stream));
-      st[i].done = st[i].conv = true;
+      c.done = c.conv = 1;
     }
+    gh[GATE_LIVE * count + i] = c.done ? 0 : 1;
+    gh[GATE_ACTIVE * count + i] = 0;
   }
-  std::vector<int> active;
-  for (int i = 0; i < count; ++i)
-    if (!st[i].done) active.push_back(i);
-  std::vector<int> built = all;
-  for (;;) {
-    if (active.empty()) break;
-    if (active != built) {
-      STCHK(build_solve_maps(P, active, S));
-      built = active;
-    }
-    // true residual of every active instance: V_0 = b - M x, beta = ||V_0||
-    STCHK(op_matvec(P, S, VS_X, 0, VS_TMP, 0));
-    HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, S.kry, S.n_kry, stream); }));
+  HIPCHK(hipMemcpyAsync(P->d_ctl, ctl.data(), count * sizeof(GmresCtl), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(P->d_gates, gh.data(), gh.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+
+  // Timing events are not recorded into graphs: a profiled solve launches directly.
+  const bool use_graph = L->opt_graphs != 0 && !P->graph_off && !L->prof;
+  if (P->graph_R != R || P->graph_prec != S.prec) {
+    HIPCHK(hipStreamSynchronize(stream));
+    graphs_invalidate(P);
+    P->graph_R = R;
+    P->graph_prec = S.prec;
+  }
+  auto restart_step = [&]() -> fde_status {
+    STCHK(op_matvec(P, Slive, VS_X, 0, VS_TMP, 0));
+    HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, Slive.kry, S.n_kry, stream); }));
     HIPCHK(run(L, "normalize", 2.0 * S.vec_bytes, [&] {
-      return launch_normalize(P->d_desc, S.kry, S.n_kry, VS_V, 0, VS_V, 0, 0, -1, stream);
+      return launch_normalize(P->d_desc, Slive.kry, S.n_kry, VS_V, 0, VS_V, 0, 0, -1, stream);
     }));
-    HIPCHK(hipMemcpyAsync(nrm.data(), P->d_nrm, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-    STCHK(sync_and_flush(L));
-    std::vector<int> cyc;
-    for (int i : active) {
-      InstState &s = st[i];
-      const double beta = nrm[(size_t)i * 2];
-      s.truer = beta / s.bnorm;
-      if (!std::isfinite(beta)) return fail(FDE_ENOCONV, "residual of instance %d is not finite", i);
-      if (beta <= tol * s.bnorm) {
-        s.done = s.conv = true;
-        continue;
-      }
-      if (s.its >= o.maxit) {
-        s.done = true;
-        continue;
-      }
-      std::fill(s.g.begin(), s.g.end(), 0.0);
-      s.g[0] = beta;
-      s.k = 0;
-      s.in_cycle = true;
-      cyc.push_back(i);
-    }
-    if (cyc.empty()) break;
-    if (cyc != built) {
-      STCHK(build_solve_maps(P, cyc, S));
-      built = cyc;
-    }
-    for (int j = 0; j < R && !cyc.empty(); ++j) {
-      STCHK(op_precond(P, S, VS_V, j, VS_Z, j));
-      STCHK(op_matvec(P, S, VS_Z, j, VS_W, 0));
+    HIPCHK(launch_gm_restart(P->d_desc, P->d_ctl, P->d_work, P->d_gates, count, stream));
+    return FDE_OK;
+  };
+  auto steps = [&](int j0, int j1) -> fde_status {
+    for (int j = j0; j < j1; ++j) {
+      g_step = j;
+      STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
+      STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
       for (int i = 0; i <= j + 1; ++i) {
         HIPCHK(run(L, "mgs", (i == 0 ? 2.0 : 4.0) * S.vec_bytes,
-                   [&] { return launch_mgs_step(P->d_desc, S.kry, S.n_kry, i, j, stream); }));
+                   [&] { return launch_mgs_step(P->d_desc, Sact.kry, S.n_kry, i, j, stream); }));
       }
       HIPCHK(run(L, "normalize", 2.0 * S.vec_bytes, [&] {
-        return launch_normalize(P->d_desc, S.kry, S.n_kry, VS_W, 0, VS_V, j + 1, (j + 1) & 1, j + 1, stream);
+        return launch_normalize(P->d_desc, Sact.kry, S.n_kry, VS_W, 0, VS_V, j + 1, (j + 1) & 1, j + 1, stream);
       }));
-      HIPCHK(hipMemcpyAsync(hbuf.data(), P->d_H, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-      STCHK(sync_and_flush(L));
-      std::vector<int> next;
-      for (int i : cyc) {
-        InstState &s = st[i];
-        const double *hc = &hbuf[(size_t)i * (R + 2)];
-        ++s.its;
-        for (int r = 0; r <= j + 1; ++r) s.H[(size_t)r * R + j] = hc[r];
-        for (int r = 0; r < j; ++r) {
-          const double a = s.H[(size_t)r * R + j], b = s.H[(size_t)(r + 1) * R + j];
-          s.H[(size_t)r * R + j] = s.cs[r] * a + s.sn[r] * b;
-          s.H[(size_t)(r + 1) * R + j] = -s.sn[r] * a + s.cs[r] * b;
-        }
-        const double a = s.H[(size_t)j * R + j], b = s.H[(size_t)(j + 1) * R + j];
-        const double dd = std::hypot(a, b);
-        s.cs[j] = dd > 0 ? a / dd : 1.0;
-        s.sn[j] = dd > 0 ? b / dd : 0.0;
-        s.H[(size_t)j * R + j] = dd;
-        s.H[(size_t)(j + 1) * R + j] = 0.0;
-        s.g[j + 1] = -s.sn[j] * s.g[j];
-        s.g[j] = s.cs[j] * s.g[j];
-        s.k = j + 1;
-        s.est = std::fabs(s.g[j + 1]) / s.bnorm;
-        if (!std::isfinite(s.est)) return fail(FDE_ENOCONV, "Arnoldi of instance %d produced a non-finite value", i);
-        if (std::fabs(s.g[j + 1]) <= tol * s.bnorm || s.its >= o.maxit) continue;
-        next.push_back(i);
-      }
-      if (next != cyc) {
-        cyc = next;
-        if (!cyc.empty()) {
-          STCHK(build_solve_maps(P, cyc, S));
-          built = cyc;
-        }
-      }
+      HIPCHK(launch_gm_givens(P->d_desc, P->d_ctl, P->d_work, P->d_gates, count, j, R, stream));
     }
-    // x += Z y for every instance of the cycle (y[0] carries k)
-    std::vector<double> ybuf((size_t)count * (R + 1), 0.0);
-    for (int i : active) {
-      InstState &s = st[i];
-      if (!s.in_cycle) continue;
-      double *y = &ybuf[(size_t)i * (R + 1)];
-      y[0] = s.k;
-      for (int r = s.k - 1; r >= 0; --r) {
-        double t = s.g[r];
-        for (int c = r + 1; c < s.k; ++c) t -= s.H[(size_t)r * R + c] * y[1 + c];
-        y[1 + r] = t / s.H[(size_t)r * R + r];
-      }
-      s.in_cycle = false;
-      ++s.restarts;
+    g_step = -1;
+    return FDE_OK;
+  };
+  auto finish_and_restart = [&]() -> fde_status {
+    HIPCHK(launch_gm_backsolve(P->d_desc, P->d_ctl, P->d_work, count, stream));
+    HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] { return launch_update_x(P->d_desc, Slive.kry, S.n_kry, stream); }));
+    return restart_step();
+  };
+  // Reads the control records.  Launches of Arnoldi steps >= j0 + (steps taken since the
+  // snapshot its0) were gated off for every instance; the profile does not count them.
+  std::vector<int> its0(count, 0);
+  int j0 = 0;
+  auto read_ctl = [&]() -> fde_status {
+    HIPCHK(hipMemcpyAsync(ctl.data(), P->d_ctl, count * sizeof(GmresCtl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    int taken = 0;
+    for (int i = 0; i < count; ++i) taken = std::max(taken, ctl[i].its - its0[i]);
+    L->prof_step_limit = j0 + taken;
+    const fde_status sf = sync_and_flush(L);
+    L->prof_step_limit = 1 << 30;
+    for (int i = 0; i < count; ++i) its0[i] = ctl[i].its;
+    return sf;
+  };
+  auto segment = [&](GraphSeg &g, const std::function<fde_status()> &emit) -> fde_status {
+    const fde_status r = run_segment(P, g, use_graph && !P->graph_off, emit);
+    g_step = -1;
+    return r;
+  };
+  // Cycle c runs its first stretch of Arnoldi steps up to the length of cycle c of the
+  // previous solve (the whole cycle if unknown), then checks on the host and continues in
+  // stretches of four steps while some instance is still active.
+  constexpr int kStretch = 4;
+  std::vector<int> taken_per_cycle;
+  STCHK(segment(P->seg_restart, restart_step));
+  STCHK(read_ctl());
+  for (int c = 0;; ++c) {
+    bool any = false;
+    for (int i = 0; i < count; ++i) any = any || !ctl[i].done;
+    if (!any) break;
+    std::vector<int> its_cycle(count);
+    for (int i = 0; i < count; ++i) its_cycle[i] = ctl[i].its;
+    const int pred = c < (int)P->pred_steps.size() ? P->pred_steps[c] : 0;
+    int j = 0, len = pred > 0 ? std::min(pred, R) : R;
+    for (;;) {
+      const int j1 = std::min(R, j + len);
+      j0 = j;
+      STCHK(segment(P->seg_steps[{j, j1}], [&] { return steps(j, j1); }));
+      j = j1;
+      if (j >= R) break;
+      STCHK(read_ctl());
+      bool active = false;
+      for (int i = 0; i < count; ++i) active = active || ctl[i].active;
+      if (!active) break;
+      len = kStretch;
     }
-    HIPCHK(hipMemcpy(P->d_y, ybuf.data(), ybuf.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (active != built) {
-      STCHK(build_solve_maps(P, active, S));
-      built = active;
-    }
-    HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] { return launch_update_x(P->d_desc, S.kry, S.n_kry, stream); }));
-    std::vector<int> still;
-    for (int i : active)
-      if (!st[i].done) still.push_back(i);
-    active = still;
+    STCHK(segment(P->seg_finish, finish_and_restart));
+    STCHK(read_ctl());
+    int cyc = 0;
+    for (int i = 0; i < count; ++i) cyc = std::max(cyc, ctl[i].its - its_cycle[i]);
+    taken_per_cycle.push_back(cyc);
   }
-  STCHK(sync_and_flush(L));
-  return check_trsv_err(P);
+  P->pred_steps = taken_per_cycle;
+  for (int i = 0; i < count; ++i) {
+    st[i].truer = ctl[i].truer;
+    st[i].est = ctl[i].est;
+    st[i].its = ctl[i].its;
+    st[i].restarts = ctl[i].restarts;
+    st[i].conv = ctl[i].conv != 0;
+    st[i].fail = ctl[i].fail != 0;
+  }
+  STCHK(check_trsv_err(P));
+  for (int i = 0; i < count; ++i)
+    if (st[i].fail) return fail(FDE_ENOCONV, "instance %d produced a non-finite residual", i);
+  return FDE_OK;
 }
 
 static fde_status check_opts(const fde_solve_opts *o, fde_solve_opts *out) {
@@ -1227,6 +1515,69 @@ static fde_status copy_out(fde_bvm *h, double *dst, const double *src, size_t co
   return FDE_OK;
 }
 
+// ---- autotuner of the block-solve launch shape ------------------------------------------
+// On the first solve of a plan shape (instance sizes + precision) the cooperative block
+// solve is timed for each candidate W (workgroups per block) within the co-residency limit,
+// on the factored blocks (the values in the work vectors do not matter for the timing); the
+// fastest is kept for the life of the process.  Skipped when W is forced by an option, when
+// autotuning is off, or when cooperative launches are unavailable.
+static fde_status autotune_trsv(Plan *P, int prec) {
+  fde_bvm *L = P->lead;
+  if (!L->opt_autotune || L->opt_trsv_w > 0 || !g_coop_ok) return FDE_OK;
+  const std::string key = plan_shape_key(P, prec);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_tuned_w.count(key)) return FDE_OK;
+  }
+  int wtop = 1;
+  for (fde_bvm *h : P->hs) wtop = std::max(wtop, trsv_wmax(P, h, prec));
+  std::vector<int> cands;
+  for (int w = 1; w <= wtop; w = w < 4 ? w + 1 : w + w / 2) cands.push_back(w);
+  if (cands.back() != wtop) cands.push_back(wtop);
+  const bool prof = L->prof;
+  L->prof = false;
+  auto set_w = [&](int w) -> fde_status {
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tuned_w[key] = w;
+    }
+    STCHK(plan_prepare(P, std::max(P->R, 1), prec));
+    return ensure_full_maps(P);
+  };
+  hipEvent_t e0 = get_event(L), e1 = get_event(L);
+  int best_w = cands.back();
+  float best = 1e30f;
+  fde_status s = FDE_OK;
+  for (int w : cands) {
+    if ((s = set_w(w)) != FDE_OK) break;
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 4 && s == FDE_OK; ++rep) {
+      (void)hipEventRecord(e0, L->stream);
+      s = op_precond(P, P->full, VS_TMP, 0, VS_TMP, 0);
+      (void)hipEventRecord(e1, L->stream);
+      if (s != FDE_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(FDE_EDEVICE, "autotuner timing failed");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tmin = std::min(tmin, ms);  // the first repetition warms up
+    }
+    if (s != FDE_OK) break;
+    if (tmin < best) {
+      best = tmin;
+      best_w = w;
+    }
+  }
+  L->evpool.push_back(e0);
+  L->evpool.push_back(e1);
+  L->prof = prof;
+  if (s == FDE_OK) s = check_trsv_err(P);
+  const fde_status s2 = set_w(best_w);
+  return s != FDE_OK ? s : s2;
+}
+
 static fde_status solve_plan(Plan *P, const double *const *u0, const double *const *f,
                              double *const *u, const double *const *x0, const fde_solve_opts &o,
                              fde_solve_info *info) {
@@ -1240,8 +1591,8 @@ static fde_status solve_plan(Plan *P, const double *const *u0, const double *con
     if (!u0[i] || !f[i] || !u[i]) return fail(FDE_EINVAL, "u0, f and u are required (instance %d)", i);
     if (h->stream != L->stream) HIPCHK(hipStreamSynchronize(h->stream));
   }
-  const int cap = prec == FDE_FP64 ? trsv_coop_capacity<double>() : trsv_coop_capacity<float>();
-  STCHK(plan_prepare(P, o.restart, cap));
+  STCHK(plan_prepare(P, o.restart, prec));
+  STCHK(autotune_trsv(P, prec));
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipEventRecord(e0, L->stream));
   for (int i = 0; i < count; ++i) {
@@ -1353,9 +1704,10 @@ extern "C" fde_status fde_bvm_solve_batch_x0(fde_bvm *const *hs, int count, cons
 // single steps (per-kernel checks), all through the handle's own plan
 // ====================================================================================
 static fde_status self_maps(fde_bvm *h, SolveMaps &S) {
-  const int cap = h->prec == FDE_MIXED_C32 ? trsv_coop_capacity<float>() : trsv_coop_capacity<double>();
-  STCHK(plan_prepare(h->self, std::max(h->self->R, 1), cap));
-  return build_solve_maps(h->self, {0}, S);
+  STCHK(plan_prepare(h->self, std::max(h->self->R, 1), h->prec));
+  STCHK(ensure_full_maps(h->self));
+  S = h->self->full;
+  return FDE_OK;
 }
 
 extern "C" fde_status fde_build_rhs(fde_bvm *h, const double *u0, const double *f, double *b,

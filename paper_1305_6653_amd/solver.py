@@ -97,6 +97,14 @@ class BvmSolver:
     def handle(self):
         return self._h
 
+    def set_option(self, option: int, value: int):
+        N.check(N.lib().fde_bvm_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = C.c_int()
+        N.check(N.lib().fde_bvm_get_option(self._h, int(option), C.byref(v)))
+        return v.value
+
     def set_stream(self, stream):
         ptr = getattr(stream, "cuda_stream", stream)
         N.check(N.lib().fde_set_stream(self._h, C.c_void_p(ptr or 0)))
@@ -208,6 +216,13 @@ class BvmSolver:
             import torch
             return torch.empty(shape, dtype=torch.float64, device=like.device)
         return np.empty(shape, dtype=np.float64)
+
+
+def autotune_report() -> str:
+    """The autotuner's choices so far, "shape=W;..."."""
+    buf = C.create_string_buffer(4096)
+    N.check(N.lib().fde_autotune_report(buf, len(buf)))
+    return buf.value.decode()
 
 
 def factor_batch(solvers, precision: str = "fp64"):

@@ -9,7 +9,8 @@
 //
 // LU step p (panel width 64):  A11 = L11 U11 in LDS (one workgroup per block), then
 //   L21 = A21 U11^{-1},  U12 = L11^{-1} A12   (k_lu_panel, 64x64x64 complex GEMMs)
-//   A22 -= L21 U12                             (k_lu_update, 64x64 tiles, K = 64)
+//   A22 -= L21 U12                             (k_lu_update, 64x64 tiles; steps are paired
+//                                               so the bulk of the update runs with K = 128)
 // Complex products use four real MFMAs on the re/im parts (gfx950 has no complex MFMA).
 #include "batch.hpp"
 #include "common.hpp"
@@ -387,18 +388,39 @@ __global__ __launch_bounds__(256) void k_lu_panel(const InstDesc *__restrict__ D
   tile_store<T>(Ct + (size_t)wr * mp + wc, mp, cre, cim);
 }
 
-// Trailing update.  Item = (instance, block, tile (ti, tj)):  A22[ti][tj] -= L21_ti U12_tj.
+// Trailing updates, in pairs of panel steps (p, p+1) so that the trailing matrix is read and
+// written once per two steps.  Tiles are indexed (ti, tj) from panel p + 1, nrem = npan - p - 1.
+//   mode 1 (band of step p): the tiles step p + 1 needs, its row and column (ti == 0 or
+//          tj == 0): A[ti][tj] -= L[ti][p] U[p][tj]                 (2 nrem - 1 tiles per block)
+//   mode 2 (rest of the pair): ti, tj >= 1:
+//          A[ti][tj] -= L[ti][p] U[p][tj] + L[ti][p+1] U[p+1][tj]    ((nrem - 1)^2 tiles, K = 128)
+//   mode 0 (single step p, no pairing): every tile, K = 64         (nrem^2 tiles)
+__device__ __forceinline__ int update_tiles(int mode, int nrem) {
+  return mode == 0 ? nrem * nrem : mode == 1 ? 2 * nrem - 1 : (nrem - 1) * (nrem - 1);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ Dd, ItemMap map,
-                                                   int p) {
+                                                   int p, int mode) {
   typedef c_t<T> C;
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
   const int local = blockIdx.x - map.pre[q];
-  const int blk = local / (nrem * nrem), t = local % (nrem * nrem);
-  const int ti = t / nrem, tj = t % nrem;
+  const int per = update_tiles(mode, nrem);
+  const int blk = local / per, t = local % per;
+  int ti, tj;
+  if (mode == 1) {
+    ti = t < nrem ? 0 : t - nrem + 1;
+    tj = t < nrem ? t : 0;
+  } else if (mode == 2) {
+    ti = 1 + t / (nrem - 1);
+    tj = 1 + t % (nrem - 1);
+  } else {
+    ti = t / nrem;
+    tj = t % nrem;
+  }
   C *Kb = (C *)d.K + (size_t)blk * mp * mp;
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -408,6 +430,7 @@ __global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ 
   acc_t<T> cre[2][2], cim[2][2];
   tile_load<T>(Ct, mp, cre, cim);
   wave_mma<T, true>(A, mp, B, mp, cre, cim);
+  if (mode == 2) wave_mma<T, true>(A + PB, mp, B + (size_t)PB * mp, mp, cre, cim);
   tile_store<T>(Ct, mp, cre, cim);
 }
 
@@ -508,26 +531,6 @@ __device__ __forceinline__ double2 ld_coh(const double2 *p) {
   return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
 }
 
-// Returns false (uniformly across the workgroup) if the wait was abandoned.
-__device__ __forceinline__ bool ts_wait(const unsigned long long *flag, unsigned long long epoch,
-                                        int *err) {
-  int ok = 1;
-  if (threadIdx.x == 0) {
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-      for (int it = 0;; ++it) {
-        __builtin_amdgcn_s_sleep(1);
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
-        if (it > TS_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          atomicOr(err, 1);
-          ok = 0;
-          break;
-        }
-      }
-    }
-  }
-  return __syncthreads_and(ok) != 0;
-}
-
 __device__ __forceinline__ void ts_publish(unsigned long long *flag, unsigned long long epoch) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's coherent stores have completed
   __syncthreads();
@@ -544,21 +547,70 @@ __device__ __forceinline__ double2 sum16(double2 v) {
   return v;
 }
 
-// acc[g] += M[rows][cols] * x, for this wave's 16 rows (4 groups of 4, row = base + 4g + lane/16)
-// over 64 columns (4 groups of 16, col = 16j + lane%16); x[j] is the column value of group j.
+// This wave's part of a 64x64 chunk: 16 rows (4 groups of 4, row = base + 4g + lane/16) by
+// 64 columns (4 groups of 16, col = 16j + lane%16).
 template <typename T>
-__device__ __forceinline__ void chunk_gemv(const c_t<T> *__restrict__ M, size_t ld,
-                                           const double2 (&x)[4], double2 (&acc)[4]) {
+__device__ __forceinline__ void chunk_load(const c_t<T> *__restrict__ M, size_t ld,
+                                           c_t<T> (&a)[4][4]) {
   const int lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
-  c_t<T> a[4][4];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int j = 0; j < 4; ++j) a[g][j] = M[(size_t)(4 * g + rs) * ld + 16 * j + cs];
+}
+
+// acc[g] += a[g][:] * x; x[j] is the column value of group j.
+template <typename T>
+__device__ __forceinline__ void chunk_fma(const c_t<T> (&a)[4][4], const double2 (&x)[4],
+                                          double2 (&acc)[4]) {
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[g] = cfma(widen(a[g][j]), x[j], acc[g]);
+}
+
+template <typename T>
+__device__ __forceinline__ void chunk_gemv(const c_t<T> *__restrict__ M, size_t ld,
+                                           const double2 (&x)[4], double2 (&acc)[4]) {
+  c_t<T> a[4][4];
+  chunk_load<T>(M, ld, a);
+  chunk_fma<T>(a, x, acc);
+}
+
+// Flags are raised in sweep order (each panel depends on the previous one), so the chunks
+// t, t+1, ... of a sweep that are ready form a prefix.  Waits for chunk t, then counts with one
+// probe per lane how many of the following chunks are ready as well; returns the first chunk
+// not known ready (> t), or -1 if the wait was abandoned.  Uniform across the workgroup;
+// *sh is a workgroup-shared slot (alternate two slots between consecutive calls).
+__device__ __forceinline__ int ts_ready(const unsigned long long *fl, int sweep, int npan, int t,
+                                        int nq, unsigned long long epoch, int *err, int *sh) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    auto flag = [&](int tt) -> const unsigned long long * {
+      const int Q = sweep == 0 ? tt : npan - 1 - tt;
+      return &fl[Q * 2 + sweep];
+    };
+    int ok = 1;
+    if (lane == 0 && __hip_atomic_load(flag(t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      for (int it = 0;; ++it) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(flag(t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (it > TS_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicOr(err, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    ok = __shfl(ok, 0, 64);
+    const int tt = t + 1 + lane;
+    const bool r = tt < nq &&
+                   __hip_atomic_load(flag(tt < nq ? tt : t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    const unsigned long long m = __ballot(r);  // bit 63 is clear: nq - t - 1 < 64
+    if (lane == 0) *sh = ok ? t + 1 + (__ffsll((long long)~m) - 1) : -1;
+  }
+  __syncthreads();
+  return *sh;
 }
 
 template <typename T>
@@ -567,6 +619,8 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
                                                    const unsigned long long *__restrict__ epoch_p,
                                                    int *__restrict__ err) {
   __shared__ double2 tmp[PB];
+  __shared__ int ready_slot[2];
+  int calls = 0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
   const int r16 = wave * 16;  // this wave's first row inside the panel
   const unsigned long long epoch =
@@ -590,13 +644,23 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
         const int nq = sweep == 0 ? P : npan - 1 - P;
+        int have = 0;  // chunks t < have are known to be published
         for (int t = 0; t < nq; ++t) {
           const int Q = sweep == 0 ? t : npan - 1 - t;
-          if (!ts_wait(&fl[Q * 2 + sweep], epoch, err)) return;
+          // FP32 chunks are loaded before a possible wait, so the loads are in flight meanwhile
+          // (FP64 chunks would need twice the registers and halve the co-resident workgroups)
+          constexpr bool early = sizeof(T) == 4;
+          c_t<T> a[4][4];
+          if (early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
+          if (t >= have) {
+            have = ts_ready(fl, sweep, npan, t, nq, epoch, err, &ready_slot[calls++ & 1]);
+            if (have < 0) return;
+          }
+          if (!early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
           double2 x[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) x[j] = ld_coh(&v[Q * PB + 16 * j + cs]);
-          chunk_gemv<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, x, acc);
+          chunk_fma<T>(a, x, acc);
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -654,10 +718,10 @@ hipError_t launch_lu_panel(const InstDesc *D, const ItemMap &map, int items, int
 }
 
 template <typename T>
-hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p,
+hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p, int mode,
                             hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lu_update<T>, dim3(items), dim3(256), 0, st, D, map, p);
+  hipLaunchKernelGGL(k_lu_update<T>, dim3(items), dim3(256), 0, st, D, map, p, mode);
   return hipGetLastError();
 }
 
@@ -710,7 +774,8 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
   template hipError_t launch_lu_diag<T>(const InstDesc *, const ItemMap &, int, int, int *,        \
                                         hipStream_t);                                           \
   template hipError_t launch_lu_panel<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
-  template hipError_t launch_lu_update<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t); \
+  template hipError_t launch_lu_update<T>(const InstDesc *, const ItemMap &, int, int, int,        \
+                                          hipStream_t);                                         \
   template hipError_t launch_trsv<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t);    \
   template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int,                 \
                                           const unsigned long long *, int *, hipStream_t);       \

@@ -39,8 +39,12 @@ hipError_t launch_lu_diag(const InstDesc *D, const ItemMap &map, int items, int 
                           hipStream_t st);
 template <typename T>
 hipError_t launch_lu_panel(const InstDesc *D, const ItemMap &map, int items, int p, hipStream_t st);
+// trailing update of panel step p, mode 0: every tile (nrem^2 items per block, K = 64);
+// 1: the first tile row and column (2 nrem - 1); 2: the other tiles with the updates of steps
+// p and p + 1 together ((nrem - 1)^2, K = 128)
 template <typename T>
-hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p, hipStream_t st);
+hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p, int mode,
+                            hipStream_t st);
 // one workgroup per block: items = nb per instance
 template <typename T>
 hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max_mp, hipStream_t st);

@@ -988,8 +988,11 @@ extern "C" fde_status fde_get_dims(const fde_bvm *h, int *dims) {
 // ====================================================================================
 // factorization
 // ====================================================================================
-// Blocked right-looking LU of every block of every instance, panel step by panel step:
-// diagonal tile, panel, trailing update (one launch each, over all blocks of all instances).
+// Blocked right-looking LU of every block of every instance, two panel steps at a time (one
+// launch per phase over all blocks of all instances):
+//   diag(p), panel(p), band update of p (row and column p + 1), diag(p+1), panel(p+1),
+//   then the rest of the trailing matrix with the updates of steps p and p + 1 together,
+// so the trailing matrix is read and written once per pair of steps.
 template <typename T>
 static fde_status factor_plan_impl(Plan *P) {
   fde_bvm *L = P->lead;
@@ -1003,45 +1006,72 @@ static fde_status factor_plan_impl(Plan *P) {
     maxpan = std::max(maxpan, P->hs[i]->npan);
     asm_bytes += (double)P->hs[i]->nb * P->hs[i]->m * P->hs[i]->m * sizeof(T) * 2.0;
   }
-  // maps: assemble, then (diag, panel, update) for every panel step
+  auto nrem_of = [&](int i, int p) { return P->hs[i]->npan - p - 1; };
+  // maps: assemble, then per pair (diag p, panel p, band p, diag p+1, panel p+1, rest p)
   std::vector<HostMap> hm;
   for (int i = 0; i < count; ++i) it[i] = assemble_items(P->hs[i]->mp, P->hs[i]->nb);
   hm.push_back(make_map(slots, it));
-  for (int p = 0; p < maxpan; ++p) {
-    for (int i = 0; i < count; ++i) it[i] = p < P->hs[i]->npan ? P->hs[i]->nb : 0;
-    hm.push_back(make_map(slots, it));
-    for (int i = 0; i < count; ++i) {
-      const int nrem = P->hs[i]->npan - p - 1;
-      it[i] = nrem > 0 ? 2 * nrem * P->hs[i]->nb : 0;
+  for (int p = 0; p < maxpan; p += 2) {
+    for (int pp = p; pp <= p + 1; ++pp) {
+      for (int i = 0; i < count; ++i) it[i] = nrem_of(i, pp) >= 0 ? P->hs[i]->nb : 0;
+      hm.push_back(make_map(slots, it));  // diag pp
+      for (int i = 0; i < count; ++i) it[i] = nrem_of(i, pp) > 0 ? 2 * nrem_of(i, pp) * P->hs[i]->nb : 0;
+      hm.push_back(make_map(slots, it));  // panel pp
+      if (pp == p) {
+        for (int i = 0; i < count; ++i) it[i] = nrem_of(i, p) > 0 ? (2 * nrem_of(i, p) - 1) * P->hs[i]->nb : 0;
+        hm.push_back(make_map(slots, it));  // band p
+      }
     }
-    hm.push_back(make_map(slots, it));
     for (int i = 0; i < count; ++i) {
-      const int nrem = P->hs[i]->npan - p - 1;
-      it[i] = nrem > 0 ? nrem * nrem * P->hs[i]->nb : 0;
+      const int n1 = nrem_of(i, p) - 1;
+      it[i] = n1 > 0 ? n1 * n1 * P->hs[i]->nb : 0;
     }
-    hm.push_back(make_map(slots, it));
+    hm.push_back(make_map(slots, it));  // rest p
   }
   std::vector<ItemMap> dm;
   STCHK(upload_maps(P, hm, dm));
   hipStream_t st = L->stream;
   HIPCHK(run(L, "assemble", asm_bytes, [&] { return launch_assemble<T>(P->d_desc, dm[0], hm[0].items, st); }));
-  for (int p = 0; p < maxpan; ++p) {
-    // algorithmic flops (complex multiply-add = 8 real flops) on the unpadded orders m
-    double wd = 0, wp = 0, wu = 0;
+  // algorithmic flops (complex multiply-add = 8 real flops) on the unpadded orders m
+  auto wdiag = [&](int p) {
+    double w = 0;
+    for (fde_bvm *h : P->hs)
+      if (p < h->npan) {
+        const double c = std::min(64, h->m - p * 64);
+        w += h->nb * 8.0 * c * c * c / 3.0;
+      }
+    return w;
+  };
+  auto wpanel = [&](int p) {
+    double w = 0;
+    for (fde_bvm *h : P->hs)
+      if (p < h->npan) w += h->nb * 8.0 * 64.0 * 64.0 * std::max(0, h->m - (p + 1) * 64);
+    return w;
+  };
+  size_t mi = 1;
+  for (int p = 0; p < maxpan; p += 2) {
+    double wband = 0, wrest = 0;
     for (fde_bvm *h : P->hs) {
       if (p >= h->npan) continue;
-      const double rem = std::max(0, h->m - (p + 1) * 64);
-      const double w = std::min(64, h->m - p * 64);
-      wd += h->nb * 8.0 * w * w * w / 3.0;
-      wp += h->nb * 8.0 * 64.0 * 64.0 * rem;
-      wu += h->nb * 8.0 * 64.0 * rem * rem;
+      const double rem = std::max(0, h->m - (p + 1) * 64), rem2 = std::max(0.0, rem - 64.0);
+      wband += h->nb * 8.0 * 64.0 * (rem * rem - rem2 * rem2);
+      wrest += h->nb * 8.0 * 128.0 * rem2 * rem2;
     }
-    const HostMap &hd = hm[1 + 3 * p], &hp = hm[2 + 3 * p], &hu = hm[3 + 3 * p];
-    HIPCHK(run(L, "lu_diag", wd, [&] { return launch_lu_diag<T>(P->d_desc, dm[1 + 3 * p], hd.items, p, P->d_flag, st); }));
-    if (hp.items > 0) {
-      HIPCHK(run(L, "lu_panel", wp, [&] { return launch_lu_panel<T>(P->d_desc, dm[2 + 3 * p], hp.items, p, st); }));
-      HIPCHK(run(L, "lu_update", wu, [&] { return launch_lu_update<T>(P->d_desc, dm[3 + 3 * p], hu.items, p, st); }));
+    for (int pp = p; pp <= p + 1; ++pp) {
+      const size_t id = mi++, ip = mi++;
+      if (hm[id].items > 0)
+        HIPCHK(run(L, "lu_diag", wdiag(pp), [&] { return launch_lu_diag<T>(P->d_desc, dm[id], hm[id].items, pp, P->d_flag, st); }));
+      if (hm[ip].items > 0)
+        HIPCHK(run(L, "lu_panel", wpanel(pp), [&] { return launch_lu_panel<T>(P->d_desc, dm[ip], hm[ip].items, pp, st); }));
+      if (pp == p) {
+        const size_t ib = mi++;
+        if (hm[ib].items > 0)
+          HIPCHK(run(L, "lu_update", wband, [&] { return launch_lu_update<T>(P->d_desc, dm[ib], hm[ib].items, p, 1, st); }));
+      }
     }
+    const size_t ir = mi++;
+    if (hm[ir].items > 0)
+      HIPCHK(run(L, "lu_update", wrest, [&] { return launch_lu_update<T>(P->d_desc, dm[ir], hm[ir].items, p, 2, st); }));
   }
   return FDE_OK;
 }

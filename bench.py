@@ -63,6 +63,24 @@ def measured_traffic(workload_name, prec, kernel):
     return PMC_TRAFFIC.get((workload_name, prec, kernel))
 
 
+def measured_read_peak():
+    """Achievable HBM read bandwidth on this GPU, GB/s: torch's sum over a 4 GiB FP32 tensor
+    (best of 5), outside the timed region.  Context for the datasheet peak."""
+    import torch
+    x = torch.ones(1 << 30, dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        x.sum()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del x
+    return round(4.0 * (1 << 30) / (best * 1e-3) / 1e9, 1)
+
+
 def calib_copy(mib):
     """One plain device-to-device copy of mib MiB (a blit dispatch) outside the timed region."""
     import torch
@@ -134,7 +152,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup):
     return ms, ms_prof, infos, prof
 
 
-def roofline(prof, prec, workload_name=None):
+def roofline(prof, prec, workload_name=None, read_peak=None):
     """Dominant kernel (largest total time) with its algorithmic work rate."""
     if not prof:
         return None
@@ -149,10 +167,14 @@ def roofline(prof, prec, workload_name=None):
                 "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
                 "work_per_launch": q["work"] / q["count"]}
     achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
-            "work_per_launch": q["work"] / q["count"]}
+    out = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+           "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
+           "work_per_launch": q["work"] / q["count"]}
+    if read_peak:
+        out["measured_read_peak"] = read_peak
+        out["frac_of_measured_read_peak"] = round(achieved / read_peak, 4)
+    return out
 
 
 def cpu_baseline(p):
@@ -279,6 +301,7 @@ def main():
     S.set_stream(torch.cuda.current_stream())
 
     ms, ms_prof, infos, prof = timed_steps(S, u0, f, out, prec, args.steps, args.warmup)
+    read_peak = measured_read_peak()
     u_main = out.cpu().numpy().copy()
     result = {
         "metric": METRIC, "value": round(1000.0 / ms, 4), "unit": "solves/s", "n_gpus": 1,
@@ -295,7 +318,7 @@ def main():
         "profiled_ms_per_step": round(ms_prof, 4),
         "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4), "count": v["count"] // args.steps}
                     for k, v in prof.items()},
-        "roofline": roofline(prof, prec, args.workload),
+        "roofline": roofline(prof, prec, args.workload, read_peak),
         "autotuned": autotune_report(),
     }
     if not args.no_mixed and prec == "fp64":
@@ -307,7 +330,7 @@ def main():
             "t_factor_ms": round(infos2[-1]["t_factor_ms"], 3),
             "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
-            "roofline": roofline(prof2, "mixed", args.workload),
+            "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
     if not args.no_cpu_baseline:
         cb, u_ref = cpu_baseline(p)

@@ -344,6 +344,23 @@ __device__ __forceinline__ void tile_store(c_t<T> *__restrict__ Cp, int ldc,
         Cp[(size_t)(r * 16 + mfma_row<T>(lk, v)) * ldc + c * 16 + li] = mk<T>(cre[r][c][v], cim[r][c][v]);
 }
 
+// C += acc for this wave's 32x32 part of a tile (layout as tile_load)
+template <typename T>
+__device__ __forceinline__ void tile_add_store(c_t<T> *__restrict__ Cp, int ldc,
+                                               const acc_t<T> (&cre)[2][2], const acc_t<T> (&cim)[2][2]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        c_t<T> *e = Cp + (size_t)(r * 16 + mfma_row<T>(lk, v)) * ldc + c * 16 + li;
+        const c_t<T> z = *e;
+        *e = mk<T>(z.x + cre[r][c][v], z.y + cim[r][c][v]);
+      }
+}
+
 template <typename T>
 __device__ __forceinline__ void tile_zero(acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
 #pragma unroll
@@ -399,10 +416,17 @@ __device__ __forceinline__ int update_tiles(int mode, int nrem) {
   return mode == 0 ? nrem * nrem : mode == 1 ? 2 * nrem - 1 : (nrem - 1) * (nrem - 1);
 }
 
+// The K operand streams through LDS in slices of US columns, double-buffered: while the MFMAs
+// of slice s read LDS, the registers already hold slice s + 1 (loaded once per workgroup,
+// 16-byte coalesced), which is stored to the other buffer before the slice's barrier.
+static constexpr int US = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ Dd, ItemMap map,
+__global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict__ Dd, ItemMap map,
                                                    int p, int mode) {
   typedef c_t<T> C;
+  __shared__ C As[2][PB][US + 1];  // L21 slice: 64 rows x US
+  __shared__ C Bs[2][US][PB + 1];  // U12 slice: US x 64 columns
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
@@ -421,17 +445,66 @@ __global__ __launch_bounds__(256) void k_lu_update(const InstDesc *__restrict__ 
     ti = t / nrem;
     tj = t % nrem;
   }
-  C *Kb = (C *)d.K + (size_t)blk * mp * mp;
-  const int wave = threadIdx.x >> 6;
+  const C *Kb = (const C *)d.K + (size_t)blk * mp * mp;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  C *Ct = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
-  const C *A = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)p * PB + (size_t)wr * mp;
-  const C *B = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + tj) * PB + wc;
+  C *Ct = (C *)Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
+  const C *A = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)p * PB;  // 64 x KT, row stride mp
+  const C *B = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + tj) * PB;  // KT x 64, row stride mp
+  const int nsl = (mode == 2 ? 2 * PB : PB) / US;
+  // staging: A slice = 64 x US (thread -> row tid / 4, columns 2 (tid % 4) + {0, 1});
+  //          B slice = US x 64 (thread -> row tid / 32, columns 2 (tid % 32) + {0, 1})
+  const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
+  const C *Ap = A + (size_t)ar * mp + ac;
+  const C *Bp = B + (size_t)br * mp + bc;
+  C ra0 = Ap[0], ra1 = Ap[1], rb0 = Bp[0], rb1 = Bp[1];  // slice 0
+  // acc = -A B from zero; C is added at the end (keeps the C tile out of the loop's registers)
   acc_t<T> cre[2][2], cim[2][2];
-  tile_load<T>(Ct, mp, cre, cim);
-  wave_mma<T, true>(A, mp, B, mp, cre, cim);
-  if (mode == 2) wave_mma<T, true>(A + PB, mp, B + (size_t)PB * mp, mp, cre, cim);
-  tile_store<T>(Ct, mp, cre, cim);
+  tile_zero<T>(cre, cim);
+  As[0][ar][ac] = ra0;
+  As[0][ar][ac + 1] = ra1;
+  Bs[0][br][bc] = rb0;
+  Bs[0][br][bc + 1] = rb1;
+  __syncthreads();
+#pragma unroll 1
+  for (int sl = 0; sl < nsl; ++sl) {
+    const int buf = sl & 1;
+    const bool more = sl + 1 < nsl;
+    if (more) {
+      const int k1 = (sl + 1) * US;
+      ra0 = Ap[k1];
+      ra1 = Ap[k1 + 1];
+      rb0 = Bp[(size_t)k1 * mp];
+      rb1 = Bp[(size_t)k1 * mp + 1];
+    }
+#pragma unroll
+    for (int kk = 0; kk < US; kk += 4) {
+      C a[2], b[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) a[r] = As[buf][wr + r * 16 + li][kk + lk];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) b[c] = Bs[buf][kk + lk][wc + c * 16 + li];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const T ar_ = -a[r].x, ai_ = -a[r].y;  // acc = C - A B
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cre[r][c] = mfma16(ar_, b[c].x, cre[r][c]);
+          cre[r][c] = mfma16(-ai_, b[c].y, cre[r][c]);
+          cim[r][c] = mfma16(ar_, b[c].y, cim[r][c]);
+          cim[r][c] = mfma16(ai_, b[c].x, cim[r][c]);
+        }
+      }
+    }
+    if (more) {
+      As[buf ^ 1][ar][ac] = ra0;
+      As[buf ^ 1][ar][ac + 1] = ra1;
+      Bs[buf ^ 1][br][bc] = rb0;
+      Bs[buf ^ 1][br][bc + 1] = rb1;
+    }
+    __syncthreads();
+  }
+  tile_add_store<T>(Ct, mp, cre, cim);
 }
 
 // ------------------------------------------------------------------------------------

@@ -287,34 +287,8 @@ __global__ __launch_bounds__(NT) void k_lu_diag(const InstDesc *__restrict__ Dd,
 }
 
 // ------------------------------------------------------------------------------------
-// One wavefront: acc (+/-)= A[32x64] * B[64x32] (complex), 2x2 MFMA 16x16 sub-tiles.
-template <typename T, bool NEG>
-__device__ __forceinline__ void wave_mma(const c_t<T> *__restrict__ A, int lda,
-                                         const c_t<T> *__restrict__ B, int ldb,
-                                         acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k0 = 0; k0 < PB; k0 += 4) {
-    c_t<T> a[2], b[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) a[r] = A[(size_t)(r * 16 + li) * lda + k0 + lk];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) b[c] = B[(size_t)(k0 + lk) * ldb + c * 16 + li];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const T ar = NEG ? -a[r].x : a[r].x;
-      const T ai = NEG ? -a[r].y : a[r].y;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        cre[r][c] = mfma16(ar, b[c].x, cre[r][c]);
-        cre[r][c] = mfma16(-ai, b[c].y, cre[r][c]);
-        cim[r][c] = mfma16(ar, b[c].y, cim[r][c]);
-        cim[r][c] = mfma16(ai, b[c].x, cim[r][c]);
-      }
-    }
-  }
-}
-
+// 64x64 complex tiles on MFMA: each of the 4 wavefronts owns a 32x32 quarter as 2x2 16x16
+// sub-tiles of real and imaginary accumulators.
 template <typename T>
 __device__ __forceinline__ void tile_load(const c_t<T> *__restrict__ Cp, int ldc,
                                           acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
@@ -374,12 +348,86 @@ __device__ __forceinline__ void tile_zero(acc_t<T> (&cre)[2][2], acc_t<T> (&cim)
       }
 }
 
-// Panel.  Item = (instance, block, t): t < nrem -> L21 tile t = A21_t U11^{-1};
-// else U12 tile t-nrem = L11^{-1} A12_t.
+// 64x64 complex GEMM on one workgroup (4 wavefronts, 32x32 each): acc (+/-)= A B with
+// A 64 x (nsl US), B (nsl US) x 64.  The K dimension streams through LDS in slices of US,
+// double-buffered: while the MFMAs of slice s read LDS, the registers already hold slice
+// s + 1 (loaded once per workgroup, 16-byte coalesced), stored to the other buffer before the
+// slice's barrier.  Every read of A and B completes before the function returns.
+static constexpr int US = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map,
-                                                  int p) {
+struct GemmLds {
+  c_t<T> As[2][PB][US + 1];  // A slice: 64 rows x US
+  c_t<T> Bs[2][US][PB + 1];  // B slice: US x 64 columns
+};
+
+template <typename T, bool NEG>
+__device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda,
+                                           const c_t<T> *__restrict__ B, int ldb, int nsl,
+                                           GemmLds<T> &sm, acc_t<T> (&cre)[2][2],
+                                           acc_t<T> (&cim)[2][2]) {
   typedef c_t<T> C;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // staging: A slice thread -> row tid / 4, columns 2 (tid % 4) + {0, 1};
+  //          B slice thread -> row tid / 32, columns 2 (tid % 32) + {0, 1}
+  const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
+  const C *Ap = A + (size_t)ar * lda + ac;
+  const C *Bp = B + (size_t)br * ldb + bc;
+  C ra0 = Ap[0], ra1 = Ap[1], rb0 = Bp[0], rb1 = Bp[1];  // slice 0
+  sm.As[0][ar][ac] = ra0;
+  sm.As[0][ar][ac + 1] = ra1;
+  sm.Bs[0][br][bc] = rb0;
+  sm.Bs[0][br][bc + 1] = rb1;
+  __syncthreads();
+#pragma unroll 1
+  for (int sl = 0; sl < nsl; ++sl) {
+    const int buf = sl & 1;
+    const bool more = sl + 1 < nsl;
+    if (more) {
+      const int k1 = (sl + 1) * US;
+      ra0 = Ap[k1];
+      ra1 = Ap[k1 + 1];
+      rb0 = Bp[(size_t)k1 * ldb];
+      rb1 = Bp[(size_t)k1 * ldb + 1];
+    }
+#pragma unroll
+    for (int kk = 0; kk < US; kk += 4) {
+      C a[2], b[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const T ar_ = NEG ? -a[r].x : a[r].x, ai_ = NEG ? -a[r].y : a[r].y;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cre[r][c] = mfma16(ar_, b[c].x, cre[r][c]);
+          cre[r][c] = mfma16(-ai_, b[c].y, cre[r][c]);
+          cim[r][c] = mfma16(ar_, b[c].y, cim[r][c]);
+          cim[r][c] = mfma16(ai_, b[c].x, cim[r][c]);
+        }
+      }
+    }
+    if (more) {
+      sm.As[buf ^ 1][ar][ac] = ra0;
+      sm.As[buf ^ 1][ar][ac + 1] = ra1;
+      sm.Bs[buf ^ 1][br][bc] = rb0;
+      sm.Bs[buf ^ 1][br][bc + 1] = rb1;
+    }
+    __syncthreads();
+  }
+}
+
+// Panel.  Item = (instance, block, t): t < nrem -> L21 tile t = A21_t U11^{-1};
+// else U12 tile t-nrem = L11^{-1} A12_t.  In place: every read of the tile completes inside
+// gemm64_lds before the result is stored.
+template <typename T>
+__global__ __launch_bounds__(256, 3) void k_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                     int p) {
+  typedef c_t<T> C;
+  __shared__ GemmLds<T> sm;
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
@@ -396,12 +444,11 @@ __global__ __launch_bounds__(256) void k_lu_panel(const InstDesc *__restrict__ D
   C *Ct;
   if (t < nrem) {
     Ct = Kb + (size_t)(p + 1 + t) * PB * mp + (size_t)p * PB;
-    wave_mma<T, false>(Ct + (size_t)wr * mp, mp, Du + wc, PB, cre, cim);
+    gemm64_lds<T, false>(Ct, mp, Du, PB, PB / US, sm, cre, cim);
   } else {
     Ct = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + t - nrem) * PB;
-    wave_mma<T, false>(Dl + (size_t)wr * PB, PB, Ct + wc, mp, cre, cim);
+    gemm64_lds<T, false>(Dl, PB, Ct, mp, PB / US, sm, cre, cim);
   }
-  __syncthreads();  // every wave has read its operands before the tile is overwritten
   tile_store<T>(Ct + (size_t)wr * mp + wc, mp, cre, cim);
 }
 
@@ -416,17 +463,11 @@ __device__ __forceinline__ int update_tiles(int mode, int nrem) {
   return mode == 0 ? nrem * nrem : mode == 1 ? 2 * nrem - 1 : (nrem - 1) * (nrem - 1);
 }
 
-// The K operand streams through LDS in slices of US columns, double-buffered: while the MFMAs
-// of slice s read LDS, the registers already hold slice s + 1 (loaded once per workgroup,
-// 16-byte coalesced), which is stored to the other buffer before the slice's barrier.
-static constexpr int US = 8;
-
 template <typename T>
 __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict__ Dd, ItemMap map,
-                                                   int p, int mode) {
+                                                      int p, int mode) {
   typedef c_t<T> C;
-  __shared__ C As[2][PB][US + 1];  // L21 slice: 64 rows x US
-  __shared__ C Bs[2][US][PB + 1];  // U12 slice: US x 64 columns
+  __shared__ GemmLds<T> sm;
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
@@ -445,65 +486,16 @@ __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict
     ti = t / nrem;
     tj = t % nrem;
   }
-  const C *Kb = (const C *)d.K + (size_t)blk * mp * mp;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  C *Kb = (C *)d.K + (size_t)blk * mp * mp;
+  const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  C *Ct = (C *)Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
-  const C *A = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)p * PB;  // 64 x KT, row stride mp
-  const C *B = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + tj) * PB;  // KT x 64, row stride mp
-  const int nsl = (mode == 2 ? 2 * PB : PB) / US;
-  // staging: A slice = 64 x US (thread -> row tid / 4, columns 2 (tid % 4) + {0, 1});
-  //          B slice = US x 64 (thread -> row tid / 32, columns 2 (tid % 32) + {0, 1})
-  const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
-  const C *Ap = A + (size_t)ar * mp + ac;
-  const C *Bp = B + (size_t)br * mp + bc;
-  C ra0 = Ap[0], ra1 = Ap[1], rb0 = Bp[0], rb1 = Bp[1];  // slice 0
+  C *Ct = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
+  const C *A = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)p * PB;  // 64 x K, row stride mp
+  const C *B = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + tj) * PB;  // K x 64, row stride mp
   // acc = -A B from zero; C is added at the end (keeps the C tile out of the loop's registers)
   acc_t<T> cre[2][2], cim[2][2];
   tile_zero<T>(cre, cim);
-  As[0][ar][ac] = ra0;
-  As[0][ar][ac + 1] = ra1;
-  Bs[0][br][bc] = rb0;
-  Bs[0][br][bc + 1] = rb1;
-  __syncthreads();
-#pragma unroll 1
-  for (int sl = 0; sl < nsl; ++sl) {
-    const int buf = sl & 1;
-    const bool more = sl + 1 < nsl;
-    if (more) {
-      const int k1 = (sl + 1) * US;
-      ra0 = Ap[k1];
-      ra1 = Ap[k1 + 1];
-      rb0 = Bp[(size_t)k1 * mp];
-      rb1 = Bp[(size_t)k1 * mp + 1];
-    }
-#pragma unroll
-    for (int kk = 0; kk < US; kk += 4) {
-      C a[2], b[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) a[r] = As[buf][wr + r * 16 + li][kk + lk];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = Bs[buf][kk + lk][wc + c * 16 + li];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const T ar_ = -a[r].x, ai_ = -a[r].y;  // acc = C - A B
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          cre[r][c] = mfma16(ar_, b[c].x, cre[r][c]);
-          cre[r][c] = mfma16(-ai_, b[c].y, cre[r][c]);
-          cim[r][c] = mfma16(ar_, b[c].y, cim[r][c]);
-          cim[r][c] = mfma16(ai_, b[c].x, cim[r][c]);
-        }
-      }
-    }
-    if (more) {
-      As[buf ^ 1][ar][ac] = ra0;
-      As[buf ^ 1][ar][ac + 1] = ra1;
-      Bs[buf ^ 1][br][bc] = rb0;
-      Bs[buf ^ 1][br][bc + 1] = rb1;
-    }
-    __syncthreads();
-  }
+  gemm64_lds<T, true>(A, mp, B, mp, (mode == 2 ? 2 * PB : PB) / US, sm, cre, cim);
   tile_add_store<T>(Ct, mp, cre, cim);
 }
 

@@ -613,18 +613,36 @@ __device__ __forceinline__ double2 sum16(double2 v) {
 }
 
 // This wave's part of a 64x64 chunk: 16 rows (4 groups of 4, row = base + 4g + lane/16) by
-// 64 columns (4 groups of 16, col = 16j + lane%16).
+// 64 columns.  Lane column set: FP64, col = 16j + lane%16 (j < 4, one complex per load);
+// FP32, col = 32(j/2) + 2(lane%16) + j%2 (two adjacent complex values per 16-byte load).
+// chunk_col gives the column of register j; the caller supplies x[j] = x[chunk_col(j)].
+template <typename T>
+__device__ __forceinline__ int chunk_col(int j, int cs) {
+  return sizeof(T) == 8 ? 16 * j + cs : 32 * (j >> 1) + 2 * cs + (j & 1);
+}
+
 template <typename T>
 __device__ __forceinline__ void chunk_load(const c_t<T> *__restrict__ M, size_t ld,
                                            c_t<T> (&a)[4][4]) {
   const int lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
+  if constexpr (sizeof(T) == 8) {
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) a[g][j] = M[(size_t)(4 * g + rs) * ld + 16 * j + cs];
+      for (int j = 0; j < 4; ++j) a[g][j] = M[(size_t)(4 * g + rs) * ld + 16 * j + cs];
+  } else {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float4 v = *reinterpret_cast<const float4 *>(M + (size_t)(4 * g + rs) * ld + 32 * h + 2 * cs);
+        a[g][2 * h] = mk<T>(v.x, v.y);
+        a[g][2 * h + 1] = mk<T>(v.z, v.w);
+      }
+  }
 }
 
-// acc[g] += a[g][:] * x; x[j] is the column value of group j.
+// acc[g] += a[g][:] * x; x[j] is the value at column chunk_col(j).
 template <typename T>
 __device__ __forceinline__ void chunk_fma(const c_t<T> (&a)[4][4], const double2 (&x)[4],
                                           double2 (&acc)[4]) {
@@ -724,7 +742,7 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
           if (!early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
           double2 x[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) x[j] = ld_coh(&v[Q * PB + 16 * j + cs]);
+          for (int j = 0; j < 4; ++j) x[j] = ld_coh(&v[Q * PB + chunk_col<T>(j, cs)]);
           chunk_fma<T>(a, x, acc);
         }
 #pragma unroll
@@ -739,7 +757,7 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
         const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
         double2 x[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = tmp[16 * j + cs];
+        for (int j = 0; j < 4; ++j) x[j] = tmp[chunk_col<T>(j, cs)];
 #pragma unroll
         for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
         chunk_gemv<T>(Di + (size_t)r16 * PB, PB, x, b);

@@ -34,6 +34,8 @@
 #ifndef FDEBVM_H
 #define FDEBVM_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -180,6 +182,11 @@ fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
 /* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);
  * FDE_EINVAL if len is too small. */
 fde_status fde_autotune_report(char *buf, int len);
+/* Measurement aid: the best of `reps` timed passes of a plain streaming-read kernel over a
+ * `bytes`-byte device buffer (allocated and freed by the call), in GB/s: the read bandwidth
+ * that bandwidth-bound kernels can practically reach on the current device.  FDE_EINVAL for
+ * bytes < 1 MiB or reps < 1; FDE_ENOMEM if the buffer cannot be allocated. */
+fde_status fde_read_bandwidth_probe(size_t bytes, int reps, double *gbs);
 
 /* ---- the individual steps of the path, for per-kernel checks ----------------------- */
 /* b = right-hand side of eq. (1.10) in s-form, [s][m]. */

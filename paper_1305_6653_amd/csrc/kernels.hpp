@@ -88,4 +88,7 @@ hipError_t launch_gm_givens(const InstDesc *D, GmresCtl *ctl, GmresWork *work, i
 hipError_t launch_gm_backsolve(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int count,
                                hipStream_t st);
 
+// ---- streaming-read probe: out has `blocks` floats; reads bytes (a multiple of 16) of x ----
+hipError_t launch_read_probe(const void *x, size_t bytes, float *out, int blocks, hipStream_t st);
+
 }  // namespace fde

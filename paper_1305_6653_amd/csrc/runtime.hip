@@ -967,6 +967,40 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
   }
 }
 
+extern "C" fde_status fde_read_bandwidth_probe(size_t bytes, int reps, double *gbs) {
+  if (!gbs || reps < 1 || bytes < (1u << 20)) return fail(FDE_EINVAL, "need bytes >= 1 MiB, reps >= 1, gbs");
+  bytes &= ~(size_t)15;
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = 8 * std::max(cus, 1);
+  void *x = nullptr, *out = nullptr;
+  STCHK(dalloc_raw(&x, bytes));
+  fde_status st = dalloc_raw(&out, sizeof(float) * blocks);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  if (st == FDE_OK && (hipMemset(x, 0, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = fail(FDE_EDEVICE, "probe set-up failed");
+  for (int r = 0; st == FDE_OK && r <= reps; ++r) {  // the first run warms up
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess || launch_read_probe(x, bytes, (float *)out, blocks, s) != hipSuccess ||
+        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      st = fail(FDE_EDEVICE, "probe launch failed");
+    else if (r > 0)
+      best = std::min(best, ms);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(out);
+  (void)hipFree(x);
+  if (st == FDE_OK) *gbs = (double)bytes / (best * 1e-3) / 1e9;
+  return st;
+}
+
 extern "C" fde_status fde_autotune_report(char *buf, int len) {
   if (!buf || len < 1) return fail(FDE_EINVAL, "invalid buffer");
   const std::string r = tuned_summary();

@@ -33,18 +33,33 @@ def short_name(name: str) -> str:
     return name.split("(")[0].replace("void ", "").strip()
 
 
+def active_stats(db: str, name: str, frac: float = 0.05):
+    """(count, average ns) over the dispatches of `name` that last at least frac x the median:
+    launches whose workgroups all found their instance gated off (nothing to do) are left out."""
+    c = sqlite3.connect(db)
+    d = sorted(r[0] for r in c.execute("select duration from kernels where name = ?", (name,)))
+    if not d:
+        return 0, 0.0
+    cut = frac * d[len(d) // 2]
+    act = [x for x in d if x >= cut]
+    return len(act), (sum(act) / len(act) if act else 0.0)
+
+
 def trace_main(a):
     rows, total = summarise(a.db)
     if a.title:
         print(a.title)
     if a.command:
         print(f"command: {a.command}")
-    print(f"{'kernel':58s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'min_us':>9s} "
-          f"{'max_us':>9s} {'pct':>6s} {'vgpr':>5s} {'agpr':>5s} {'lds':>7s} {'grid':>10s} {'wg':>5s}")
+    print("act_calls / act_avg_us: dispatches lasting at least 5% of the kernel's median (the others "
+          "found every instance gated off)")
+    print(f"{'kernel':50s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'min_us':>9s} "
+          f"{'max_us':>9s} {'act_calls':>9s} {'act_avg_us':>10s} {'pct':>6s} {'vgpr':>5s} {'lds':>7s} {'grid':>10s} {'wg':>5s}")
     for name, n, tot, avg, mn, mx, vg, ag, lds, grid, wg in rows:
-        short = short_name(name)[:58]
-        print(f"{short:58s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:10.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f} "
-              f"{100 * tot / total:6.2f} {vg:5d} {ag:5d} {lds:7d} {grid:10d} {wg:5d}")
+        short = short_name(name)[:50]
+        na, aa = active_stats(a.db, name)
+        print(f"{short:50s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:10.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f} "
+              f"{na:9d} {aa / 1e3:10.2f} {100 * tot / total:6.2f} {vg:5d} {lds:7d} {grid:10d} {wg:5d}")
 
 
 def _col(header, *keys):
@@ -75,6 +90,29 @@ def read_counter(path: str, counter: str):
     return out
 
 
+def traffic_per_dispatch(fetch, write, frac: float = 0.05):
+    """{kernel: [n_fetch, sum_fetch, n_write, sum_write]} over the dispatches whose FETCH_SIZE is
+    at least frac x the kernel's median (gated-off launches, which read only their control
+    data, are left out)."""
+    by_name = defaultdict(list)
+    for n, v in fetch.values():
+        by_name[short_name(n)].append(v)
+    cut = {k: frac * sorted(v)[len(v) // 2] for k, v in by_name.items()}
+    keep = {d for d, (n, v) in fetch.items() if v >= cut[short_name(n)]}
+    agg = defaultdict(lambda: [0, 0.0, 0, 0.0])
+    for d, (n, v) in fetch.items():
+        if d in keep:
+            e = agg[short_name(n)]
+            e[0] += 1
+            e[1] += v
+    for d, (n, v) in write.items():
+        if d in keep or d not in fetch:
+            e = agg[short_name(n)]
+            e[2] += 1
+            e[3] += v
+    return agg
+
+
 def pmc_main(a):
     fetch = read_counter(a.fetch_csv, "FETCH_SIZE")
     write = read_counter(a.write_csv, "WRITE_SIZE")
@@ -89,15 +127,7 @@ def pmc_main(a):
     kib = a.copy_bytes / 1024.0
     f_scale = kib / largest_copy(fetch)
     w_scale = kib / largest_copy(write)
-    agg = defaultdict(lambda: [0, 0.0, 0, 0.0])
-    for n, v in fetch.values():
-        e = agg[short_name(n)]
-        e[0] += 1
-        e[1] += v
-    for n, v in write.values():
-        e = agg[short_name(n)]
-        e[2] += 1
-        e[3] += v
+    agg = traffic_per_dispatch(fetch, write)
     if a.title:
         print(a.title)
     for c in a.command or []:

@@ -31,7 +31,8 @@ __all__ = [
     "trapezoidal", "gbdf3", "formula", "bvm_matrices", "s_form", "all_at_once",
     "problem_matrices", "problem_system", "solve_direct", "strang_columns",
     "strang_circulant", "strang_eigs", "strang_dense", "StrangPreconditioner",
-    "apply_M", "gmres", "GmresResult", "solve_gmres", "true_relres",
+    "apply_M", "gmres", "GmresResult", "solve_gmres", "true_relres", "strang_space_column",
+    "strang_space_symbol", "bccb_eigs", "bccb_dense", "BccbPreconditioner",
 ]
 
 
@@ -265,6 +266,76 @@ class StrangPreconditioner:
         return np.fft.irfft(Wh, n=self.s, axis=0)
 
 
+# ======================================================================================
+# Section 3.1, BCCB variants: S2 = s(A) (x) I - h s(B) (x) s(J), eq. (x1), and the shifted
+# S2~ = s~(A) (x) I - h s(B) (x) s(J), eq. (xc); Section 3.2 (their 2-D FFT diagonalisation)
+# ======================================================================================
+def strang_space_column(g: np.ndarray, N: int) -> np.ndarray:
+    """First column of the order-N circulant s(G_alpha) as printed in Section 3.1:
+    g_1, ..., g_{floor((N+1)/2)}, then zeros, then g_0 in the last position."""
+    c = np.zeros(N)
+    h = (N + 1) // 2
+    c[:h] = g[1:h + 1]
+    if N - 1 >= h:
+        c[N - 1] = g[0]
+    return c
+
+
+def strang_space_symbol(alpha: float, d_plus: np.ndarray, d_minus: np.ndarray, dx: float):
+    """Eigenvalues of s(J_N) = dx^{-alpha} (dbar+ s(G) + dbar- s(G^T)) with dbar the means of
+    d+ and d- (Section 3.1), in the DFT convention C = F^{-1} diag(fft(c)) F.
+
+    s(G^T) is read as s(G)^T (the printed first column of s(G^T) is garbled), whose first
+    column is c[(-i) mod N] and whose eigenvalues are those of s(G) at frequency -j."""
+    N = len(d_plus)
+    g = grunwald_weights(alpha, N)
+    cG = strang_space_column(g, N)
+    cGT = cG[(-np.arange(N)) % N]
+    dbp, dbm = float(np.mean(d_plus)), float(np.mean(d_minus))
+    c = dx ** (-alpha) * (dbp * cG + dbm * cGT)
+    return np.fft.fft(c), c
+
+
+def bccb_eigs(p, shifted: bool = False):
+    """Eigenvalues of S2 (or S2~) as an [s][m] array: phi_k - h psi_k lambda_j(s(J)),
+    eq. (1.13) rebased to the order-s circulants of the s-form.  The shifted variant replaces
+    phi_0 (= rho(1) = 0) by Re(phi_{s-1}), the last eigenvalue of s(A)."""
+    J, F, tau, dx = problem_matrices(p)
+    phi, psi = strang_eigs(F, p.s)
+    if shifted:
+        phi = phi.copy()
+        phi[0] = phi[p.s - 1].real
+    lam, _ = strang_space_symbol(p.alpha, p.d_plus, p.d_minus, dx)
+    return phi[:, None] - tau * psi[:, None] * lam[None, :]
+
+
+def bccb_dense(p, shifted: bool = False) -> np.ndarray:
+    """S2 (S2~) assembled from circulants: the time circulants from their first columns (for
+    S2~, s~(A) = F^{-1} diag(phi~) F) and s(J) from its first column."""
+    J, F, tau, dx = problem_matrices(p)
+    cA, cB = strang_columns(F, p.s)
+    if shifted:
+        phi = np.fft.fft(cA)
+        phi[0] = phi[p.s - 1].real
+        cA = np.fft.ifft(phi).real
+    _, cJ = strang_space_symbol(p.alpha, p.d_plus, p.d_minus, dx)
+    return np.kron(strang_circulant(cA), np.eye(p.m)) - tau * np.kron(strang_circulant(cB),
+                                                                      strang_circulant(cJ))
+
+
+class BccbPreconditioner:
+    """S2^{-1} v (or S2~^{-1} v) by the 2-D DFT: FFT along time and space, divide by the
+    eigenvalues, inverse FFTs (Section 3.2)."""
+
+    def __init__(self, p, shifted: bool = False):
+        self.s, self.m = p.s, p.m
+        self.eig = bccb_eigs(p, shifted)
+
+    def apply(self, V: np.ndarray) -> np.ndarray:
+        V = np.asarray(V, dtype=np.float64).reshape(self.s, self.m)
+        return np.fft.ifft2(np.fft.fft2(V) / self.eig).real
+
+
 def apply_M(J: np.ndarray, A: np.ndarray, B: np.ndarray, tau: float, Z: np.ndarray) -> np.ndarray:
     """M z for z = U[s][m]: (A (x) I) z - tau (B (x) J) z = A U - tau B U J^T (dense J, no FFT)."""
     return A @ Z - tau * (B @ Z) @ J.T
@@ -355,13 +426,22 @@ def true_relres(p, U: np.ndarray) -> float:
 
 
 def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
-                x0: Optional[np.ndarray] = None, preconditioned: bool = True) -> GmresResult:
-    """O2: Strang-preconditioned GMRES(restart) on the s-form system of a Problem."""
+                x0: Optional[np.ndarray] = None, preconditioned: bool = True,
+                precond: str = "strang") -> GmresResult:
+    """O2: preconditioned GMRES(restart) on the s-form system of a Problem; precond is
+    "strang" (S, eq. (1.11)), "bccb" (S2, eq. (x1)) or "bccb_shifted" (S2~, eq. (xc))."""
     J, F, tau, _ = problem_matrices(p)
     A, B, a0, b0, Bfull = s_form(F, p.s)
     b = (tau * (Bfull @ p.f) - np.outer(a0, p.u0) + tau * np.outer(b0, J @ p.u0)).reshape(-1)
     mv = lambda z: apply_M(J, A, B, tau, z.reshape(p.s, p.m)).reshape(-1)
-    pc = StrangPreconditioner(J, F, p.s, tau).apply if preconditioned else None
+    if not preconditioned:
+        pc = None
+    elif precond == "strang":
+        pc = StrangPreconditioner(J, F, p.s, tau).apply
+    elif precond in ("bccb", "bccb_shifted"):
+        pc = BccbPreconditioner(p, shifted=precond == "bccb_shifted").apply
+    else:
+        raise ValueError(f"unknown preconditioner {precond!r}")
     res = gmres(mv, (lambda v: pc(v).reshape(-1)) if pc else None, b, x0, tol, restart, maxit)
     res.x = res.x.reshape(p.s, p.m)
     return res

@@ -1,0 +1,89 @@
+"""Pins of the oracle's BCCB preconditioners S2 (eq. (x1)) and S2~ (eq. (xc)) of Section 3.1
+and their 2-D FFT diagonalisation (Section 3.2)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+
+def _strang_of_toeplitz(T: np.ndarray) -> np.ndarray:
+    """Generic Strang circulant of a Toeplitz matrix: copy the central diagonals.  For order
+    N, the first column holds t_i (i = 0 .. floor((N-1)/2)) and t_{-i} at N - i for the
+    remaining i (t_k = T[k][0], t_{-k} = T[0][k])."""
+    N = T.shape[0]
+    c = np.zeros(N)
+    for i in range(N):
+        c[i] = T[i, 0] if i <= (N - 1) // 2 else T[0, N - i]
+    return c
+
+
+@pytest.mark.parametrize("N", [2, 3, 7, 8, 15, 16])
+@pytest.mark.parametrize("alpha", [1.2, 1.7])
+def test_space_column_is_the_strang_circulant_of_G(N, alpha):
+    g = O.grunwald_weights(alpha, N)
+    G = O.space_matrix(alpha, np.ones(N), np.zeros(N), 1.0)  # dx = 1, d+ = 1, d- = 0: J = G
+    np.testing.assert_array_equal(O.strang_space_column(g, N), _strang_of_toeplitz(G))
+
+
+@pytest.mark.parametrize("N", [5, 16, 31, 64, 255])
+@pytest.mark.parametrize("alpha", [1.05, 1.5, 1.95])
+def test_strang_space_eigenvalues_in_the_disc(N, alpha):
+    """Theorem of Section 3.1: every eigenvalue of s(G) and s(G^T) lies in |z + alpha| < alpha,
+    so Re lambda(s(J)) < 0 and S2 is invertible for a stable BVM."""
+    g = O.grunwald_weights(alpha, N)
+    c = O.strang_space_column(g, N)
+    for lam in (np.fft.fft(c), np.fft.fft(c[(-np.arange(N)) % N])):
+        assert np.all(np.abs(lam + alpha) < alpha)
+    lamJ, _ = O.strang_space_symbol(alpha, np.full(N, 0.6), np.full(N, 0.5), 0.1)
+    assert np.all(lamJ.real < 0.0)
+
+
+def test_space_symbol_matches_J_on_the_central_diagonals():
+    """With constant d+-, J is Toeplitz and s(J) agrees with it on the central diagonals."""
+    N, alpha, dx = 15, 1.6, 2.0 / 16
+    dp, dm = np.full(N, 0.6), np.full(N, 0.5)
+    J = O.space_matrix(alpha, dp, dm, dx)
+    _, c = O.strang_space_symbol(alpha, dp, dm, dx)
+    C = O.strang_circulant(c)
+    for i in range(N):
+        for j in range(N):
+            if abs(i - j) <= (N - 1) // 2:
+                assert abs(C[i, j] - J[i, j]) <= 1e-12 * np.abs(J).max()
+
+
+@pytest.mark.parametrize("shifted", [False, True])
+@pytest.mark.parametrize("kind", ["trapezoidal", "gbdf3"])
+def test_bccb_fft_form_inverts_the_dense_matrix(kind, shifted):
+    p = W.tiny(15, 16, 1.6, 1, kind)
+    D = O.bccb_dense(p, shifted)
+    P = O.BccbPreconditioner(p, shifted)
+    v = np.random.default_rng(0).standard_normal(p.s * p.m)
+    assert np.linalg.norm(D @ P.apply(v).reshape(-1) - v) <= 1e-13 * np.linalg.norm(v)
+    # eigenvalues of the dense matrix = eq. (1.13), matched one to one
+    from scipy.optimize import linear_sum_assignment
+    ev = np.linalg.eigvals(D)
+    ref = O.bccb_eigs(p, shifted).reshape(-1)
+    dist = np.abs(ev[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(dist)
+    assert dist[r, c].max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_shifted_variant_moves_only_the_zero_frequency():
+    p = W.tiny(7, 8, 1.5, 2, "gbdf3")
+    e0, e1 = O.bccb_eigs(p, False), O.bccb_eigs(p, True)
+    F = O.formula("gbdf3")
+    phi, _ = O.strang_eigs(F, p.s)
+    assert abs(phi[0]) < 1e-15                     # phi_0 = rho(1) = 0
+    np.testing.assert_array_equal(e0[1:], e1[1:])
+    np.testing.assert_allclose(e1[0] - e0[0], np.full(p.m, phi[p.s - 1].real), rtol=1e-13)
+
+
+@pytest.mark.parametrize("pc", ["bccb", "bccb_shifted"])
+def test_bccb_gmres_reaches_the_direct_solution(pc):
+    p = W.tiny(15, 16, 1.6, 1, "gbdf3")
+    U = O.solve_direct(p)
+    r = O.solve_gmres(p, tol=1e-12, precond=pc)
+    assert r.converged and np.linalg.norm(r.x - U) <= 1e-9 * np.linalg.norm(U)
+    # more iterations than the block-circulant S on the same system (Tables 1-2 ordering)
+    assert r.iters > O.solve_gmres(p, tol=1e-12).iters

@@ -175,8 +175,20 @@ typedef enum {
   FDE_OPT_AUTOTUNE = 1,
   FDE_OPT_TRSV_W = 2,
   FDE_OPT_TRSV_W_IN_USE = 3,
-  FDE_OPT_GRAPHS_IN_USE = 4
+  FDE_OPT_GRAPHS_IN_USE = 4,
+  FDE_OPT_PRECOND = 5
 } fde_option;
+/* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
+ * discards the current factorization):
+ *   FDE_PC_STRANG        S = s(A) (x) I - tau s(B) (x) J, eq. (1.11) (default): s/2+1 block LUs.
+ *   FDE_PC_BCCB          S2 = s(A) (x) I - tau s(B) (x) s(J), eq. (x1), with s(J) the Strang
+ *                        circulant of J built on the mean coefficients dbar+- (Section 3.1);
+ *                        diagonalised by the 2-D DFT (Section 3.2): no block factors, an apply
+ *                        costs O(s m log m).  Always FP64; the precision argument is recorded.
+ *   FDE_PC_BCCB_SHIFTED  S2~ of eq. (xc): as S2 with the zero eigenvalue of s(A) moved to
+ *                        Re of its last eigenvalue, invertible even if s(J) is singular.
+ * All instances of a batch call must use the same kind. */
+typedef enum { FDE_PC_STRANG = 0, FDE_PC_BCCB = 1, FDE_PC_BCCB_SHIFTED = 2 } fde_precond_kind;
 fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
 fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
 /* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);

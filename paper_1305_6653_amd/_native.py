@@ -38,6 +38,8 @@ class FdeProblem(C.Structure):
 
 FDE_X0_SOLUTION, FDE_X0_LOWRANK = 0, 1
 FDE_OPT_GRAPHS, FDE_OPT_AUTOTUNE, FDE_OPT_TRSV_W, FDE_OPT_TRSV_W_IN_USE, FDE_OPT_GRAPHS_IN_USE = 0, 1, 2, 3, 4
+FDE_OPT_PRECOND = 5
+FDE_PC_STRANG, FDE_PC_BCCB, FDE_PC_BCCB_SHIFTED = 0, 1, 2
 
 
 class FdeSolveOpts(C.Structure):

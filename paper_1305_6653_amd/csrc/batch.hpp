@@ -24,6 +24,12 @@ struct InstDesc {
   // published panel, [nb][npan][2])
   void *K, *dinv;
   unsigned long long *tsflags;
+  // BCCB preconditioners (pc = 1: S2, 2: S2~ with the zero time frequency moved to lam0s):
+  // chirp w_n = e^{-i pi n^2/m} [m], FFT_L of the chirp filter in bit-reversed order [L], and
+  // the eigenvalues of s(J) [m]
+  int pc;
+  double lam0s;
+  const double2 *chirp, *bh, *lamx;
   // vectors (FP64, [s][m] unless noted)
   double *V, *Z;              // (R+1) and R vectors
   double *w, *x, *b, *tmp, *sio;

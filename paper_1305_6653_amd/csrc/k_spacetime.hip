@@ -226,6 +226,53 @@ __global__ __launch_bounds__(ST_NT) void k_time_irfft(const InstDesc *__restrict
   }
 }
 
+// BCCB preconditioners (the 2-D diagonalisation of Section 3.2): after the time DFT, each time
+// frequency k needs Y = F_m^{-1} diag(1/(lam_k - tau mu_k lamx_j)) F_m X over the space index.
+// DFT of order m (any m) by Bluestein's method: with w_n = e^{-i pi n^2/m} (nj = (n^2 + j^2 -
+// (j-n)^2)/2),  X_j = w_j sum_n (x_n w_n) conj(w_{j-n}),  a linear convolution done through the
+// power-of-two FFT of length L >= 2m - 1 with the stored spectrum of conj(w) (bit-reversed).
+// The inverse uses F^{-1} y = conj(F conj(y)) / m.  Item = (instance, k); one LDS buffer.
+__device__ __forceinline__ void chirp_filter(double2 *buf, const InstDesc &d) {
+  fft_dif<ST_NT>(buf, d.log2L, 1, d.twL);
+  const int L = 1 << d.log2L;
+  for (int i = threadIdx.x; i < L; i += ST_NT) buf[i] = cmul(buf[i], d.bh[i]);
+  __syncthreads();
+  fft_dit_inv<ST_NT>(buf, d.log2L, 1, d.twL);
+}
+
+__global__ __launch_bounds__(ST_NT) void k_bccb_solve(const InstDesc *__restrict__ D, ItemMap map) {
+  extern __shared__ double2 buf[];
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = D[map.ids[q]];
+  const int k = blockIdx.x - map.pre[q];
+  const int m = d.m, L = 1 << d.log2L;
+  double2 *v = d.Vh + (size_t)k * d.mp;
+  const double invL = 1.0 / (double)L;
+  double2 lk = d.lam[k];
+  if (k == 0 && d.pc == 2) lk = make_double2(d.lam0s, 0.0);
+  const double2 tmk = cscale(d.mu[k], -d.tau);
+  for (int i = threadIdx.x; i < L; i += ST_NT) buf[i] = i < m ? cmul(v[i], d.chirp[i]) : make_double2(0.0, 0.0);
+  __syncthreads();
+  chirp_filter(buf, d);
+  // X_j = w_j conv_j / L; Y_j = X_j / (lam_k - tau mu_k lamx_j); next input conj(Y_j) w_j
+  for (int j = threadIdx.x; j < L; j += ST_NT) {
+    double2 t = make_double2(0.0, 0.0);
+    if (j < m) {
+      const double2 X = cscale(cmul(d.chirp[j], buf[j]), invL);
+      const double2 e = cadd(lk, cmul(tmk, d.lamx[j]));
+      const double ee = e.x * e.x + e.y * e.y;
+      const double2 Y = cscale(cmulc(X, e), 1.0 / ee);
+      t = cmul(cconj(Y), d.chirp[j]);
+    }
+    buf[j] = t;
+  }
+  __syncthreads();
+  chirp_filter(buf, d);
+  const double sc = invL / (double)m;
+  for (int n = threadIdx.x; n < m; n += ST_NT) v[n] = cscale(cconj(cmul(d.chirp[n], buf[n])), sc);
+}
+
 // ------------------------------------------------------------------------------------
 static hipError_t set_lds(const void *fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -279,6 +326,16 @@ hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, i
   hipError_t e = set_lds((const void *)k_time_irfft, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_time_irfft, dim3(items), dim3(ST_NT), lds, st, D, map, dst_sel, dst_j);
+  return hipGetLastError();
+}
+
+hipError_t launch_bccb_solve(const InstDesc *D, const ItemMap &map, int items, int max_log2L,
+                             hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double2) << max_log2L;
+  hipError_t e = set_lds((const void *)k_bccb_solve, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bccb_solve, dim3(items), dim3(ST_NT), lds, st, D, map);
   return hipGetLastError();
 }
 

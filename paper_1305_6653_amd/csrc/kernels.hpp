@@ -28,6 +28,11 @@ hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, in
 hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
                              int dst_sel, int dst_j, hipStream_t st);
 int time_fft_cols_per_item();
+// BCCB preconditioner solve in the time-frequency domain: for every time frequency k < nb,
+// Vh[k] <- F_m^{-1} diag(1 / (lam_k - tau mu_k lamx)) F_m Vh[k] (space DFTs of order m by
+// Bluestein's chirp method on the power-of-two FFT of length L).  items = nb per instance.
+hipError_t launch_bccb_solve(const InstDesc *D, const ItemMap &map, int items, int max_log2L,
+                             hipStream_t st);
 
 // ---- preconditioner blocks (T = double or float factor storage) ----
 int assemble_items(int mp, int nb);

@@ -146,10 +146,15 @@ struct fde_bvm {
   double *d_w = nullptr, *d_x = nullptr, *d_b = nullptr, *d_tmp = nullptr, *d_sio = nullptr;
   double *d_u0 = nullptr, *d_f = nullptr, *d_Ju0 = nullptr;
   double2 *d_Vh = nullptr;
+  // ---- BCCB preconditioner tables (allocated when a BCCB preconditioner is factored)
+  double2 *d_chirp = nullptr, *d_bh = nullptr, *d_lamx = nullptr;
+  double lam0s = 0.0;
   // ---- the plan of this handle alone
   Plan *self = nullptr;
   // ---- options (fde_bvm_set_option)
   int opt_graphs = 1, opt_autotune = 1, opt_trsv_w = 0;
+  int opt_precond = FDE_PC_STRANG;  // chosen kind; pc = the kind of the current factorization
+  int pc = FDE_PC_STRANG;
   // ---- profiling
   bool prof = false;
   int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
@@ -286,8 +291,9 @@ struct HostMap {
 
 // Item maps of the solve-phase launches over every instance of a plan.
 struct SolveMaps {
-  ItemMap mv, tfft, trsv, kry, rhs, ju0;
-  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0;
+  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk;
+  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0;
+  int pc = 0;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int prec = -1;
   double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0;
@@ -296,7 +302,7 @@ struct SolveMaps {
 // The same maps with their items skipped for instances whose gate entry is zero.
 static SolveMaps gated(const SolveMaps &S, const int *gate) {
   SolveMaps G = S;
-  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0}) m->gate = gate;
+  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk}) m->gate = gate;
   return G;
 }
 
@@ -462,6 +468,11 @@ static InstDesc make_desc(fde_bvm *h) {
   d.f = h->d_f;
   d.Ju0 = h->d_Ju0;
   d.Vh = h->d_Vh;
+  d.pc = h->pc;
+  d.lam0s = h->lam0s;
+  d.chirp = h->d_chirp;
+  d.bh = h->d_bh;
+  d.lamx = h->d_lamx;
   return d;
 }
 
@@ -723,6 +734,99 @@ static std::vector<double2> twiddles(int N) {
   return t;
 }
 
+// In-place radix-2 FFT (e^{-2 pi i jk/N}, N a power of two), natural order in and out.
+static void host_fft(std::vector<cd> &a) {
+  const size_t N = a.size();
+  for (size_t i = 1, j = 0; i < N; ++i) {
+    size_t bit = N >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= N; len <<= 1) {
+    const double th = -2.0 * M_PI / (double)len;
+    for (size_t i = 0; i < N; i += len)
+      for (size_t k = 0; k < len / 2; ++k) {
+        const cd w = std::polar(1.0, th * (double)k);
+        const cd u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
+// Tables of the BCCB preconditioners (Section 3.1, eq. (x1) and (xc)):
+//  * s(J) = dx^{-alpha} (dbar+ s(G) + dbar- s(G)^T), dbar the means of d+-, s(G) the order-m
+//    circulant with first column g_1..g_{floor((m+1)/2)}, 0.., g_0 (s(G^T) read as s(G)^T);
+//    its eigenvalues lamx_j = DFT of the first column (by the same Bluestein route as on the
+//    device, through the host FFT of length L);
+//  * the chirp w_n = e^{-i pi n^2/m} (n^2 taken mod 2m, exact) and the FFT of the chirp filter
+//    b_k = conj(w_k), b_{L-k} = conj(w_k), stored bit-reversed for the device's DIF/DIT pair;
+//  * for S2~ the zero time frequency lam_0 = rho(1) = 0 becomes Re(lam_{s-1}).
+static fde_status bccb_prepare(fde_bvm *h) {
+  const int m = h->m, L = h->L;
+  std::vector<cd> w(m);
+  for (int n = 0; n < m; ++n) {
+    const long long r = ((long long)n * n) % (2LL * m);
+    w[n] = std::polar(1.0, -M_PI * (double)r / (double)m);
+  }
+  std::vector<cd> bf(L, cd(0.0, 0.0));
+  for (int k = 0; k < m; ++k) {
+    bf[k] = std::conj(w[k]);
+    if (k > 0) bf[L - k] = std::conj(w[k]);
+  }
+  host_fft(bf);
+  std::vector<double2> bh(L);
+  for (int i = 0; i < L; ++i) {
+    int r = 0;
+    for (int b = 0; b < h->log2L; ++b) r |= ((i >> b) & 1) << (h->log2L - 1 - b);
+    bh[i] = make_double2(bf[r].real(), bf[r].imag());  // position i holds frequency bitrev(i)
+  }
+  // first column of s(J)
+  std::vector<double> cG(m, 0.0);
+  const int hh = (m + 1) / 2;
+  for (int i = 0; i < hh; ++i) cG[i] = h->g[i + 1];
+  if (m - 1 >= hh) cG[m - 1] = h->g[0];
+  double dbp = 0.0, dbm = 0.0;
+  for (int i = 0; i < m; ++i) {
+    dbp += h->dp[i];
+    dbm += h->dm[i];
+  }
+  dbp /= m;
+  dbm /= m;
+  std::vector<cd> a(L, cd(0.0, 0.0));
+  for (int n = 0; n < m; ++n) {
+    const double cJ = h->scale * (dbp * cG[n] + dbm * cG[(m - n) % m]);
+    a[n] = cJ * w[n];
+  }
+  host_fft(a);
+  std::vector<cd> bnat(L, cd(0.0, 0.0));
+  for (int k = 0; k < m; ++k) {
+    bnat[k] = std::conj(w[k]);
+    if (k > 0) bnat[L - k] = std::conj(w[k]);
+  }
+  host_fft(bnat);
+  for (int i = 0; i < L; ++i) a[i] = std::conj(a[i] * bnat[i]);  // inverse FFT via conj(FFT(conj))
+  host_fft(a);
+  std::vector<double2> lamx(m);
+  for (int j = 0; j < m; ++j) {
+    const cd X = w[j] * std::conj(a[j]) / (double)L;
+    lamx[j] = make_double2(X.real(), X.imag());
+  }
+  h->lam0s = h->lam[h->s - 1 < h->nb ? h->s - 1 : 1].real();  // Re(lam_{s-1}) = Re(lam_1)
+  if (!h->d_chirp) {
+    STCHK(dalloc_t(h, &h->d_chirp, (size_t)m));
+    STCHK(dalloc_t(h, &h->d_bh, (size_t)L));
+    STCHK(dalloc_t(h, &h->d_lamx, (size_t)m));
+  }
+  std::vector<double2> wd(m);
+  for (int n = 0; n < m; ++n) wd[n] = make_double2(w[n].real(), w[n].imag());
+  HIPCHK(hipMemcpy(h->d_chirp, wd.data(), sizeof(double2) * m, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_bh, bh.data(), sizeof(double2) * L, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_lamx, lamx.data(), sizeof(double2) * m, hipMemcpyHostToDevice));
+  return FDE_OK;
+}
+
 static void destroy_handle(fde_bvm *h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
@@ -950,6 +1054,12 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
       if (value < 0 || value > 1024) return fail(FDE_EINVAL, "FDE_OPT_TRSV_W must be in 0..1024");
       h->opt_trsv_w = value;
       return FDE_OK;
+    case FDE_OPT_PRECOND:
+      if (value != FDE_PC_STRANG && value != FDE_PC_BCCB && value != FDE_PC_BCCB_SHIFTED)
+        return fail(FDE_EINVAL, "unknown preconditioner %d", value);
+      if (value != h->opt_precond) h->prec = -1;  // factor again before the next solve
+      h->opt_precond = value;
+      return FDE_OK;
     default:
       return fail(FDE_EINVAL, "unknown or read-only option %d", option);
   }
@@ -963,6 +1073,7 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_TRSV_W: *value = h->opt_trsv_w; return FDE_OK;
     case FDE_OPT_TRSV_W_IN_USE: *value = h->self->desc.empty() ? 0 : h->self->desc[0].W; return FDE_OK;
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
+    case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
   }
 }
@@ -1110,9 +1221,39 @@ static fde_status factor_plan_impl(Plan *P) {
   return FDE_OK;
 }
 
+static fde_status bccb_prepare(fde_bvm *h);
+
 static fde_status factor_plan(Plan *P, fde_precision prec) {
   if (prec != FDE_FP64 && prec != FDE_MIXED_C32) return fail(FDE_EINVAL, "unknown precision %d", (int)prec);
   fde_bvm *L = P->lead;
+  const int kind = P->hs[0]->opt_precond;
+  for (fde_bvm *h : P->hs)
+    if (h->opt_precond != kind) return fail(FDE_EINVAL, "all instances of a batch need the same preconditioner");
+  if (kind != FDE_PC_STRANG) {
+    // BCCB: no block factors; the "factorization" is the space symbol and the chirp tables
+    hipEvent_t e0 = get_event(L), e1 = get_event(L);
+    HIPCHK(hipEventRecord(e0, L->stream));
+    for (fde_bvm *h : P->hs) {
+      h->prec = -1;
+      h->pc = kind;
+      STCHK(bccb_prepare(h));
+      if (h->self) h->self->desc_dirty = true;
+    }
+    P->desc_dirty = true;
+    STCHK(plan_prepare(P, std::max(P->R, 1), prec));
+    HIPCHK(hipEventRecord(e1, L->stream));
+    STCHK(sync_and_flush(L));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    L->evpool.push_back(e0);
+    L->evpool.push_back(e1);
+    for (fde_bvm *h : P->hs) {
+      h->prec = prec;
+      h->t_factor_ms = ms;
+    }
+    return FDE_OK;
+  }
+  for (fde_bvm *h : P->hs) h->pc = FDE_PC_STRANG;
   const size_t esz = prec == FDE_FP64 ? sizeof(double2) : sizeof(float2);
   for (fde_bvm *h : P->hs) {
     const size_t Kb = (size_t)h->nb * h->mp * h->mp * esz;
@@ -1166,12 +1307,13 @@ extern "C" fde_status fde_precond_factor(fde_bvm *h, fde_precision prec) {
 static fde_status ensure_full_maps(Plan *P) {
   const int count = (int)P->hs.size();
   const int prec = P->hs[0]->prec;
-  if (P->full_ok && P->full.prec == prec) return FDE_OK;
-  std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count);
+  if (P->full_ok && P->full.prec == prec && P->full.pc == P->hs[0]->pc) return FDE_OK;
+  std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count);
   SolveMaps S;
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
     slots[q] = q;
+    g[q] = h->nb;
     a[q] = h->s;
     b[q] = h->mp / time_fft_cols_per_item();
     c[q] = h->nb * P->desc[q].W;
@@ -1187,7 +1329,8 @@ static fde_status ensure_full_maps(Plan *P) {
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
-                                   make_map(slots, d), make_map(slots, e), make_map(slots, f)};
+                                   make_map(slots, d), make_map(slots, e), make_map(slots, f),
+                                   make_map(slots, g)};
   size_t need = 0;
   for (const HostMap &m : hm) need += m.ids.size() + m.pre.size();
   HIPCHK(hipStreamSynchronize(P->lead->stream));
@@ -1222,6 +1365,9 @@ static fde_status ensure_full_maps(Plan *P) {
   S.kry = dm[3];
   S.rhs = dm[4];
   S.ju0 = dm[5];
+  S.blk = dm[6];
+  S.n_blk = hm[6].items;
+  S.pc = P->hs[0]->pc;
   S.n_mv = hm[0].items;
   S.n_tfft = hm[1].items;
   S.n_trsv = hm[2].items;
@@ -1249,6 +1395,18 @@ static bool g_coop_ok = true;
 static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int dst, int dj) {
   fde_bvm *L = P->lead;
   hipStream_t st = L->stream;
+  if (S.pc != FDE_PC_STRANG) {  // BCCB: time DFT, space-Fourier diagonal solve, inverse time DFT
+    HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
+      return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st);
+    }));
+    HIPCHK(run(L, "bccb_solve", 2.0 * S.tfft_bytes, [&] {
+      return launch_bccb_solve(P->d_desc, S.blk, S.n_blk, S.max_log2L, st);
+    }));
+    HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
+      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
+    }));
+    return FDE_OK;
+  }
   unsigned long long *ctr = nullptr;
   STCHK(epoch_counter(&ctr));
   HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
@@ -1587,7 +1745,7 @@ static fde_status copy_out(fde_bvm *h, double *dst, const double *src, size_t co
 // autotuning is off, or when cooperative launches are unavailable.
 static fde_status autotune_trsv(Plan *P, int prec) {
   fde_bvm *L = P->lead;
-  if (!L->opt_autotune || L->opt_trsv_w > 0 || !g_coop_ok) return FDE_OK;
+  if (!L->opt_autotune || L->opt_trsv_w > 0 || !g_coop_ok || L->pc != FDE_PC_STRANG) return FDE_OK;
   const std::string key = plan_shape_key(P, prec);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -1652,6 +1810,7 @@ static fde_status solve_plan(Plan *P, const double *const *u0, const double *con
     fde_bvm *h = P->hs[i];
     if (h->prec < 0) return fail(FDE_EINVAL, "fde_precond_factor must succeed before solving (instance %d)", i);
     if (h->prec != prec) return fail(FDE_EINVAL, "all instances of a batch need the same precision");
+    if (h->pc != P->hs[0]->pc) return fail(FDE_EINVAL, "all instances of a batch need the same preconditioner");
     if (!u0[i] || !f[i] || !u[i]) return fail(FDE_EINVAL, "u0, f and u are required (instance %d)", i);
     if (h->stream != L->stream) HIPCHK(hipStreamSynchronize(h->stream));
   }

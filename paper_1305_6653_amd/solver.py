@@ -15,6 +15,7 @@ from . import _native as N
 
 _KINDS = {"trapezoidal": N.FDE_BVM_TRAPEZOIDAL, "gbdf3": N.FDE_BVM_GBDF3}
 _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
+_PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED}
 
 
 def _is_torch_cuda(x) -> bool:
@@ -110,7 +111,12 @@ class BvmSolver:
         N.check(N.lib().fde_set_stream(self._h, C.c_void_p(ptr or 0)))
 
     # ---- the three calls
-    def factor(self, precision: str = "fp64"):
+    def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None):
+        """Build the preconditioner: "strang" (block LUs), "bccb" or "bccb_shifted" (2-D DFT)."""
+        if preconditioner is not None:
+            kind = _PC[preconditioner]
+            if self.get_option(N.FDE_OPT_PRECOND) != kind:
+                self.set_option(N.FDE_OPT_PRECOND, kind)
         N.check(N.lib().fde_precond_factor(self._h, _PREC[precision]))
 
     def solve(self, u0, f, x0=None, out=None, rtol: float = 1e-10, restart: int = 20,

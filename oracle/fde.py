@@ -13,14 +13,19 @@ Readings taken where the paper is silent or garbled (all listed in the design no
   the right-hand side, so M is (s m) x (s m) and the Strang circulants have order s.
 * Formulas.  The paper prints no BVM coefficients.  Trapezoidal (nu=mu=1) and the
   third-order generalized BDF (nu=2, mu=3) with one initial and one final formula are
-  used; each formula is the unique four-point formula of order 3 whose beta is
-  supported only on the derivative node.
-* Stopping rule.  True residual ||b - M x||_2 / ||b||_2 <= tol, right preconditioning.
+  used; each GBDF3 formula is the unique four-point formula of order 3 whose beta is
+  supported only on the derivative node.  The fifth-order GAM of Section 4 (nu=2, mu=4)
+  takes, for its one initial and two final formulas, one-step Adams formulas on the five
+  nodes nearest the boundary.
+* Stopping rule.  True residual ||b - M x||_2 / ||b||_2 <= tol, right preconditioning;
+  left preconditioning with the preconditioned residual (the convention under which
+  Section 4 counts iterations) is available for reproducing its tables.
 * Diffusion coefficients depend on x only (eq. (1.10) needs a time-independent J).
 """
 from __future__ import annotations
 
 import dataclasses
+from fractions import Fraction
 from typing import Callable, Optional
 
 import numpy as np
@@ -28,7 +33,7 @@ import scipy.linalg
 
 __all__ = [
     "grunwald_weights", "space_matrix", "space_matrix_entries", "Formula",
-    "trapezoidal", "gbdf3", "formula", "bvm_matrices", "s_form", "all_at_once",
+    "trapezoidal", "gbdf3", "gam5", "formula", "bvm_matrices", "s_form", "all_at_once",
     "problem_matrices", "problem_system", "solve_direct", "strang_columns",
     "strang_circulant", "strang_eigs", "strang_dense", "StrangPreconditioner",
     "apply_M", "gmres", "GmresResult", "solve_gmres", "true_relres", "strang_space_column",
@@ -129,8 +134,57 @@ def gbdf3() -> Formula:
     )
 
 
+def _poly_mul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def _adams_weights(nodes, lo, hi):
+    """w_j = integral over [lo, hi] of the Lagrange basis polynomial of node j (exact
+    rationals): the weights of the quadrature that integrates the interpolant of g through
+    the given nodes."""
+    w = []
+    for j, tj in enumerate(nodes):
+        poly, den = [Fraction(1)], Fraction(1)
+        for i, ti in enumerate(nodes):
+            if i != j:
+                poly = _poly_mul(poly, [Fraction(-ti), Fraction(1)])
+                den *= tj - ti
+        w.append(sum(c * (Fraction(hi) ** (q + 1) - Fraction(lo) ** (q + 1)) / (q + 1)
+                     for q, c in enumerate(poly)) / den)
+    return w
+
+
+def gam5() -> Formula:
+    """Fifth-order generalized Adams method, mu = 4, nu = 2 (the BVM of Section 4).
+
+    Every row is a one-step Adams formula u_r - u_{r-1} = h sum_i beta_i g_{c+i}: beta
+    integrates, over [t_{r-1}, t_r], the quartic interpolating g at the five consecutive
+    nodes t_c..t_{c+4}.  The main formula (rows 2..s-2) centres those nodes on u_r
+    (c = r - 2); the initial row r = 1 uses t_0..t_4 and the final rows r = s-1, s use
+    t_{s-4}..t_s."""
+    nodes = range(5)
+    z = [Fraction(0)] * 5
+
+    def row(r_local):
+        a = list(z)
+        a[r_local - 1], a[r_local] = Fraction(-1), Fraction(1)
+        return a, _adams_weights(nodes, r_local - 1, r_local)
+
+    a_main, b_main = row(2)
+    a_i1, b_i1 = row(1)
+    a_f1, b_f1 = row(3)
+    a_f2, b_f2 = row(4)
+    f = lambda rows: np.array([[float(v) for v in r] for r in rows])
+    return Formula("gam5", 2, 4, f([a_main])[0], f([b_main])[0], f([a_i1]), f([b_i1]),
+                   f([a_f1, a_f2]), f([b_f1, b_f2]))
+
+
 def formula(kind: str) -> Formula:
-    return {"trapezoidal": trapezoidal, "gbdf3": gbdf3}[kind]()
+    return {"trapezoidal": trapezoidal, "gbdf3": gbdf3, "gam5": gam5}[kind]()
 
 
 def bvm_matrices(F: Formula, s: int):
@@ -355,11 +409,21 @@ class GmresResult:
 
 
 def gmres(matvec: Callable, precond: Optional[Callable], b: np.ndarray, x0: Optional[np.ndarray] = None,
-          tol: float = 1e-10, restart: int = 20, maxit: int = 1000) -> GmresResult:
+          tol: float = 1e-10, restart: int = 20, maxit: int = 1000,
+          side: str = "right") -> GmresResult:
     """Restarted GMRES(restart) with right preconditioning, as flexible GMRES (the
     preconditioned directions z_j are kept), modified Gram-Schmidt Arnoldi and Givens
     rotations for the small least-squares problem.  Convergence is declared only on
-    the recomputed true residual ||b - M x|| <= tol ||b||."""
+    the recomputed true residual ||b - M x|| <= tol ||b||.
+
+    side="left" runs GMRES on P^{-1} M x = P^{-1} b instead (the form in which Section 3.3
+    states its convergence theorem and Section 4 counts iterations): the Arnoldi vectors
+    span P^{-1} M's Krylov space, x is updated with them directly, and the stopping test
+    is on the preconditioned residual, ||P^{-1}(b - M x)|| <= tol ||P^{-1} b||."""
+    if side == "left":
+        return _gmres_left(matvec, precond, b, x0, tol, restart, maxit)
+    if side != "right":
+        raise ValueError(f"side must be 'right' or 'left', got {side!r}")
     n = b.size
     bnorm = np.linalg.norm(b)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
@@ -416,6 +480,57 @@ def gmres(matvec: Callable, precond: Optional[Callable], b: np.ndarray, x0: Opti
         restarts += 1
 
 
+def _gmres_left(matvec, precond, b, x0, tol, restart, maxit) -> GmresResult:
+    """Left-preconditioned restarted GMRES (see ``gmres``); relres is the preconditioned one."""
+    n = b.size
+    P = precond if precond is not None else (lambda v: v)
+    op = lambda v: np.asarray(P(matvec(v)), dtype=np.float64).reshape(-1)
+    pb = np.asarray(P(b), dtype=np.float64).reshape(-1)
+    pbnorm = np.linalg.norm(pb)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
+    its, restarts, history = 0, 0, []
+    if pbnorm == 0.0:
+        return GmresResult(np.zeros(n), 0, 0, True, 0.0, history)
+    while True:
+        r = np.asarray(P(b - matvec(x)), dtype=np.float64).reshape(-1)
+        beta = np.linalg.norm(r)
+        history.append(beta / pbnorm)
+        if beta <= tol * pbnorm:
+            return GmresResult(x, its, restarts, True, beta / pbnorm, history)
+        if its >= maxit:
+            return GmresResult(x, its, restarts, False, beta / pbnorm, history)
+        V = np.zeros((restart + 1, n))
+        H = np.zeros((restart + 1, restart))
+        cs, sn, g = np.zeros(restart), np.zeros(restart), np.zeros(restart + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(restart):
+            w = op(V[j])
+            its += 1
+            for i in range(j + 1):
+                H[i, j] = V[i] @ w
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            d = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / d, H[j + 1, j] / d
+            H[j, j], H[j + 1, j] = d, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            history.append(abs(g[j + 1]) / pbnorm)
+            if abs(g[j + 1]) <= tol * pbnorm or its >= maxit:
+                break
+        x = x + V[:k].T @ scipy.linalg.solve_triangular(H[:k, :k], g[:k])
+        restarts += 1
+
+
 def true_relres(p, U: np.ndarray) -> float:
     """||b - M u||_2 / ||b||_2 in FP64 with the dense-J product (any size that fits in RAM)."""
     J, F, tau, _ = problem_matrices(p)
@@ -427,14 +542,15 @@ def true_relres(p, U: np.ndarray) -> float:
 
 def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
                 x0: Optional[np.ndarray] = None, preconditioned: bool = True,
-                precond: str = "strang") -> GmresResult:
+                precond: str = "strang", side: str = "right") -> GmresResult:
     """O2: preconditioned GMRES(restart) on the s-form system of a Problem; precond is
-    "strang" (S, eq. (1.11)), "bccb" (S2, eq. (x1)) or "bccb_shifted" (S2~, eq. (xc))."""
+    "strang" (S, eq. (1.11)), "bccb" (S2, eq. (x1)), "bccb_shifted" (S2~, eq. (xc)) or
+    "none" (the unpreconditioned column I of Tables 1-2)."""
     J, F, tau, _ = problem_matrices(p)
     A, B, a0, b0, Bfull = s_form(F, p.s)
     b = (tau * (Bfull @ p.f) - np.outer(a0, p.u0) + tau * np.outer(b0, J @ p.u0)).reshape(-1)
     mv = lambda z: apply_M(J, A, B, tau, z.reshape(p.s, p.m)).reshape(-1)
-    if not preconditioned:
+    if not preconditioned or precond == "none":
         pc = None
     elif precond == "strang":
         pc = StrangPreconditioner(J, F, p.s, tau).apply
@@ -442,6 +558,7 @@ def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
         pc = BccbPreconditioner(p, shifted=precond == "bccb_shifted").apply
     else:
         raise ValueError(f"unknown preconditioner {precond!r}")
-    res = gmres(mv, (lambda v: pc(v).reshape(-1)) if pc else None, b, x0, tol, restart, maxit)
+    res = gmres(mv, (lambda v: pc(v).reshape(-1)) if pc else None, b, x0, tol, restart, maxit,
+                side)
     res.x = res.x.reshape(p.s, p.m)
     return res

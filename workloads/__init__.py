@@ -20,6 +20,9 @@ Workloads (all on x in (0, 2), t in [0, 1], homogeneous Dirichlet boundary):
   alpha ~ U(1.1, 1.9), d+- = 1 + 0.5 tanh(sum_{p<=6} e_p sin(p pi x/2)/p), f and u0 as
   above, GBDF3.
 * ``warmstart_instance`` m=255, s=128, GBDF3, the batch generators for alpha/d+-/f, u0=0.
+* ``example41``         the analytic example of Section 4 (no random draws): f = 0,
+  d+ = 0.6, d- = 0.5, u(x,0) a Gaussian pulse centred at 1.2 of width 0.08, fifth-order
+  GAM; alpha in {1.2, 1.5}, m in {24, 48, 96}, s in {16, 32, 64, 128} in its tables.
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ import numpy as np
 
 TRAPEZOIDAL = "trapezoidal"
 GBDF3 = "gbdf3"
+GAM5 = "gam5"
 
 
 @dataclasses.dataclass
@@ -224,3 +228,16 @@ def tiny(m: int, s: int, alpha: float = 1.5, seed: int = 0, bvm: str = GBDF3) ->
     p = smooth_random(m, s, alpha, seed, bvm)
     p.name = f"tiny_m{m}_s{s}_a{alpha}_{bvm}_seed{seed}"
     return p
+
+
+def example41(alpha: float, m: int, s: int, bvm: str = GAM5) -> Problem:
+    """Example 4.1: f = 0, constant d+ = 0.6 and d- = 0.5, Gaussian initial pulse
+    exp(-(x - 1.2)^2 / (2 * 0.08^2)) on (0, 2), t in [0, 1]."""
+    x = grid_x(m)
+    u0 = np.exp(-((x - 1.2) ** 2) / (2.0 * 0.08 ** 2))
+    return Problem(alpha=float(alpha), m=m, s=s, d_plus=np.full(m, 0.6), d_minus=np.full(m, 0.5),
+                   f=np.zeros((s + 1, m)), u0=u0, bvm=bvm, name=f"example41_a{alpha}_m{m}_s{s}")
+
+
+# (alpha, m, s) of the rows of Tables 1 and 2
+EXAMPLE41_GRID = [(a, m, s) for a in (1.2, 1.5) for m in (24, 48, 96) for s in (16, 32, 64, 128)]

@@ -95,9 +95,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "ex41"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-bccb", action="store_true",
+                    help="skip the BCCB-preconditioned solves reported beside the main one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this many MiB "
                          "(the reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -113,19 +115,19 @@ def workload(name):
     return W.smooth_c2(), "fp64"
 
 
-def timed_steps(S, u0, f, out, prec, steps, warmup):
+def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     """W warmup steps, then K timed steps (the value), then the same K steps again with every
     launch bracketed by HIP events on the library's stream (the per-kernel profile: the
     events cost a few microseconds per launch, so they are kept out of the first pass)."""
     import torch
     for _ in range(warmup):
-        S.factor(prec)
+        S.factor(prec, pc)
         S.solve(u0, f, out=out, rtol=1e-10)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        S.factor(prec)
+        S.factor(prec, pc)
         _, info = S.solve(u0, f, out=out, rtol=1e-10)
         infos.append(info)
     torch.cuda.synchronize()
@@ -134,12 +136,12 @@ def timed_steps(S, u0, f, out, prec, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        S.factor(prec)
+        S.factor(prec, pc)
         S.solve(u0, f, out=out, rtol=1e-10)
     torch.cuda.synchronize()
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
-    for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "time_rfft",
+    for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
               "time_irfft", "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot"):
         q = S.profile_query(k)
         if q["count"]:
@@ -279,8 +281,67 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_example41(args):
+    """Example 4.1 of Section 4 (GAM5, f = 0, Gaussian pulse): every (alpha, m, s) of Tables 1-2
+    with each preconditioner (I, S, S2, S2~), left-preconditioned GMRES(20) to 1e-8 of the
+    initial preconditioned residual from a zero start (the tables' convention).  One step =
+    fde_precond_factor + fde_bvm_solve of one case; reported per case (ITS, ms) and as the
+    rate over all 96 cases."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1305_6653_amd import BvmSolver
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cases, total_ms = [], 0.0
+    for a, m, s in W.EXAMPLE41_GRID:
+        p = W.example41(a, m, s)
+        u0 = torch.from_numpy(np.ascontiguousarray(p.u0)).to(dev)
+        f = torch.from_numpy(np.ascontiguousarray(p.f)).to(dev)
+        out = torch.empty((s, m), dtype=torch.float64, device=dev)
+        S = BvmSolver(p)
+        S.set_stream(stream)
+        row = {"alpha": a, "m": m, "s": s}
+        for pc, key in (("none", "I"), ("strang", "S"), ("bccb", "S2"), ("bccb_shifted", "S2t")):
+            for _ in range(max(1, args.warmup)):
+                S.factor("fp64", pc)
+                S.solve(u0, f, out=out, rtol=1e-8, maxit=3000, side="left")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                S.factor("fp64", pc)
+                _, info = S.solve(u0, f, out=out, rtol=1e-8, maxit=3000, side="left")
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            total_ms += ms
+            row[key] = {"its": info["iters"], "ms": round(ms, 4),
+                        "true_relres": float("%.3g" % info["true_relres"])}
+        S.close()
+        cases.append(row)
+    result = {
+        "metric": "Example 4.1 (Tables 1-2): factor + left-preconditioned GMRES(20) solves to 1e-8, "
+                  "solves/s over all 96 (alpha, m, s, preconditioner) cases",
+        "value": round(96 * 1000.0 / total_ms, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / 96, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "analytic (Example 4.1: f = 0, d+ = 0.6, d- = 0.5, Gaussian pulse u0)",
+        "config": {"workload": "Example 4.1, GAM5, alpha in {1.2, 1.5}, m in {24, 48, 96}, "
+                               "s in {16, 32, 64, 128}", "precision": "fp64", "side": "left",
+                   "rtol": 1e-8, "restart": 20, "step": "fde_precond_factor + fde_bvm_solve"},
+        "cases": cases,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "ex41":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_example41(args)
+        return
     if args.workload == "c4":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -335,6 +396,26 @@ def main():
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
+    if not args.no_bccb and prec == "fp64":
+        # the paper's other preconditioners on the same system (Section 3.1): S2 = s(A) x I -
+        # tau s(B) x s(J) and its shifted form, each a 2-D FFT diagonal solve per iteration
+        result["bccb"] = {}
+        for pc in ("bccb", "bccb_shifted"):
+            ms3, _, infos3, prof3 = timed_steps(S, u0, f, out, "fp64", max(1, args.steps // 2),
+                                                1, pc)
+            u3 = out.cpu().numpy()
+            result["bccb"][pc] = {
+                "ms_per_step": round(ms3, 4), "value": round(1000.0 / ms3, 4),
+                "iters": infos3[-1]["iters"], "true_relres": infos3[-1]["true_relres"],
+                "rel_diff_vs_strang": float(np.linalg.norm(u3 - u_main) / np.linalg.norm(u_main)),
+                "kernels": {k: {"total_ms": round(v["total_ms"] / max(1, args.steps // 2), 4),
+                                "avg_us": round(1e3 * v["total_ms"] / v["count"], 2)}
+                            for k, v in prof3.items() if k in ("bccb_solve", "bvm_matvec", "mgs",
+                                                               "time_rfft", "time_irfft")},
+                "bccb_solve_GBs": round(prof3["bccb_solve"]["work"]
+                                        / (prof3["bccb_solve"]["total_ms"] * 1e-3) / 1e9, 1)
+                if "bccb_solve" in prof3 else None,
+            }
     if not args.no_cpu_baseline:
         cb, u_ref = cpu_baseline(p)
         result["cpu_baseline"] = cb

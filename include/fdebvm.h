@@ -52,7 +52,22 @@ typedef enum {
   FDE_EUNSUPPORTED = -6  /* valid input this build does not handle (e.g. s not 2^k)  */
 } fde_status;
 
-typedef enum { FDE_BVM_TRAPEZOIDAL = 0, FDE_BVM_GBDF3 = 1, FDE_BVM_CUSTOM = 2 } fde_bvm_kind;
+/* Built-in BVMs (Section 2.2; the paper prints no coefficients, so each is stated here):
+ *   FDE_BVM_TRAPEZOIDAL  (nu1, nu2) = (1, 0): u_n - u_{n-1} = tau/2 (g_{n-1} + g_n), order 2.
+ *   FDE_BVM_GBDF3        (2, 1): third-order generalized BDF; main formula on u_{n-2..n+1}
+ *                        with beta at u_n, one initial and one final (BDF3) formula.
+ *   FDE_BVM_GAM5         (2, 2): fifth-order generalized Adams method, the BVM of the
+ *                        experiments of Section 4.  Every row is u_r - u_{r-1} = tau sum_i
+ *                        beta_i g_{c+i}, beta integrating over [t_{r-1}, t_r] the quartic
+ *                        through five consecutive nodes: centred on u_r for the main formula,
+ *                        the first five nodes for row 1, the last five for rows s-1 and s.
+ *   FDE_BVM_CUSTOM       the formula in fde_problem.custom. */
+typedef enum {
+  FDE_BVM_TRAPEZOIDAL = 0,
+  FDE_BVM_GBDF3 = 1,
+  FDE_BVM_CUSTOM = 2,
+  FDE_BVM_GAM5 = 3
+} fde_bvm_kind;
 
 /* A mu-step BVM, mu = nu1 + nu2 (eq. (1.7)-(1.9)).  Coefficient i of the main formula
  * multiplies u_{n-nu1+i}; of initial formula j (1 <= j < nu1, row j-1 of the *_init
@@ -176,7 +191,8 @@ typedef enum {
   FDE_OPT_TRSV_W = 2,
   FDE_OPT_TRSV_W_IN_USE = 3,
   FDE_OPT_GRAPHS_IN_USE = 4,
-  FDE_OPT_PRECOND = 5
+  FDE_OPT_PRECOND = 5,
+  FDE_OPT_SIDE = 6
 } fde_option;
 /* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
  * discards the current factorization):
@@ -187,8 +203,24 @@ typedef enum {
  *                        costs O(s m log m).  Always FP64; the precision argument is recorded.
  *   FDE_PC_BCCB_SHIFTED  S2~ of eq. (xc): as S2 with the zero eigenvalue of s(A) moved to
  *                        Re of its last eigenvalue, invertible even if s(J) is singular.
+ *   FDE_PC_NONE          no preconditioner (column I of the tables of Section 4).
  * All instances of a batch call must use the same kind. */
-typedef enum { FDE_PC_STRANG = 0, FDE_PC_BCCB = 1, FDE_PC_BCCB_SHIFTED = 2 } fde_precond_kind;
+typedef enum {
+  FDE_PC_STRANG = 0,
+  FDE_PC_BCCB = 1,
+  FDE_PC_BCCB_SHIFTED = 2,
+  FDE_PC_NONE = 3
+} fde_precond_kind;
+/* FDE_OPT_SIDE selects how GMRES uses the preconditioner P:
+ *   FDE_SIDE_RIGHT (default)  flexible right preconditioning, M P^{-1} y = b, x = P^{-1} y; the
+ *                             stopping test is on the true residual ||b - M x|| <= rtol ||b||.
+ *   FDE_SIDE_LEFT             GMRES on P^{-1} M x = P^{-1} b (the form of the convergence
+ *                             theorem of Section 3.3 and of the iteration counts of Section 4):
+ *                             the Krylov basis updates x directly and the stopping test is on
+ *                             the preconditioned residual, ||P^{-1}(b - M x)|| <= rtol
+ *                             ||P^{-1} b||.  fde_solve_info.true_relres is still ||b - M x|| /
+ *                             ||b||, computed once after the last cycle. */
+typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
 fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
 fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
 /* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);

@@ -15,7 +15,7 @@ FDE_OK, FDE_EINVAL, FDE_ENOMEM, FDE_ESINGULAR, FDE_ENOCONV, FDE_EDEVICE, FDE_EUN
     0, -1, -2, -3, -4, -5, -6)
 STATUS_NAMES = {0: "FDE_OK", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -3: "FDE_ESINGULAR",
                 -4: "FDE_ENOCONV", -5: "FDE_EDEVICE", -6: "FDE_EUNSUPPORTED"}
-FDE_BVM_TRAPEZOIDAL, FDE_BVM_GBDF3, FDE_BVM_CUSTOM = 0, 1, 2
+FDE_BVM_TRAPEZOIDAL, FDE_BVM_GBDF3, FDE_BVM_CUSTOM, FDE_BVM_GAM5 = 0, 1, 2, 3
 FDE_FP64, FDE_MIXED_C32 = 0, 1
 FDE_MEM_HOST, FDE_MEM_DEVICE = 0, 1
 
@@ -38,8 +38,9 @@ class FdeProblem(C.Structure):
 
 FDE_X0_SOLUTION, FDE_X0_LOWRANK = 0, 1
 FDE_OPT_GRAPHS, FDE_OPT_AUTOTUNE, FDE_OPT_TRSV_W, FDE_OPT_TRSV_W_IN_USE, FDE_OPT_GRAPHS_IN_USE = 0, 1, 2, 3, 4
-FDE_OPT_PRECOND = 5
-FDE_PC_STRANG, FDE_PC_BCCB, FDE_PC_BCCB_SHIFTED = 0, 1, 2
+FDE_OPT_PRECOND, FDE_OPT_SIDE = 5, 6
+FDE_SIDE_RIGHT, FDE_SIDE_LEFT = 0, 1
+FDE_PC_STRANG, FDE_PC_BCCB, FDE_PC_BCCB_SHIFTED, FDE_PC_NONE = 0, 1, 2, 3
 
 
 class FdeSolveOpts(C.Structure):

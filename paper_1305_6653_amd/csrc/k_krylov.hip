@@ -155,17 +155,37 @@ __global__ __launch_bounds__(KR_NT) void k_scale_x(const InstDesc *__restrict__ 
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) d.x[e] *= g;
 }
 
-// x += sum_{j<k} y[1+j] Z_j with k = (int) y[0].
-__global__ __launch_bounds__(KR_NT) void k_update_x(const InstDesc *__restrict__ D, ItemMap map) {
+// x += sum_{j<k} y[1+j] Q_j with k = (int) y[0]; Q = Z (right preconditioning) or V (left).
+__global__ __launch_bounds__(KR_NT) void k_update_x(const InstDesc *__restrict__ D, ItemMap map,
+                                                    int basis_sel) {
   const Chunk c = chunk_of(D, map);
   if (!c.d) return;
   const InstDesc &d = *c.d;
   const int k = (int)d.y[0];
+  const double *Q = basis_sel == VS_V ? d.V : d.Z;
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
     double acc = d.x[e];
-    for (int j = 0; j < k; ++j) acc = fma(d.y[1 + j], d.Z[(size_t)j * c.n + e], acc);
+    for (int j = 0; j < k; ++j) acc = fma(d.y[1 + j], Q[(size_t)j * c.n + e], acc);
     d.x[e] = acc;
   }
+}
+
+// dst = src (vector selectors with basis index)
+__global__ __launch_bounds__(KR_NT) void k_copy(const InstDesc *__restrict__ D, ItemMap map,
+                                                int src_sel, int src_j, int dst_sel, int dst_j) {
+  const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
+  const InstDesc &d = *c.d;
+  const double *src = vsel(d, src_sel, src_j);
+  double *dst = vsel(d, dst_sel, dst_j);
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) dst[e] = src[e];
+}
+
+hipError_t launch_copy(const InstDesc *D, const ItemMap &map, int items, int src_sel, int src_j,
+                       int dst_sel, int dst_j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(items), dim3(KR_NT), 0, st, D, map, src_sel, src_j, dst_sel, dst_j);
+  return hipGetLastError();
 }
 
 hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
@@ -202,9 +222,10 @@ hipError_t launch_scale_x(const InstDesc *D, const ItemMap &map, int items, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, int basis_sel,
+                           hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update_x, dim3(items), dim3(KR_NT), 0, st, D, map);
+  hipLaunchKernelGGL(k_update_x, dim3(items), dim3(KR_NT), 0, st, D, map, basis_sel);
   return hipGetLastError();
 }
 

@@ -78,7 +78,10 @@ hipError_t launch_axpy(const InstDesc *D, const ItemMap &map, int items, int dst
                        double a, hipStream_t st);
 // x *= y[0] per instance
 hipError_t launch_scale_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
-hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
+hipError_t launch_update_x(const InstDesc *D, const ItemMap &map, int items, int basis_sel,
+                           hipStream_t st);
+hipError_t launch_copy(const InstDesc *D, const ItemMap &map, int items, int src_sel, int src_j,
+                       int dst_sel, int dst_j, hipStream_t st);
 
 // ---- restarted GMRES control on the device (one thread per instance of the plan) ----
 // restart: beta = nrm[0] of every live instance -> converged / out of iterations / new cycle;

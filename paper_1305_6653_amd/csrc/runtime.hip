@@ -89,6 +89,28 @@ HostFormula formula_gbdf3() {
   return F;
 }
 
+// Fifth-order generalized Adams method, (nu, mu-nu) = (2, 2).  Each row r reads
+// u_r - u_{r-1} = tau sum_i beta_i g_{c+i}, where beta_i is the integral over the step
+// [r-1, r] of the Lagrange basis polynomial of node i of the five nodes c..c+4 (in units of
+// tau).  Main formula: nodes centred on r (c = r-2); row 1: nodes 0..4; rows s-1, s: nodes
+// s-4..s.  Weights in 720ths; e.g. the main formula's are those of the quartic integrated
+// over its second panel, the mirror image of the third.
+HostFormula formula_gam5() {
+  HostFormula F;
+  F.nu = 2;
+  F.mu = 4;
+  const double d = 720.0;
+  F.a = {0.0, -1.0, 1.0, 0.0, 0.0};
+  F.b = {-19.0 / d, 346.0 / d, 456.0 / d, -74.0 / d, 11.0 / d};
+  F.ai = {-1.0, 1.0, 0.0, 0.0, 0.0};
+  F.bi = {251.0 / d, 646.0 / d, -264.0 / d, 106.0 / d, -19.0 / d};
+  F.af = {0.0, 0.0, -1.0, 1.0, 0.0,  // row s-1: step [2, 3] of the last five nodes
+          0.0, 0.0, 0.0, -1.0, 1.0};  // row s:   step [3, 4]
+  F.bf = {11.0 / d, -74.0 / d, 456.0 / d, 346.0 / d, -19.0 / d,
+          -19.0 / d, 106.0 / d, -264.0 / d, 646.0 / d, 251.0 / d};
+  return F;
+}
+
 struct ProfEntry {
   double ms = 0.0;
   int count = 0;
@@ -155,6 +177,7 @@ struct fde_bvm {
   int opt_graphs = 1, opt_autotune = 1, opt_trsv_w = 0;
   int opt_precond = FDE_PC_STRANG;  // chosen kind; pc = the kind of the current factorization
   int pc = FDE_PC_STRANG;
+  int opt_side = FDE_SIDE_RIGHT;
   // ---- profiling
   bool prof = false;
   int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
@@ -296,7 +319,7 @@ struct SolveMaps {
   int pc = 0;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int prec = -1;
-  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0;
+  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0;
 };
 
 // The same maps with their items skipped for instances whose gate entry is zero.
@@ -337,7 +360,7 @@ struct Plan {
   // and the end of a cycle (least-squares update) followed by the next restart step
   GraphSeg seg_restart, seg_finish;
   std::map<std::pair<int, int>, GraphSeg> seg_steps;
-  int graph_R = -1, graph_prec = -1;
+  int graph_R = -1, graph_prec = -1, graph_side = -1;
   bool graph_off = false;
   std::vector<int> pred_steps;  // Arnoldi steps of each cycle of the previous solve
 };
@@ -364,7 +387,7 @@ static void graphs_invalidate(Plan *P) {
   graph_release(P, P->seg_finish);
   for (auto &kv : P->seg_steps) graph_release(P, kv.second);
   P->seg_steps.clear();
-  P->graph_R = P->graph_prec = -1;
+  P->graph_R = P->graph_prec = P->graph_side = -1;
 }
 
 static void plan_free(Plan *P) {
@@ -865,6 +888,8 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
     F = formula_trapezoidal();
   } else if (p->kind == FDE_BVM_GBDF3) {
     F = formula_gbdf3();
+  } else if (p->kind == FDE_BVM_GAM5) {
+    F = formula_gam5();
   } else if (p->kind == FDE_BVM_CUSTOM) {
     const fde_bvm_formula *c = p->custom;
     if (!c) return fail(FDE_EINVAL, "custom formula is NULL");
@@ -1055,10 +1080,16 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
       h->opt_trsv_w = value;
       return FDE_OK;
     case FDE_OPT_PRECOND:
-      if (value != FDE_PC_STRANG && value != FDE_PC_BCCB && value != FDE_PC_BCCB_SHIFTED)
+      if (value != FDE_PC_STRANG && value != FDE_PC_BCCB && value != FDE_PC_BCCB_SHIFTED &&
+          value != FDE_PC_NONE)
         return fail(FDE_EINVAL, "unknown preconditioner %d", value);
       if (value != h->opt_precond) h->prec = -1;  // factor again before the next solve
       h->opt_precond = value;
+      return FDE_OK;
+    case FDE_OPT_SIDE:
+      if (value != FDE_SIDE_RIGHT && value != FDE_SIDE_LEFT)
+        return fail(FDE_EINVAL, "FDE_OPT_SIDE must be FDE_SIDE_RIGHT or FDE_SIDE_LEFT");
+      h->opt_side = value;
       return FDE_OK;
     default:
       return fail(FDE_EINVAL, "unknown or read-only option %d", option);
@@ -1073,6 +1104,7 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_TRSV_W: *value = h->opt_trsv_w; return FDE_OK;
     case FDE_OPT_TRSV_W_IN_USE: *value = h->self->desc.empty() ? 0 : h->self->desc[0].W; return FDE_OK;
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
+    case FDE_OPT_SIDE: *value = h->opt_side; return FDE_OK;
     case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
   }
@@ -1230,13 +1262,14 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   for (fde_bvm *h : P->hs)
     if (h->opt_precond != kind) return fail(FDE_EINVAL, "all instances of a batch need the same preconditioner");
   if (kind != FDE_PC_STRANG) {
-    // BCCB: no block factors; the "factorization" is the space symbol and the chirp tables
+    // BCCB: no block factors; the "factorization" is the space symbol and the chirp tables.
+    // No preconditioner: nothing to build.
     hipEvent_t e0 = get_event(L), e1 = get_event(L);
     HIPCHK(hipEventRecord(e0, L->stream));
     for (fde_bvm *h : P->hs) {
       h->prec = -1;
       h->pc = kind;
-      STCHK(bccb_prepare(h));
+      if (kind != FDE_PC_NONE) STCHK(bccb_prepare(h));
       if (h->self) h->self->desc_dirty = true;
     }
     P->desc_dirty = true;
@@ -1327,6 +1360,7 @@ static fde_status ensure_full_maps(Plan *P) {
     S.trsv_bytes += (double)h->nb * h->m * h->m * esz + 32.0 * h->nb * h->m;
     S.vec_bytes += 8.0 * h->n();
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
+    S.bccb_bytes += 32.0 * h->nb * h->m;  // one complex read and write per (frequency, node)
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
                                    make_map(slots, d), make_map(slots, e), make_map(slots, f),
@@ -1395,11 +1429,18 @@ static bool g_coop_ok = true;
 static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int dst, int dj) {
   fde_bvm *L = P->lead;
   hipStream_t st = L->stream;
+  if (S.pc == FDE_PC_NONE) {  // identity
+    if (src == dst && sj == dj) return FDE_OK;
+    HIPCHK(run(L, "copy", 2.0 * S.vec_bytes, [&] {
+      return launch_copy(P->d_desc, S.kry, S.n_kry, src, sj, dst, dj, st);
+    }));
+    return FDE_OK;
+  }
   if (S.pc != FDE_PC_STRANG) {  // BCCB: time DFT, space-Fourier diagonal solve, inverse time DFT
     HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
       return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st);
     }));
-    HIPCHK(run(L, "bccb_solve", 2.0 * S.tfft_bytes, [&] {
+    HIPCHK(run(L, "bccb_solve", S.bccb_bytes, [&] {
       return launch_bccb_solve(P->d_desc, S.blk, S.n_blk, S.max_log2L, st);
     }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
@@ -1554,6 +1595,21 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     bnorm[i] = std::sqrt(part_sum(P, parts, i, 0));
     if (!std::isfinite(bnorm[i])) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
   }
+  // Left preconditioning measures residuals after the preconditioner: the reference norm of
+  // the stopping test is ||P^{-1} b||.  (With no preconditioner both sides are the same.)
+  const bool left = L->opt_side == FDE_SIDE_LEFT && S.pc != FDE_PC_NONE;
+  const std::vector<double> bnorm_true = bnorm;
+  if (left) {
+    STCHK(op_precond(P, S, VS_B, 0, VS_TMP, 0));
+    HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_TMP, VS_TMP, 0, stream); }));
+    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
+    STCHK(sync_and_flush(L));
+    STCHK(check_trsv_err(P));
+    for (int i = 0; i < count; ++i) {
+      bnorm[i] = bnorm_true[i] == 0.0 ? 0.0 : std::sqrt(part_sum(P, parts, i, 0));
+      if (!std::isfinite(bnorm[i])) return fail(FDE_ESINGULAR, "P^{-1} b of instance %d is not finite", i);
+    }
+  }
   // An initial guess is first scaled by the gamma minimising ||b - gamma M x0|| (one step of
   // minimal residual along x0), so that ||r_0|| <= ||b||: a poor guess never starts worse
   // than the zero start.
@@ -1604,26 +1660,39 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
 
   // Timing events are not recorded into graphs: a profiled solve launches directly.
   const bool use_graph = L->opt_graphs != 0 && !P->graph_off && !L->prof;
-  if (P->graph_R != R || P->graph_prec != S.prec) {
+  if (P->graph_R != R || P->graph_prec != S.prec || P->graph_side != (int)left) {
     HIPCHK(hipStreamSynchronize(stream));
     graphs_invalidate(P);
     P->graph_R = R;
     P->graph_prec = S.prec;
+    P->graph_side = (int)left;
   }
+  // v_0 = r / ||r|| with r = b - M x (right) or P^{-1}(b - M x) (left); the norm goes to the
+  // control record's restart test.
   auto restart_step = [&]() -> fde_status {
     STCHK(op_matvec(P, Slive, VS_X, 0, VS_TMP, 0));
     HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, Slive.kry, S.n_kry, stream); }));
+    if (left) {
+      STCHK(op_precond(P, Slive, VS_V, 0, VS_V, 0));
+      HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, Slive.kry, S.n_kry, VS_V, VS_V, 0, stream); }));
+    }
     HIPCHK(run(L, "normalize", 2.0 * S.vec_bytes, [&] {
       return launch_normalize(P->d_desc, Slive.kry, S.n_kry, VS_V, 0, VS_V, 0, 0, -1, stream);
     }));
     HIPCHK(launch_gm_restart(P->d_desc, P->d_ctl, P->d_work, P->d_gates, count, stream));
     return FDE_OK;
   };
+  // Arnoldi step j: w = M P^{-1} v_j (right; z_j = P^{-1} v_j is kept) or P^{-1} M v_j (left).
   auto steps = [&](int j0, int j1) -> fde_status {
     for (int j = j0; j < j1; ++j) {
       g_step = j;
-      STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
-      STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
+      if (left) {
+        STCHK(op_matvec(P, Sact, VS_V, j, VS_TMP, 0));
+        STCHK(op_precond(P, Sact, VS_TMP, 0, VS_W, 0));
+      } else {
+        STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
+        STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
+      }
       for (int i = 0; i <= j + 1; ++i) {
         HIPCHK(run(L, "mgs", (i == 0 ? 2.0 : 4.0) * S.vec_bytes,
                    [&] { return launch_mgs_step(P->d_desc, Sact.kry, S.n_kry, i, j, stream); }));
@@ -1638,7 +1707,9 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   };
   auto finish_and_restart = [&]() -> fde_status {
     HIPCHK(launch_gm_backsolve(P->d_desc, P->d_ctl, P->d_work, count, stream));
-    HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] { return launch_update_x(P->d_desc, Slive.kry, S.n_kry, stream); }));
+    HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] {
+      return launch_update_x(P->d_desc, Slive.kry, S.n_kry, left ? VS_V : VS_Z, stream);
+    }));
     return restart_step();
   };
   // Reads the control records.  Launches of Arnoldi steps >= j0 + (steps taken since the
@@ -1695,6 +1766,14 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     taken_per_cycle.push_back(cyc);
   }
   P->pred_steps = taken_per_cycle;
+  if (left) {  // the control records hold preconditioned residuals: report the true one
+    STCHK(op_matvec(P, S, VS_X, 0, VS_TMP, 0));
+    HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, S.kry, S.n_kry, stream); }));
+    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
+    STCHK(sync_and_flush(L));
+    for (int i = 0; i < count; ++i)
+      ctl[i].truer = bnorm_true[i] > 0.0 ? std::sqrt(part_sum(P, parts, i, 0)) / bnorm_true[i] : 0.0;
+  }
   for (int i = 0; i < count; ++i) {
     st[i].truer = ctl[i].truer;
     st[i].est = ctl[i].est;

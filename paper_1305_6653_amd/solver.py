@@ -13,9 +13,11 @@ import numpy as np
 
 from . import _native as N
 
-_KINDS = {"trapezoidal": N.FDE_BVM_TRAPEZOIDAL, "gbdf3": N.FDE_BVM_GBDF3}
+_KINDS = {"trapezoidal": N.FDE_BVM_TRAPEZOIDAL, "gbdf3": N.FDE_BVM_GBDF3, "gam5": N.FDE_BVM_GAM5}
 _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
-_PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED}
+_PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED,
+       "none": N.FDE_PC_NONE}
+_SIDE = {"right": N.FDE_SIDE_RIGHT, "left": N.FDE_SIDE_LEFT}
 
 
 def _is_torch_cuda(x) -> bool:
@@ -52,7 +54,7 @@ def _same_space(*spaces):
 class BvmSolver:
     """One all-at-once BVM system: ``setup`` on construction, then ``factor`` and ``solve``.
 
-    problem: any object with alpha, m, s, d_plus, d_minus, bvm ('trapezoidal'|'gbdf3')
+    problem: any object with alpha, m, s, d_plus, d_minus, bvm ('trapezoidal'|'gbdf3'|'gam5')
     and optional xL, xR, t0, T (a ``workloads.Problem`` works).
     """
 
@@ -112,7 +114,8 @@ class BvmSolver:
 
     # ---- the three calls
     def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None):
-        """Build the preconditioner: "strang" (block LUs), "bccb" or "bccb_shifted" (2-D DFT)."""
+        """Build the preconditioner: "strang" (block LUs), "bccb" or "bccb_shifted" (2-D DFT),
+        or "none"."""
         if preconditioner is not None:
             kind = _PC[preconditioner]
             if self.get_option(N.FDE_OPT_PRECOND) != kind:
@@ -120,9 +123,14 @@ class BvmSolver:
         N.check(N.lib().fde_precond_factor(self._h, _PREC[precision]))
 
     def solve(self, u0, f, x0=None, out=None, rtol: float = 1e-10, restart: int = 20,
-              maxit: int = 1000, raise_on_noconv: bool = True, x0_kind: int = N.FDE_X0_SOLUTION):
+              maxit: int = 1000, raise_on_noconv: bool = True, x0_kind: int = N.FDE_X0_SOLUTION,
+              side: Optional[str] = None):
         """Returns (u [s][m], info dict).  u0 [m], f [s+1][m], x0 [s][m] or None
-        (x0_kind: FDE_X0_SOLUTION, or FDE_X0_LOWRANK for a guess of (S - M) u)."""
+        (x0_kind: FDE_X0_SOLUTION, or FDE_X0_LOWRANK for a guess of (S - M) u).  side: "right"
+        or "left" sets the handle's preconditioning side (None keeps it)."""
+        if side is not None:
+            if self.get_option(N.FDE_OPT_SIDE) != _SIDE[side]:
+                self.set_option(N.FDE_OPT_SIDE, _SIDE[side])
         pu0, s1, k1 = _arg(u0, self.m, "u0")
         pf, s2, k2 = _arg(f, (self.s + 1) * self.m, "f")
         sx = None

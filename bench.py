@@ -28,21 +28,22 @@ PEAK_HBM_GBS = 8000.0
 # each scaled by the same counter's reading for a plain device-to-device copy of known size.
 # Keyed by (workload, precision, kernel); valid only while the kernel sources hash to
 # PMC_SOURCE_HASH, otherwise "traffic" is reported as null.
-PMC_SOURCE_HASH = "e4efcf6b6705c0e2"
+PMC_SOURCE_HASH = "f5e1832effbc822f"
 PMC_TRAFFIC = {
     ("c2", "fp64", "assemble"): 4.3131e+09,
-    ("c2", "mixed", "assemble"): 2.1569e+09,
+    ("c2", "fp64", "bccb_solve"): 9.2170e+06,
     ("c2", "fp64", "bvm_matvec"): 2.1762e+07,
     ("c2", "fp64", "lu_diag"): 6.7539e+07,
-    ("c2", "mixed", "lu_diag"): 3.3784e+07,
     ("c2", "fp64", "lu_panel"): 7.4818e+08,
-    ("c2", "mixed", "lu_panel"): 3.8818e+08,
-    ("c2", "fp64", "lu_update"): 3.3667e+09,
-    ("c2", "mixed", "lu_update"): 1.6690e+09,
-    ("c2", "fp64", "mgs"): 1.5796e+07,
-    ("c2", "fp64", "time_irfft"): 9.2718e+06,
-    ("c2", "fp64", "time_rfft"): 1.2418e+07,
+    ("c2", "fp64", "lu_update"): 3.3665e+09,
+    ("c2", "fp64", "mgs"): 1.5956e+07,
+    ("c2", "fp64", "time_irfft"): 9.2600e+06,
+    ("c2", "fp64", "time_rfft"): 1.2419e+07,
     ("c2", "fp64", "trsv"): 4.6746e+09,
+    ("c2", "mixed", "assemble"): 2.1569e+09,
+    ("c2", "mixed", "lu_diag"): 3.3784e+07,
+    ("c2", "mixed", "lu_panel"): 3.8826e+08,
+    ("c2", "mixed", "lu_update"): 1.6688e+09,
     ("c2", "mixed", "trsv"): 2.3812e+09,
 }
 

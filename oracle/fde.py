@@ -38,6 +38,7 @@ __all__ = [
     "strang_circulant", "strang_eigs", "strang_dense", "StrangPreconditioner",
     "apply_M", "gmres", "GmresResult", "solve_gmres", "true_relres", "strang_space_column",
     "strang_space_symbol", "bccb_eigs", "bccb_dense", "BccbPreconditioner",
+    "hessenberg_lu", "hessenberg_lu_solve", "HessenbergPreconditioner",
 ]
 
 
@@ -321,6 +322,65 @@ class StrangPreconditioner:
 
 
 # ======================================================================================
+# The blocks of S through one Hessenberg form of J (not in the paper): every block
+# K_k = lambda_k I - tau mu_k J is a shift of the same matrix, so with J = Q H Q^T
+# (Q orthogonal, H upper Hessenberg) K_k = Q (lambda_k I - tau mu_k H) Q^T, and each shifted
+# Hessenberg matrix is factored in O(m^2).
+# ======================================================================================
+def hessenberg_lu(C: np.ndarray):
+    """Gaussian elimination with partial pivoting on an upper Hessenberg matrix C: at step i
+    only rows i and i+1 hold entries in column i, so the pivot is the larger of the two.
+    Returns (U, l, swapped): U upper triangular, l[i] the multiplier of step i, swapped[i]
+    whether rows i and i+1 were exchanged first; C = P_0 L_0 P_1 L_1 ... U in product form."""
+    U = np.array(C, dtype=np.complex128)
+    m = U.shape[0]
+    l = np.zeros(max(m - 1, 0), dtype=np.complex128)
+    swapped = np.zeros(max(m - 1, 0), dtype=bool)
+    for i in range(m - 1):
+        if abs(U[i + 1, i]) > abs(U[i, i]):
+            U[[i, i + 1], i:] = U[[i + 1, i], i:]
+            swapped[i] = True
+        l[i] = U[i + 1, i] / U[i, i]
+        U[i + 1, i:] -= l[i] * U[i, i:]
+        U[i + 1, i] = 0.0
+    return U, l, swapped
+
+
+def hessenberg_lu_solve(U: np.ndarray, l: np.ndarray, swapped: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Solve C z = y with the factors of ``hessenberg_lu``: replay the row exchanges and
+    eliminations on y, then back substitution with U."""
+    z = np.array(y, dtype=np.complex128)
+    for i in range(len(l)):
+        if swapped[i]:
+            z[[i, i + 1]] = z[[i + 1, i]]
+        z[i + 1] -= l[i] * z[i]
+    return scipy.linalg.solve_triangular(U, z, lower=False, check_finite=False)
+
+
+class HessenbergPreconditioner:
+    """S^{-1} v with the blocks solved through J = Q H Q^T (scipy's Householder reduction):
+    time rfft, then for each k: Q^T v_k, the shifted Hessenberg solve, Q times the result;
+    inverse rfft.  The same operator as ``StrangPreconditioner`` up to rounding."""
+
+    def __init__(self, J: np.ndarray, F: Formula, s: int, tau: float):
+        self.s, self.m = s, J.shape[0]
+        H, Q = scipy.linalg.hessenberg(J, calc_q=True)
+        self.H, self.Q = H, Q
+        lam, mu = strang_eigs(F, s)
+        self.lam, self.mu = lam[: s // 2 + 1], mu[: s // 2 + 1]
+        eye = np.eye(self.m)
+        self.factors = [hessenberg_lu(lk * eye - tau * mk * H) for lk, mk in zip(self.lam, self.mu)]
+
+    def apply(self, V: np.ndarray) -> np.ndarray:
+        V = V.reshape(self.s, self.m)
+        Vh = np.fft.rfft(V, axis=0)
+        Wh = np.empty_like(Vh)
+        for k, (U, l, sw) in enumerate(self.factors):
+            Wh[k] = self.Q @ hessenberg_lu_solve(U, l, sw, self.Q.T @ Vh[k])
+        return np.fft.irfft(Wh, n=self.s, axis=0)
+
+
+# ======================================================================================
 # Section 3.1, BCCB variants: S2 = s(A) (x) I - h s(B) (x) s(J), eq. (x1), and the shifted
 # S2~ = s~(A) (x) I - h s(B) (x) s(J), eq. (xc); Section 3.2 (their 2-D FFT diagonalisation)
 # ======================================================================================
@@ -554,6 +614,8 @@ def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
         pc = None
     elif precond == "strang":
         pc = StrangPreconditioner(J, F, p.s, tau).apply
+    elif precond == "strang_hessenberg":
+        pc = HessenbergPreconditioner(J, F, p.s, tau).apply
     elif precond in ("bccb", "bccb_shifted"):
         pc = BccbPreconditioner(p, shifted=precond == "bccb_shifted").apply
     else:

@@ -192,7 +192,8 @@ typedef enum {
   FDE_OPT_TRSV_W_IN_USE = 3,
   FDE_OPT_GRAPHS_IN_USE = 4,
   FDE_OPT_PRECOND = 5,
-  FDE_OPT_SIDE = 6
+  FDE_OPT_SIDE = 6,
+  FDE_OPT_BLOCKS = 7
 } fde_option;
 /* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
  * discards the current factorization):
@@ -221,6 +222,19 @@ typedef enum {
  *                             ||P^{-1} b||.  fde_solve_info.true_relres is still ||b - M x|| /
  *                             ||b||, computed once after the last cycle. */
 typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
+/* FDE_OPT_BLOCKS selects how the blocks K_k = lambda_k I - tau mu_k J of S are factored and
+ * solved (the operator S^{-1} is the same up to rounding; changing it discards the current
+ * factorization):
+ *   FDE_BLOCKS_LU          (default) a pivot-free LU of every block (s/2+1 dense LUs on MFMA);
+ *                          the solves read the full L and U factors.
+ *   FDE_BLOCKS_HESSENBERG  every block is a shift of J: one Householder reduction J = Q H Q^T
+ *                          (H upper Hessenberg, Q orthogonal; FP64) and, per block, Gaussian
+ *                          elimination with partial pivoting of lambda_k I - tau mu_k H (rows i
+ *                          and i+1 compete in step i).  An apply is Q^T v_k, the exchanges and
+ *                          eliminations, U^{-1}, Q: the solves read only the U factors (half the
+ *                          bytes).  Not in the paper.  m <= 1024 (FDE_EUNSUPPORTED beyond);
+ *                          needs cooperative launches. */
+typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1 } fde_block_solver;
 fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
 fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
 /* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);
@@ -248,6 +262,10 @@ fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, int mem_spa
 /* Copies the stored LU factors of block k (unit-lower L below the diagonal, U on and above
  * it, complex interleaved, [m][m] row-major, widened to FP64) to the host array out. */
 fde_status fde_get_factor_block(fde_bvm *h, int k, double *out);
+/* With FDE_BLOCKS_HESSENBERG factors stored: copies H and Q of J = Q H Q^T ([m][m] row-major,
+ * host arrays) to the caller; the factor block of fde_get_factor_block then holds U on and
+ * above the diagonal (below it: unspecified).  FDE_EINVAL without such a factorization. */
+fde_status fde_get_hessenberg(fde_bvm *h, double *H, double *Q);
 
 /* ---- per-kernel timing ------------------------------------------------------------- */
 /* When enabled, every kernel launch is bracketed by HIP events on the handle's stream and

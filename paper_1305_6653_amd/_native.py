@@ -38,7 +38,8 @@ class FdeProblem(C.Structure):
 
 FDE_X0_SOLUTION, FDE_X0_LOWRANK = 0, 1
 FDE_OPT_GRAPHS, FDE_OPT_AUTOTUNE, FDE_OPT_TRSV_W, FDE_OPT_TRSV_W_IN_USE, FDE_OPT_GRAPHS_IN_USE = 0, 1, 2, 3, 4
-FDE_OPT_PRECOND, FDE_OPT_SIDE = 5, 6
+FDE_OPT_PRECOND, FDE_OPT_SIDE, FDE_OPT_BLOCKS = 5, 6, 7
+FDE_BLOCKS_LU, FDE_BLOCKS_HESSENBERG = 0, 1
 FDE_SIDE_RIGHT, FDE_SIDE_LEFT = 0, 1
 FDE_PC_STRANG, FDE_PC_BCCB, FDE_PC_BCCB_SHIFTED, FDE_PC_NONE = 0, 1, 2, 3
 
@@ -99,6 +100,7 @@ SIGNATURES = [
     ("fde_time_rfft", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("fde_apply_precond", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("fde_get_factor_block", C.c_int, [_VP, C.c_int, _VP]),
+    ("fde_get_hessenberg", C.c_int, [_VP, _VP, _VP]),
     ("fde_profile_enable", C.c_int, [_VP, C.c_int]),
     ("fde_profile_query", C.c_int, [_VP, C.c_char_p, _dp, C.POINTER(C.c_int), _dp]),
     ("fde_bvm_set_coefficients", C.c_int, [_VP, C.c_double, _dp, _dp]),

@@ -30,6 +30,15 @@ struct InstDesc {
   int pc;
   double lam0s;
   const double2 *chirp, *bh, *lamx;
+  // Hessenberg route to the blocks (blk = 1): H, Q and Q^T of J = Q H Q^T (real, [m][mp]);
+  // per block the multipliers and row exchanges of the shifted Hessenberg LU ([nb][mp]).
+  // Vts is the frequency-domain vector the block solve works on: Vh for the LU route, a
+  // second [nb][mp] buffer for the Hessenberg route (Q^T is applied out of place).
+  int blk;
+  const double *hH, *hQ, *hQt;
+  double2 *hl;
+  int *hpiv;
+  double2 *Vts;
   // vectors (FP64, [s][m] unless noted)
   double *V, *Z;              // (R+1) and R vectors
   double *w, *x, *b, *tmp, *sio;

@@ -286,6 +286,65 @@ __global__ __launch_bounds__(NT) void k_lu_diag(const InstDesc *__restrict__ Dd,
   }
 }
 
+// Inverse of the upper triangle of a diagonal 64x64 tile of U (the Hessenberg route: U comes
+// from the shifted Hessenberg LU).  Item = (instance, block, panel); 512 threads as in the FP64
+// diagonal factorization: thread (r, cq) holds row r, columns cq + 8j of the inverse.
+template <typename T>
+__global__ __launch_bounds__(512) void k_hess_uinv(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                   int *__restrict__ flag) {
+  typedef c_t<T> C;
+  __shared__ C a[PB][PB + 1];
+  __shared__ C prowU[2][PB];
+  __shared__ C dgi[PB];
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = Dd[map.ids[q]];
+  const int local = blockIdx.x - map.pre[q], tid = threadIdx.x;
+  const int mp = d.mp, npan = d.npan, blk = local / npan, p = local % npan;
+  const C *A = (const C *)d.K + (size_t)blk * mp * mp + (size_t)p * PB * mp + (size_t)p * PB;
+  const int r = tid >> 3, cq = tid & 7;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int c = cq + 8 * j;
+    a[r][c] = c >= r ? A[(size_t)r * mp + c] : mk<T>((T)0, (T)0);
+  }
+  __syncthreads();
+  int bad = 0;
+  if (cq == 0) {
+    bool ok;
+    dgi[r] = recip_checked<T>(a[r][r], ok);
+    bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+  C y[8];
+  unit_rows<T>(y, r, cq);
+  if (r == PB - 1) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      y[j] = tmul<T>(y[j], dgi[PB - 1]);
+      prowU[1][cq + 8 * j] = y[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int k = PB - 1; k >= 1; --k) {
+    inv_upper_step<T>(y, a, dgi, r, cq, k, prowU[k & 1], prowU[(k & 1) ^ 1]);
+    __syncthreads();
+  }
+  C *Du = (C *)d.dinv + ((size_t)(blk * npan + p) * 2 + 1) * PB * PB;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = y[j];
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename T>
+hipError_t launch_hess_uinv(const InstDesc *D, const ItemMap &map, int items, int *flag,
+                            hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hess_uinv<T>, dim3(items), dim3(512), 0, st, D, map, flag);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------
 // 64x64 complex tiles on MFMA: each of the 4 wavefronts owns a 32x32 quarter as 2x2 16x16
 // sub-tiles of real and imaginary accumulators.
@@ -520,7 +579,7 @@ __global__ __launch_bounds__(TS_NT) void k_trsv(const InstDesc *__restrict__ Dd,
   double2 *tmp = sh + mp;
   const c_t<T> *dinv = (const c_t<T> *)d.dinv;
   const c_t<T> *A = (const c_t<T> *)d.K + (size_t)blk * mp * mp;
-  double2 *v = d.Vh + (size_t)blk * mp;
+  double2 *v = d.Vts + (size_t)blk * mp;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int NW = TS_NT / 64;
   for (int i = threadIdx.x; i < mp; i += TS_NT) y[i] = v[i];
@@ -700,7 +759,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
                                                    int items,
                                                    const unsigned long long *__restrict__ epoch_p,
-                                                   int *__restrict__ err) {
+                                                   int *__restrict__ err, int first_sweep) {
   __shared__ double2 tmp[PB];
   __shared__ int ready_slot[2];
   int calls = 0;
@@ -717,9 +776,9 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
     const int k = local / W, w = local % W;
     const c_t<T> *dinv = (const c_t<T> *)d.dinv;
     const c_t<T> *A = (const c_t<T> *)d.K + (size_t)k * mp * mp;
-    double2 *v = d.Vh + (size_t)k * mp;
+    double2 *v = d.Vts + (size_t)k * mp;
     unsigned long long *fl = d.tsflags + (size_t)k * npan * 2;
-    for (int sweep = 0; sweep < 2; ++sweep) {
+    for (int sweep = first_sweep; sweep < 2; ++sweep) {
       const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
       for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
         const int p0 = P * PB;
@@ -843,12 +902,14 @@ int trsv_coop_capacity() {
 
 template <typename T>
 hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
-                            const unsigned long long *epoch, int *err, hipStream_t st) {
+                            const unsigned long long *epoch, int *err, hipStream_t st,
+                            int first_sweep) {
   if (items <= 0) return hipSuccess;
   const int cap = trsv_coop_capacity<T>();
   if (cap <= 0) return hipErrorNotSupported;
   const int grid = items < cap ? items : cap;
-  void *args[] = {(void *)&D, (void *)&map, (void *)&items, (void *)&epoch, (void *)&err};
+  void *args[] = {(void *)&D, (void *)&map, (void *)&items, (void *)&epoch, (void *)&err,
+                  (void *)&first_sweep};
   return hipLaunchCooperativeKernel((const void *)k_trsv_coop<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
@@ -861,7 +922,9 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                                           hipStream_t);                                         \
   template hipError_t launch_trsv<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t);    \
   template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int,                 \
-                                          const unsigned long long *, int *, hipStream_t);       \
+                                          const unsigned long long *, int *, hipStream_t, int);  \
+  template hipError_t launch_hess_uinv<T>(const InstDesc *, const ItemMap &, int, int *,          \
+                                          hipStream_t);                                         \
   template int trsv_coop_capacity<T>();
 FDE_INST(double)
 FDE_INST(float)

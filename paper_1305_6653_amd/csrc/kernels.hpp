@@ -56,10 +56,12 @@ hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max
 // several workgroups per block (descriptor field W), cooperative launch: items = nb W per
 // instance; flags in the descriptors hold the epoch of the last published panel; the epoch of
 // this launch is read from *epoch (device memory, written by the preceding time FFT); *err is
-// raised if a dependency wait had to be abandoned.
+// raised if a dependency wait had to be abandoned.  first_sweep = 1 runs the U sweep only (the
+// Hessenberg route, whose lower factor is applied by launch_hess_lsolve).
 template <typename T>
 hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
-                            const unsigned long long *epoch, int *err, hipStream_t st);
+                            const unsigned long long *epoch, int *err, hipStream_t st,
+                            int first_sweep = 0);
 // co-resident workgroups of the cooperative block solve on this device (0 if unknown)
 template <typename T>
 int trsv_coop_capacity();
@@ -95,6 +97,36 @@ hipError_t launch_gm_givens(const InstDesc *D, GmresCtl *ctl, GmresWork *work, i
 // end of cycle: y = H^{-1} g into the descriptors' y (y[0] = k, 0 if the instance did not run)
 hipError_t launch_gm_backsolve(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int count,
                                hipStream_t st);
+
+// ---- Hessenberg route to the blocks (k_hessenberg.hip) ----
+// Workspace of one reduction of an instance of order m (mp padded, G workgroups):
+// sync [2], err [1], vbuf [2][mp+1], part [G][2][mp], ybuf [2][mp]; outputs H, Q, Q^T
+// [m][mp] row-major.
+struct HessWork {
+  unsigned *sync;
+  int *err;
+  double *vbuf, *part, *ybuf;
+  double *H, *Q, *Qt;
+};
+int hess_reduce_groups(int m);   // G
+int hess_reduce_max_m();         // largest order the register-resident reduction takes
+// J = Q H Q^T of instance `inst` of D (cooperative launch; err set if it could not finish)
+hipError_t launch_hess_reduce(const InstDesc *D, int inst, int m, const HessWork &wk, hipStream_t st);
+// item = (instance, block): pivoted LU of lambda_k I - tau mu_k H into K (upper part), hl, hpiv
+template <typename T>
+hipError_t launch_hess_lu(const InstDesc *D, const ItemMap &map, int items, int max_mp, int *flag,
+                          hipStream_t st);
+// item = (instance, block, panel): inverse of U's diagonal 64x64 tile into dinv[..][1]
+template <typename T>
+hipError_t launch_hess_uinv(const InstDesc *D, const ItemMap &map, int items, int *flag,
+                            hipStream_t st);
+// item = (instance, block): the exchanges and eliminations applied to Vts in place
+hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, int max_mp,
+                              hipStream_t st);
+// Vts = Vh Q (trans 0, src2 0) or Vh = Vts Q^T (trans 1, src2 1)
+int qgemm_items(int nb, int mp);
+hipError_t launch_qgemm(const InstDesc *D, const ItemMap &map, int items, int trans, int src2,
+                        hipStream_t st);
 
 // ---- streaming-read probe: out has `blocks` floats; reads bytes (a multiple of 16) of x ----
 hipError_t launch_read_probe(const void *x, size_t bytes, float *out, int blocks, hipStream_t st);

@@ -168,6 +168,14 @@ struct fde_bvm {
   double *d_w = nullptr, *d_x = nullptr, *d_b = nullptr, *d_tmp = nullptr, *d_sio = nullptr;
   double *d_u0 = nullptr, *d_f = nullptr, *d_Ju0 = nullptr;
   double2 *d_Vh = nullptr;
+  // ---- Hessenberg route to the blocks (allocated when first factored that way): H, Q, Q^T
+  // [m][mp], multipliers and exchanges [nb][mp], the block-solve vector [nb][mp], and the
+  // reduction's workspace
+  int blk_route = FDE_BLOCKS_LU;
+  double *d_hH = nullptr, *d_hQ = nullptr, *d_hQt = nullptr;
+  double2 *d_hl = nullptr, *d_Vh2 = nullptr;
+  int *d_hpiv = nullptr;
+  HessWork hwk{};
   // ---- BCCB preconditioner tables (allocated when a BCCB preconditioner is factored)
   double2 *d_chirp = nullptr, *d_bh = nullptr, *d_lamx = nullptr;
   double lam0s = 0.0;
@@ -178,6 +186,7 @@ struct fde_bvm {
   int opt_precond = FDE_PC_STRANG;  // chosen kind; pc = the kind of the current factorization
   int pc = FDE_PC_STRANG;
   int opt_side = FDE_SIDE_RIGHT;
+  int opt_blocks = FDE_BLOCKS_LU;
   // ---- profiling
   bool prof = false;
   int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
@@ -314,18 +323,18 @@ struct HostMap {
 
 // Item maps of the solve-phase launches over every instance of a plan.
 struct SolveMaps {
-  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk;
-  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0;
-  int pc = 0;
+  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk, qg;
+  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0;
+  int pc = 0, route = FDE_BLOCKS_LU;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int prec = -1;
-  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0;
+  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0;
 };
 
 // The same maps with their items skipped for instances whose gate entry is zero.
 static SolveMaps gated(const SolveMaps &S, const int *gate) {
   SolveMaps G = S;
-  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk}) m->gate = gate;
+  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk, &G.qg}) m->gate = gate;
   return G;
 }
 
@@ -491,6 +500,13 @@ static InstDesc make_desc(fde_bvm *h) {
   d.f = h->d_f;
   d.Ju0 = h->d_Ju0;
   d.Vh = h->d_Vh;
+  d.blk = h->blk_route;
+  d.hH = h->d_hH;
+  d.hQ = h->d_hQ;
+  d.hQt = h->d_hQt;
+  d.hl = h->d_hl;
+  d.hpiv = h->d_hpiv;
+  d.Vts = h->blk_route == FDE_BLOCKS_HESSENBERG ? h->d_Vh2 : h->d_Vh;
   d.pc = h->pc;
   d.lam0s = h->lam0s;
   d.chirp = h->d_chirp;
@@ -525,6 +541,7 @@ static std::map<std::string, int> g_tuned_w;
 
 static std::string plan_shape_key(const Plan *P, int prec) {
   std::string k = prec == FDE_FP64 ? "f64" : "c32";
+  if (!P->hs.empty() && P->hs[0]->blk_route == FDE_BLOCKS_HESSENBERG) k += "h";
   char buf[32];
   for (const fde_bvm *h : P->hs) {
     snprintf(buf, sizeof buf, ":%dx%d", h->m, h->s);
@@ -1091,6 +1108,12 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
         return fail(FDE_EINVAL, "FDE_OPT_SIDE must be FDE_SIDE_RIGHT or FDE_SIDE_LEFT");
       h->opt_side = value;
       return FDE_OK;
+    case FDE_OPT_BLOCKS:
+      if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG)
+        return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU or FDE_BLOCKS_HESSENBERG");
+      if (value != h->opt_blocks) h->prec = -1;  // factor again before the next solve
+      h->opt_blocks = value;
+      return FDE_OK;
     default:
       return fail(FDE_EINVAL, "unknown or read-only option %d", option);
   }
@@ -1105,6 +1128,7 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_TRSV_W_IN_USE: *value = h->self->desc.empty() ? 0 : h->self->desc[0].W; return FDE_OK;
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
     case FDE_OPT_SIDE: *value = h->opt_side; return FDE_OK;
+    case FDE_OPT_BLOCKS: *value = h->opt_blocks; return FDE_OK;
     case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
   }
@@ -1253,6 +1277,61 @@ static fde_status factor_plan_impl(Plan *P) {
   return FDE_OK;
 }
 
+// The Hessenberg route: J = Q H Q^T per instance (one cooperative launch each), then the
+// shifted Hessenberg LUs of all blocks of all instances and the inverses of U's diagonal
+// tiles (one launch each).
+template <typename T>
+static fde_status hess_factor(Plan *P) {
+  fde_bvm *L = P->lead;
+  const int count = (int)P->hs.size();
+  hipStream_t st = L->stream;
+  std::vector<int> slots(count), a(count), b(count);
+  int max_mp = 64;
+  double wlu = 0.0;
+  for (int i = 0; i < count; ++i) {
+    fde_bvm *h = P->hs[i];
+    const double m = h->m;
+    HIPCHK(run(L, "hess_reduce", 10.0 / 3.0 * m * m * m + 4.0 * m * m * m, [&] {
+      return launch_hess_reduce(P->d_desc, i, h->m, h->hwk, st);
+    }));
+    slots[i] = i;
+    a[i] = h->nb;
+    b[i] = h->nb * h->npan;
+    max_mp = std::max(max_mp, h->mp);
+    wlu += h->nb * 8.0 * m * m / 2.0;
+  }
+  std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b)};
+  std::vector<ItemMap> dm;
+  STCHK(upload_maps(P, hm, dm));
+  HIPCHK(run(L, "hess_lu", wlu, [&] { return launch_hess_lu<T>(P->d_desc, dm[0], hm[0].items, max_mp, P->d_flag, st); }));
+  double winv = 0.0;
+  for (fde_bvm *h : P->hs) winv += h->nb * h->npan * 8.0 * 64.0 * 64.0 * 64.0 / 6.0;
+  HIPCHK(run(L, "hess_uinv", winv, [&] { return launch_hess_uinv<T>(P->d_desc, dm[1], hm[1].items, P->d_flag, st); }));
+  return FDE_OK;
+}
+
+static fde_status hess_alloc(fde_bvm *h) {
+  if (h->d_hH) return FDE_OK;
+  const size_t mp = h->mp, nb = h->nb, G = hess_reduce_groups(h->m);
+  STCHK(dalloc_t(h, &h->d_hH, mp * mp));
+  STCHK(dalloc_t(h, &h->d_hQ, mp * mp));
+  STCHK(dalloc_t(h, &h->d_hQt, mp * mp));
+  STCHK(dalloc_t(h, &h->d_hl, nb * mp));
+  STCHK(dalloc_t(h, &h->d_hpiv, nb * mp));
+  STCHK(dalloc_t(h, &h->d_Vh2, nb * mp));
+  HIPCHK(hipMemsetAsync(h->d_Vh2, 0, nb * mp * sizeof(double2), h->stream));
+  HessWork &w = h->hwk;
+  STCHK(dalloc_t(h, &w.sync, 4));
+  w.err = (int *)(w.sync + 2);
+  STCHK(dalloc_t(h, &w.vbuf, 2 * (mp + 1)));
+  STCHK(dalloc_t(h, &w.part, G * 2 * mp));
+  STCHK(dalloc_t(h, &w.ybuf, 2 * mp));
+  w.H = h->d_hH;
+  w.Q = h->d_hQ;
+  w.Qt = h->d_hQt;
+  return FDE_OK;
+}
+
 static fde_status bccb_prepare(fde_bvm *h);
 
 static fde_status factor_plan(Plan *P, fde_precision prec) {
@@ -1286,7 +1365,18 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
     }
     return FDE_OK;
   }
-  for (fde_bvm *h : P->hs) h->pc = FDE_PC_STRANG;
+  const int route = P->hs[0]->opt_blocks;
+  for (fde_bvm *h : P->hs) {
+    if (h->opt_blocks != route) return fail(FDE_EINVAL, "all instances of a batch need the same block solver");
+    if (route == FDE_BLOCKS_HESSENBERG && h->m > hess_reduce_max_m())
+      return fail(FDE_EUNSUPPORTED, "the Hessenberg route takes m <= %d (m = %d)", hess_reduce_max_m(), h->m);
+  }
+  for (fde_bvm *h : P->hs) {
+    h->pc = FDE_PC_STRANG;
+    if (h->blk_route != route && h->self) h->self->desc_dirty = true;
+    h->blk_route = route;
+    if (route == FDE_BLOCKS_HESSENBERG) STCHK(hess_alloc(h));
+  }
   const size_t esz = prec == FDE_FP64 ? sizeof(double2) : sizeof(float2);
   for (fde_bvm *h : P->hs) {
     const size_t Kb = (size_t)h->nb * h->mp * h->mp * esz;
@@ -1309,11 +1399,20 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipMemsetAsync(P->d_flag, 0, sizeof(int), L->stream));
   HIPCHK(hipEventRecord(e0, L->stream));
-  STCHK(prec == FDE_FP64 ? factor_plan_impl<double>(P) : factor_plan_impl<float>(P));
+  if (route == FDE_BLOCKS_HESSENBERG)
+    STCHK(prec == FDE_FP64 ? hess_factor<double>(P) : hess_factor<float>(P));
+  else
+    STCHK(prec == FDE_FP64 ? factor_plan_impl<double>(P) : factor_plan_impl<float>(P));
   HIPCHK(hipEventRecord(e1, L->stream));
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, L->stream));
+  std::vector<int> herr(P->hs.size(), 0);
+  if (route == FDE_BLOCKS_HESSENBERG)
+    for (size_t i = 0; i < P->hs.size(); ++i)
+      HIPCHK(hipMemcpyAsync(&herr[i], P->hs[i]->hwk.err, sizeof(int), hipMemcpyDeviceToHost, L->stream));
   STCHK(sync_and_flush(L));
+  for (size_t i = 0; i < herr.size(); ++i)
+    if (herr[i]) return fail(FDE_EDEVICE, "the Hessenberg reduction of instance %zu did not complete", i);
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   L->evpool.push_back(e0);
@@ -1340,8 +1439,11 @@ extern "C" fde_status fde_precond_factor(fde_bvm *h, fde_precision prec) {
 static fde_status ensure_full_maps(Plan *P) {
   const int count = (int)P->hs.size();
   const int prec = P->hs[0]->prec;
-  if (P->full_ok && P->full.prec == prec && P->full.pc == P->hs[0]->pc) return FDE_OK;
-  std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count);
+  if (P->full_ok && P->full.prec == prec && P->full.pc == P->hs[0]->pc &&
+      P->full.route == P->hs[0]->blk_route)
+    return FDE_OK;
+  std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count),
+      qq(count);
   SolveMaps S;
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
@@ -1356,15 +1458,19 @@ static fde_status ensure_full_maps(Plan *P) {
     S.max_log2L = std::max(S.max_log2L, h->log2L);
     S.max_log2s = std::max(S.max_log2s, h->log2s);
     S.max_mp = std::max(S.max_mp, h->mp);
+    qq[q] = qgemm_items(h->nb, h->mp);
     const double esz = h->prec == FDE_FP64 ? 16.0 : 8.0;
-    S.trsv_bytes += (double)h->nb * h->m * h->m * esz + 32.0 * h->nb * h->m;
+    const double fac = h->blk_route == FDE_BLOCKS_HESSENBERG ? 0.5 * h->m * (h->m + 1.0)
+                                                             : (double)h->m * h->m;
+    S.trsv_bytes += (double)h->nb * fac * esz + 32.0 * h->nb * h->m;
+    S.qg_bytes += 8.0 * h->m * h->m + 32.0 * h->nb * h->m;  // Q once, X in and Y out
     S.vec_bytes += 8.0 * h->n();
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
     S.bccb_bytes += 32.0 * h->nb * h->m;  // one complex read and write per (frequency, node)
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
                                    make_map(slots, d), make_map(slots, e), make_map(slots, f),
-                                   make_map(slots, g)};
+                                   make_map(slots, g), make_map(slots, qq)};
   size_t need = 0;
   for (const HostMap &m : hm) need += m.ids.size() + m.pre.size();
   HIPCHK(hipStreamSynchronize(P->lead->stream));
@@ -1401,7 +1507,10 @@ static fde_status ensure_full_maps(Plan *P) {
   S.ju0 = dm[5];
   S.blk = dm[6];
   S.n_blk = hm[6].items;
+  S.qg = dm[7];
+  S.n_qg = hm[7].items;
   S.pc = P->hs[0]->pc;
+  S.route = P->hs[0]->blk_route;
   S.n_mv = hm[0].items;
   S.n_tfft = hm[1].items;
   S.n_trsv = hm[2].items;
@@ -1453,6 +1562,25 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
   HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
     return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st, ctr, P->d_epoch);
   }));
+  if (S.route == FDE_BLOCKS_HESSENBERG) {
+    // Q^T v_k, the row exchanges and eliminations, U^{-1}, then Q (the frequency vectors are
+    // rows, so Q^T v_k is the row v_k^T Q)
+    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
+    HIPCHK(run(L, "hess_lsolve", S.bccb_bytes, [&] {
+      return launch_hess_lsolve(P->d_desc, S.blk, S.n_blk, S.max_mp, st);
+    }));
+    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
+      if (!g_coop_ok) return hipErrorNotSupported;
+      return S.prec == FDE_FP64
+                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1)
+                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1);
+    }));
+    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
+    HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
+      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
+    }));
+    return FDE_OK;
+  }
   HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
     hipError_t e = hipErrorNotSupported;
     if (g_coop_ok) {
@@ -2103,6 +2231,19 @@ extern "C" fde_status fde_toeplitz_apply(fde_bvm *h, const double *x, double *y,
   }));
   STCHK(copy_out(h, y, h->d_tmp, cnt, mem_space));
   return sync_and_flush(h);
+}
+
+extern "C" fde_status fde_get_hessenberg(fde_bvm *h, double *H, double *Q) {
+  if (!h || !H || !Q) return fail(FDE_EINVAL, "NULL argument");
+  if (h->prec < 0 || h->blk_route != FDE_BLOCKS_HESSENBERG || !h->d_hH)
+    return fail(FDE_EINVAL, "no Hessenberg factorization stored");
+  const size_t m = h->m, mp = h->mp;
+  HIPCHK(hipMemcpy2DAsync(H, m * sizeof(double), h->d_hH, mp * sizeof(double), m * sizeof(double), m,
+                          hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpy2DAsync(Q, m * sizeof(double), h->d_hQ, mp * sizeof(double), m * sizeof(double), m,
+                          hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FDE_OK;
 }
 
 extern "C" fde_status fde_get_factor_block(fde_bvm *h, int k, double *out) {

@@ -18,6 +18,7 @@ _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
 _PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED,
        "none": N.FDE_PC_NONE}
 _SIDE = {"right": N.FDE_SIDE_RIGHT, "left": N.FDE_SIDE_LEFT}
+_BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG}
 
 
 def _is_torch_cuda(x) -> bool:
@@ -113,9 +114,15 @@ class BvmSolver:
         N.check(N.lib().fde_set_stream(self._h, C.c_void_p(ptr or 0)))
 
     # ---- the three calls
-    def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None):
+    def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None,
+               blocks: Optional[str] = None):
         """Build the preconditioner: "strang" (block LUs), "bccb" or "bccb_shifted" (2-D DFT),
-        or "none"."""
+        or "none".  blocks: "lu" or "hessenberg" (how the blocks of "strang" are factored);
+        None keeps the handle's setting."""
+        if blocks is not None:
+            kind = _BLOCKS[blocks]
+            if self.get_option(N.FDE_OPT_BLOCKS) != kind:
+                self.set_option(N.FDE_OPT_BLOCKS, kind)
         if preconditioner is not None:
             kind = _PC[preconditioner]
             if self.get_option(N.FDE_OPT_PRECOND) != kind:
@@ -208,6 +215,13 @@ class BvmSolver:
         N.check(N.lib().fde_time_rfft(self._h, C.c_void_p(v.ctypes.data),
                                        C.c_void_p(out.ctypes.data), N.FDE_MEM_HOST))
         return out
+
+    def hessenberg(self):
+        """(H, Q) of J = Q H Q^T from a FDE_BLOCKS_HESSENBERG factorization."""
+        H = np.empty((self.m, self.m))
+        Q = np.empty((self.m, self.m))
+        N.check(N.lib().fde_get_hessenberg(self._h, C.c_void_p(H.ctypes.data), C.c_void_p(Q.ctypes.data)))
+        return H, Q
 
     def factor_block(self, k: int) -> np.ndarray:
         out = np.empty((self.m, self.m), dtype=np.complex128)

@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "ex41"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-hessenberg", action="store_true",
+                    help="skip the solves with the blocks factored through a Hessenberg form of J")
     ap.add_argument("--no-bccb", action="store_true",
                     help="skip the BCCB-preconditioned solves reported beside the main one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -143,7 +145,8 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
-              "time_irfft", "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot"):
+              "time_irfft", "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot",
+              "hess_reduce", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
             prof[k] = q
@@ -158,6 +161,12 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
     name, q = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = q["total_ms"] / q["count"]
     traffic = measured_traffic(workload_name, prec, name)
+    if name.startswith("hess_"):  # the Hessenberg reduction / shifted LUs: latency-bound flops
+        achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 4),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+                "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
+                "work_per_launch": q["work"] / q["count"]}
     if name.startswith("lu_"):
         achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
         peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
@@ -356,6 +365,7 @@ def main():
     import numpy as np
     import torch
     from paper_1305_6653_amd import BvmSolver, autotune_report
+    from paper_1305_6653_amd import _native as N
 
     p, prec = workload(args.workload)
     dev = torch.device("cuda:0")
@@ -397,6 +407,24 @@ def main():
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
+    if not args.no_hessenberg and prec == "fp64":
+        # the same preconditioner S with its blocks through one Hessenberg form of J
+        result["hessenberg"] = {}
+        for form in ("fp64", "mixed"):
+            S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_HESSENBERG)
+            ms4, _, infos4, prof4 = timed_steps(S, u0, f, out, form, args.steps, args.warmup)
+            u4 = out.cpu().numpy()
+            result["hessenberg"][form] = {
+                "ms_per_step": round(ms4, 4), "value": round(1000.0 / ms4, 4),
+                "iters": infos4[-1]["iters"], "true_relres": infos4[-1]["true_relres"],
+                "t_factor_ms": round(infos4[-1]["t_factor_ms"], 3),
+                "t_solve_ms": round(infos4[-1]["t_solve_ms"], 3),
+                "rel_diff_vs_lu": float(np.linalg.norm(u4 - u_main) / np.linalg.norm(u_main)),
+                "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4),
+                                "count": v["count"] // args.steps} for k, v in prof4.items()},
+                "roofline": roofline(prof4, form, None, read_peak),
+            }
+        S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_LU)
     if not args.no_bccb and prec == "fp64":
         # the paper's other preconditioners on the same system (Section 3.1): S2 = s(A) x I -
         # tau s(B) x s(J) and its shifted form, each a 2-D FFT diagonal solve per iteration

@@ -11,14 +11,14 @@
 //
 // Kernels:
 //   k_hess_reduce  cooperative; the columns of J live in registers across the grid
-//                  (workgroup g owns columns g, g+G, ...; thread t rows t, t+256, ...).  Step k:
-//                  the owner of column k builds the Householder vector v (x = A[k+1:, k],
-//                  alpha = -sign(x_0)|x|, v = x - alpha e_1, beta = 2 / v^T v) and publishes it;
-//                  every workgroup applies the left reflection to its columns (column sums are
-//                  local), forms partial sums of A v and Q v over its columns; a grid barrier;
-//                  each workgroup reduces a slice of rows; a grid barrier; every workgroup
-//                  applies A -= beta (A v) v^T and Q -= beta (Q v) v^T (Q accumulates
-//                  P_0 P_1 ... so that H = Q^T J Q).  Writes H, Q and Q^T.
+//                  (workgroup g owns columns g, g+G, ...; thread t rows t, t+512).  Step k:
+//                  with the Householder vector v of column k (x = A[k+1:, k], alpha =
+//                  -sign(x_0)|x|, v = x - alpha e_1, beta = 2 / v^T v), every workgroup applies
+//                  the left reflection to its columns (column sums are local) and forms partial
+//                  sums of A v and Q v over its columns; a grid barrier; each workgroup reduces
+//                  a slice of rows; a grid barrier; every workgroup applies A -= beta (A v) v^T
+//                  and Q -= beta (Q v) v^T (Q accumulates P_0 P_1 ... so that H = Q^T J Q) and
+//                  computes the next v itself from a snapshot of column k+1.  Writes H, Q, Q^T.
 //   k_hess_lu      one workgroup per block: the pivoted elimination, U rows into the factor
 //                  storage (row i of U is final after step i), multipliers and exchanges.
 //   k_hess_lsolve  the exchanges and eliminations replayed on a right-hand side (a serial
@@ -33,8 +33,8 @@
 
 namespace fde {
 
-static constexpr int HR_NT = 256;
-static constexpr int HR_CPW = 4;  // columns per workgroup
+static constexpr int HR_NT = 512;
+static constexpr int HR_CPW = 8;  // columns per workgroup
 static constexpr int HR_SPIN_MAX = 1 << 21;
 
 __device__ __forceinline__ void st_cd(double *p, double v) {
@@ -47,22 +47,31 @@ __device__ __forceinline__ double ld_cd(const double *p) {
       reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
-// Waits (thread 0, bounded) until *word >= target; uniform result: false if abandoned.
-__device__ __forceinline__ bool hr_wait(const unsigned *word, unsigned target, int *err, int *sh) {
-  if (threadIdx.x == 0) {
+// Grid barrier b (b = 1, 2, ... within a launch): workgroup g raises arrive[g] to b, then the
+// first wavefront polls all G entries (one load per lane) until every one has reached b.  No
+// atomic read-modify-write, so arrivals do not serialise.  Every thread's coherent stores
+// complete before its workgroup arrives.  Bounded: after HR_SPIN_MAX polls, or once any
+// workgroup has raised *err, the wait is abandoned (uniform false).
+__device__ __forceinline__ bool hr_barrier(unsigned *arrive, int G, unsigned b, int *err, int *sh) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) __hip_atomic_store(arrive + blockIdx.x, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
-    if (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      for (int it = 0;; ++it) {
-        __builtin_amdgcn_s_sleep(1);
-        if (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-        if (it > HR_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          atomicOr(err, 1);
-          ok = 0;
-          break;
-        }
+    for (int it = 0;; ++it) {
+      bool done = true;
+      for (int q = lane; q < G; q += 64)
+        done = done && __hip_atomic_load(arrive + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
+      if (__all(done)) break;
+      if (it > HR_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (lane == 0) atomicOr(err, 1);
+        ok = 0;
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
-    *sh = ok;
+    if (lane == 0) *sh = ok;
   }
   __syncthreads();
   const bool ok = *sh != 0;
@@ -70,26 +79,18 @@ __device__ __forceinline__ bool hr_wait(const unsigned *word, unsigned target, i
   return ok;
 }
 
-// Grid barrier on a monotone counter: the n-th barrier of a launch waits for n * G arrivals.
-// Every thread's coherent stores complete before its workgroup arrives.
-__device__ __forceinline__ bool hr_barrier(unsigned *ctr, unsigned target, int *err, int *sh) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return hr_wait(ctr, target, err, sh);
-}
-
-// sums of CPW per-thread values over the workgroup (fixed order), result in every thread
-__device__ __forceinline__ void hr_colsum(double (&v)[HR_CPW], double (*red)[HR_CPW]) {
+// Sums over the workgroup of NV per-thread values (fixed order), result in every thread.
+template <int NV>
+__device__ __forceinline__ void hr_sum(double (&v)[NV], double (*red)[HR_CPW]) {
   const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < HR_CPW; ++c) {
+  for (int c = 0; c < NV; ++c) {
     v[c] = wave_sum(v[c]);
     if ((threadIdx.x & 63) == 0) red[w][c] = v[c];
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < HR_CPW; ++c) {
+  for (int c = 0; c < NV; ++c) {
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < HR_NT / 64; ++q) t += red[q][c];
@@ -98,110 +99,103 @@ __device__ __forceinline__ void hr_colsum(double (&v)[HR_CPW], double (*red)[HR_
   __syncthreads();
 }
 
-// Householder vector of column kk, by its owner (workgroup kk % G, register slot kk / G):
-// publishes v (zero in rows <= kk) and beta, sets column kk to (.., alpha, 0, ..), raises the
-// v flag to kk + 1.  With sigma = |x_1..|^2 = 0 no reflection is needed (beta = 0).
+// Householder vector of a column x (this thread's rows in c[]) for step kk: acts on rows
+// >= kk+1; x0 = x[kk+1], sigma = |x[kk+2..]|^2; v = x - alpha e_{kk+1}, alpha = -sign(x0)|x|,
+// beta = 2 / v^T v (beta = 0: nothing to eliminate).  Every workgroup computes it from the same
+// data in the same order, so all hold bitwise-equal copies: vr (own rows) and vl (all rows, LDS).
 template <int RPT>
-__device__ __forceinline__ void hr_make_v(double (&a)[RPT][HR_CPW], int kk, int G, int m, int mp,
-                                          const HessWork &wk, double (*red)[HR_CPW], double *bc) {
-  const int tid = threadIdx.x, cs = kk / G;
-  double sv[HR_CPW];
-#pragma unroll
-  for (int c = 0; c < HR_CPW; ++c) sv[c] = 0.0;
+__device__ __forceinline__ void hr_house(const double (&c)[RPT], int kk, int m, double (&vr)[RPT],
+                                         double *vl, double (*red)[HR_CPW], double *bc,
+                                         double &alpha, double &beta) {
+  const int tid = threadIdx.x;
+  double sv[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + HR_NT * r;
-#pragma unroll
-    for (int c = 0; c < HR_CPW; ++c) {
-      if (c != cs) continue;
-      if (i == kk + 1) bc[0] = a[r][c];
-      if (i >= kk + 2 && i < m) sv[0] = fma(a[r][c], a[r][c], sv[0]);
-    }
+    if (i == kk + 1) bc[0] = c[r];
+    if (i >= kk + 2 && i < m) sv[0] = fma(c[r], c[r], sv[0]);
   }
-  hr_colsum(sv, red);  // its barriers also publish bc[0]
+  hr_sum<1>(sv, red);  // its barriers also publish bc[0]
   const double x0 = bc[0], sig = sv[0];
-  double alpha = x0, beta = 0.0, v0 = 1.0;
+  alpha = x0;
+  beta = 0.0;
+  double v0 = 1.0;
   if (sig > 0.0) {
     const double nrm = sqrt(fma(x0, x0, sig));
     alpha = x0 >= 0.0 ? -nrm : nrm;
     v0 = x0 - alpha;
     beta = 1.0 / (alpha * (alpha - x0));
   }
-  double *vb = wk.vbuf + (size_t)(kk & 1) * (mp + 1);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + HR_NT * r;
-    if (i < m) {
-      double vi = 0.0;
-#pragma unroll
-      for (int c = 0; c < HR_CPW; ++c)
-        if (c == cs) vi = (i == kk + 1) ? v0 : (i >= kk + 2 ? a[r][c] : 0.0);
-      st_cd(vb + i, vi);
-      if (beta != 0.0) {
-#pragma unroll
-        for (int c = 0; c < HR_CPW; ++c)
-          if (c == cs && i >= kk + 1) a[r][c] = (i == kk + 1) ? alpha : 0.0;
-      }
-    }
+    vr[r] = (i == kk + 1) ? v0 : ((i >= kk + 2 && i < m) ? c[r] : 0.0);
+    vl[i] = vr[r];
   }
-  if (tid == 0) st_cd(vb + mp, beta);
-  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (tid == 0)
-    __hip_atomic_store(wk.sync + 1, (unsigned)(kk + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workspace of one reduction (HessWork in kernels.hpp): sync = {barrier counter, v flag},
-// vbuf [2][mp + 1] (v, then beta), part [G][2][mp], ybuf [2][mp].
+// Workspace of one reduction (HessWork in kernels.hpp): sync = arrival flags [G], err;
+// vbuf [mp] (the column snapshot), part [G][2][mp], ybuf [2][mp].
+//
+// Step k: (b) left reflection on the columns j >= k+1 (column sums are local), partial sums
+// of A v and Q v over this workgroup's columns, and the owner of column k+1 publishes that
+// column; barrier; (c) each workgroup sums a slice of rows over the workgroups; barrier;
+// (d) right reflection A -= beta (A v) v^T, Q -= beta (Q v) v^T; every workgroup then forms
+// column k+1 after step k from the snapshot and A v, and derives the next Householder vector
+// itself (no wait on the owner).
 template <int RPT>
 __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restrict__ D, int inst,
                                                        HessWork wk, int G) {
   __shared__ double red[HR_NT / 64][HR_CPW];
-  __shared__ int sh;
+  __shared__ double vl[HR_NT * RPT];
   __shared__ double bc[2];
+  __shared__ int sh;
   const InstDesc &d = D[inst];
   const int m = d.m, mp = d.mp, g = blockIdx.x, tid = threadIdx.x;
-  unsigned *ctr = wk.sync, *vflag = wk.sync + 1;
+  unsigned *arrive = wk.sync;
   int *err = wk.err;
-  double a[RPT][HR_CPW], q[RPT][HR_CPW];
+  double a[RPT][HR_CPW], q[RPT][HR_CPW], vr[RPT], col[RPT];
   // J[i][j] = dx^{-alpha} (d+_i g_{i-j+1} + d-_i g_{j-i+1}), g_k = 0 outside 0..m
+  auto jent = [&](int i, int j) -> double {
+    const int k1 = i - j + 1, k2 = j - i + 1;
+    const double gp = (k1 >= 0 && k1 <= m) ? d.g[k1] : 0.0;
+    const double gm = (k2 >= 0 && k2 <= m) ? d.g[k2] : 0.0;
+    return d.scale * (d.dp[i] * gp + d.dm[i] * gm);
+  };
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + HR_NT * r;
 #pragma unroll
     for (int c = 0; c < HR_CPW; ++c) {
       const int j = g + G * c;
-      double v = 0.0;
-      if (i < m && j < m) {
-        const int k1 = i - j + 1, k2 = j - i + 1;
-        const double gp = (k1 >= 0 && k1 <= m) ? d.g[k1] : 0.0;
-        const double gm = (k2 >= 0 && k2 <= m) ? d.g[k2] : 0.0;
-        v = d.scale * (d.dp[i] * gp + d.dm[i] * gm);
-      }
-      a[r][c] = v;
+      a[r][c] = (i < m && j < m) ? jent(i, j) : 0.0;
       q[r][c] = (i == j && i < m) ? 1.0 : 0.0;
     }
+    col[r] = i < m ? jent(i, 0) : 0.0;
   }
   const int nsteps = m - 2;  // steps k = 0 .. m-3
-  const int rpw = (m + G - 1) / G;  // rows reduced per workgroup
+  const int rpw = (m + G - 1) / G;
   unsigned nbar = 0;
-  if (nsteps > 0 && g == 0) hr_make_v<RPT>(a, 0, G, m, mp, wk, red, bc);
-  for (int k = 0; k < nsteps; ++k) {
-    if (!hr_wait(vflag, (unsigned)(k + 1), err, &sh)) return;
-    const double *vb = wk.vbuf + (size_t)(k & 1) * (mp + 1);
-    const double beta = ld_cd(vb + mp);
-    double vr[RPT], vc[HR_CPW];
+  double alpha = 0.0, beta = 0.0;
+  if (nsteps > 0) {
+    hr_house<RPT>(col, 0, m, vr, vl, red, bc, alpha, beta);
+    if (g == 0 && beta != 0.0) {  // column 0 (slot 0 of workgroup 0) becomes (x, alpha, 0, ..)
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + HR_NT * r;
-      vr[r] = i < m ? ld_cd(vb + i) : 0.0;
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + HR_NT * r;
+        if (i >= 1) a[r][0] = (i == 1) ? alpha : 0.0;
+      }
     }
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    double vc[HR_CPW];
 #pragma unroll
     for (int c = 0; c < HR_CPW; ++c) {
       const int j = g + G * c;
-      vc[c] = j < m ? ld_cd(vb + j) : 0.0;
+      vc[c] = j < m ? vl[j] : 0.0;
     }
-    // left reflection on the columns j >= k+1 (column k was set by its owner)
+    // (b) left reflection on the columns j >= k+1
     double w[HR_CPW];
 #pragma unroll
     for (int c = 0; c < HR_CPW; ++c) {
@@ -210,7 +204,7 @@ __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restric
       for (int r = 0; r < RPT; ++r) t = fma(vr[r], a[r][c], t);
       w[c] = t;
     }
-    hr_colsum(w, red);
+    hr_sum<HR_CPW>(w, red);
 #pragma unroll
     for (int c = 0; c < HR_CPW; ++c) {
       const int j = g + G * c;
@@ -220,8 +214,8 @@ __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restric
         for (int r = 0; r < RPT; ++r) a[r][c] = fma(-bw, vr[r], a[r][c]);
       }
     }
-    // partial sums of A v and Q v over this workgroup's columns (v_j = 0 for j <= k)
     double *pg = wk.part + (size_t)g * 2 * mp;
+    const int own1 = (k + 1) % G == g && k + 1 < nsteps, cs1 = (k + 1) / G;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = tid + HR_NT * r;
@@ -231,13 +225,14 @@ __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restric
         for (int c = 0; c < HR_CPW; ++c) {
           pa = fma(a[r][c], vc[c], pa);
           pq = fma(q[r][c], vc[c], pq);
+          if (own1 && c == cs1) st_cd(wk.vbuf + i, a[r][c]);  // snapshot of column k+1
         }
         st_cd(pg + i, pa);
         st_cd(pg + mp + i, pq);
       }
     }
-    if (!hr_barrier(ctr, (unsigned)G * ++nbar, err, &sh)) return;
-    // rows g*rpw .. : y = A v, z = Q v summed over the workgroups in index order
+    if (!hr_barrier(arrive, G, ++nbar, err, &sh)) return;
+    // (c) rows g*rpw ..: y = A v, z = Q v summed over the workgroups in index order
     {
       const int wv = tid >> 6, lane = tid & 63;
       for (int rl = wv; rl < rpw; rl += HR_NT / 64) {
@@ -256,21 +251,37 @@ __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restric
         }
       }
     }
-    if (!hr_barrier(ctr, (unsigned)G * ++nbar, err, &sh)) return;
-    // right reflection: A -= beta (A v) v^T, Q -= beta (Q v) v^T on this workgroup's columns
+    if (!hr_barrier(arrive, G, ++nbar, err, &sh)) return;
+    // (d) right reflection, then the next Householder vector from column k+1
+    const double vk1 = vl[k + 1 < m ? k + 1 : 0];  // v at row k+1 (read before vl is rewritten)
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = tid + HR_NT * r;
+      double by = 0.0;
       if (i < m) {
-        const double by = beta * ld_cd(wk.ybuf + i), bz = beta * ld_cd(wk.ybuf + mp + i);
+        by = beta * ld_cd(wk.ybuf + i);
+        const double bz = beta * ld_cd(wk.ybuf + mp + i);
 #pragma unroll
         for (int c = 0; c < HR_CPW; ++c) {
           a[r][c] = fma(-by, vc[c], a[r][c]);
           q[r][c] = fma(-bz, vc[c], q[r][c]);
         }
       }
+      if (k + 1 < nsteps) col[r] = i < m ? fma(-by, vk1, ld_cd(wk.vbuf + i)) : 0.0;
     }
-    if (k + 1 < nsteps && (k + 1) % G == g) hr_make_v<RPT>(a, k + 1, G, m, mp, wk, red, bc);
+    if (k + 1 < nsteps) {
+      __syncthreads();  // every thread has read vl (vc, vk1) before it is rewritten
+      hr_house<RPT>(col, k + 1, m, vr, vl, red, bc, alpha, beta);
+      if (own1 && beta != 0.0) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + HR_NT * r;
+#pragma unroll
+          for (int c = 0; c < HR_CPW; ++c)
+            if (c == cs1 && i >= k + 2) a[r][c] = (i == k + 2) ? alpha : 0.0;
+        }
+      }
+    }
   }
   // H, Q and Q^T, row-major with leading dimension mp
 #pragma unroll
@@ -288,24 +299,22 @@ __global__ __launch_bounds__(HR_NT) void k_hess_reduce(const InstDesc *__restric
   }
 }
 
-__global__ void k_hess_init(HessWork wk) {
-  if (threadIdx.x == 0) {
-    wk.sync[0] = 0u;
-    wk.sync[1] = 0u;
-    *wk.err = 0;
-  }
+// arrival flags and the error word (G + 1 words)
+__global__ void k_hess_init(HessWork wk, int G) {
+  for (int i = threadIdx.x; i < G; i += blockDim.x) wk.sync[i] = 0u;
+  if (threadIdx.x == 0) *wk.err = 0;
 }
 
 int hess_reduce_groups(int m) { return (m + HR_CPW - 1) / HR_CPW; }
 
 static int hess_rpt(int m) {
   const int r = (m + HR_NT - 1) / HR_NT;
-  return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 0;
+  return r <= 1 ? 1 : r <= 2 ? 2 : 0;
 }
 
-// Up to four rows per thread: with eight the register file holds one workgroup per CU, fewer
-// than the m/4 workgroups a cooperative launch would need.
-int hess_reduce_max_m() { return 4 * HR_NT; }
+// Up to two rows per thread (m <= 1024): the register-resident columns then keep two
+// workgroups per CU, more than the m/8 workgroups the cooperative launch needs.
+int hess_reduce_max_m() { return 2 * HR_NT; }
 
 template <int RPT>
 static hipError_t hess_launch(const InstDesc *D, int inst, const HessWork &wk, int G, hipStream_t st) {
@@ -323,13 +332,12 @@ static hipError_t hess_launch(const InstDesc *D, int inst, const HessWork &wk, i
 
 hipError_t launch_hess_reduce(const InstDesc *D, int inst, int m, const HessWork &wk, hipStream_t st) {
   const int G = hess_reduce_groups(m);
-  hipLaunchKernelGGL(k_hess_init, dim3(1), dim3(64), 0, st, wk);
+  hipLaunchKernelGGL(k_hess_init, dim3(1), dim3(256), 0, st, wk, G);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (hess_rpt(m)) {
     case 1: return hess_launch<1>(D, inst, wk, G, st);
     case 2: return hess_launch<2>(D, inst, wk, G, st);
-    case 4: return hess_launch<4>(D, inst, wk, G, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -450,22 +458,34 @@ hipError_t launch_hess_lu(const InstDesc *D, const ItemMap &map, int items, int 
 }
 
 // ------------------------------------------------------------------------------------
-// Row exchanges and eliminations of the shifted Hessenberg LU applied to y (in place on
-// Vts row k): a serial chain per block, run by one lane from LDS copies.
+// Row exchanges and eliminations of the shifted Hessenberg LU applied to y (in place on Vts
+// row k).  Step i maps the carried value c (current entry i) to
+//   no exchange: out_i = c,       c' = y_{i+1} - l_i c      (c' = -l_i c + y_{i+1})
+//   exchange:    out_i = y_{i+1}, c' = c - l_i y_{i+1}      (c' =  1  c - l_i y_{i+1})
+// an affine recurrence c' = A_i c + B_i with |A_i| <= 1.  One wavefront per block: lane t
+// composes the maps of its segment of steps, an inclusive scan over the lanes (shuffles)
+// gives every segment its incoming carry, and each lane replays its segment.
 static constexpr int LS_NT = 64;
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 shfl_up2(double2 v, int o) {
+  return make_double2(__shfl_up(v.x, o, 64), __shfl_up(v.y, o, 64));
+}
 
 __global__ __launch_bounds__(LS_NT) void k_hess_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
   extern __shared__ double2 lsm[];
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
-  const int blk = blockIdx.x - map.pre[q], m = d.m, mp = d.mp;
+  const int blk = blockIdx.x - map.pre[q], m = d.m, mp = d.mp, lane = threadIdx.x;
   double2 *z = lsm, *ll = lsm + mp;
   int *pp = reinterpret_cast<int *>(lsm + 2 * mp);
   double2 *v = d.Vts + (size_t)blk * mp;
   const double2 *lo = d.hl + (size_t)blk * mp;
   const int *pivo = d.hpiv + (size_t)blk * mp;
-  for (int i = threadIdx.x; i < m; i += LS_NT) {
+  for (int i = lane; i < m; i += LS_NT) {
     z[i] = v[i];
     if (i + 1 < m) {
       ll[i] = lo[i];
@@ -473,17 +493,46 @@ __global__ __launch_bounds__(LS_NT) void k_hess_lsolve(const InstDesc *__restric
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double2 carry = z[0];
-    for (int i = 0; i + 1 < m; ++i) {
-      const double2 nx = z[i + 1], l = ll[i];
-      const bool sw = pp[i] != 0;
-      const double2 out = sw ? nx : carry, oth = sw ? carry : nx;
-      carry = make_double2(oth.x - (l.x * out.x - l.y * out.y), oth.y - (l.x * out.y + l.y * out.x));
-      v[i] = out;
+  const int nst = m - 1;  // steps 0 .. m-2
+  const int seg = (nst + LS_NT - 1) / LS_NT;
+  const int i0 = lane * seg, i1 = i0 + seg < nst ? i0 + seg : nst;
+  // (A, B) of this lane's segment: c_out = A c_in + B
+  double2 A = make_double2(1.0, 0.0), B = make_double2(0.0, 0.0);
+  for (int i = i0; i < i1; ++i) {
+    const double2 l = ll[i], y = z[i + 1];
+    if (pp[i]) {
+      B = make_double2(B.x - (l.x * y.x - l.y * y.y), B.y - (l.x * y.y + l.y * y.x));
+    } else {
+      const double2 nl = make_double2(-l.x, -l.y);
+      A = cm(nl, A);
+      B = make_double2(fma(nl.x, B.x, fma(-nl.y, B.y, y.x)), fma(nl.x, B.y, fma(nl.y, B.x, y.y)));
     }
-    v[m - 1] = carry;
   }
+  // inclusive scan of the maps over the lanes: lane t ends with segments 0..t composed
+#pragma unroll
+  for (int o = 1; o < LS_NT; o <<= 1) {
+    const double2 Ap = shfl_up2(A, o), Bp = shfl_up2(B, o);
+    if (lane >= o) {  // (A, B) after (Ap, Bp): c -> A (Ap c + Bp) + B
+      const double2 AB = cm(A, Bp);
+      B = make_double2(AB.x + B.x, AB.y + B.y);
+      A = cm(A, Ap);
+    }
+  }
+  const double2 z0 = z[0];
+  const double2 endc = make_double2(A.x * z0.x - A.y * z0.y + B.x, A.x * z0.y + A.y * z0.x + B.y);
+  double2 c = shfl_up2(endc, 1);
+  if (lane == 0) c = z0;
+  __syncthreads();  // every lane has read z[0] and its segment's inputs
+  // replay: out_i into a register list first (z[i + 1] of this segment is still needed)
+  for (int i = i0; i < i1; ++i) {
+    const double2 l = ll[i], y = z[i + 1];
+    const bool sw = pp[i] != 0;
+    const double2 out = sw ? y : c, oth = sw ? c : y;
+    c = make_double2(oth.x - (l.x * out.x - l.y * out.y), oth.y - (l.x * out.y + l.y * out.x));
+    v[i] = out;
+  }
+  if (i0 < i1 && i1 == nst) v[nst] = c;
+  if (nst == 0 && lane == 0) v[0] = z0;
 }
 
 hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, int max_mp,
@@ -502,52 +551,104 @@ hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, 
 // ------------------------------------------------------------------------------------
 // Y[k][j] = sum_{i<m} X[k][i] B[i][j] with B = Q (trans = 0) or Q^T (trans = 1), both stored
 // row-major with leading dimension mp; X, Y are [nb][mp] complex; Y[k][j] = 0 for j >= m.
-// Workgroup tile 32 (k) x 32 (j); wave w owns the 16x16 sub-tile (w / 2, w % 2) for the real
-// and the imaginary part (two MFMA accumulators sharing the B operand).  Item = (instance,
-// row tile, column tile).
+// Workgroup tile 32 (k) x 32 (j), split over K: wave w accumulates the whole tile (2 x 2 MFMA
+// 16x16 tiles, real and imaginary parts sharing the B operand) over the w-th quarter of K,
+// with the operands of four K-steps loaded ahead; the four partial tiles are summed through
+// LDS in wave order.  Item = (instance, row tile, column tile).
 static constexpr int QG_T = 32;
 
 __global__ __launch_bounds__(256) void k_qgemm(const InstDesc *__restrict__ Dd, ItemMap map,
                                                int trans, int src2) {
+  __shared__ v4d part[3][8][64];
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int local = blockIdx.x - map.pre[q];
   const int m = d.m, mp = d.mp, nb = d.nb;
-  const int ncol = mp / QG_T;
-  const int rt = local / ncol, ct = local % ncol;
+  const int ncol = mp / QG_T, nrow = (nb + QG_T - 1) / QG_T;
+  // consecutive workgroups go to different XCDs: give XCD x the column tiles ct = x mod 8, so
+  // each XCD's L2 holds an eighth of B (when the column tiles split evenly)
+  int rt, ct;
+  if (ncol % 8 == 0) {
+    const int x = local % 8, r = local / 8;
+    ct = x + 8 * (r / nrow);
+    rt = r % nrow;
+  } else {
+    rt = local / ncol;
+    ct = local % ncol;
+  }
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = rt * QG_T + 16 * (wv >> 1), c0 = ct * QG_T + 16 * (wv & 1);
+  const int r0 = rt * QG_T, c0 = ct * QG_T;
   const double2 *X = src2 ? d.Vts : d.Vh;
   double2 *Y = src2 ? d.Vh : d.Vts;
   const double *B = trans ? d.hQt : d.hQ;
   const int li = lane & 15, lk = lane >> 4;
-  const int arow = r0 + li;  // A operand row of this lane
-  const int bcol = c0 + li;  // B operand column of this lane
-  const bool arow_ok = arow < nb;
-  v4d cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
-  const double2 *Xr = X + (size_t)(arow_ok ? arow : 0) * mp;
-  for (int k0 = 0; k0 < m; k0 += 16) {
-    double2 xa[4];
-    double bb[4];
+  const int ar0 = r0 + li, ar1 = r0 + 16 + li;  // A rows of this lane (two 16-row halves)
+  const int bc0 = c0 + li, bc1 = c0 + 16 + li;  // B columns of this lane
+  const bool a0ok = ar0 < nb, a1ok = ar1 < nb, b0ok = bc0 < m, b1ok = bc1 < m;
+  const double2 *X0 = X + (size_t)(a0ok ? ar0 : 0) * mp, *X1 = X + (size_t)(a1ok ? ar1 : 0) * mp;
+  v4d acc[8];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = k0 + 4 * s + lk;
-      xa[s] = (arow_ok && kk < m) ? Xr[kk] : make_double2(0.0, 0.0);
-      bb[s] = (kk < m && bcol < m) ? B[(size_t)kk * mp + bcol] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      cre = mfma16(xa[s].x, bb[s], cre);
-      cim = mfma16(xa[s].y, bb[s], cim);
-    }
+  for (int t = 0; t < 8; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  // this wave's K range; 16 K values per operand set, two sets in flight (loaded one set
+  // ahead of the MFMAs that use the other)
+  const int kq = ((m + 63) / 64) * 16;
+  const int kb = wv * kq, ke = kb + kq < m ? kb + kq : m;
+  double2 pa0[4], pa1[4], qa0[4], qa1[4];
+  double pb0[4], pb1[4], qb0[4], qb1[4];
+#define QG_LOAD(A0, A1, B0, B1, K0)                                               \
+  _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                             \
+    const int kk = (K0) + 4 * s4 + lk;                                           \
+    const bool kok = kk < ke;                                                    \
+    A0[s4] = (kok && a0ok) ? X0[kk] : make_double2(0.0, 0.0);                    \
+    A1[s4] = (kok && a1ok) ? X1[kk] : make_double2(0.0, 0.0);                    \
+    B0[s4] = (kok && b0ok) ? B[(size_t)kk * mp + bc0] : 0.0;                     \
+    B1[s4] = (kok && b1ok) ? B[(size_t)kk * mp + bc1] : 0.0;                     \
   }
-  // D element v of this lane: row lk + 4v, column li (FP64 layout)
+#define QG_MMA(A0, A1, B0, B1)                                                    \
+  _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                             \
+    acc[0] = mfma16(A0[s4].x, B0[s4], acc[0]);                                   \
+    acc[1] = mfma16(A0[s4].y, B0[s4], acc[1]);                                   \
+    acc[2] = mfma16(A0[s4].x, B1[s4], acc[2]);                                   \
+    acc[3] = mfma16(A0[s4].y, B1[s4], acc[3]);                                   \
+    acc[4] = mfma16(A1[s4].x, B0[s4], acc[4]);                                   \
+    acc[5] = mfma16(A1[s4].y, B0[s4], acc[5]);                                   \
+    acc[6] = mfma16(A1[s4].x, B1[s4], acc[6]);                                   \
+    acc[7] = mfma16(A1[s4].y, B1[s4], acc[7]);                                   \
+  }
+  QG_LOAD(pa0, pa1, pb0, pb1, kb)
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    QG_LOAD(qa0, qa1, qb0, qb1, k0 + 16)
+    QG_MMA(pa0, pa1, pb0, pb1)
+    QG_LOAD(pa0, pa1, pb0, pb1, k0 + 32)
+    QG_MMA(qa0, qa1, qb0, qb1)
+  }
+#undef QG_LOAD
+#undef QG_MMA
+  if (wv > 0) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = r0 + mfma_row<double>(lk, v), col = c0 + li;
-    if (row < nb && col < mp)
-      Y[(size_t)row * mp + col] = col < m ? make_double2(cre[v], cim[v]) : make_double2(0.0, 0.0);
+    for (int t = 0; t < 8; ++t) part[wv - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int w = 0; w < 3; ++w) acc[t] += part[w][t][lane];
+    // acc[2*(2h + c) + p]: row half h, column half c, real (p = 0) or imaginary part; element v
+    // of this lane is row lk + 4v, column li of the 16x16 tile (FP64 layout)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 16 * h + mfma_row<double>(lk, v), col = c0 + 16 * c + li;
+          if (row < nb && col < mp) {
+            const v4d re = acc[2 * (2 * h + c)], im = acc[2 * (2 * h + c) + 1];
+            Y[(size_t)row * mp + col] = col < m ? make_double2(re[v], im[v]) : make_double2(0.0, 0.0);
+          }
+        }
   }
 }
 

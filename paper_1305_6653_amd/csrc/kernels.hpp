@@ -100,8 +100,8 @@ hipError_t launch_gm_backsolve(const InstDesc *D, GmresCtl *ctl, GmresWork *work
 
 // ---- Hessenberg route to the blocks (k_hessenberg.hip) ----
 // Workspace of one reduction of an instance of order m (mp padded, G workgroups):
-// sync [2], err [1], vbuf [2][mp+1], part [G][2][mp], ybuf [2][mp]; outputs H, Q, Q^T
-// [m][mp] row-major.
+// sync [G] (arrival flags), err [1], vbuf [mp] (column snapshot), part [G][2][mp],
+// ybuf [2][mp]; outputs H, Q, Q^T [m][mp] row-major.
 struct HessWork {
   unsigned *sync;
   int *err;

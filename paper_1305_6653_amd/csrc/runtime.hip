@@ -1321,9 +1321,9 @@ static fde_status hess_alloc(fde_bvm *h) {
   STCHK(dalloc_t(h, &h->d_Vh2, nb * mp));
   HIPCHK(hipMemsetAsync(h->d_Vh2, 0, nb * mp * sizeof(double2), h->stream));
   HessWork &w = h->hwk;
-  STCHK(dalloc_t(h, &w.sync, 4));
-  w.err = (int *)(w.sync + 2);
-  STCHK(dalloc_t(h, &w.vbuf, 2 * (mp + 1)));
+  STCHK(dalloc_t(h, &w.sync, G + 4));
+  w.err = (int *)(w.sync + G);
+  STCHK(dalloc_t(h, &w.vbuf, mp));
   STCHK(dalloc_t(h, &w.part, G * 2 * mp));
   STCHK(dalloc_t(h, &w.ybuf, 2 * mp));
   w.H = h->d_hH;

@@ -146,7 +146,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
               "time_irfft", "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot",
-              "hess_reduce", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
+              "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
             prof[k] = q

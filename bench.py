@@ -36,7 +36,6 @@ PMC_TRAFFIC = {
     ("c2", "fp64", "lu_diag"): 6.7539e+07,
     ("c2", "fp64", "lu_panel"): 7.4818e+08,
     ("c2", "fp64", "lu_update"): 3.3665e+09,
-    ("c2", "fp64", "mgs"): 1.5956e+07,
     ("c2", "fp64", "time_irfft"): 9.2600e+06,
     ("c2", "fp64", "time_rfft"): 1.2419e+07,
     ("c2", "fp64", "trsv"): 4.6746e+09,
@@ -145,7 +144,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
-              "time_irfft", "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot",
+              "time_irfft", "bvm_matvec", "cgs", "cgs_sum", "normalize", "residual", "update_x", "rhs", "dot",
               "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
@@ -246,7 +245,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "time_rfft", "time_irfft",
-              "bvm_matvec", "mgs", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
+              "bvm_matvec", "cgs", "cgs_sum", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
         q = lead.profile_query(k)
         if q["count"]:
             prof[k] = q
@@ -439,7 +438,7 @@ def main():
                 "rel_diff_vs_strang": float(np.linalg.norm(u3 - u_main) / np.linalg.norm(u_main)),
                 "kernels": {k: {"total_ms": round(v["total_ms"] / max(1, args.steps // 2), 4),
                                 "avg_us": round(1e3 * v["total_ms"] / v["count"], 2)}
-                            for k, v in prof3.items() if k in ("bccb_solve", "bvm_matvec", "mgs",
+                            for k, v in prof3.items() if k in ("bccb_solve", "bvm_matvec", "cgs",
                                                                "time_rfft", "time_irfft")},
                 "bccb_solve_GBs": round(prof3["bccb_solve"]["work"]
                                         / (prof3["bccb_solve"]["total_ms"] * 1e-3) / 1e9, 1)

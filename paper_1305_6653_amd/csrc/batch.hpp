@@ -45,7 +45,9 @@ struct InstDesc {
   double *u0, *f, *Ju0;       // [m], [s+1][m], [m]
   double2 *Vh;                // [nb][mp]
   double *part0, *part1;      // [nblk] reduction partials
+  double *partm;              // [R+1][nblk] partials of the Gram-Schmidt projections
   double *H, *y, *nrm;        // Hessenberg column [R+2], LSQ solution [R], norms [2]
+  double *h2;                 // [R+2] second Gram-Schmidt pass of the current column
 };
 
 // vector selectors resolved on the device

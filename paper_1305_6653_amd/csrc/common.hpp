@@ -83,6 +83,34 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
   return v;
 }
 
+// 64-lane sum with DPP lane permutes instead of LDS shuffles: butterflies inside each 16-lane
+// row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], half-row mirror, row mirror leave the row sum
+// in every lane of the row), then the four row sums in row order (fixed order; result valid
+// in every lane).  Needs all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)(b & 0xffffffff), hi = (int)(b >> 32);
+  double r = 0.0;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const long long x = ((long long)__builtin_amdgcn_readlane(hi, 16 * row) << 32) |
+                        (unsigned)__builtin_amdgcn_readlane(lo, 16 * row);
+    r += __longlong_as_double(x);
+  }
+  return r;
+}
+
 // Block sum in a fixed order (deterministic): wave tree, then waves in index order.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *red /* >= NT/64 */) {

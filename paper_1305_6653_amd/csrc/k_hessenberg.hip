@@ -79,34 +79,6 @@ __device__ __forceinline__ bool hr_barrier(unsigned *arrive, int G, unsigned b, 
   return ok;
 }
 
-// Sum over a wavefront with DPP lane permutes (no LDS traffic): butterflies inside each
-// 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], half-row mirror, row mirror leave the
-// row sum in every lane of the row), then the four row sums in row order.  A fixed order, so
-// every workgroup gets the same bits from the same inputs.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  const long long b = __double_as_longlong(v);
-  const int lo = (int)(b & 0xffffffff), hi = (int)(b >> 32);
-  double r = 0.0;
-#pragma unroll
-  for (int row = 0; row < 4; ++row) {
-    const long long x = ((long long)__builtin_amdgcn_readlane(hi, 16 * row) << 32) |
-                        (unsigned)__builtin_amdgcn_readlane(lo, 16 * row);
-    r += __longlong_as_double(x);
-  }
-  return r;
-}
-
 // sums of CPW per-thread values over the workgroup (fixed order), result in every thread
 template <int NV>
 __device__ __forceinline__ void hr_sum(double (&v)[NV], double (*red)[HR_CPW]) {

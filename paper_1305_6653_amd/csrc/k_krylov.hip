@@ -1,8 +1,14 @@
 // FP64 Krylov vector kernels for GMRES, batched over instances (item = (instance, chunk)):
-// modified Gram-Schmidt as a chain of launches (launch i subtracts the projection on v_{i-1}
-// and accumulates the dot with v_i, so the MGS order is kept exactly), normalisation,
-// residual, solution update.  Every reduction has a fixed order (chunk partials summed in
-// index order), so results are bitwise reproducible run to run.
+// Gram-Schmidt orthogonalisation of the new Arnoldi vector, normalisation, residual, solution
+// update.  Every reduction has a fixed order (chunk partials summed in index order), so results
+// are bitwise reproducible run to run.
+//
+// Orthogonalisation: classical Gram-Schmidt applied twice (CGS2), h = V^T w, w -= V h, then
+// h' = V^T w, w -= V h', column = h + h'.  In exact arithmetic it equals modified Gram-Schmidt;
+// in floating point the second pass makes the basis orthogonal to working precision, as MGS
+// does for GMRES.  It takes five launches per Arnoldi step whatever j (projection partials, sum,
+// update + second partials, sum, update + norm partial) instead of the j + 2 dependent launches
+// of MGS.
 #include "batch.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -47,36 +53,122 @@ __device__ __forceinline__ Chunk chunk_of(const InstDesc *__restrict__ D, const 
   return c;
 }
 
-// i = 0..j+1.  i > 0: h_{i-1} = <v_{i-1}, w> from the partials of launch i-1; w -= h v_{i-1}.
-// i <= j: partial <v_i, w>;  i == j+1: partial <w, w>.  Launch i reads part[(i+1)&1] and
-// writes part[i&1].
-__global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__ D, ItemMap map,
-                                                    int i, int j) {
-  __shared__ double red[KR_NT / 64];
+// Partial sums over chunk b of V_i . w, i = 0..j, into partm[i][b]: up to 16 dot products per
+// pass accumulated together (w is read once per pass), wave sums by DPP, one barrier per pass.
+static constexpr int CG_G = 16;
+
+__device__ __forceinline__ void cgs_partials(const InstDesc &d, const Chunk &c, int j, double *red) {
+  const double *w = d.w;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i0 = 0; i0 <= j; i0 += CG_G) {
+    const int ng = j + 1 - i0 < CG_G ? j + 1 - i0 : CG_G;
+    double acc[CG_G];
+#pragma unroll
+    for (int t = 0; t < CG_G; ++t) acc[t] = 0.0;
+    for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
+      const double we = w[e];
+#pragma unroll
+      for (int t = 0; t < CG_G; ++t)
+        if (t < ng) acc[t] = fma(d.V[(size_t)(i0 + t) * c.n + e], we, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < CG_G; ++t) {
+      if (t < ng) {
+        const double s = wave_sum_dpp(acc[t]);
+        if (lane == 0) red[wv * CG_G + t] = s;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < ng) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < KR_NT / 64; ++q) s += red[q * CG_G + threadIdx.x];
+      d.partm[(size_t)(i0 + threadIdx.x) * d.nblk + c.b] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(KR_NT) void k_cgs_dot(const InstDesc *__restrict__ D, ItemMap map, int j) {
+  __shared__ double red[(KR_NT / 64) * CG_G];
+  const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
+  cgs_partials(*c.d, c, j, red);
+}
+
+// One workgroup per instance, one wavefront per coefficient: h_i = sum_b partm[i][b] (lanes
+// stride over b, then the DPP wave sum: a fixed order).  pass 0: H[i] = h_i; pass 1:
+// h2[i] = h_i and H[i] += h_i.
+__global__ __launch_bounds__(KR_NT) void k_cgs_sum(const InstDesc *__restrict__ D, ItemMap map, int j,
+                                                   int pass) {
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = D[map.ids[q]];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = wv; i <= j; i += KR_NT / 64) {
+    const double *p = d.partm + (size_t)i * d.nblk;
+    double t = 0.0;
+    for (int b = lane; b < d.nblk; b += 64) t += p[b];
+    const double h = wave_sum_dpp(t);
+    if (lane == 0) {
+      if (pass == 0) {
+        d.H[i] = h;
+      } else {
+        d.h2[i] = h;
+        d.H[i] += h;
+      }
+    }
+  }
+}
+
+// w -= sum_{i<=j} c_i V_i with c = H (pass 0) or h2 (pass 1), in i order for every element;
+// then pass 0: the partials of the second projection V^T w; pass 1: the partial of w . w into
+// part[(j+1) & 1] (read by the normalisation that follows).
+__global__ __launch_bounds__(KR_NT) void k_cgs_update(const InstDesc *__restrict__ D, ItemMap map, int j,
+                                                      int pass) {
+  __shared__ double red[(KR_NT / 64) * CG_G];
+  __shared__ double cf[GM_RMAX + 1];
   const Chunk c = chunk_of(D, map);
   if (!c.d) return;
   const InstDesc &d = *c.d;
-  const double *pin = (i & 1) ? d.part0 : d.part1;
-  double *pout = (i & 1) ? d.part1 : d.part0;
-  double h = 0.0;
-  if (i > 0) {
-    h = sum_partials(pin, d.nblk, red);
-    if (c.b == 0 && threadIdx.x == 0) d.H[i - 1] = h;
-  }
-  const double *vp = d.V + (size_t)(i > 0 ? i - 1 : 0) * c.n;
-  const double *vc = d.V + (size_t)(i <= j ? i : 0) * c.n;
+  const double *co = pass == 0 ? d.H : d.h2;
+  for (int i = threadIdx.x; i <= j; i += KR_NT) cf[i] = co[i];
+  __syncthreads();
   double *w = d.w;
-  double acc = 0.0;
+  double nn = 0.0;
   for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
     double we = w[e];
-    if (i > 0) {
-      we = fma(-h, vp[e], we);
-      w[e] = we;
-    }
-    acc = (i <= j) ? fma(vc[e], we, acc) : fma(we, we, acc);
+    for (int i = 0; i <= j; ++i) we = fma(-cf[i], d.V[(size_t)i * c.n + e], we);
+    w[e] = we;
+    nn = fma(we, we, nn);
   }
-  acc = block_sum<KR_NT>(acc, red);
-  if (threadIdx.x == 0) pout[c.b] = acc;
+  if (pass == 0) {
+    __syncthreads();
+    cgs_partials(d, c, j, red);
+  } else {
+    nn = block_sum<KR_NT>(nn, red);
+    if (threadIdx.x == 0) (((j + 1) & 1) ? d.part1 : d.part0)[c.b] = nn;
+  }
+}
+
+hipError_t launch_cgs_dot(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cgs_dot, dim3(items), dim3(KR_NT), 0, st, D, map, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_sum(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
+                          hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cgs_sum, dim3(items), dim3(KR_NT), 0, st, D, map, j, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_update(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
+                             hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cgs_update, dim3(items), dim3(KR_NT), 0, st, D, map, j, pass);
+  return hipGetLastError();
 }
 
 // nrm = sqrt(sum of part[psel]); dst = src / nrm (0 if nrm == 0).  The norm is stored in
@@ -185,13 +277,6 @@ hipError_t launch_copy(const InstDesc *D, const ItemMap &map, int items, int src
                        int dst_sel, int dst_j, hipStream_t st) {
   if (items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy, dim3(items), dim3(KR_NT), 0, st, D, map, src_sel, src_j, dst_sel, dst_j);
-  return hipGetLastError();
-}
-
-hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
-                           hipStream_t st) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mgs_step, dim3(items), dim3(KR_NT), 0, st, D, map, i, j);
   return hipGetLastError();
 }
 

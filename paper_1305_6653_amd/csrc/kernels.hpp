@@ -68,8 +68,14 @@ int trsv_coop_capacity();
 
 // ---- Krylov BLAS-1 (FP64, deterministic reductions), items = nblk per instance ----
 int krylov_blocks(size_t n);
-hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
-                           hipStream_t st);
+// Arnoldi orthogonalisation by classical Gram-Schmidt twice (k_krylov.hip): partials of V^T w
+// (items = chunks), their sums (items = one per instance, pass 0 -> H, pass 1 -> h2 and H += h2),
+// w -= V c with the next partials (pass 0) or the norm partial (pass 1).
+hipError_t launch_cgs_dot(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st);
+hipError_t launch_cgs_sum(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
+                          hipStream_t st);
+hipError_t launch_cgs_update(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
+                             hipStream_t st);
 hipError_t launch_normalize(const InstDesc *D, const ItemMap &map, int items, int src_sel,
                             int src_j, int dst_sel, int dst_j, int psel, int hidx, hipStream_t st);
 hipError_t launch_residual(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);

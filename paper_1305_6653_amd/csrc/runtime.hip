@@ -323,8 +323,8 @@ struct HostMap {
 
 // Item maps of the solve-phase launches over every instance of a plan.
 struct SolveMaps {
-  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk, qg;
-  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0;
+  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk, qg, one;
+  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0, n_one = 0;
   int pc = 0, route = FDE_BLOCKS_LU;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int prec = -1;
@@ -334,7 +334,7 @@ struct SolveMaps {
 // The same maps with their items skipped for instances whose gate entry is zero.
 static SolveMaps gated(const SolveMaps &S, const int *gate) {
   SolveMaps G = S;
-  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk, &G.qg}) m->gate = gate;
+  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk, &G.qg, &G.one}) m->gate = gate;
   return G;
 }
 
@@ -343,7 +343,7 @@ struct Plan {
   fde_bvm *lead = nullptr;  // stream and profiling owner
   int R = 0;
   InstDesc *d_desc = nullptr;
-  double *d_part = nullptr, *d_H = nullptr, *d_y = nullptr, *d_nrm = nullptr;
+  double *d_part = nullptr, *d_H = nullptr, *d_y = nullptr, *d_nrm = nullptr, *d_h2 = nullptr;
   int *d_err = nullptr, *d_flag = nullptr;
   int *d_arena = nullptr;
   size_t arena_ints = 0;
@@ -590,7 +590,7 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
   const int count = (int)P->hs.size();
   for (fde_bvm *h : P->hs) STCHK(ensure_krylov(h, R));
   if (P->R < R || !P->d_H) {
-    for (void *p : {(void *)P->d_part, (void *)P->d_H, (void *)P->d_y, (void *)P->d_nrm}) {
+    for (void *p : {(void *)P->d_part, (void *)P->d_H, (void *)P->d_y, (void *)P->d_nrm, (void *)P->d_h2}) {
       if (!p) continue;
       auto it = std::find(P->allocs.begin(), P->allocs.end(), p);
       if (it != P->allocs.end()) P->allocs.erase(it);
@@ -598,9 +598,9 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     }
     size_t parts = 0;
     P->part_off.assign(count, 0);
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < count; ++i) {  // part0, part1, then the [R+1][nblk] projection partials
       P->part_off[i] = parts;
-      parts += 2 * (size_t)P->hs[i]->nblk;
+      parts += (size_t)(R + 3) * P->hs[i]->nblk;
     }
     void *p = nullptr;
     STCHK(plan_alloc(P, &p, parts * sizeof(double)));
@@ -611,6 +611,8 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     P->d_y = (double *)p;
     STCHK(plan_alloc(P, &p, (size_t)count * 2 * sizeof(double)));
     P->d_nrm = (double *)p;
+    STCHK(plan_alloc(P, &p, (size_t)count * (R + 2) * sizeof(double)));
+    P->d_h2 = (double *)p;
     P->R = R;
     P->desc_dirty = true;
   }
@@ -622,6 +624,8 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     if (d.W != P->desc[i].W) P->full_ok = false;  // item counts change: new maps, new graphs
     d.part0 = P->d_part + P->part_off[i];
     d.part1 = d.part0 + h->nblk;
+    d.partm = d.part0 + 2 * (size_t)h->nblk;
+    d.h2 = P->d_h2 + (size_t)i * (R + 2);
     d.H = P->d_H + (size_t)i * (R + 2);
     d.y = P->d_y + (size_t)i * (R + 1);
     d.nrm = P->d_nrm + (size_t)i * 2;
@@ -1443,7 +1447,7 @@ static fde_status ensure_full_maps(Plan *P) {
       P->full.route == P->hs[0]->blk_route)
     return FDE_OK;
   std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count),
-      qq(count);
+      qq(count), one(count, 1);
   SolveMaps S;
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
@@ -1470,7 +1474,7 @@ static fde_status ensure_full_maps(Plan *P) {
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
                                    make_map(slots, d), make_map(slots, e), make_map(slots, f),
-                                   make_map(slots, g), make_map(slots, qq)};
+                                   make_map(slots, g), make_map(slots, qq), make_map(slots, one)};
   size_t need = 0;
   for (const HostMap &m : hm) need += m.ids.size() + m.pre.size();
   HIPCHK(hipStreamSynchronize(P->lead->stream));
@@ -1509,6 +1513,8 @@ static fde_status ensure_full_maps(Plan *P) {
   S.n_blk = hm[6].items;
   S.qg = dm[7];
   S.n_qg = hm[7].items;
+  S.one = dm[8];
+  S.n_one = hm[8].items;
   S.pc = P->hs[0]->pc;
   S.route = P->hs[0]->blk_route;
   S.n_mv = hm[0].items;
@@ -1713,8 +1719,9 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // right-hand sides and their norms
   STCHK(op_rhs(P, S));
   HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_B, VS_B, 0, stream); }));
-  size_t nparts = 0;
-  for (fde_bvm *h : P->hs) nparts += 2 * (size_t)h->nblk;
+  // part0 and part1 of the last instance end the range the host sums (each instance's block
+  // also holds its Gram-Schmidt partials after part1)
+  const size_t nparts = P->part_off.back() + 2 * (size_t)P->hs.back()->nblk;
   std::vector<double> parts(nparts);
   HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
   STCHK(sync_and_flush(L));
@@ -1821,10 +1828,15 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
         STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
         STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
       }
-      for (int i = 0; i <= j + 1; ++i) {
-        HIPCHK(run(L, "mgs", (i == 0 ? 2.0 : 4.0) * S.vec_bytes,
-                   [&] { return launch_mgs_step(P->d_desc, Sact.kry, S.n_kry, i, j, stream); }));
-      }
+      // classical Gram-Schmidt twice: V^T w, w -= V h, V^T w, w -= V h', column h + h'
+      HIPCHK(run(L, "cgs", (j + 2.0) * S.vec_bytes,
+                 [&] { return launch_cgs_dot(P->d_desc, Sact.kry, S.n_kry, j, stream); }));
+      HIPCHK(run(L, "cgs_sum", 0.0, [&] { return launch_cgs_sum(P->d_desc, Sact.one, S.n_one, j, 0, stream); }));
+      HIPCHK(run(L, "cgs", (2.0 * j + 5.0) * S.vec_bytes,
+                 [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 0, stream); }));
+      HIPCHK(run(L, "cgs_sum", 0.0, [&] { return launch_cgs_sum(P->d_desc, Sact.one, S.n_one, j, 1, stream); }));
+      HIPCHK(run(L, "cgs", (j + 3.0) * S.vec_bytes,
+                 [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 1, stream); }));
       HIPCHK(run(L, "normalize", 2.0 * S.vec_bytes, [&] {
         return launch_normalize(P->d_desc, Sact.kry, S.n_kry, VS_W, 0, VS_V, j + 1, (j + 1) & 1, j + 1, stream);
       }));

@@ -91,5 +91,6 @@ def test_profile_counts_the_steps_that_ran(graphs):
     u, info = S.solve(p.u0, p.f)
     q = S.profile_query("trsv")
     assert q["count"] == info["iters"] and q["total_ms"] > 0.0
-    assert S.profile_query("mgs")["count"] == sum(j + 2 for j in range(info["iters"]))
+    assert S.profile_query("cgs")["count"] == 3 * info["iters"]       # two Gram-Schmidt passes
+    assert S.profile_query("cgs_sum")["count"] == 2 * info["iters"]
     S.profile(False)

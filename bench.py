@@ -26,43 +26,68 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs),
 # each scaled by the same counter's reading for a plain device-to-device copy of known size.
-# Keyed by (workload, precision, kernel); valid only while the kernel sources hash to
-# PMC_SOURCE_HASH, otherwise "traffic" is reported as null.
-PMC_SOURCE_HASH = "f5e1832effbc822f"
+# Keyed by (workload, precision, kernel).  A figure is valid only while the sources of its
+# kernel's group hash to the value recorded with it; otherwise "traffic" is reported as null.
+PMC_GROUPS = {
+    "factor": ("k_factor.hip", "common.hpp", "batch.hpp"),
+    "spacetime": ("k_spacetime.hip", "fft_lds.hpp", "common.hpp", "batch.hpp"),
+    "krylov": ("k_krylov.hip", "common.hpp", "batch.hpp"),
+    "hessenberg": ("k_hessenberg.hip", "common.hpp", "batch.hpp"),
+}
+PMC_KERNEL_GROUP = {
+    "assemble": "factor", "lu_diag": "factor", "lu_panel": "factor", "lu_update": "factor",
+    "trsv": "factor", "hess_uinv": "factor",
+    "bvm_matvec": "spacetime", "time_rfft": "spacetime", "time_irfft": "spacetime",
+    "bccb_solve": "spacetime", "rhs": "spacetime",
+    "cgs": "krylov", "cgs_sum": "krylov", "normalize": "krylov", "residual": "krylov",
+    "update_x": "krylov", "dot": "krylov",
+    "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
+    "hess_lsolve": "hessenberg",
+}
+PMC_SOURCE_HASH = {"factor": "0a1d6721aae4db63", "spacetime": "f36a8af3e0052fb3", "krylov": "d3ccded5515d4027", "hessenberg": "29d6762cb79270aa"}
 PMC_TRAFFIC = {
     ("c2", "fp64", "assemble"): 4.3131e+09,
     ("c2", "fp64", "bccb_solve"): 9.2170e+06,
     ("c2", "fp64", "bvm_matvec"): 2.1762e+07,
-    ("c2", "fp64", "lu_diag"): 6.7539e+07,
-    ("c2", "fp64", "lu_panel"): 7.4818e+08,
-    ("c2", "fp64", "lu_update"): 3.3665e+09,
+    ("c2", "fp64", "cgs"): 7.3505e+07,
+    ("c2", "fp64", "lu_diag"): 6.7555e+07,
+    ("c2", "fp64", "lu_panel"): 7.4810e+08,
+    ("c2", "fp64", "lu_update"): 3.3657e+09,
     ("c2", "fp64", "time_irfft"): 9.2600e+06,
     ("c2", "fp64", "time_rfft"): 1.2419e+07,
-    ("c2", "fp64", "trsv"): 4.6746e+09,
+    ("c2", "fp64", "trsv"): 4.6745e+09,
     ("c2", "mixed", "assemble"): 2.1569e+09,
-    ("c2", "mixed", "lu_diag"): 3.3784e+07,
-    ("c2", "mixed", "lu_panel"): 3.8826e+08,
-    ("c2", "mixed", "lu_update"): 1.6688e+09,
+    ("c2", "mixed", "lu_diag"): 3.3791e+07,
+    ("c2", "mixed", "lu_panel"): 3.8801e+08,
+    ("c2", "mixed", "lu_update"): 1.6674e+09,
     ("c2", "mixed", "trsv"): 2.3812e+09,
+    ("c2h", "fp64", "hess_lsolve"): 1.3739e+07,
+    ("c2h", "fp64", "hess_lu"): 2.2024e+09,
+    ("c2h", "fp64", "hess_reduce"): 6.8193e+09,
+    ("c2h", "fp64", "hess_uinv"): 4.2124e+08,
+    ("c2h", "fp64", "qgemm"): 5.2827e+07,
+    ("c2h", "fp64", "trsv"): 2.3382e+09,
+    ("c2h", "mixed", "hess_lsolve"): 1.3739e+07,
+    ("c2h", "mixed", "hess_lu"): 1.1254e+09,
+    ("c2h", "mixed", "hess_reduce"): 6.8193e+09,
+    ("c2h", "mixed", "hess_uinv"): 2.1904e+08,
+    ("c2h", "mixed", "qgemm"): 5.2827e+07,
+    ("c2h", "mixed", "trsv"): 1.1907e+09,
 }
 
 
-# the sources of the kernels whose traffic is recorded, and the device headers they include
-PMC_SOURCES = ("k_factor.hip", "k_spacetime.hip", "k_krylov.hip", "common.hpp", "batch.hpp",
-               "fft_lds.hpp")
-
-
-def kernel_source_hash() -> str:
+def group_source_hash(group: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in PMC_SOURCES:
+    for name in PMC_GROUPS[group]:
         with open(os.path.join(ROOT, "paper_1305_6653_amd", "csrc", name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(workload_name, prec, kernel):
-    if PMC_SOURCE_HASH is None or kernel_source_hash() != PMC_SOURCE_HASH:
+    group = PMC_KERNEL_GROUP.get(kernel)
+    if group is None or PMC_SOURCE_HASH.get(group) != group_source_hash(group):
         return None
     return PMC_TRAFFIC.get((workload_name, prec, kernel))
 
@@ -421,7 +446,7 @@ def main():
                 "rel_diff_vs_lu": float(np.linalg.norm(u4 - u_main) / np.linalg.norm(u_main)),
                 "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4),
                                 "count": v["count"] // args.steps} for k, v in prof4.items()},
-                "roofline": roofline(prof4, form, None, read_peak),
+                "roofline": roofline(prof4, form, args.workload + "h", read_peak),
             }
         S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_LU)
     if not args.no_bccb and prec == "fp64":

@@ -9,7 +9,8 @@ Hardware counters (CSV written by ``rocprofv3 --pmc FETCH_SIZE -f csv`` and, in 
 by a reference copy dispatch of known size (the largest dispatch whose name matches
 ``--copy-kernel``, which read and wrote ``--copy-bytes`` bytes):
 
-    python -m paper_1305_6653_amd.profile_summary pmc <fetch.csv> <write.csv> --copy-bytes N
+    python -m paper_1305_6653_amd.profile_summary pmc <fetch.csv> <write.csv> --copy-bytes N \
+        [--split NAME_SUBSTRING:KiB ...]
 """
 import argparse
 import csv
@@ -18,26 +19,36 @@ import sqlite3
 from collections import defaultdict
 
 
-def summarise(db: str, top: int = 25):
+def summarise(db: str, top: int = 25, splits=()):
+    """Per-kernel rows; splits = ["name_substring:us", ...] report a kernel's dispatches shorter
+    and longer than us apart (e.g. one block-solve kernel applying full LU factors or U only)."""
     c = sqlite3.connect(db)
+    rules = [(sub, float(us)) for sub, us in (x.rsplit(":", 1) for x in splits)]
+    tag = "name"
+    for sub, us in rules:
+        tag = (f"case when instr(name, '{sub}') > 0 then name || case when duration >= {us * 1e3} "
+               f"then ' [>={us:g} us]' else ' [<{us:g} us]' end else {tag} end")
     rows = list(c.execute(
-        "select name, count(*), sum(duration), avg(duration), min(duration), max(duration), "
+        f"select {tag} as nm, count(*), sum(duration), avg(duration), min(duration), max(duration), "
         "max(vgpr_count), max(accum_vgpr_count), max(lds_size), max(grid_x*grid_y*grid_z), "
-        "max(workgroup_x*workgroup_y*workgroup_z) from kernels group by name "
+        "max(workgroup_x*workgroup_y*workgroup_z), min(name) from kernels group by nm "
         "order by sum(duration) desc"))
     total = sum(r[2] for r in rows) or 1.0
     return rows[:top], total
 
 
 def short_name(name: str) -> str:
-    return name.split("(")[0].replace("void ", "").strip()
+    tail = name[name.rindex(" ["):] if name.endswith("]") and " [" in name else ""
+    return name.split("(")[0].replace("void ", "").strip() + tail
 
 
-def active_stats(db: str, name: str, frac: float = 0.05):
-    """(count, average ns) over the dispatches of `name` that last at least frac x the median:
-    launches whose workgroups all found their instance gated off (nothing to do) are left out."""
+def active_stats(db: str, name: str, frac: float = 0.05, lo_ns: float = 0.0, hi_ns: float = 1e30):
+    """(count, average ns) over the dispatches of `name` (with durations in [lo_ns, hi_ns)) that
+    last at least frac x the median: launches whose workgroups all found their instance gated
+    off (nothing to do) are left out."""
     c = sqlite3.connect(db)
-    d = sorted(r[0] for r in c.execute("select duration from kernels where name = ?", (name,)))
+    d = sorted(r[0] for r in c.execute("select duration from kernels where name = ?", (name,))
+               if lo_ns <= r[0] < hi_ns)
     if not d:
         return 0, 0.0
     cut = frac * d[len(d) // 2]
@@ -46,7 +57,7 @@ def active_stats(db: str, name: str, frac: float = 0.05):
 
 
 def trace_main(a):
-    rows, total = summarise(a.db)
+    rows, total = summarise(a.db, splits=a.split or [])
     if a.title:
         print(a.title)
     if a.command:
@@ -55,9 +66,16 @@ def trace_main(a):
           "found every instance gated off)")
     print(f"{'kernel':50s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'min_us':>9s} "
           f"{'max_us':>9s} {'act_calls':>9s} {'act_avg_us':>10s} {'pct':>6s} {'vgpr':>5s} {'lds':>7s} {'grid':>10s} {'wg':>5s}")
-    for name, n, tot, avg, mn, mx, vg, ag, lds, grid, wg in rows:
-        short = short_name(name)[:50]
-        na, aa = active_stats(a.db, name)
+    for name, n, tot, avg, mn, mx, vg, ag, lds, grid, wg, raw in rows:
+        short = short_name(name)[-50:] if name.endswith("]") else short_name(name)[:50]
+        lo, hi = 0.0, 1e30
+        if name.endswith(" us]"):  # a split row: "[>=X us]" or "[<X us]"
+            tag = name[name.rindex("[") + 1:-4]
+            if tag.startswith(">="):
+                lo = float(tag[2:]) * 1e3
+            else:
+                hi = float(tag[1:]) * 1e3
+        na, aa = active_stats(a.db, raw, lo_ns=lo, hi_ns=hi)
         print(f"{short:50s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:10.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f} "
               f"{na:9d} {aa / 1e3:10.2f} {100 * tot / total:6.2f} {vg:5d} {lds:7d} {grid:10d} {wg:5d}")
 
@@ -88,6 +106,29 @@ def read_counter(path: str, counter: str):
             prev = out.get(d)
             out[d] = (name, v + (prev[1] if prev else 0.0))
     return out
+
+
+def split_names(fetch, write, splits):
+    """Renames the dispatches of a kernel by FETCH_SIZE: for each "name_substring:KiB" in splits,
+    dispatches of a matching kernel fetching at least KiB become "<name> [>=KiB]" and the
+    others "<name> [<KiB]" (e.g. the same block-solve kernel applying full LU factors or only
+    U factors in one run)."""
+    if not splits:
+        return fetch, write
+    rules = [(sub, float(kib)) for sub, kib in (x.rsplit(":", 1) for x in splits)]
+    f2, w2 = {}, {}
+    for d, (n, v) in fetch.items():
+        tag = n
+        for sub, kib in rules:
+            if sub in n:
+                tag = f"{short_name(n)} [{'>=' if v >= kib else '<'}{kib:g} KiB]"
+        f2[d] = (tag, v)
+        if d in write:
+            w2[d] = (tag, write[d][1])
+    for d, (n, v) in write.items():
+        if d not in w2:
+            w2[d] = (n, v)
+    return f2, w2
 
 
 def traffic_per_dispatch(fetch, write, frac: float = 0.05):
@@ -127,6 +168,7 @@ def pmc_main(a):
     kib = a.copy_bytes / 1024.0
     f_scale = kib / largest_copy(fetch)
     w_scale = kib / largest_copy(write)
+    fetch, write = split_names(fetch, write, a.split or [])
     agg = traffic_per_dispatch(fetch, write)
     if a.title:
         print(a.title)
@@ -152,6 +194,8 @@ def main():
     t.add_argument("db")
     t.add_argument("--title", default="")
     t.add_argument("--command", default="")
+    t.add_argument("--split", action="append",
+                   help="NAME_SUBSTRING:us: report a kernel's dispatches shorter and longer than us apart")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -160,6 +204,8 @@ def main():
     p.add_argument("--title", default="")
     p.add_argument("--command", action="append")
     p.add_argument("--top", type=int, default=25)
+    p.add_argument("--split", action="append",
+                   help="NAME_SUBSTRING:KiB: report a kernel's dispatches below and above KiB apart")
     a = ap.parse_args()
     trace_main(a) if a.mode == "trace" else pmc_main(a)
 

@@ -39,7 +39,7 @@ PMC_KERNEL_GROUP = {
     "trsv": "factor", "hess_uinv": "factor",
     "bvm_matvec": "spacetime", "time_rfft": "spacetime", "time_irfft": "spacetime",
     "bccb_solve": "spacetime", "rhs": "spacetime",
-    "cgs": "krylov", "cgs_sum": "krylov", "normalize": "krylov", "residual": "krylov",
+    "mgs": "krylov", "cgs": "krylov", "normalize": "krylov", "residual": "krylov",
     "update_x": "krylov", "dot": "krylov",
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
@@ -169,7 +169,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
-              "time_irfft", "bvm_matvec", "cgs", "cgs_sum", "normalize", "residual", "update_x", "rhs", "dot",
+              "time_irfft", "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot",
               "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
@@ -270,7 +270,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "time_rfft", "time_irfft",
-              "bvm_matvec", "cgs", "cgs_sum", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
+              "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
         q = lead.profile_query(k)
         if q["count"]:
             prof[k] = q
@@ -463,7 +463,7 @@ def main():
                 "rel_diff_vs_strang": float(np.linalg.norm(u3 - u_main) / np.linalg.norm(u_main)),
                 "kernels": {k: {"total_ms": round(v["total_ms"] / max(1, args.steps // 2), 4),
                                 "avg_us": round(1e3 * v["total_ms"] / v["count"], 2)}
-                            for k, v in prof3.items() if k in ("bccb_solve", "bvm_matvec", "cgs",
+                            for k, v in prof3.items() if k in ("bccb_solve", "bvm_matvec", "mgs", "cgs",
                                                                "time_rfft", "time_irfft")},
                 "bccb_solve_GBs": round(prof3["bccb_solve"]["work"]
                                         / (prof3["bccb_solve"]["total_ms"] * 1e-3) / 1e9, 1)

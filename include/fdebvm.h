@@ -193,7 +193,8 @@ typedef enum {
   FDE_OPT_GRAPHS_IN_USE = 4,
   FDE_OPT_PRECOND = 5,
   FDE_OPT_SIDE = 6,
-  FDE_OPT_BLOCKS = 7
+  FDE_OPT_BLOCKS = 7,
+  FDE_OPT_ORTHO = 8
 } fde_option;
 /* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
  * discards the current factorization):
@@ -235,6 +236,11 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
  *                          bytes).  Not in the paper.  m <= 1024 (FDE_EUNSUPPORTED beyond);
  *                          needs cooperative launches. */
 typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1 } fde_block_solver;
+/* FDE_OPT_ORTHO selects the Arnoldi orthogonalisation (FP64 either way):
+ *   FDE_ORTHO_MGS   (default) modified Gram-Schmidt, j + 2 dependent launches at step j.
+ *   FDE_ORTHO_CGS2  classical Gram-Schmidt applied twice: three launches per step whatever j;
+ *                   the same basis in exact arithmetic, orthogonal to working precision. */
+typedef enum { FDE_ORTHO_MGS = 0, FDE_ORTHO_CGS2 = 1 } fde_ortho;
 fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
 fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
 /* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);

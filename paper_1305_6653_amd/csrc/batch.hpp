@@ -48,6 +48,7 @@ struct InstDesc {
   double *partm;              // [R+1][nblk] partials of the Gram-Schmidt projections
   double *H, *y, *nrm;        // Hessenberg column [R+2], LSQ solution [R], norms [2]
   double *h2;                 // [R+2] second Gram-Schmidt pass of the current column
+  unsigned *gctr;             // [1] chunks done in the current Gram-Schmidt launch (0 between)
 };
 
 // vector selectors resolved on the device

@@ -3,12 +3,18 @@
 // update.  Every reduction has a fixed order (chunk partials summed in index order), so results
 // are bitwise reproducible run to run.
 //
-// Orthogonalisation: classical Gram-Schmidt applied twice (CGS2), h = V^T w, w -= V h, then
+// Orthogonalisation, two forms selected per solve:
+// * modified Gram-Schmidt (the default) as a chain of launches: launch i subtracts the
+//   projection on v_{i-1} and accumulates the dot with v_i, so the MGS order is kept exactly;
+// * classical Gram-Schmidt applied twice (CGS2), h = V^T w, w -= V h, then
 // h' = V^T w, w -= V h', column = h + h'.  In exact arithmetic it equals modified Gram-Schmidt;
 // in floating point the second pass makes the basis orthogonal to working precision, as MGS
-// does for GMRES.  It takes five launches per Arnoldi step whatever j (projection partials, sum,
-// update + second partials, sum, update + norm partial) instead of the j + 2 dependent launches
-// of MGS.
+// does for GMRES.  It takes three launches per Arnoldi step whatever j (projection partials;
+// update + second partials; update + norm partial) instead of the j + 2 dependent launches of
+// MGS: the chunk that finishes last in a launch sums every chunk's partials (index order) and
+// writes the coefficients, so no separate reduction launch is needed.  Partials go through
+// agent-coherent stores and loads, and a chunk counts itself done only after its stores have
+// completed.
 #include "batch.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -53,6 +59,16 @@ __device__ __forceinline__ Chunk chunk_of(const InstDesc *__restrict__ D, const 
   return c;
 }
 
+__device__ __forceinline__ void st_coh1(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh1(const double *p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // Partial sums over chunk b of V_i . w, i = 0..j, into partm[i][b]: up to 16 dot products per
 // pass accumulated together (w is read once per pass), wave sums by DPP, one barrier per pass.
 static constexpr int CG_G = 16;
@@ -83,32 +99,35 @@ __device__ __forceinline__ void cgs_partials(const InstDesc &d, const Chunk &c, 
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < KR_NT / 64; ++q) s += red[q * CG_G + threadIdx.x];
-      d.partm[(size_t)(i0 + threadIdx.x) * d.nblk + c.b] = s;
+      st_coh1(d.partm + (size_t)(i0 + threadIdx.x) * d.nblk + c.b, s);
     }
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(KR_NT) void k_cgs_dot(const InstDesc *__restrict__ D, ItemMap map, int j) {
-  __shared__ double red[(KR_NT / 64) * CG_G];
-  const Chunk c = chunk_of(D, map);
-  if (!c.d) return;
-  cgs_partials(*c.d, c, j, red);
+// After this chunk's partials are stored: returns true in the chunk that finishes last (every
+// thread), which then owns the sums.  The counter is reset for the next launch.
+__device__ __forceinline__ bool cgs_last_chunk(const InstDesc &d, int *sh) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned done = __hip_atomic_fetch_add(d.gctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = done == (unsigned)d.nblk - 1;
+    if (last) __hip_atomic_store(d.gctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sh = last;
+  }
+  __syncthreads();
+  return *sh != 0;
 }
 
-// One workgroup per instance, one wavefront per coefficient: h_i = sum_b partm[i][b] (lanes
-// stride over b, then the DPP wave sum: a fixed order).  pass 0: H[i] = h_i; pass 1:
-// h2[i] = h_i and H[i] += h_i.
-__global__ __launch_bounds__(KR_NT) void k_cgs_sum(const InstDesc *__restrict__ D, ItemMap map, int j,
-                                                   int pass) {
-  const int q = item_slot(map, blockIdx.x);
-  if (item_gated(map, q)) return;
-  const InstDesc &d = D[map.ids[q]];
+// In the last chunk: h_i = sum_b partm[i][b] (index order; one wavefront per coefficient, DPP
+// wave sum).  pass 0: H[i] = h_i; pass 1: h2[i] = h_i and H[i] += h_i.
+__device__ __forceinline__ void cgs_sums(const InstDesc &d, int j, int pass) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = wv; i <= j; i += KR_NT / 64) {
     const double *p = d.partm + (size_t)i * d.nblk;
     double t = 0.0;
-    for (int b = lane; b < d.nblk; b += 64) t += p[b];
+    for (int b = lane; b < d.nblk; b += 64) t += ld_coh1(p + b);
     const double h = wave_sum_dpp(t);
     if (lane == 0) {
       if (pass == 0) {
@@ -121,13 +140,23 @@ __global__ __launch_bounds__(KR_NT) void k_cgs_sum(const InstDesc *__restrict__ 
   }
 }
 
+__global__ __launch_bounds__(KR_NT) void k_cgs_dot(const InstDesc *__restrict__ D, ItemMap map, int j) {
+  __shared__ double red[(KR_NT / 64) * CG_G];
+  __shared__ int sh;
+  const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
+  cgs_partials(*c.d, c, j, red);
+  if (cgs_last_chunk(*c.d, &sh)) cgs_sums(*c.d, j, 0);
+}
+
 // w -= sum_{i<=j} c_i V_i with c = H (pass 0) or h2 (pass 1), in i order for every element;
-// then pass 0: the partials of the second projection V^T w; pass 1: the partial of w . w into
-// part[(j+1) & 1] (read by the normalisation that follows).
+// then pass 0: the partials of the second projection V^T w and, in the last chunk, h2 and
+// H += h2; pass 1: the partial of w . w into part[(j+1) & 1] (read by the normalisation).
 __global__ __launch_bounds__(KR_NT) void k_cgs_update(const InstDesc *__restrict__ D, ItemMap map, int j,
                                                       int pass) {
   __shared__ double red[(KR_NT / 64) * CG_G];
   __shared__ double cf[GM_RMAX + 1];
+  __shared__ int sh;
   const Chunk c = chunk_of(D, map);
   if (!c.d) return;
   const InstDesc &d = *c.d;
@@ -145,6 +174,7 @@ __global__ __launch_bounds__(KR_NT) void k_cgs_update(const InstDesc *__restrict
   if (pass == 0) {
     __syncthreads();
     cgs_partials(d, c, j, red);
+    if (cgs_last_chunk(d, &sh)) cgs_sums(d, j, 1);
   } else {
     nn = block_sum<KR_NT>(nn, red);
     if (threadIdx.x == 0) (((j + 1) & 1) ? d.part1 : d.part0)[c.b] = nn;
@@ -157,18 +187,43 @@ hipError_t launch_cgs_dot(const InstDesc *D, const ItemMap &map, int items, int 
   return hipGetLastError();
 }
 
-hipError_t launch_cgs_sum(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
-                          hipStream_t st) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cgs_sum, dim3(items), dim3(KR_NT), 0, st, D, map, j, pass);
-  return hipGetLastError();
-}
-
 hipError_t launch_cgs_update(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
                              hipStream_t st) {
   if (items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cgs_update, dim3(items), dim3(KR_NT), 0, st, D, map, j, pass);
   return hipGetLastError();
+}
+
+// i = 0..j+1.  i > 0: h_{i-1} = <v_{i-1}, w> from the partials of launch i-1; w -= h v_{i-1}.
+// i <= j: partial <v_i, w>;  i == j+1: partial <w, w>.  Launch i reads part[(i+1)&1] and
+// writes part[i&1].
+__global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__ D, ItemMap map,
+                                                    int i, int j) {
+  __shared__ double red[KR_NT / 64];
+  const Chunk c = chunk_of(D, map);
+  if (!c.d) return;
+  const InstDesc &d = *c.d;
+  const double *pin = (i & 1) ? d.part0 : d.part1;
+  double *pout = (i & 1) ? d.part1 : d.part0;
+  double h = 0.0;
+  if (i > 0) {
+    h = sum_partials(pin, d.nblk, red);
+    if (c.b == 0 && threadIdx.x == 0) d.H[i - 1] = h;
+  }
+  const double *vp = d.V + (size_t)(i > 0 ? i - 1 : 0) * c.n;
+  const double *vc = d.V + (size_t)(i <= j ? i : 0) * c.n;
+  double *w = d.w;
+  double acc = 0.0;
+  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
+    double we = w[e];
+    if (i > 0) {
+      we = fma(-h, vp[e], we);
+      w[e] = we;
+    }
+    acc = (i <= j) ? fma(vc[e], we, acc) : fma(we, we, acc);
+  }
+  acc = block_sum<KR_NT>(acc, red);
+  if (threadIdx.x == 0) pout[c.b] = acc;
 }
 
 // nrm = sqrt(sum of part[psel]); dst = src / nrm (0 if nrm == 0).  The norm is stored in
@@ -277,6 +332,13 @@ hipError_t launch_copy(const InstDesc *D, const ItemMap &map, int items, int src
                        int dst_sel, int dst_j, hipStream_t st) {
   if (items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy, dim3(items), dim3(KR_NT), 0, st, D, map, src_sel, src_j, dst_sel, dst_j);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
+                           hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mgs_step, dim3(items), dim3(KR_NT), 0, st, D, map, i, j);
   return hipGetLastError();
 }
 

@@ -68,12 +68,14 @@ int trsv_coop_capacity();
 
 // ---- Krylov BLAS-1 (FP64, deterministic reductions), items = nblk per instance ----
 int krylov_blocks(size_t n);
-// Arnoldi orthogonalisation by classical Gram-Schmidt twice (k_krylov.hip): partials of V^T w
-// (items = chunks), their sums (items = one per instance, pass 0 -> H, pass 1 -> h2 and H += h2),
-// w -= V c with the next partials (pass 0) or the norm partial (pass 1).
+// Modified Gram-Schmidt step i of Arnoldi column j (i = 0..j+1, one launch each): h_{i-1} from
+// the partials of launch i-1, w -= h_{i-1} v_{i-1}, partial <v_i, w> (<w, w> for i = j+1).
+hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,
+                           hipStream_t st);
+// Arnoldi orthogonalisation by classical Gram-Schmidt twice (k_krylov.hip), items = chunks:
+// V^T w (the last chunk writes H[0..j]); w -= V H then pass 0: V^T w again (the last chunk
+// writes h2 and adds it to H), pass 1: w -= V h2 and the norm partial.
 hipError_t launch_cgs_dot(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st);
-hipError_t launch_cgs_sum(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
-                          hipStream_t st);
 hipError_t launch_cgs_update(const InstDesc *D, const ItemMap &map, int items, int j, int pass,
                              hipStream_t st);
 hipError_t launch_normalize(const InstDesc *D, const ItemMap &map, int items, int src_sel,

@@ -187,6 +187,7 @@ struct fde_bvm {
   int pc = FDE_PC_STRANG;
   int opt_side = FDE_SIDE_RIGHT;
   int opt_blocks = FDE_BLOCKS_LU;
+  int opt_ortho = FDE_ORTHO_MGS;
   // ---- profiling
   bool prof = false;
   int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
@@ -323,8 +324,8 @@ struct HostMap {
 
 // Item maps of the solve-phase launches over every instance of a plan.
 struct SolveMaps {
-  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk, qg, one;
-  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0, n_one = 0;
+  ItemMap mv, tfft, trsv, kry, rhs, ju0, blk, qg;
+  int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0;
   int pc = 0, route = FDE_BLOCKS_LU;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int prec = -1;
@@ -334,7 +335,7 @@ struct SolveMaps {
 // The same maps with their items skipped for instances whose gate entry is zero.
 static SolveMaps gated(const SolveMaps &S, const int *gate) {
   SolveMaps G = S;
-  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk, &G.qg, &G.one}) m->gate = gate;
+  for (ItemMap *m : {&G.mv, &G.tfft, &G.trsv, &G.kry, &G.rhs, &G.ju0, &G.blk, &G.qg}) m->gate = gate;
   return G;
 }
 
@@ -344,6 +345,7 @@ struct Plan {
   int R = 0;
   InstDesc *d_desc = nullptr;
   double *d_part = nullptr, *d_H = nullptr, *d_y = nullptr, *d_nrm = nullptr, *d_h2 = nullptr;
+  unsigned *d_gctr = nullptr;
   int *d_err = nullptr, *d_flag = nullptr;
   int *d_arena = nullptr;
   size_t arena_ints = 0;
@@ -369,7 +371,7 @@ struct Plan {
   // and the end of a cycle (least-squares update) followed by the next restart step
   GraphSeg seg_restart, seg_finish;
   std::map<std::pair<int, int>, GraphSeg> seg_steps;
-  int graph_R = -1, graph_prec = -1, graph_side = -1;
+  int graph_R = -1, graph_prec = -1, graph_side = -1, graph_ortho = -1;
   bool graph_off = false;
   std::vector<int> pred_steps;  // Arnoldi steps of each cycle of the previous solve
 };
@@ -396,7 +398,7 @@ static void graphs_invalidate(Plan *P) {
   graph_release(P, P->seg_finish);
   for (auto &kv : P->seg_steps) graph_release(P, kv.second);
   P->seg_steps.clear();
-  P->graph_R = P->graph_prec = P->graph_side = -1;
+  P->graph_R = P->graph_prec = P->graph_side = P->graph_ortho = -1;
 }
 
 static void plan_free(Plan *P) {
@@ -590,7 +592,8 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
   const int count = (int)P->hs.size();
   for (fde_bvm *h : P->hs) STCHK(ensure_krylov(h, R));
   if (P->R < R || !P->d_H) {
-    for (void *p : {(void *)P->d_part, (void *)P->d_H, (void *)P->d_y, (void *)P->d_nrm, (void *)P->d_h2}) {
+    for (void *p : {(void *)P->d_part, (void *)P->d_H, (void *)P->d_y, (void *)P->d_nrm, (void *)P->d_h2,
+                    (void *)P->d_gctr}) {
       if (!p) continue;
       auto it = std::find(P->allocs.begin(), P->allocs.end(), p);
       if (it != P->allocs.end()) P->allocs.erase(it);
@@ -613,6 +616,9 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     P->d_nrm = (double *)p;
     STCHK(plan_alloc(P, &p, (size_t)count * (R + 2) * sizeof(double)));
     P->d_h2 = (double *)p;
+    STCHK(plan_alloc(P, &p, (size_t)count * sizeof(unsigned)));
+    P->d_gctr = (unsigned *)p;
+    HIPCHK(hipMemset(P->d_gctr, 0, (size_t)count * sizeof(unsigned)));
     P->R = R;
     P->desc_dirty = true;
   }
@@ -626,6 +632,7 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     d.part1 = d.part0 + h->nblk;
     d.partm = d.part0 + 2 * (size_t)h->nblk;
     d.h2 = P->d_h2 + (size_t)i * (R + 2);
+    d.gctr = P->d_gctr + i;
     d.H = P->d_H + (size_t)i * (R + 2);
     d.y = P->d_y + (size_t)i * (R + 1);
     d.nrm = P->d_nrm + (size_t)i * 2;
@@ -1112,6 +1119,11 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
         return fail(FDE_EINVAL, "FDE_OPT_SIDE must be FDE_SIDE_RIGHT or FDE_SIDE_LEFT");
       h->opt_side = value;
       return FDE_OK;
+    case FDE_OPT_ORTHO:
+      if (value != FDE_ORTHO_MGS && value != FDE_ORTHO_CGS2)
+        return fail(FDE_EINVAL, "FDE_OPT_ORTHO must be FDE_ORTHO_MGS or FDE_ORTHO_CGS2");
+      h->opt_ortho = value;
+      return FDE_OK;
     case FDE_OPT_BLOCKS:
       if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG)
         return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU or FDE_BLOCKS_HESSENBERG");
@@ -1133,6 +1145,7 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
     case FDE_OPT_SIDE: *value = h->opt_side; return FDE_OK;
     case FDE_OPT_BLOCKS: *value = h->opt_blocks; return FDE_OK;
+    case FDE_OPT_ORTHO: *value = h->opt_ortho; return FDE_OK;
     case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
   }
@@ -1447,7 +1460,7 @@ static fde_status ensure_full_maps(Plan *P) {
       P->full.route == P->hs[0]->blk_route)
     return FDE_OK;
   std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count),
-      qq(count), one(count, 1);
+      qq(count);
   SolveMaps S;
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
@@ -1474,7 +1487,7 @@ static fde_status ensure_full_maps(Plan *P) {
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
                                    make_map(slots, d), make_map(slots, e), make_map(slots, f),
-                                   make_map(slots, g), make_map(slots, qq), make_map(slots, one)};
+                                   make_map(slots, g), make_map(slots, qq)};
   size_t need = 0;
   for (const HostMap &m : hm) need += m.ids.size() + m.pre.size();
   HIPCHK(hipStreamSynchronize(P->lead->stream));
@@ -1513,8 +1526,6 @@ static fde_status ensure_full_maps(Plan *P) {
   S.n_blk = hm[6].items;
   S.qg = dm[7];
   S.n_qg = hm[7].items;
-  S.one = dm[8];
-  S.n_one = hm[8].items;
   S.pc = P->hs[0]->pc;
   S.route = P->hs[0]->blk_route;
   S.n_mv = hm[0].items;
@@ -1795,12 +1806,15 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
 
   // Timing events are not recorded into graphs: a profiled solve launches directly.
   const bool use_graph = L->opt_graphs != 0 && !P->graph_off && !L->prof;
-  if (P->graph_R != R || P->graph_prec != S.prec || P->graph_side != (int)left) {
+  const int ortho = L->opt_ortho;
+  if (P->graph_R != R || P->graph_prec != S.prec || P->graph_side != (int)left ||
+      P->graph_ortho != ortho) {
     HIPCHK(hipStreamSynchronize(stream));
     graphs_invalidate(P);
     P->graph_R = R;
     P->graph_prec = S.prec;
     P->graph_side = (int)left;
+    P->graph_ortho = ortho;
   }
   // v_0 = r / ||r|| with r = b - M x (right) or P^{-1}(b - M x) (left); the norm goes to the
   // control record's restart test.
@@ -1828,15 +1842,20 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
         STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
         STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
       }
-      // classical Gram-Schmidt twice: V^T w, w -= V h, V^T w, w -= V h', column h + h'
-      HIPCHK(run(L, "cgs", (j + 2.0) * S.vec_bytes,
-                 [&] { return launch_cgs_dot(P->d_desc, Sact.kry, S.n_kry, j, stream); }));
-      HIPCHK(run(L, "cgs_sum", 0.0, [&] { return launch_cgs_sum(P->d_desc, Sact.one, S.n_one, j, 0, stream); }));
-      HIPCHK(run(L, "cgs", (2.0 * j + 5.0) * S.vec_bytes,
-                 [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 0, stream); }));
-      HIPCHK(run(L, "cgs_sum", 0.0, [&] { return launch_cgs_sum(P->d_desc, Sact.one, S.n_one, j, 1, stream); }));
-      HIPCHK(run(L, "cgs", (j + 3.0) * S.vec_bytes,
-                 [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 1, stream); }));
+      if (ortho == FDE_ORTHO_CGS2) {
+        // classical Gram-Schmidt twice: V^T w, w -= V h, V^T w, w -= V h', column h + h'
+        HIPCHK(run(L, "cgs", (j + 2.0) * S.vec_bytes,
+                   [&] { return launch_cgs_dot(P->d_desc, Sact.kry, S.n_kry, j, stream); }));
+        HIPCHK(run(L, "cgs", (2.0 * j + 5.0) * S.vec_bytes,
+                   [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 0, stream); }));
+        HIPCHK(run(L, "cgs", (j + 3.0) * S.vec_bytes,
+                   [&] { return launch_cgs_update(P->d_desc, Sact.kry, S.n_kry, j, 1, stream); }));
+      } else {
+        for (int i = 0; i <= j + 1; ++i) {
+          HIPCHK(run(L, "mgs", (i == 0 ? 2.0 : 4.0) * S.vec_bytes,
+                     [&] { return launch_mgs_step(P->d_desc, Sact.kry, S.n_kry, i, j, stream); }));
+        }
+      }
       HIPCHK(run(L, "normalize", 2.0 * S.vec_bytes, [&] {
         return launch_normalize(P->d_desc, Sact.kry, S.n_kry, VS_W, 0, VS_V, j + 1, (j + 1) & 1, j + 1, stream);
       }));

@@ -91,6 +91,24 @@ def test_profile_counts_the_steps_that_ran(graphs):
     u, info = S.solve(p.u0, p.f)
     q = S.profile_query("trsv")
     assert q["count"] == info["iters"] and q["total_ms"] > 0.0
-    assert S.profile_query("cgs")["count"] == 3 * info["iters"]       # two Gram-Schmidt passes
-    assert S.profile_query("cgs_sum")["count"] == 2 * info["iters"]
+    assert S.profile_query("mgs")["count"] == sum(j + 2 for j in range(info["iters"]))
     S.profile(False)
+
+
+@pytest.mark.parametrize("restart", [20, 7])
+def test_cgs2_orthogonalisation_matches_mgs(restart):
+    """Classical Gram-Schmidt twice builds the same Krylov basis as MGS in exact arithmetic: the
+    solves agree to rounding with the same iteration count (three launches per step)."""
+    p = W.tiny(200, 32, 1.7, 4, "gbdf3")
+    S = BvmSolver(p)
+    S.factor("fp64")
+    u1, i1 = S.solve(p.u0, p.f, restart=restart)
+    S.set_option(N.FDE_OPT_ORTHO, N.FDE_ORTHO_CGS2)
+    S.profile(True)
+    u2, i2 = S.solve(p.u0, p.f, restart=restart)
+    assert S.profile_query("cgs")["count"] == 3 * i2["iters"]
+    S.profile(False)
+    assert abs(i1["iters"] - i2["iters"]) <= 1 and i2["true_relres"] <= 1e-10
+    assert _rel(u2, u1) <= 1e-10
+    ref = O.solve_gmres(p, tol=1e-12)
+    assert _rel(u2, ref.x) <= 1e-9

@@ -44,34 +44,34 @@ PMC_KERNEL_GROUP = {
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
 }
-PMC_SOURCE_HASH = {"factor": "0a1d6721aae4db63", "spacetime": "f36a8af3e0052fb3", "krylov": "d3ccded5515d4027", "hessenberg": "29d6762cb79270aa"}
+PMC_SOURCE_HASH = {"factor": "3b549ee33724b2f8", "spacetime": "9ef9c2748fb47a38", "krylov": "c686c348b5a1e52e", "hessenberg": "68dafd4a8cd526e2"}
 PMC_TRAFFIC = {
     ("c2", "fp64", "assemble"): 4.3131e+09,
     ("c2", "fp64", "bccb_solve"): 9.2170e+06,
     ("c2", "fp64", "bvm_matvec"): 2.1762e+07,
-    ("c2", "fp64", "cgs"): 7.3505e+07,
     ("c2", "fp64", "lu_diag"): 6.7555e+07,
     ("c2", "fp64", "lu_panel"): 7.4810e+08,
-    ("c2", "fp64", "lu_update"): 3.3657e+09,
+    ("c2", "fp64", "lu_update"): 3.3661e+09,
+    ("c2", "fp64", "mgs"): 1.5951e+07,
     ("c2", "fp64", "time_irfft"): 9.2600e+06,
     ("c2", "fp64", "time_rfft"): 1.2419e+07,
-    ("c2", "fp64", "trsv"): 4.6745e+09,
+    ("c2", "fp64", "trsv"): 4.6746e+09,
     ("c2", "mixed", "assemble"): 2.1569e+09,
     ("c2", "mixed", "lu_diag"): 3.3791e+07,
-    ("c2", "mixed", "lu_panel"): 3.8801e+08,
-    ("c2", "mixed", "lu_update"): 1.6674e+09,
+    ("c2", "mixed", "lu_panel"): 3.8792e+08,
+    ("c2", "mixed", "lu_update"): 1.6676e+09,
     ("c2", "mixed", "trsv"): 2.3812e+09,
     ("c2h", "fp64", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "fp64", "hess_lu"): 2.2024e+09,
-    ("c2h", "fp64", "hess_reduce"): 6.8193e+09,
-    ("c2h", "fp64", "hess_uinv"): 4.2124e+08,
-    ("c2h", "fp64", "qgemm"): 5.2827e+07,
+    ("c2h", "fp64", "hess_lu"): 2.2034e+09,
+    ("c2h", "fp64", "hess_reduce"): 6.8197e+09,
+    ("c2h", "fp64", "hess_uinv"): 4.2121e+08,
+    ("c2h", "fp64", "qgemm"): 5.2878e+07,
     ("c2h", "fp64", "trsv"): 2.3382e+09,
     ("c2h", "mixed", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "mixed", "hess_lu"): 1.1254e+09,
-    ("c2h", "mixed", "hess_reduce"): 6.8193e+09,
+    ("c2h", "mixed", "hess_lu"): 1.1248e+09,
+    ("c2h", "mixed", "hess_reduce"): 6.8197e+09,
     ("c2h", "mixed", "hess_uinv"): 2.1904e+08,
-    ("c2h", "mixed", "qgemm"): 5.2827e+07,
+    ("c2h", "mixed", "qgemm"): 5.2878e+07,
     ("c2h", "mixed", "trsv"): 1.1907e+09,
 }
 

@@ -38,6 +38,9 @@ def summarise(db: str, top: int = 25, splits=()):
 
 
 def short_name(name: str) -> str:
+    """Kernel name without its argument list; a split tag (" [...]") is kept."""
+    if "(" not in name:
+        return name.replace("void ", "").strip()
     tail = name[name.rindex(" ["):] if name.endswith("]") and " [" in name else ""
     return name.split("(")[0].replace("void ", "").strip() + tail
 
@@ -108,49 +111,52 @@ def read_counter(path: str, counter: str):
     return out
 
 
-def split_names(fetch, write, splits):
-    """Renames the dispatches of a kernel by FETCH_SIZE: for each "name_substring:KiB" in splits,
-    dispatches of a matching kernel fetching at least KiB become "<name> [>=KiB]" and the
-    others "<name> [<KiB]" (e.g. the same block-solve kernel applying full LU factors or only
-    U factors in one run)."""
-    if not splits:
-        return fetch, write
+def pair_by_order(fetch, write):
+    """The two counter runs are separate executions of the same program: the k-th dispatch of a
+    kernel in one matches the k-th dispatch of that kernel in the other (dispatch ids can shift
+    when other kernels' launch counts differ).  Returns [(name, fetch, write or None)]."""
+    fl, wl = defaultdict(list), defaultdict(list)
+    for d in sorted(fetch, key=lambda x: int(x) if str(x).isdigit() else x):
+        fl[fetch[d][0]].append(fetch[d][1])
+    for d in sorted(write, key=lambda x: int(x) if str(x).isdigit() else x):
+        wl[write[d][0]].append(write[d][1])
+    out = []
+    for n, fv in fl.items():
+        wv = wl.get(n, [])
+        for k, v in enumerate(fv):
+            out.append((n, v, wv[k] if k < len(wv) else None))
+    return out
+
+
+def traffic_per_dispatch(pairs, splits=(), frac: float = 0.05):
+    """{kernel: [n, sum_fetch, n_write, sum_write]} over the dispatches whose FETCH_SIZE is at
+    least frac x the kernel's median (gated-off launches, which read only their control data,
+    are left out).  splits = ["name_substring:KiB", ...] report a kernel's dispatches fetching
+    at least KiB apart from the others (e.g. one block-solve kernel applying full LU factors or
+    U only)."""
     rules = [(sub, float(kib)) for sub, kib in (x.rsplit(":", 1) for x in splits)]
-    f2, w2 = {}, {}
-    for d, (n, v) in fetch.items():
-        tag = n
+
+    def tagged(n, v):
+        t = short_name(n)
         for sub, kib in rules:
             if sub in n:
-                tag = f"{short_name(n)} [{'>=' if v >= kib else '<'}{kib:g} KiB]"
-        f2[d] = (tag, v)
-        if d in write:
-            w2[d] = (tag, write[d][1])
-    for d, (n, v) in write.items():
-        if d not in w2:
-            w2[d] = (n, v)
-    return f2, w2
-
-
-def traffic_per_dispatch(fetch, write, frac: float = 0.05):
-    """{kernel: [n_fetch, sum_fetch, n_write, sum_write]} over the dispatches whose FETCH_SIZE is
-    at least frac x the kernel's median (gated-off launches, which read only their control
-    data, are left out)."""
+                t += f" [{'>=' if v >= kib else '<'}{kib:g} KiB]"
+        return t
     by_name = defaultdict(list)
-    for n, v in fetch.values():
-        by_name[short_name(n)].append(v)
+    for n, v, _ in pairs:
+        by_name[tagged(n, v)].append(v)
     cut = {k: frac * sorted(v)[len(v) // 2] for k, v in by_name.items()}
-    keep = {d for d, (n, v) in fetch.items() if v >= cut[short_name(n)]}
     agg = defaultdict(lambda: [0, 0.0, 0, 0.0])
-    for d, (n, v) in fetch.items():
-        if d in keep:
-            e = agg[short_name(n)]
-            e[0] += 1
-            e[1] += v
-    for d, (n, v) in write.items():
-        if d in keep or d not in fetch:
-            e = agg[short_name(n)]
+    for n, v, w in pairs:
+        t = tagged(n, v)
+        if v < cut[t]:
+            continue
+        e = agg[t]
+        e[0] += 1
+        e[1] += v
+        if w is not None:
             e[2] += 1
-            e[3] += v
+            e[3] += w
     return agg
 
 
@@ -168,8 +174,7 @@ def pmc_main(a):
     kib = a.copy_bytes / 1024.0
     f_scale = kib / largest_copy(fetch)
     w_scale = kib / largest_copy(write)
-    fetch, write = split_names(fetch, write, a.split or [])
-    agg = traffic_per_dispatch(fetch, write)
+    agg = traffic_per_dispatch(pair_by_order(fetch, write), a.split or [])
     if a.title:
         print(a.title)
     for c in a.command or []:

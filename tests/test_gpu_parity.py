@@ -200,3 +200,29 @@ def test_batch_equals_single():
     for a, b, i in zip(outs, singles, infos):
         assert i["converged"] == 1
         assert _rel(a, b) <= 1e-12
+
+
+def test_options_validate_and_read_back():
+    p, S = _setup("gbdf3_m7_s8")
+    defaults = {N.FDE_OPT_GRAPHS: 1, N.FDE_OPT_AUTOTUNE: 1, N.FDE_OPT_TRSV_W: 0,
+                N.FDE_OPT_PRECOND: N.FDE_PC_STRANG, N.FDE_OPT_SIDE: N.FDE_SIDE_RIGHT,
+                N.FDE_OPT_BLOCKS: N.FDE_BLOCKS_LU, N.FDE_OPT_ORTHO: N.FDE_ORTHO_MGS}
+    for opt, v in defaults.items():
+        assert S.get_option(opt) == v, opt
+    for opt, bad in [(N.FDE_OPT_PRECOND, 7), (N.FDE_OPT_SIDE, 2), (N.FDE_OPT_BLOCKS, -1),
+                     (N.FDE_OPT_ORTHO, 5), (N.FDE_OPT_TRSV_W, -3), (N.FDE_OPT_TRSV_W_IN_USE, 1),
+                     (99, 0)]:
+        with pytest.raises(FdeError) as e:
+            S.set_option(opt, bad)
+        assert e.value.status == N.FDE_EINVAL, opt
+    for opt, v in [(N.FDE_OPT_PRECOND, N.FDE_PC_NONE), (N.FDE_OPT_SIDE, N.FDE_SIDE_LEFT),
+                   (N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_HESSENBERG), (N.FDE_OPT_ORTHO, N.FDE_ORTHO_CGS2)]:
+        S.set_option(opt, v)
+        assert S.get_option(opt) == v
+    # a changed preconditioner or block solver discards the factorization
+    with pytest.raises(FdeError) as e:
+        S.solve(p.u0, p.f)
+    assert e.value.status == N.FDE_EINVAL
+    S.factor("fp64")
+    u, info = S.solve(p.u0, p.f, rtol=1e-10, maxit=2000)
+    assert info["converged"] == 1

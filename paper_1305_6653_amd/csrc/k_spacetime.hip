@@ -140,24 +140,34 @@ __global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, I
 }
 
 // Time-axis real DFT.  Item = (instance, group of 2*TP spatial columns); TP complex FFTs of
-// length s per workgroup.
-static constexpr int TP = 8;
+// length s per workgroup (TP = 2, 4 or 8, chosen per plan so that the launch has enough
+// workgroups).  Workgroups are dispatched to the eight XCDs in turn; xcd_item() hands each XCD a
+// contiguous range of items, so the column groups that share a cache line of a row are read
+// through the same L2.  The twiddle table (s/2 entries) is copied into LDS behind the data.
+__device__ __forceinline__ int xcd_item(int bid, int n) {
+  const int per = n >> 3, rem = n & 7, x = bid & 7;
+  return x * per + (x < rem ? x : rem) + (bid >> 3);
+}
 
 // If epoch_ctr is set, the first workgroup also draws the next block-solve epoch from the
 // device-wide counter into *epoch_slot (read by the block solve that follows on the stream),
 // so a recorded launch sequence gets a fresh epoch on every replay.
+template <int TP>
 __global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict__ D, ItemMap map,
-                                                     int src_sel, int src_j,
+                                                     int src_sel, int src_j, int max_log2s,
                                                      unsigned long long *epoch_ctr,
                                                      unsigned long long *epoch_slot) {
   extern __shared__ double2 buf[];
   if (epoch_ctr && blockIdx.x == 0 && threadIdx.x == 0) *epoch_slot = atomicAdd(epoch_ctr, 1ull) + 1ull;
-  const int q = item_slot(map, blockIdx.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
   const double *V = vsel(d, src_sel, src_j);
-  const int col0 = (blockIdx.x - map.pre[q]) * 2 * TP;
+  const int col0 = (item - map.pre[q]) * 2 * TP;
+  double2 *twl = buf + ((size_t)TP << max_log2s);
+  for (int i = threadIdx.x; i < s / 2; i += ST_NT) twl[i] = d.tws[i];
   for (int e = threadIdx.x; e < s * 2 * TP; e += ST_NT) {
     const int n = e / (2 * TP), c = e % (2 * TP);
     const int col = col0 + c;
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict_
     reinterpret_cast<double *>(&buf[(c >> 1) * s + n])[c & 1] = v;
   }
   __syncthreads();
-  fft_dif<ST_NT>(buf, log2s, TP, d.tws);
+  fft_dif<ST_NT>(buf, log2s, TP, twl);
   const int nbk = s / 2 + 1;
   for (int e = threadIdx.x; e < nbk * 2 * TP; e += ST_NT) {
     const int k = e / (2 * TP), c = e % (2 * TP), f = c >> 1;
@@ -185,16 +195,20 @@ __global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict_
   }
 }
 
+template <int TP>
 __global__ __launch_bounds__(ST_NT) void k_time_irfft(const InstDesc *__restrict__ D, ItemMap map,
-                                                      int dst_sel, int dst_j) {
+                                                      int dst_sel, int dst_j, int max_log2s) {
   extern __shared__ double2 buf[];
-  const int q = item_slot(map, blockIdx.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int m = d.m, mp = d.mp, log2s = d.log2s, s = 1 << log2s;
   double *W = vsel(d, dst_sel, dst_j);
   const double2 *Wh = d.Vh;
-  const int col0 = (blockIdx.x - map.pre[q]) * 2 * TP;
+  const int col0 = (item - map.pre[q]) * 2 * TP;
+  double2 *twl = buf + ((size_t)TP << max_log2s);
+  for (int i = threadIdx.x; i < s / 2; i += ST_NT) twl[i] = d.tws[i];
   // position p of the bit-reversed input holds Z[k], k = bitrev(p); Z = What_a + i What_b
   for (int e = threadIdx.x; e < s * TP; e += ST_NT) {
     const int p = e / TP, f = e % TP;
@@ -215,7 +229,7 @@ __global__ __launch_bounds__(ST_NT) void k_time_irfft(const InstDesc *__restrict
     buf[f * s + p] = make_double2(a.x - b.y, a.y + b.x);
   }
   __syncthreads();
-  fft_dit_inv<ST_NT>(buf, log2s, TP, d.tws);
+  fft_dit_inv<ST_NT>(buf, log2s, TP, twl);
   const double inv_s = 1.0 / (double)s;
   for (int e = threadIdx.x; e < s * 2 * TP; e += ST_NT) {
     const int n = e / (2 * TP), c = e % (2 * TP);
@@ -307,26 +321,50 @@ hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_
   return hipGetLastError();
 }
 
-hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                            int src_sel, int src_j, hipStream_t st, unsigned long long *epoch_ctr,
-                            unsigned long long *epoch_slot) {
-  if (items <= 0) return hipSuccess;
-  const size_t lds = (sizeof(double2) * TP) << max_log2s;
-  hipError_t e = set_lds((const void *)k_time_rfft, lds);
+template <int TP>
+static hipError_t rfft_tp(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                          int src_sel, int src_j, hipStream_t st, unsigned long long *epoch_ctr,
+                          unsigned long long *epoch_slot) {
+  const size_t lds = ((sizeof(double2) * (2 * TP + 1)) << max_log2s) / 2;
+  hipError_t e = set_lds((const void *)k_time_rfft<TP>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_time_rfft, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j,
-                     epoch_ctr, epoch_slot);
+  hipLaunchKernelGGL(k_time_rfft<TP>, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j,
+                     max_log2s, epoch_ctr, epoch_slot);
   return hipGetLastError();
 }
 
-hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                             int dst_sel, int dst_j, hipStream_t st) {
-  if (items <= 0) return hipSuccess;
-  const size_t lds = (sizeof(double2) * TP) << max_log2s;
-  hipError_t e = set_lds((const void *)k_time_irfft, lds);
+template <int TP>
+static hipError_t irfft_tp(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                           int dst_sel, int dst_j, hipStream_t st) {
+  const size_t lds = ((sizeof(double2) * (2 * TP + 1)) << max_log2s) / 2;
+  hipError_t e = set_lds((const void *)k_time_irfft<TP>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_time_irfft, dim3(items), dim3(ST_NT), lds, st, D, map, dst_sel, dst_j);
+  hipLaunchKernelGGL(k_time_irfft<TP>, dim3(items), dim3(ST_NT), lds, st, D, map, dst_sel, dst_j,
+                     max_log2s);
   return hipGetLastError();
+}
+
+hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                            int cols, int src_sel, int src_j, hipStream_t st,
+                            unsigned long long *epoch_ctr, unsigned long long *epoch_slot) {
+  if (items <= 0) return hipSuccess;
+  switch (cols) {
+    case 4: return rfft_tp<2>(D, map, items, max_log2s, src_sel, src_j, st, epoch_ctr, epoch_slot);
+    case 8: return rfft_tp<4>(D, map, items, max_log2s, src_sel, src_j, st, epoch_ctr, epoch_slot);
+    case 16: return rfft_tp<8>(D, map, items, max_log2s, src_sel, src_j, st, epoch_ctr, epoch_slot);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
+                             int cols, int dst_sel, int dst_j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  switch (cols) {
+    case 4: return irfft_tp<2>(D, map, items, max_log2s, dst_sel, dst_j, st);
+    case 8: return irfft_tp<4>(D, map, items, max_log2s, dst_sel, dst_j, st);
+    case 16: return irfft_tp<8>(D, map, items, max_log2s, dst_sel, dst_j, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_bccb_solve(const InstDesc *D, const ItemMap &map, int items, int max_log2L,
@@ -339,6 +377,12 @@ hipError_t launch_bccb_solve(const InstDesc *D, const ItemMap &map, int items, i
   return hipGetLastError();
 }
 
-int time_fft_cols_per_item() { return 2 * TP; }
+// Spatial columns per time-FFT workgroup: 16 (128-byte row segments) while that still gives
+// the launch at least two workgroups per CU, else 8, else 4.
+int time_fft_cols_per_item(long long total_mp, int cus) {
+  for (int cols = 16; cols > 4; cols >>= 1)
+    if (total_mp / cols >= 2LL * cus) return cols;
+  return 4;
+}
 
 }  // namespace fde

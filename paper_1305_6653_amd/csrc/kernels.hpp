@@ -19,15 +19,16 @@ hipError_t launch_bvm_matvec(const InstDesc *D, const ItemMap &map, int items, i
                              hipStream_t st);
 // b = tau Bhat f - a0 u0 (+ tau b0 J u0), items = s per instance
 hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_ju0, hipStream_t st);
-// items = mp / time_fft_cols_per_item() per instance.  With epoch_ctr set, the launch also
-// draws the next block-solve epoch into *epoch_slot (see launch_trsv_coop).
+// items = mp / cols per instance, cols = time_fft_cols_per_item(sum of mp, CUs) (4, 8 or 16).
+// With epoch_ctr set, the launch also draws the next block-solve epoch into *epoch_slot (see
+// launch_trsv_coop).
 hipError_t launch_time_rfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                            int src_sel, int src_j, hipStream_t st,
+                            int cols, int src_sel, int src_j, hipStream_t st,
                             unsigned long long *epoch_ctr = nullptr,
                             unsigned long long *epoch_slot = nullptr);
 hipError_t launch_time_irfft(const InstDesc *D, const ItemMap &map, int items, int max_log2s,
-                             int dst_sel, int dst_j, hipStream_t st);
-int time_fft_cols_per_item();
+                             int cols, int dst_sel, int dst_j, hipStream_t st);
+int time_fft_cols_per_item(long long total_mp, int cus);
 // BCCB preconditioner solve in the time-frequency domain: for every time frequency k < nb,
 // Vh[k] <- F_m^{-1} diag(1 / (lam_k - tau mu_k lamx)) F_m Vh[k] (space DFTs of order m by
 // Bluestein's chirp method on the power-of-two FFT of length L).  items = nb per instance.

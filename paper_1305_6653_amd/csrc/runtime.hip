@@ -328,6 +328,7 @@ struct SolveMaps {
   int n_mv = 0, n_tfft = 0, n_trsv = 0, n_kry = 0, n_rhs = 0, n_ju0 = 0, n_blk = 0, n_qg = 0;
   int pc = 0, route = FDE_BLOCKS_LU;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
+  int tfft_cols = 16;  // spatial columns per time-FFT workgroup
   int prec = -1;
   double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0;
 };
@@ -1462,12 +1463,20 @@ static fde_status ensure_full_maps(Plan *P) {
   std::vector<int> slots(count), a(count), b(count), c(count), d(count), e(count), f(count), g(count),
       qq(count);
   SolveMaps S;
+  {
+    long long total_mp = 0;
+    for (int q = 0; q < count; ++q) total_mp += P->hs[q]->mp;
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    S.tfft_cols = time_fft_cols_per_item(total_mp, std::max(cus, 1));
+  }
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
     slots[q] = q;
     g[q] = h->nb;
     a[q] = h->s;
-    b[q] = h->mp / time_fft_cols_per_item();
+    b[q] = h->mp / S.tfft_cols;
     c[q] = h->nb * P->desc[q].W;
     d[q] = h->nblk;
     e[q] = h->s;
@@ -1564,20 +1573,20 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
   }
   if (S.pc != FDE_PC_STRANG) {  // BCCB: time DFT, space-Fourier diagonal solve, inverse time DFT
     HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
-      return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st);
+      return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, src, sj, st);
     }));
     HIPCHK(run(L, "bccb_solve", S.bccb_bytes, [&] {
       return launch_bccb_solve(P->d_desc, S.blk, S.n_blk, S.max_log2L, st);
     }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
-      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
+      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
     }));
     return FDE_OK;
   }
   unsigned long long *ctr = nullptr;
   STCHK(epoch_counter(&ctr));
   HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
-    return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, src, sj, st, ctr, P->d_epoch);
+    return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, src, sj, st, ctr, P->d_epoch);
   }));
   if (S.route == FDE_BLOCKS_HESSENBERG) {
     // Q^T v_k, the row exchanges and eliminations, U^{-1}, then Q (the frequency vectors are
@@ -1594,7 +1603,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
     }));
     HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
-      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
+      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
     }));
     return FDE_OK;
   }
@@ -1613,7 +1622,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
                               : launch_trsv<float>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st);
   }));
   HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
-    return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, dst, dj, st);
+    return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
   }));
   return FDE_OK;
 }
@@ -2237,7 +2246,7 @@ extern "C" fde_status fde_time_rfft(fde_bvm *h, const double *v, double *vhat, i
   SolveMaps S;
   STCHK(self_maps(h, S));
   STCHK(copy_in(h, h->d_sio, v, h->n(), mem_space));
-  HIPCHK(launch_time_rfft(h->self->d_desc, S.tfft, S.n_tfft, S.max_log2s, VS_SIO, 0, h->stream));
+  HIPCHK(launch_time_rfft(h->self->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, VS_SIO, 0, h->stream));
   HIPCHK(hipMemcpy2DAsync(vhat, sizeof(double2) * h->m, h->d_Vh, sizeof(double2) * h->mp,
                           sizeof(double2) * h->m, h->nb,
                           mem_space == FDE_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,

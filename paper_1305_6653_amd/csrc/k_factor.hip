@@ -72,10 +72,8 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D
 // computed once, by the pivot's owner), so a step costs one barrier, one batch of LDS reads
 // and at most 64^2/NT complex multiply-adds per thread.
 //
-// Inverses (eight threads per row, eight columns each): forward substitution for L^{-1} and
-// backward substitution for U^{-1}, 63 barrier-separated steps each, the row of the inverse
-// that became final being published every step.  With 1024 threads the two run at once on
-// the two halves of the workgroup; with 512 they run one after the other.
+// Inverses: both triangles at once by recursive doubling (tri_inv_doubling), in the LDS copy
+// of the factored tile.
 template <typename T> struct DiagThreads { static constexpr int value = 1024; };
 template <> struct DiagThreads<double> { static constexpr int value = 512; };
 
@@ -95,53 +93,109 @@ __device__ __forceinline__ c_t<T> recip_checked(c_t<T> z, bool &ok) {
   return mk<T>(z.x * inv, -z.y * inv);
 }
 
-// One step of L^{-1} (unit lower) by rows: rows r > k receive -L[r][k] X[k][:] on the columns
-// c <= k; row k + 1 is then final and is published into pub.
+// acc + a b in T
 template <typename T>
-__device__ __forceinline__ void inv_lower_step(c_t<T> (&y)[8], const c_t<T> (*a)[PB + 1], int r,
-                                               int cq, int k, const c_t<T> *pr, c_t<T> *pub) {
-  if (r > k) {
-    const c_t<T> f = a[r][k];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c = cq + 8 * j;
-      y[j] = csel<T>(c <= k, tsub<T>(y[j], tmul<T>(f, pr[c])), y[j]);
-    }
-  }
-  if (r == k + 1) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) pub[cq + 8 * j] = y[j];
-  }
+__device__ __forceinline__ c_t<T> tfma(c_t<T> a, c_t<T> b, c_t<T> acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
 }
 
-// One step of U^{-1} by rows: rows r < k receive -U[r][k] X[k][:] on the columns c >= k;
-// row k - 1 is then final, is scaled by 1/U[k-1][k-1] and is published into pub.
-template <typename T>
-__device__ __forceinline__ void inv_upper_step(c_t<T> (&y)[8], const c_t<T> (*a)[PB + 1],
-                                               const c_t<T> *dgi, int r, int cq, int k,
-                                               const c_t<T> *pr, c_t<T> *pub) {
-  if (r < k) {
-    const c_t<T> f = a[r][k];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c = cq + 8 * j;
-      y[j] = csel<T>(c >= k, tsub<T>(y[j], tmul<T>(f, pr[c])), y[j]);
-    }
-  }
-  if (r == k - 1) {
-    const c_t<T> iu = dgi[k - 1];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      y[j] = tmul<T>(y[j], iu);
-      pub[cq + 8 * j] = y[j];
-    }
-  }
+// Output e of a doubling level (b = 2^lb): side (lower / upper), block offset o and entry
+// (i, j) of the b x b off-diagonal block; per side there are (32 / b) blocks of b^2 entries.
+struct DblIdx {
+  bool up;
+  int o, i, j;
+};
+template <bool LOWER>
+__device__ __forceinline__ DblIdx dbl_idx(int e, int lb) {
+  const int per = 32 << lb;
+  DblIdx x;
+  x.up = !LOWER || e >= per;
+  const int e2 = (LOWER && x.up) ? e - per : e;
+  const int b = 1 << lb;
+  x.o = (e2 >> (2 * lb)) << (lb + 1);
+  x.i = (e2 >> lb) & (b - 1);
+  x.j = e2 & (b - 1);
+  return x;
 }
 
-template <typename T>
-__device__ __forceinline__ void unit_rows(c_t<T> (&y)[8], int r, int cq) {
+// The inverses of both triangles of a 64x64 LU tile in a[][] (L strictly below the diagonal
+// with an implicit unit diagonal; U on and above it, its diagonal already replaced by the
+// reciprocals), in place, by recursive doubling.  At level b = 1, 2, ..., 32 every diagonal
+// block of size 2b is inverted from its two inverted halves:
+//   lower  [X1 0; L21 X2]^{-1}  has the off-diagonal block  -X2 (L21 X1),
+//   upper  [Y1 U12; 0 Y2]^{-1}  has the off-diagonal block  -Y1 (U12 Y2);
+// the product in parentheses is formed in registers and stored over L21 / U12, then the outer
+// one replaces it.  Six levels of four barriers each, instead of two substitutions of 63
+// barrier-separated steps.  LOWER = false: the upper triangle only.
+template <typename T, int NT, bool LOWER>
+__device__ __forceinline__ void tri_inv_doubling(c_t<T> (*a)[PB + 1]) {
+  typedef c_t<T> C;
+  constexpr int SIDES = LOWER ? 2 : 1;
+  constexpr int NO = (SIDES * 32 * 32 + NT - 1) / NT;  // outputs per thread at b = 32
+  const C zero = mk<T>((T)0, (T)0);
+#pragma unroll 1
+  for (int lb = 0; lb < 6; ++lb) {
+    const int b = 1 << lb, tot = SIDES * (32 << lb);
+    C t[NO];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) y[j] = mk<T>((cq + 8 * j) == r ? (T)1 : (T)0, (T)0);
+    for (int u = 0; u < NO; ++u) {  // inner products
+      const int e = threadIdx.x + NT * u;
+      C acc = zero;
+      if (e < tot) {
+        const DblIdx x = dbl_idx<LOWER>(e, lb);
+        const int o = x.o, i = x.i, j = x.j;
+        if (!x.up) {  // (L21 X1)[i][j] = L21[i][j] + sum_{k > j} L21[i][k] X1[k][j]
+          acc = a[o + b + i][o + j];
+          for (int k = j + 1; k < b; ++k) acc = tfma<T>(a[o + b + i][o + k], a[o + k][o + j], acc);
+        } else {  // (U12 Y2)[i][j] = sum_{k <= j} U12[i][k] Y2[k][j]
+          for (int k = 0; k <= j; ++k) acc = tfma<T>(a[o + i][o + b + k], a[o + b + k][o + b + j], acc);
+        }
+      }
+      t[u] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+      const int e = threadIdx.x + NT * u;
+      if (e < tot) {
+        const DblIdx x = dbl_idx<LOWER>(e, lb);
+        if (!x.up) a[x.o + b + x.i][x.o + x.j] = t[u];
+        else a[x.o + x.i][x.o + b + x.j] = t[u];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {  // outer products, negated
+      const int e = threadIdx.x + NT * u;
+      C acc = zero;
+      if (e < tot) {
+        const DblIdx x = dbl_idx<LOWER>(e, lb);
+        const int o = x.o, i = x.i, j = x.j;
+        if (!x.up) {  // X21[i][j] = -(T[i][j] + sum_{k < i} X2[i][k] T[k][j])
+          acc = a[o + b + i][o + j];
+          for (int k = 0; k < i; ++k) acc = tfma<T>(a[o + b + i][o + b + k], a[o + b + k][o + j], acc);
+        } else {  // Y12[i][j] = -sum_{k >= i} Y1[i][k] T[k][j]
+          for (int k = i; k < b; ++k) acc = tfma<T>(a[o + i][o + k], a[o + k][o + b + j], acc);
+        }
+      }
+      t[u] = mk<T>(-acc.x, -acc.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+      const int e = threadIdx.x + NT * u;
+      if (e < tot) {
+        const DblIdx x = dbl_idx<LOWER>(e, lb);
+        if (!x.up) a[x.o + b + x.i][x.o + x.j] = t[u];
+        else a[x.o + x.i][x.o + b + x.j] = t[u];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 template <typename T, int NT>
@@ -152,7 +206,6 @@ __global__ __launch_bounds__(NT) void k_lu_diag(const InstDesc *__restrict__ Dd,
   __shared__ C a[PB][PB + 1];
   __shared__ C prow[2][PB];
   __shared__ C pcol[2][PB];
-  __shared__ C prowU[2][PB];
   __shared__ C dgi[PB];  // reciprocals of U's diagonal
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
@@ -216,124 +269,59 @@ __global__ __launch_bounds__(NT) void k_lu_diag(const InstDesc *__restrict__ Dd,
     }
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      A[(size_t)r * mp + cl + TPR * j] = x[j];
-      a[r][cl + TPR * j] = x[j];
+      const int c = cl + TPR * j;
+      A[(size_t)r * mp + c] = x[j];
+      a[r][c] = csel<T>(c == r, dgi[r], x[j]);  // U's diagonal by its reciprocal
     }
   }
   if (bad) atomicOr(flag, 1);
+  __syncthreads();  // a[][] complete
+  tri_inv_doubling<T, NT, true>(a);
   C *Dl = dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   C *Du = Dl + PB * PB;
-  C y[8];
-  if (NT == 1024) {
-    const bool lower = tid < 512;  // uniform per wavefront
-    const int tt = tid & 511, r = tt >> 3, cq = tt & 7;
-    unit_rows<T>(y, r, cq);
-    __syncthreads();  // a[][] complete
-    if (lower) {
-      if (r == 0) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = y[j];
-      }
-    } else if (r == PB - 1) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        y[j] = tmul<T>(y[j], dgi[PB - 1]);
-        prowU[1][cq + 8 * j] = y[j];
-      }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int t = 0; t < PB - 1; ++t) {
-      if (lower) inv_lower_step<T>(y, a, r, cq, t, prow[t & 1], prow[(t & 1) ^ 1]);
-      else inv_upper_step<T>(y, a, dgi, r, cq, PB - 1 - t, prowU[(PB - 1 - t) & 1], prowU[(PB - t) & 1]);
-      __syncthreads();
-    }
-    C *Dx = lower ? Dl : Du;  // pointer select
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Dx[r * PB + cq + 8 * j] = y[j];
-  } else {
-    const int r = tid >> 3, cq = tid & 7;
-    unit_rows<T>(y, r, cq);
-    __syncthreads();  // a[][] complete
-    if (r == 0) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) prow[0][cq + 8 * j] = y[j];
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int k = 0; k < PB - 1; ++k) {
-      inv_lower_step<T>(y, a, r, cq, k, prow[k & 1], prow[(k & 1) ^ 1]);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Dl[r * PB + cq + 8 * j] = y[j];
-    unit_rows<T>(y, r, cq);
-    if (r == PB - 1) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        y[j] = tmul<T>(y[j], dgi[PB - 1]);
-        prowU[1][cq + 8 * j] = y[j];
-      }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int k = PB - 1; k >= 1; --k) {
-      inv_upper_step<T>(y, a, dgi, r, cq, k, prowU[k & 1], prowU[(k & 1) ^ 1]);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = y[j];
+  const C zero = mk<T>((T)0, (T)0), one = mk<T>((T)1, (T)0);
+  for (int e = tid; e < PB * PB; e += NT) {
+    const int r = e / PB, c = e % PB;
+    const C v = a[r][c];
+    Dl[e] = csel<T>(r > c, v, csel<T>(r == c, one, zero));
+    Du[e] = csel<T>(r <= c, v, zero);
   }
 }
 
 // Inverse of the upper triangle of a diagonal 64x64 tile of U (the Hessenberg route: U comes
-// from the shifted Hessenberg LU).  Item = (instance, block, panel); 512 threads as in the FP64
-// diagonal factorization: thread (r, cq) holds row r, columns cq + 8j of the inverse.
+// from the shifted Hessenberg LU), by the same recursive doubling as the LU route.
+// Item = (instance, block, panel); 512 threads.
 template <typename T>
 __global__ __launch_bounds__(512) void k_hess_uinv(const InstDesc *__restrict__ Dd, ItemMap map,
                                                    int *__restrict__ flag) {
   typedef c_t<T> C;
   __shared__ C a[PB][PB + 1];
-  __shared__ C prowU[2][PB];
-  __shared__ C dgi[PB];
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int local = blockIdx.x - map.pre[q], tid = threadIdx.x;
   const int mp = d.mp, npan = d.npan, blk = local / npan, p = local % npan;
   const C *A = (const C *)d.K + (size_t)blk * mp * mp + (size_t)p * PB * mp + (size_t)p * PB;
-  const int r = tid >> 3, cq = tid & 7;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int c = cq + 8 * j;
-    a[r][c] = c >= r ? A[(size_t)r * mp + c] : mk<T>((T)0, (T)0);
-  }
-  __syncthreads();
+  const C zero = mk<T>((T)0, (T)0);
   int bad = 0;
-  if (cq == 0) {
-    bool ok;
-    dgi[r] = recip_checked<T>(a[r][r], ok);
-    bad = ok ? 0 : 1;
-  }
-  __syncthreads();
-  C y[8];
-  unit_rows<T>(y, r, cq);
-  if (r == PB - 1) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      y[j] = tmul<T>(y[j], dgi[PB - 1]);
-      prowU[1][cq + 8 * j] = y[j];
+  for (int e = tid; e < PB * PB; e += 512) {
+    const int r = e / PB, c = e % PB;
+    C v = zero;
+    if (c >= r) v = A[(size_t)r * mp + c];
+    if (c == r) {
+      bool ok;
+      v = recip_checked<T>(v, ok);
+      bad |= ok ? 0 : 1;
     }
+    a[r][c] = v;
   }
   __syncthreads();
-#pragma unroll 1
-  for (int k = PB - 1; k >= 1; --k) {
-    inv_upper_step<T>(y, a, dgi, r, cq, k, prowU[k & 1], prowU[(k & 1) ^ 1]);
-    __syncthreads();
-  }
+  tri_inv_doubling<T, 512, false>(a);
   C *Du = (C *)d.dinv + ((size_t)(blk * npan + p) * 2 + 1) * PB * PB;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) Du[r * PB + cq + 8 * j] = y[j];
+  for (int e = tid; e < PB * PB; e += 512) {
+    const int r = e / PB, c = e % PB;
+    Du[e] = csel<T>(r <= c, a[r][c], zero);
+  }
   if (bad) atomicOr(flag, 1);
 }
 

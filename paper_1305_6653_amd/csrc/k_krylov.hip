@@ -197,6 +197,23 @@ hipError_t launch_cgs_update(const InstDesc *D, const ItemMap &map, int items, i
 // i = 0..j+1.  i > 0: h_{i-1} = <v_{i-1}, w> from the partials of launch i-1; w -= h v_{i-1}.
 // i <= j: partial <v_i, w>;  i == j+1: partial <w, w>.  Launch i reads part[(i+1)&1] and
 // writes part[i&1].
+static constexpr int MGS_U = 4;
+
+__device__ __forceinline__ void mgs_load(const double *w, const double *vp, const double *vc,
+                                         size_t e0, size_t end, int i, int j, double (&we)[MGS_U],
+                                         double (&pe)[MGS_U], double (&ce)[MGS_U]) {
+#pragma unroll
+  for (int u = 0; u < MGS_U; ++u) {
+    const size_t e = e0 + (size_t)u * KR_NT;
+    we[u] = pe[u] = ce[u] = 0.0;
+    if (e < end) {
+      we[u] = w[e];
+      if (i > 0) pe[u] = vp[e];
+      if (i <= j) ce[u] = vc[e];
+    }
+  }
+}
+
 __global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__ D, ItemMap map,
                                                     int i, int j) {
   __shared__ double red[KR_NT / 64];
@@ -205,22 +222,40 @@ __global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__
   const InstDesc &d = *c.d;
   const double *pin = (i & 1) ? d.part0 : d.part1;
   double *pout = (i & 1) ? d.part1 : d.part0;
+  const double *vp = d.V + (size_t)(i > 0 ? i - 1 : 0) * c.n;
+  const double *vc = d.V + (size_t)(i <= j ? i : 0) * c.n;
+  double *w = d.w;
+  // MGS_U elements per thread and pass, all loaded before any is stored (the stores to w could
+  // alias the loads for the compiler, which would otherwise serialise the passes); the first
+  // pass is loaded before the coefficient of the previous projection is summed.
+  double we[MGS_U], pe[MGS_U], ce[MGS_U];
+  size_t e0 = c.begin + threadIdx.x;
+  mgs_load(w, vp, vc, e0, c.end, i, j, we, pe, ce);
   double h = 0.0;
   if (i > 0) {
     h = sum_partials(pin, d.nblk, red);
     if (c.b == 0 && threadIdx.x == 0) d.H[i - 1] = h;
   }
-  const double *vp = d.V + (size_t)(i > 0 ? i - 1 : 0) * c.n;
-  const double *vc = d.V + (size_t)(i <= j ? i : 0) * c.n;
-  double *w = d.w;
   double acc = 0.0;
-  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) {
-    double we = w[e];
-    if (i > 0) {
-      we = fma(-h, vp[e], we);
-      w[e] = we;
+  for (;;) {
+    // out-of-range elements were loaded as zeros and add nothing; the stores come last so that
+    // no wait for a store's completion lands between them
+#pragma unroll
+    for (int u = 0; u < MGS_U; ++u) {
+      const double x = i > 0 ? fma(-h, pe[u], we[u]) : we[u];
+      acc = fma(i <= j ? ce[u] : x, x, acc);
+      we[u] = x;
     }
-    acc = (i <= j) ? fma(vc[e], we, acc) : fma(we, we, acc);
+    if (i > 0) {
+#pragma unroll
+      for (int u = 0; u < MGS_U; ++u) {
+        const size_t e = e0 + (size_t)u * KR_NT;
+        if (e < c.end) w[e] = we[u];
+      }
+    }
+    e0 += (size_t)MGS_U * KR_NT;
+    if (e0 >= c.end) break;
+    mgs_load(w, vp, vc, e0, c.end, i, j, we, pe, ce);
   }
   acc = block_sum<KR_NT>(acc, red);
   if (threadIdx.x == 0) pout[c.b] = acc;
@@ -235,15 +270,35 @@ __global__ __launch_bounds__(KR_NT) void k_normalize(const InstDesc *__restrict_
   const Chunk c = chunk_of(D, map);
   if (!c.d) return;
   const InstDesc &d = *c.d;
+  const double *src = vsel(d, src_sel, src_j);
+  double *dst = vsel(d, dst_sel, dst_j);
+  double x[MGS_U];  // the first pass is loaded before the norm is summed
+  size_t e0 = c.begin + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < MGS_U; ++u) {
+    const size_t e = e0 + (size_t)u * KR_NT;
+    x[u] = e < c.end ? src[e] : 0.0;
+  }
   const double nrm = sqrt(sum_partials(psel ? d.part1 : d.part0, d.nblk, red));
   if (c.b == 0 && threadIdx.x == 0) {
     if (hidx >= 0) d.H[hidx] = nrm;
     else d.nrm[0] = nrm;
   }
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  const double *src = vsel(d, src_sel, src_j);
-  double *dst = vsel(d, dst_sel, dst_j);
-  for (size_t e = c.begin + threadIdx.x; e < c.end; e += KR_NT) dst[e] = src[e] * inv;
+  for (;;) {
+#pragma unroll
+    for (int u = 0; u < MGS_U; ++u) {
+      const size_t e = e0 + (size_t)u * KR_NT;
+      if (e < c.end) dst[e] = x[u] * inv;
+    }
+    e0 += (size_t)MGS_U * KR_NT;
+    if (e0 >= c.end) break;
+#pragma unroll
+    for (int u = 0; u < MGS_U; ++u) {
+      const size_t e = e0 + (size_t)u * KR_NT;
+      x[u] = e < c.end ? src[e] : 0.0;
+    }
+  }
 }
 
 // v_0 = b - tmp (tmp = M x), partial <v_0, v_0> into part0.

@@ -105,6 +105,14 @@ struct GmresWork {
 enum GateSel : int { GATE_LIVE = 0, GATE_ACTIVE, GATE_X0, GATE_COUNT };
 
 // Returns the position q in the map with pre[q] <= item < pre[q+1].
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD b mod 8).  This
+// bijection of [0, n) gives XCD x a contiguous range of item indices, so items that share data
+// (neighbouring columns, the tiles of one block) are served by the same L2.
+__device__ __forceinline__ int xcd_item(int bid, int n) {
+  const int per = n >> 3, rem = n & 7, x = bid & 7;
+  return x * per + (x < rem ? x : rem) + (bid >> 3);
+}
+
 __device__ __forceinline__ int item_slot(const ItemMap &mp, int item) {
   int lo = 0, hi = mp.count - 1;
   while (lo < hi) {

@@ -395,11 +395,14 @@ __device__ __forceinline__ void tile_zero(acc_t<T> (&cre)[2][2], acc_t<T> (&cim)
       }
 }
 
-// 64x64 complex GEMM on one workgroup (4 wavefronts, 32x32 each): acc (+/-)= A B with
-// A 64 x (nsl US), B (nsl US) x 64.  The K dimension streams through LDS in slices of US,
+// 64x64 complex GEMM on one workgroup (4 wavefronts, 32x32 each): (cre, cim) = (+/-) A B
+// with A 64 x (nsl US), B (nsl US) x 64.  The K dimension streams through LDS in slices of US,
 // double-buffered: while the MFMAs of slice s read LDS, the registers already hold slice
 // s + 1 (loaded once per workgroup, 16-byte coalesced), stored to the other buffer before the
 // slice's barrier.  Every read of A and B completes before the function returns.
+// Complex products take three real MFMAs instead of four (the 3M form of a complex GEMM):
+//   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),   Re = P1 - P2,  Im = P3 - P1 - P2,
+// with three accumulators; the operand sums cost two additions per LDS read.
 static constexpr int US = 8;
 
 template <typename T>
@@ -421,6 +424,14 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
   const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
   const C *Ap = A + (size_t)ar * lda + ac;
   const C *Bp = B + (size_t)br * ldb + bc;
+  acc_t<T> p1[2][2], p2[2][2], p3[2][2];
+  tile_zero<T>(p1, p2);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
   C ra0 = Ap[0], ra1 = Ap[1], rb0 = Bp[0], rb1 = Bp[1];  // slice 0
   sm.As[0][ar][ac] = ra0;
   sm.As[0][ar][ac + 1] = ra1;
@@ -445,15 +456,18 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
       for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
 #pragma unroll
       for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
+      T bs[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const T ar_ = NEG ? -a[r].x : a[r].x, ai_ = NEG ? -a[r].y : a[r].y;
+        const T as_ = ar_ + ai_;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          cre[r][c] = mfma16(ar_, b[c].x, cre[r][c]);
-          cre[r][c] = mfma16(-ai_, b[c].y, cre[r][c]);
-          cim[r][c] = mfma16(ar_, b[c].y, cim[r][c]);
-          cim[r][c] = mfma16(ai_, b[c].x, cim[r][c]);
+          p1[r][c] = mfma16(ar_, b[c].x, p1[r][c]);
+          p2[r][c] = mfma16(ai_, b[c].y, p2[r][c]);
+          p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
         }
       }
     }
@@ -465,6 +479,15 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cre[r][c][v] = p1[r][c][v] - p2[r][c][v];
+        cim[r][c][v] = p3[r][c][v] - p1[r][c][v] - p2[r][c][v];
+      }
 }
 
 // Panel.  Item = (instance, block, t): t < nrem -> L21 tile t = A21_t U11^{-1};
@@ -475,17 +498,17 @@ __global__ __launch_bounds__(256, 3) void k_lu_panel(const InstDesc *__restrict_
                                                      int p) {
   typedef c_t<T> C;
   __shared__ GemmLds<T> sm;
-  const int q = item_slot(map, blockIdx.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
-  const int local = blockIdx.x - map.pre[q];
+  const int local = item - map.pre[q];
   const int blk = local / (2 * nrem), t = local % (2 * nrem);
   C *Kb = (C *)d.K + (size_t)blk * mp * mp;
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   acc_t<T> cre[2][2], cim[2][2];
-  tile_zero<T>(cre, cim);
   const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   const C *Du = Dl + PB * PB;
   C *Ct;
@@ -515,11 +538,12 @@ __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict
                                                       int p, int mode) {
   typedef c_t<T> C;
   __shared__ GemmLds<T> sm;
-  const int q = item_slot(map, blockIdx.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - p - 1;
-  const int local = blockIdx.x - map.pre[q];
+  const int local = item - map.pre[q];
   const int per = update_tiles(mode, nrem);
   const int blk = local / per, t = local % per;
   int ti, tj;
@@ -539,9 +563,8 @@ __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict
   C *Ct = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)(p + 1 + tj) * PB + (size_t)wr * mp + wc;
   const C *A = Kb + (size_t)(p + 1 + ti) * PB * mp + (size_t)p * PB;  // 64 x K, row stride mp
   const C *B = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + tj) * PB;  // K x 64, row stride mp
-  // acc = -A B from zero; C is added at the end (keeps the C tile out of the loop's registers)
+  // acc = -A B; C is added at the end (keeps the C tile out of the loop's registers)
   acc_t<T> cre[2][2], cim[2][2];
-  tile_zero<T>(cre, cim);
   gemm64_lds<T, true>(A, mp, B, mp, (mode == 2 ? 2 * PB : PB) / US, sm, cre, cim);
   tile_add_store<T>(Ct, mp, cre, cim);
 }

@@ -141,13 +141,9 @@ __global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, I
 
 // Time-axis real DFT.  Item = (instance, group of 2*TP spatial columns); TP complex FFTs of
 // length s per workgroup (TP = 2, 4 or 8, chosen per plan so that the launch has enough
-// workgroups).  Workgroups are dispatched to the eight XCDs in turn; xcd_item() hands each XCD a
-// contiguous range of items, so the column groups that share a cache line of a row are read
-// through the same L2.  The twiddle table (s/2 entries) is copied into LDS behind the data.
-__device__ __forceinline__ int xcd_item(int bid, int n) {
-  const int per = n >> 3, rem = n & 7, x = bid & 7;
-  return x * per + (x < rem ? x : rem) + (bid >> 3);
-}
+// workgroups).  Items in XCD-contiguous order (xcd_item), so the column groups that share a
+// cache line of a row are read through the same L2.  The twiddle table (s/2 entries) is copied
+// into LDS behind the data.
 
 // If epoch_ctr is set, the first workgroup also draws the next block-solve epoch from the
 // device-wide counter into *epoch_slot (read by the block solve that follows on the stream),

@@ -793,6 +793,16 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
       const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
       for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
         const int p0 = P * PB;
+        const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
+        // FP32: touch every 128-byte line of the diagonal inverse now, so that its read after
+        // the off-diagonal GEMV (on the dependency chain of the sweep) hits L2; the touched
+        // values enter the result as x * 0 (they are finite), which keeps the loads.  (For FP64
+        // factors the extra loads cost more than they save.)
+        constexpr int TL = sizeof(T) == 4 ? 1 : 0;  // lines per thread
+        double touch[TL > 0 ? TL : 1];
+#pragma unroll
+        for (int u = 0; u < TL; ++u)
+          touch[u] = (double)reinterpret_cast<const T *>(Di)[(size_t)(threadIdx.x * TL + u) * (128 / sizeof(T))];
         double2 acc[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
@@ -824,12 +834,13 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
           }
         }
         __syncthreads();
-        const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
         double2 x[4], b[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) x[j] = tmp[chunk_col<T>(j, cs)];
 #pragma unroll
         for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < TL; ++u) b[0].x = fma(touch[u], 0.0, b[0].x);
         chunk_gemv<T>(Di + (size_t)r16 * PB, PB, x, b);
 #pragma unroll
         for (int g = 0; g < 4; ++g) {

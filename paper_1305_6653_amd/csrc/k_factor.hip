@@ -21,8 +21,57 @@ namespace fde {
 static constexpr int PB = 64;  // panel width / tile size
 
 // ------------------------------------------------------------------------------------
-// Assembly.  Item = (instance, row i, chunk of kchunk blocks).
-// J[i][j] = dx^{-a} (d+_i g_{i-j+1} + d-_i g_{j-i+1}), g_k = 0 outside 0..m.
+// Assembly.  K_k[i][j] = lam_k delta_ij - tau mu_k J[i][j],
+// J[i][j] = dx^{-a} (d+_i g_{i-j+1} + d-_i g_{j-i+1}), g_k = 0 outside 0..m; the pad rows and
+// columns (i or j >= m) carry the unit diagonal.  Computed in FP64, rounded once to T.
+struct EntryGen {  // the scalars of one block, read once (stores to K could alias them)
+  double tau, scale;
+  double2 mu, lam;
+  int m;
+  const double *g, *dp, *dm;
+};
+__device__ __forceinline__ EntryGen entry_gen(const InstDesc &d, int k) {
+  EntryGen e;
+  e.tau = d.tau;
+  e.scale = d.scale;
+  e.mu = d.mu[k];
+  e.lam = d.lam[k];
+  e.m = d.m;
+  e.g = d.g;
+  e.dp = d.dp;
+  e.dm = d.dm;
+  return e;
+}
+
+__device__ __forceinline__ double j_entry(const EntryGen &e, int i, int j) {
+  if (i >= e.m || j >= e.m) return 0.0;
+  const int dd = i - j, m = e.m;
+  const double gp = (dd >= -1 && dd + 1 <= m) ? e.g[dd + 1] : 0.0;
+  const double gm = (dd <= 1 && 1 - dd <= m) ? e.g[1 - dd] : 0.0;
+  return e.scale * fma(e.dp[i], gp, e.dm[i] * gm);
+}
+
+template <typename T>
+__device__ __forceinline__ c_t<T> block_entry(const EntryGen &e, int i, int j, double Jij) {
+  double re = -e.tau * e.mu.x * Jij, im = -e.tau * e.mu.y * Jij;
+  if (i == j) {
+    if (i < e.m) {
+      re += e.lam.x;
+      im += e.lam.y;
+    } else {
+      re = 1.0;
+      im = 0.0;
+    }
+  }
+  return mk<T>((T)re, (T)im);
+}
+
+// The LU reads the entries of the first two block rows and columns (i or j < ASM_LEAD) before
+// any update; the others are first read by the trailing update of the first pair of steps,
+// which forms them itself (k_lu_update, p = 0).  So the assembly writes only the former.
+// Item = (instance, row i, chunk of kchunk blocks).
+static constexpr int ASM_LEAD = 2 * PB;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D, ItemMap map,
                                                   int kchunk) {
@@ -30,33 +79,21 @@ __global__ __launch_bounds__(256) void k_assemble(const InstDesc *__restrict__ D
   if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
   const int local = blockIdx.x - map.pre[q];
-  const int m = d.m, mp = d.mp, nb = d.nb;
+  const int mp = d.mp, nb = d.nb;
   const int nkc = (nb + kchunk - 1) / kchunk;
   const int i = local / nkc;
   const int k0 = (local % nkc) * kchunk;
   const int k1 = min(nb, k0 + kchunk);
+  const int jend = i < ASM_LEAD ? mp : min(mp, ASM_LEAD);
   c_t<T> *K = (c_t<T> *)d.K;
-  const double tau = d.tau, scale = d.scale;
-  for (int j = threadIdx.x; j < mp; j += 256) {
-    double Jij = 0.0;
-    if (i < m && j < m) {
-      const int dd = i - j;
-      const double gp = (dd >= -1 && dd + 1 <= m) ? d.g[dd + 1] : 0.0;
-      const double gm = (dd <= 1 && 1 - dd <= m) ? d.g[1 - dd] : 0.0;
-      Jij = scale * fma(d.dp[i], gp, d.dm[i] * gm);
-    }
+  const EntryGen e0 = entry_gen(d, 0);
+  for (int j = threadIdx.x; j < jend; j += 256) {
+    const double Jij = j_entry(e0, i, j);
     for (int k = k0; k < k1; ++k) {
-      double re = -tau * d.mu[k].x * Jij, im = -tau * d.mu[k].y * Jij;
-      if (i == j) {
-        if (i < m) {
-          re += d.lam[k].x;
-          im += d.lam[k].y;
-        } else {
-          re = 1.0;
-          im = 0.0;
-        }
-      }
-      K[((size_t)k * mp + i) * mp + j] = mk<T>((T)re, (T)im);
+      EntryGen e = e0;
+      e.mu = d.mu[k];
+      e.lam = d.lam[k];
+      K[((size_t)k * mp + i) * mp + j] = block_entry<T>(e, i, j, Jij);
     }
   }
 }
@@ -566,7 +603,25 @@ __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict
   // acc = -A B; C is added at the end (keeps the C tile out of the loop's registers)
   acc_t<T> cre[2][2], cim[2][2];
   gemm64_lds<T, true>(A, mp, B, mp, (mode == 2 ? 2 * PB : PB) / US, sm, cre, cim);
-  tile_add_store<T>(Ct, mp, cre, cim);
+  if (mode == 2 && p == 0) {  // first touch of these tiles: C is formed here, not read
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int i0 = (p + 1 + ti) * PB + wr, j0 = (p + 1 + tj) * PB + wc;
+    const EntryGen e = entry_gen(d, blk);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + r * 16 + mfma_row<T>(lk, v), j = j0 + c * 16 + li;
+          const C z = block_entry<T>(e, i, j, j_entry(e, i, j));
+          cre[r][c][v] += z.x;
+          cim[r][c][v] += z.y;
+        }
+    tile_store<T>(Ct, mp, cre, cim);
+  } else {
+    tile_add_store<T>(Ct, mp, cre, cim);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -856,6 +911,7 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
 // ------------------------------------------------------------------------------------
 static constexpr int ASM_KCHUNK = 8;
 int assemble_items(int mp, int nb) { return mp * ((nb + ASM_KCHUNK - 1) / ASM_KCHUNK); }
+int assemble_lead() { return ASM_LEAD; }
 
 template <typename T>
 hipError_t launch_assemble(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {

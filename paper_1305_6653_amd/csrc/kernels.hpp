@@ -37,6 +37,9 @@ hipError_t launch_bccb_solve(const InstDesc *D, const ItemMap &map, int items, i
 
 // ---- preconditioner blocks (T = double or float factor storage) ----
 int assemble_items(int mp, int nb);
+// rows and columns of every block written by the assembly (the first trailing update forms
+// the rest)
+int assemble_lead();
 template <typename T>
 hipError_t launch_assemble(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 // items: nb (diag), 2 nrem nb (panel), nrem^2 nb (update) per instance, nrem = mp/64 - p - 1

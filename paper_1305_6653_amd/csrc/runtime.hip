@@ -1223,7 +1223,10 @@ static fde_status factor_plan_impl(Plan *P) {
   for (int i = 0; i < count; ++i) {
     slots[i] = i;
     maxpan = std::max(maxpan, P->hs[i]->npan);
-    asm_bytes += (double)P->hs[i]->nb * P->hs[i]->m * P->hs[i]->m * sizeof(T) * 2.0;
+    // the assembly writes the first two block rows and columns (the rest is formed by the
+    // first trailing update)
+    const double mm = P->hs[i]->m, rest = std::max(0.0, mm - assemble_lead());
+    asm_bytes += (double)P->hs[i]->nb * (mm * mm - rest * rest) * sizeof(T) * 2.0;
   }
   auto nrem_of = [&](int i, int p) { return P->hs[i]->npan - p - 1; };
   // maps: assemble, then per pair (diag p, panel p, band p, diag p+1, panel p+1, rest p)

@@ -93,6 +93,45 @@ def measured_traffic(workload_name, prec, kernel):
     return PMC_TRAFFIC.get((workload_name, prec, kernel))
 
 
+_MFMA_PEAK = {}
+
+
+def measured_mfma_peak(prec):
+    """Matrix-core rate on this GPU, TFLOP/s: the library's probe of back-to-back 16x16x4 MFMAs
+    (FP64, or FP32 for the mixed form; best of 5), outside the timed region."""
+    if prec not in _MFMA_PEAK:
+        import ctypes as C
+        from paper_1305_6653_amd import _native as N
+        v = C.c_double()
+        N.check(N.lib().fde_mfma_peak_probe(1 if prec == "fp64" else 0, 5, C.byref(v)))
+        _MFMA_PEAK[prec] = round(v.value, 2)
+    return _MFMA_PEAK[prec]
+
+
+FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "hess_uinv")
+
+
+def kernel_table(prof, steps, prec):
+    """Per kernel and step: time, launches, average launch, and the algorithmic rate of its
+    launches (bytes or flops recorded by the library per launch) as a fraction of the roofline
+    that bounds it (HBM 8 TB/s; FP64/FP32 MFMA for the LU GEMMs; FP64 vector for the others)."""
+    out = {}
+    for k, v in prof.items():
+        row = {"total_ms": round(v["total_ms"] / steps, 4), "count": v["count"] // steps,
+               "avg_us": round(1e3 * v["total_ms"] / max(1, v["count"]), 2)}
+        if v.get("work") and v["total_ms"] > 0:
+            rate = v["work"] / (v["total_ms"] * 1e-3)
+            if k in FLOP_KERNELS:
+                peak = PEAK_FP32_TFLOPS if (prec == "mixed" and k in ("lu_panel", "lu_update")) else PEAK_FP64_TFLOPS
+                row["TFLOPs"] = round(rate / 1e12, 3)
+                row["frac"] = round(rate / 1e12 / peak, 4)
+            else:
+                row["GBs"] = round(rate / 1e9, 1)
+                row["frac"] = round(rate / 1e9 / PEAK_HBM_GBS, 4)
+        out[k] = row
+    return out
+
+
 def measured_read_peak():
     """Achievable HBM read bandwidth on this GPU, GB/s: the library's streaming-read probe over
     4 GiB (best of 5), outside the timed region.  Context for the datasheet peak."""
@@ -203,6 +242,9 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
             # the work is counted as 8 real flops per complex multiply-add; the 3M form of the
             # complex GEMM issues 3 real MFMA products per complex one, i.e. 6 of those 8 flops
             out["mfma_executed_frac"] = round(0.75 * achieved / peak, 4)
+            mp = measured_mfma_peak(prec)
+            out["measured_mfma_peak"] = mp
+            out["mfma_executed_frac_of_measured_peak"] = round(0.75 * achieved / mp, 4)
         return out
     achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e9
     out = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
@@ -238,8 +280,15 @@ def cpu_baseline(p):
     sample = (f"{len(times)} full oracle solves of the same workload (m={p.m}, s={p.s}, {p.bvm}): "
               f"{p.s // 2 + 1} LAPACK block LUs + {res.iters} GMRES iterations each, tol 1e-10; "
               f"median time per solve")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 4), "repeats": len(times), "iters": res.iters}, res.x
+            "sample": sample, "seconds": round(dt, 4), "repeats": len(times), "iters": res.iters,
+            "cpu_model": model, "logical_cpus": os.cpu_count()}, res.x
 
 
 def bench_batch(args):
@@ -311,8 +360,7 @@ def bench_batch(args):
         "sequential_fp64_ms": round(ms_seq, 3),
         "speedup_vs_sequential_fp64": round(ms_seq / ms, 3),
         "iters_fp64_mean": float(np.mean(iters_fp64)),
-        "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4), "count": v["count"] // args.steps}
-                    for k, v in prof.items()},
+        "kernels": kernel_table(prof, args.steps, "mixed"),
         "roofline": roofline(prof, "mixed", "c4"), "cpu_baseline": None,
     }
     calib_copy(args.calib_copy_mib)
@@ -421,8 +469,7 @@ def main():
         "t_factor_ms": round(infos[-1]["t_factor_ms"], 3),
         "t_solve_ms": round(infos[-1]["t_solve_ms"], 3),
         "profiled_ms_per_step": round(ms_prof, 4),
-        "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4), "count": v["count"] // args.steps}
-                    for k, v in prof.items()},
+        "kernels": kernel_table(prof, args.steps, prec),
         "roofline": roofline(prof, prec, args.workload, read_peak),
         "autotuned": autotune_report(),
     }
@@ -435,7 +482,22 @@ def main():
             "t_factor_ms": round(infos2[-1]["t_factor_ms"], 3),
             "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
+            "kernels": kernel_table(prof2, args.steps, "mixed"),
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
+        }
+    if not args.no_mixed and prec == "mixed":
+        # the plain FP64 form of the same workload, for the mixed-vs-FP64 comparison
+        ms2, _, infos2, prof2 = timed_steps(S, u0, f, out, "fp64", args.steps, args.warmup)
+        u_fp64 = out.cpu().numpy()
+        result["fp64"] = {
+            "ms_per_step": round(ms2, 4), "value": round(1000.0 / ms2, 4), "iters": infos2[-1]["iters"],
+            "true_relres": infos2[-1]["true_relres"],
+            "t_factor_ms": round(infos2[-1]["t_factor_ms"], 3),
+            "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
+            "rel_diff_vs_mixed": float(np.linalg.norm(u_fp64 - u_main) / np.linalg.norm(u_main)),
+            "mixed_speedup": round(ms2 / ms, 3),
+            "kernels": kernel_table(prof2, args.steps, "fp64"),
+            "roofline": roofline(prof2, "fp64", args.workload, read_peak),
         }
     if not args.no_hessenberg and prec == "fp64":
         # the same preconditioner S with its blocks through one Hessenberg form of J
@@ -450,8 +512,7 @@ def main():
                 "t_factor_ms": round(infos4[-1]["t_factor_ms"], 3),
                 "t_solve_ms": round(infos4[-1]["t_solve_ms"], 3),
                 "rel_diff_vs_lu": float(np.linalg.norm(u4 - u_main) / np.linalg.norm(u_main)),
-                "kernels": {k: {"total_ms": round(v["total_ms"] / args.steps, 4),
-                                "count": v["count"] // args.steps} for k, v in prof4.items()},
+                "kernels": kernel_table(prof4, args.steps, form),
                 "roofline": roofline(prof4, form, args.workload + "h", read_peak),
             }
         S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_LU)

@@ -251,6 +251,11 @@ fde_status fde_autotune_report(char *buf, int len);
  * that bandwidth-bound kernels can practically reach on the current device.  FDE_EINVAL for
  * bytes < 1 MiB or reps < 1; FDE_ENOMEM if the buffer cannot be allocated. */
 fde_status fde_read_bandwidth_probe(size_t bytes, int reps, double *gbs);
+/* Measurement aid: the best of `reps` timed launches of a kernel that issues back-to-back
+ * 16x16x4 MFMA products on register operands (FP64 if fp64 != 0, else FP32 — the instructions
+ * of the blocked LU) on every SIMD, in TFLOP/s: the matrix-core rate MFMA-bound kernels can
+ * practically reach on the current device.  FDE_EINVAL for reps < 1 or a null tflops. */
+fde_status fde_mfma_peak_probe(int fp64, int reps, double *tflops);
 
 /* ---- the individual steps of the path, for per-kernel checks ----------------------- */
 /* b = right-hand side of eq. (1.10) in s-form, [s][m]. */

@@ -95,6 +95,7 @@ SIGNATURES = [
     ("fde_bvm_get_option", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
     ("fde_autotune_report", C.c_int, [C.c_char_p, C.c_int]),
     ("fde_read_bandwidth_probe", C.c_int, [C.c_size_t, C.c_int, _dp]),
+    ("fde_mfma_peak_probe", C.c_int, [C.c_int, C.c_int, _dp]),
     ("fde_build_rhs", C.c_int, [_VP, _VP, _VP, _VP, C.c_int]),
     ("fde_apply_matvec", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("fde_toeplitz_apply", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_int]),

@@ -16,16 +16,54 @@
 
 namespace fde {
 
-// Two consecutive radix-2 stages are done together in registers (a radix-4 pass: a thread
-// loads the four elements i, i+h, i+2h, i+3h of a group of 4h, applies both stages and stores
-// them back), so a length-N transform takes ceil(log2 N / 2) barriers instead of log2 N.  Each
-// element sees exactly the operations of the radix-2 stages, in the same order.
+// Consecutive radix-2 stages are done together in registers: three per pass (a radix-8 pass:
+// a thread loads the eight elements i + r h, r < 8, of a group of 8h, applies the three stages
+// and stores them back), the one or two left over in a radix-2 or radix-4 pass, so a length-N
+// transform takes about log2(N) / 3 barriers instead of log2 N.  Each element sees exactly the
+// operations of the radix-2 stages, in the same order.
 
+// DIF stage with half-span H on a pair at offset o of its group: (a, c) -> (a + c, (a - c) w),
+// w = tw[o << (log2 N - 1 - log2 H)].
 template <int NT>
 __device__ __forceinline__ void fft_dif(double2 *buf, int log2N, int nbatch,
                                         const double2 *__restrict__ tw) {
   const int N = 1 << log2N;
   int lh = log2N - 1;  // half-span of the next radix-2 stage is 2^lh
+  for (; lh >= 2; lh -= 3) {
+    // stages with half-spans 4h (= 2^lh), 2h and h: groups of 8h
+    const int h = 1 << (lh - 2);
+    const int q8 = N >> 3, tsh = log2N - 1 - lh;
+    const int total = nbatch * q8;
+    for (int b = threadIdx.x; b < total; b += NT) {
+      const int f = b >> (log2N - 3), bb = b & (q8 - 1);
+      const int j = bb & (h - 1), grp = bb >> (lh - 2);
+      const int i0 = (f << log2N) + (grp << (lh + 1)) + j;
+      double2 x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = buf[i0 + r * h];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // half-span 4h, offset j + r h
+        const double2 a = x[r], c = x[r + 4];
+        x[r] = cadd(a, c);
+        x[r + 4] = cmul(csub(a, c), tw[(j + r * h) << tsh]);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; r += (r & 1) ? 3 : 1) {  // r = 0, 1, 4, 5: half-span 2h, offset j + (r & 1) h
+        const double2 a = x[r], c = x[r + 2];
+        x[r] = cadd(a, c);
+        x[r + 2] = cmul(csub(a, c), tw[(j + (r & 1) * h) << (tsh + 1)]);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; r += 2) {  // half-span h, offset j
+        const double2 a = x[r], c = x[r + 1];
+        x[r] = cadd(a, c);
+        x[r + 1] = cmul(csub(a, c), tw[j << (tsh + 2)]);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[i0 + r * h] = x[r];
+    }
+    __syncthreads();
+  }
   for (; lh >= 1; lh -= 2) {
     // stages with half-spans 2h (= 2^lh) and h: groups of 4h
     const int h = 1 << (lh - 1);
@@ -58,12 +96,15 @@ __device__ __forceinline__ void fft_dif(double2 *buf, int log2N, int nbatch,
   }
 }
 
+// DIT stage with half-span H on a pair at offset o of its group: (a, c) -> (a + c w*, a - c w*),
+// w = tw[o << (log2 N - 1 - log2 H)], w* its conjugate.  The one or two stages that log2 N
+// leaves over when divided by three come first (radix-2 / radix-4), then radix-8 passes.
 template <int NT>
 __device__ __forceinline__ void fft_dit_inv(double2 *buf, int log2N, int nbatch,
                                             const double2 *__restrict__ tw) {
   const int N = 1 << log2N;
   int lh = 0;  // half-span of the next radix-2 stage is 2^lh
-  if (log2N & 1) {  // odd log2N: the first radix-2 stage (half-span 1, twiddle 1)
+  if (log2N % 3 == 1) {  // the first radix-2 stage (half-span 1, twiddle 1)
     const int half = N >> 1, total = nbatch * half;
     for (int b = threadIdx.x; b < total; b += NT) {
       const int i0 = b << 1;
@@ -74,7 +115,7 @@ __device__ __forceinline__ void fft_dit_inv(double2 *buf, int log2N, int nbatch,
     __syncthreads();
     lh = 1;
   }
-  for (; lh + 1 < log2N + 1 && lh < log2N; lh += 2) {
+  for (; log2N % 3 == 2 && lh == 0; lh += 2) {
     // stages with half-spans h (= 2^lh) and 2h: groups of 4h
     const int h = 1 << lh;
     const int q4 = N >> 2, tsh1 = log2N - 1 - lh, tsh2 = tsh1 - 1;
@@ -92,6 +133,41 @@ __device__ __forceinline__ void fft_dit_inv(double2 *buf, int log2N, int nbatch,
       buf[i0 + 2 * h] = csub(a0, c2);
       buf[i0 + h] = cadd(a1, c4);
       buf[i0 + 3 * h] = csub(a1, c4);
+    }
+    __syncthreads();
+  }
+  for (; lh < log2N; lh += 3) {
+    // stages with half-spans h (= 2^lh), 2h and 4h: groups of 8h
+    const int h = 1 << lh;
+    const int q8 = N >> 3, tsh = log2N - 1 - lh;
+    const int total = nbatch * q8;
+    for (int b = threadIdx.x; b < total; b += NT) {
+      const int f = b >> (log2N - 3), bb = b & (q8 - 1);
+      const int j = bb & (h - 1), grp = bb >> lh;
+      const int i0 = (f << log2N) + (grp << (lh + 3)) + j;
+      double2 x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = buf[i0 + r * h];
+#pragma unroll
+      for (int r = 0; r < 8; r += 2) {  // half-span h, offset j
+        const double2 a = x[r], c = cmulc(x[r + 1], tw[j << tsh]);
+        x[r] = cadd(a, c);
+        x[r + 1] = csub(a, c);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; r += (r & 1) ? 3 : 1) {  // r = 0, 1, 4, 5: half-span 2h, offset j + (r & 1) h
+        const double2 a = x[r], c = cmulc(x[r + 2], tw[(j + (r & 1) * h) << (tsh - 1)]);
+        x[r] = cadd(a, c);
+        x[r + 2] = csub(a, c);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // half-span 4h, offset j + r h
+        const double2 a = x[r], c = cmulc(x[r + 4], tw[(j + r * h) << (tsh - 2)]);
+        x[r] = cadd(a, c);
+        x[r + 4] = csub(a, c);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[i0 + r * h] = x[r];
     }
     __syncthreads();
   }

@@ -1,5 +1,7 @@
-// Streaming-read probe: the HBM read bandwidth a plain kernel reaches on this device, the
-// practical ceiling next to the datasheet figure for the bandwidth-bound kernels.
+// Measurement probes: the HBM read bandwidth a plain streaming kernel reaches on this device,
+// and the rate of back-to-back MFMA products (the instructions the LU uses), the practical
+// ceilings next to the datasheet figures.
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace fde {
@@ -26,6 +28,37 @@ hipError_t launch_read_probe(const void *x, size_t bytes, float *out, int blocks
   hipLaunchKernelGGL(k_read_probe, dim3(blocks), dim3(PR_NT), 0, st, (const float4 *)x, bytes / 16,
                      out);
   return hipGetLastError();
+}
+
+// Each wavefront issues `iters` rounds of four independent 16x16x4 MFMAs (v_mfma_f64_16x16x4f64
+// or v_mfma_f32_16x16x4f32) on register operands; 2 * 16 * 16 * 4 flops each.
+template <typename T>
+__global__ __launch_bounds__(PR_NT) void k_mfma_probe(int iters, float *__restrict__ out) {
+  acc_t<T> c0, c1, c2, c3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) c0[v] = c1[v] = c2[v] = c3[v] = (T)0;
+  const T a = (T)(threadIdx.x & 7) * (T)1e-3, b = (T)1e-3;
+  for (int i = 0; i < iters; ++i) {
+    c0 = mfma16(a, b, c0);
+    c1 = mfma16(b, a, c1);
+    c2 = mfma16(a, a, c2);
+    c3 = mfma16(b, b, c3);
+  }
+  const T t = (c0[0] + c1[1]) + (c2[2] + c3[3]);
+  if (t == (T)-1) out[blockIdx.x] = (float)t;  // never taken for these operands; keeps the chain live
+}
+
+hipError_t launch_mfma_probe(int fp64, int iters, float *out, int blocks, hipStream_t st) {
+  if (iters < 1 || blocks <= 0) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL(k_mfma_probe<double>, dim3(blocks), dim3(PR_NT), 0, st, iters, out);
+  else
+    hipLaunchKernelGGL(k_mfma_probe<float>, dim3(blocks), dim3(PR_NT), 0, st, iters, out);
+  return hipGetLastError();
+}
+
+double mfma_probe_flops(int iters, int blocks) {
+  return (double)blocks * (PR_NT / 64) * iters * 4.0 * (2.0 * 16 * 16 * 4);
 }
 
 }  // namespace fde

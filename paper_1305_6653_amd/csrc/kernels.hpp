@@ -142,5 +142,9 @@ hipError_t launch_qgemm(const InstDesc *D, const ItemMap &map, int items, int tr
 
 // ---- streaming-read probe: out has `blocks` floats; reads bytes (a multiple of 16) of x ----
 hipError_t launch_read_probe(const void *x, size_t bytes, float *out, int blocks, hipStream_t st);
+// back-to-back 16x16x4 MFMAs (FP64 if fp64, else FP32) in `blocks` workgroups of 256 threads;
+// mfma_probe_flops gives the real flops of one launch
+hipError_t launch_mfma_probe(int fp64, int iters, float *out, int blocks, hipStream_t st);
+double mfma_probe_flops(int iters, int blocks);
 
 }  // namespace fde

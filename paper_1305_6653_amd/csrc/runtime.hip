@@ -1186,6 +1186,38 @@ extern "C" fde_status fde_read_bandwidth_probe(size_t bytes, int reps, double *g
   return st;
 }
 
+extern "C" fde_status fde_mfma_peak_probe(int fp64, int reps, double *tflops) {
+  if (!tflops || reps < 1) return fail(FDE_EINVAL, "need reps >= 1, tflops");
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = 8 * std::max(cus, 1), iters = 4096;  // eight waves per SIMD
+  void *out = nullptr;
+  STCHK(dalloc_raw(&out, sizeof(float) * blocks));
+  fde_status st = FDE_OK;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    st = fail(FDE_EDEVICE, "probe set-up failed");
+  for (int r = 0; st == FDE_OK && r <= reps; ++r) {  // the first run warms up
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess || launch_mfma_probe(fp64, iters, (float *)out, blocks, s) != hipSuccess ||
+        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      st = fail(FDE_EDEVICE, "probe launch failed");
+    else if (r > 0)
+      best = std::min(best, ms);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(out);
+  if (st == FDE_OK) *tflops = mfma_probe_flops(iters, blocks) / (best * 1e-3) / 1e12;
+  return st;
+}
+
 extern "C" fde_status fde_autotune_report(char *buf, int len) {
   if (!buf || len < 1) return fail(FDE_EINVAL, "invalid buffer");
   const std::string r = tuned_summary();

@@ -86,4 +86,6 @@ def test_null_arguments(lib):
     assert lib.fde_precond_factor(None, 0) == N.FDE_EINVAL
     assert lib.fde_bvm_solve(None, None, None, None, None, None) == N.FDE_EINVAL
     assert lib.fde_apply_matvec(None, None, None, 0) == N.FDE_EINVAL
+    assert lib.fde_read_bandwidth_probe(1 << 20, 1, None) == N.FDE_EINVAL
+    assert lib.fde_mfma_peak_probe(1, 0, None) == N.FDE_EINVAL
     lib.fde_bvm_destroy(None)

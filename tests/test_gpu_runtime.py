@@ -112,3 +112,15 @@ def test_cgs2_orthogonalisation_matches_mgs(restart):
     assert _rel(u2, u1) <= 1e-10
     ref = O.solve_gmres(p, tol=1e-12)
     assert _rel(u2, ref.x) <= 1e-9
+
+
+def test_measurement_probes_report_rates_within_the_device_limits():
+    """The bandwidth and matrix-core probes the bench divides by: positive, and not above the
+    datasheet peaks (8 TB/s HBM; 78.6 / 157.3 TFLOP/s FP64 / FP32 MFMA) by more than rounding."""
+    import ctypes as C
+    v = C.c_double()
+    N.check(N.lib().fde_read_bandwidth_probe(1 << 28, 2, C.byref(v)))
+    assert 500.0 < v.value < 8000.0 * 1.02
+    for fp64, peak in ((1, 78.6), (0, 157.3)):
+        N.check(N.lib().fde_mfma_peak_probe(fp64, 2, C.byref(v)))
+        assert 0.2 * peak < v.value < 1.02 * peak, (fp64, v.value)

@@ -1,5 +1,5 @@
-// LDS-resident radix-2 complex FFTs (FP64) for power-of-two lengths, batched over
-// `nbatch` contiguous sequences buf[f*N + t].
+// LDS-resident complex FFTs (FP64) for power-of-two lengths, made of radix-2 stages (applied
+// three at a time), batched over `nbatch` contiguous sequences buf[f*N + t].
 //
 // fft_dif: natural order in, bit-reversed order out, kernel e^{-2 pi i jk/N}
 //          (Gentleman-Sande decimation in frequency).

@@ -30,26 +30,35 @@ hipError_t launch_read_probe(const void *x, size_t bytes, float *out, int blocks
   return hipGetLastError();
 }
 
-// Each wavefront issues `iters` rounds of four independent 16x16x4 MFMAs (v_mfma_f64_16x16x4f64
-// or v_mfma_f32_16x16x4f32) on register operands; 2 * 16 * 16 * 4 flops each.
+// Each wavefront issues `iters` rounds of PR_ACC independent 16x16x4 MFMAs
+// (v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32) on register operands, 2 * 16 * 16 * 4
+// flops each; PR_ACC accumulators keep dependent products far enough apart for the pipeline.
+static constexpr int PR_ACC = 8;
+
 template <typename T>
 __global__ __launch_bounds__(PR_NT) void k_mfma_probe(int iters, float *__restrict__ out) {
-  acc_t<T> c0, c1, c2, c3;
+  acc_t<T> c[PR_ACC];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) c0[v] = c1[v] = c2[v] = c3[v] = (T)0;
+  for (int q = 0; q < PR_ACC; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[q][v] = (T)0;
   const T a = (T)(threadIdx.x & 7) * (T)1e-3, b = (T)1e-3;
-  for (int i = 0; i < iters; ++i) {
-    c0 = mfma16(a, b, c0);
-    c1 = mfma16(b, a, c1);
-    c2 = mfma16(a, a, c2);
-    c3 = mfma16(b, b, c3);
+  // sixteen rounds per trip, so that the register-class copies the compiler places at the loop
+  // edge are rare (iters is a multiple of 16)
+  for (int i = 0; i < iters; i += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+#pragma unroll
+      for (int q = 0; q < PR_ACC; ++q) c[q] = mfma16((q & 1) ? a : b, (q & 2) ? a : b, c[q]);
   }
-  const T t = (c0[0] + c1[1]) + (c2[2] + c3[3]);
-  if (t == (T)-1) out[blockIdx.x] = (float)t;  // never taken for these operands; keeps the chain live
+  T t = (T)0;
+#pragma unroll
+  for (int q = 0; q < PR_ACC; ++q) t += c[q][q & 3];
+  if (t == (T)-1) out[blockIdx.x] = (float)t;  // never taken for these operands; keeps the chains live
 }
 
 hipError_t launch_mfma_probe(int fp64, int iters, float *out, int blocks, hipStream_t st) {
-  if (iters < 1 || blocks <= 0) return hipErrorInvalidValue;
+  if (iters < 16 || iters % 16 != 0 || blocks <= 0) return hipErrorInvalidValue;
   if (fp64)
     hipLaunchKernelGGL(k_mfma_probe<double>, dim3(blocks), dim3(PR_NT), 0, st, iters, out);
   else
@@ -58,7 +67,7 @@ hipError_t launch_mfma_probe(int fp64, int iters, float *out, int blocks, hipStr
 }
 
 double mfma_probe_flops(int iters, int blocks) {
-  return (double)blocks * (PR_NT / 64) * iters * 4.0 * (2.0 * 16 * 16 * 4);
+  return (double)blocks * (PR_NT / 64) * iters * (double)PR_ACC * (2.0 * 16 * 16 * 4);
 }
 
 }  // namespace fde

@@ -1191,7 +1191,7 @@ extern "C" fde_status fde_mfma_peak_probe(int fp64, int reps, double *tflops) {
   int dev = 0, cus = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int blocks = 8 * std::max(cus, 1), iters = 4096;  // eight waves per SIMD
+  const int blocks = 4 * std::max(cus, 1), iters = 2048;  // four waves per SIMD
   void *out = nullptr;
   STCHK(dalloc_raw(&out, sizeof(float) * blocks));
   fde_status st = FDE_OK;

@@ -76,3 +76,24 @@ def test_uneven_64_instance_batch_mixed():
     for i in order[:4]:
         ref = O.solve_gmres(ps[i], tol=1e-12)
         assert _rel(outs[i], ref.x) <= 1e-8, ps[i].name
+
+
+@pytest.mark.parametrize("count", [5, 9])
+def test_time_fft_column_groups_do_not_change_results(count):
+    """The time-axis FFTs put 4, 8 or 16 spatial columns in a workgroup, chosen from the plan's
+    total padded order (one instance of order ~1000 takes 4; five such take 8, nine take 16 on a
+    256-CU device).  Every column sees the same arithmetic either way, so the batched solves
+    equal the single ones bitwise."""
+    ps = [W.tiny(1000 - 7 * i, 16, 1.3 + 0.05 * i, 20 + i, "gbdf3") for i in range(count)]
+    batch = [BvmSolver(p) for p in ps]
+    factor_batch(batch, "fp64")
+    outs, infos = solve_batch(batch, [p.u0 for p in ps], [p.f for p in ps])
+    for p, u, info in zip(ps[:2], outs[:2], infos[:2]):
+        assert info["converged"] == 1
+        S = BvmSolver(p)
+        S.factor("fp64")
+        u1, _ = S.solve(p.u0, p.f)
+        assert np.array_equal(u, u1), (p.name, _rel(u, u1))
+        S.close()
+    for S in batch:
+        S.close()

@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times.
+
+* 1023 x 512 GBDF3 (seed 2): the FP64 and the mixed-form solutions against the oracle's
+  (textbook preconditioned GMRES to 1e-11 with LAPACK block solves, ~10-20 s), plus the
+  true residual with the oracle's dense operator, and sampled factor blocks.
+* 4095 x 256 GBDF3 (seed 3, mixed form): the oracle's whole solve takes about a minute, so the
+  checks are the properties that hold at any size: the true residual of the GPU solution with
+  the oracle's dense operator, and sampled FP32 factor blocks against the oracle's K_k by
+  products with random vectors."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_1305_6653_amd import BvmSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _factor_product_error(S, p, k, rng):
+    """||K_k x - L (U x)|| / ||K_k x|| for a random complex x, K_k = lambda_k I - tau mu_k J
+    from the oracle's matrices and Strang eigenvalues, L and U from the GPU's factors."""
+    J, F, tau, _ = O.problem_matrices(p)
+    lam, mu = O.strang_eigs(F, p.s)
+    x = rng.standard_normal(p.m) + 1j * rng.standard_normal(p.m)
+    y = lam[k] * x - tau * mu[k] * (J @ x)
+    Fk = S.factor_block(k)
+    ux = np.triu(Fk) @ x
+    z = np.tril(Fk, -1) @ ux + ux
+    return _rel(z, y)
+
+
+def test_m1023_s512_fp64_and_mixed_match_the_oracle():
+    p = W.smooth_c2()
+    S = BvmSolver(p)
+    ref = O.solve_gmres(p, tol=1e-11, maxit=200)  # true rel-res ~4e-12
+    rng = np.random.default_rng(5)
+    nb = p.s // 2 + 1
+    for prec, tol, ftol in (("fp64", 1e-9, 1e-12), ("mixed", 1e-8, 1e-5)):
+        S.factor(prec)
+        u, info = S.solve(p.u0, p.f, rtol=1e-10)
+        assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+        assert _rel(u, ref.x) <= tol, (prec, _rel(u, ref.x))
+        assert O.true_relres(p, u) <= 1.5e-10
+        for k in (0, 1, nb // 2, nb - 1):
+            e = _factor_product_error(S, p, k, rng)
+            assert e <= ftol, (prec, k, e)
+    S.close()
+
+
+def test_m4095_s256_mixed_full_size_properties():
+    p = W.smooth_c3()
+    S = BvmSolver(p)
+    S.factor("mixed")
+    u, info = S.solve(p.u0, p.f, rtol=1e-10)
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+    assert O.true_relres(p, u) <= 1.5e-10
+    rng = np.random.default_rng(6)
+    nb = p.s // 2 + 1
+    for k in (0, 1, nb // 2, nb - 1):
+        e = _factor_product_error(S, p, k, rng)
+        assert e <= 1e-4, (k, e)
+    S.close()

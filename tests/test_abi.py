@@ -89,3 +89,11 @@ def test_null_arguments(lib):
     assert lib.fde_read_bandwidth_probe(1 << 20, 1, None) == N.FDE_EINVAL
     assert lib.fde_mfma_peak_probe(1, 0, None) == N.FDE_EINVAL
     lib.fde_bvm_destroy(None)
+
+
+def test_empty_and_negative_batches(lib):
+    # an empty batch is a no-op (nothing is launched); a negative count is an error
+    assert lib.fde_precond_factor_batch(None, 0, 0) == N.FDE_OK
+    assert lib.fde_bvm_solve_batch(None, 0, None, None, None, None, None) == N.FDE_OK
+    assert lib.fde_precond_factor_batch(None, -1, 0) == N.FDE_EINVAL
+    assert lib.fde_bvm_solve_batch(None, -1, None, None, None, None, None) == N.FDE_EINVAL

@@ -226,3 +226,18 @@ def test_options_validate_and_read_back():
     S.factor("fp64")
     u, info = S.solve(p.u0, p.f, rtol=1e-10, maxit=2000)
     assert info["converged"] == 1
+
+
+@pytest.mark.parametrize("bvm", ["trapezoidal", "gbdf3"])
+def test_largest_step_count(bvm):
+    """s = 1024, the largest step count the library takes (the time FFT's LDS buffers and the
+    widest frequency range), with a ragged m: solution and true residual against the oracle."""
+    p = W.tiny(33, 1024, 1.6, 8, bvm)
+    S = BvmSolver(p)
+    S.factor("fp64")
+    u, info = S.solve(p.u0, p.f, rtol=1e-10)
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+    ref = O.solve_gmres(p, tol=1e-12, maxit=400)
+    assert _rel(u, ref.x) <= 1e-9, _rel(u, ref.x)
+    assert O.true_relres(p, u) <= 1.5e-10
+    S.close()

@@ -69,13 +69,26 @@ __global__ __launch_bounds__(GM_NT) void k_gm_givens(const InstDesc *__restrict_
   GmresWork &w = work[i];
   const double *hc = D[i].H;  // h_{0..j+1, j} from the Arnoldi launches
   c.its += 1;
-  for (int r = 0; r <= j + 1; ++r) w.H[r][j] = hc[r];
-  for (int r = 0; r < j; ++r) {
-    const double a = w.H[r][j], b = w.H[r + 1][j];
-    w.H[r][j] = w.cs[r] * a + w.sn[r] * b;
-    w.H[r + 1][j] = -w.sn[r] * a + w.cs[r] * b;
+  // the column and the previous rotations are loaded together into registers (unrolled with
+  // constant indices), then rotated through a carried value: no memory round trip per rotation
+  double h[GM_RMAX + 1], cs[GM_RMAX], sn[GM_RMAX];
+#pragma unroll
+  for (int r = 0; r <= GM_RMAX; ++r) h[r] = r <= j + 1 ? hc[r] : 0.0;
+#pragma unroll
+  for (int r = 0; r < GM_RMAX; ++r) {
+    cs[r] = r < j ? w.cs[r] : 0.0;
+    sn[r] = r < j ? w.sn[r] : 0.0;
   }
-  const double a = w.H[j][j], b = w.H[j + 1][j];
+  double a = h[0], b = h[1];  // rows j and j+1 of the column once rotation j-1 is applied
+#pragma unroll
+  for (int r = 0; r < GM_RMAX; ++r) {
+    if (r < j) {
+      const double hb = h[r + 1];
+      w.H[r][j] = cs[r] * a + sn[r] * hb;
+      a = -sn[r] * a + cs[r] * hb;
+    }
+    if (r == j) b = h[r + 1];
+  }
   const double dd = hypot(a, b);
   w.cs[j] = dd > 0.0 ? a / dd : 1.0;
   w.sn[j] = dd > 0.0 ? b / dd : 0.0;

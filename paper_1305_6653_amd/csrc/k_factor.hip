@@ -822,7 +822,7 @@ __device__ __forceinline__ int ts_ready(const unsigned long long *fl, int sweep,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
+__global__ __launch_bounds__(256, 4) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
                                                    int items,
                                                    const unsigned long long *__restrict__ epoch_p,
                                                    int *__restrict__ err, int first_sweep) {
@@ -875,9 +875,15 @@ __global__ __launch_bounds__(256) void k_trsv_coop(const InstDesc *__restrict__ 
             if (have < 0) return;
           }
           if (!early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
+          // the published piece y_Q: one coherent load per lane (entry `lane`), then each lane
+          // takes its four entries from the wavefront by shuffles
+          const double2 xl = ld_coh(&v[Q * PB + lane]);
           double2 x[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) x[j] = ld_coh(&v[Q * PB + chunk_col<T>(j, cs)]);
+          for (int j = 0; j < 4; ++j) {
+            const int src = chunk_col<T>(j, cs);
+            x[j] = make_double2(__shfl(xl.x, src, 64), __shfl(xl.y, src, 64));
+          }
           chunk_fma<T>(a, x, acc);
         }
 #pragma unroll

@@ -438,7 +438,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards across "
-              "GPUs by frequency block, which this build does not run", file=sys.stderr)
+              "GPUs by frequency block, which this library does not run", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

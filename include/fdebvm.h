@@ -49,7 +49,7 @@ typedef enum {
   FDE_ESINGULAR = -3,    /* zero/non-finite pivot in a preconditioner block          */
   FDE_ENOCONV = -4,      /* maxit reached; u holds the last iterate, info is filled  */
   FDE_EDEVICE = -5,      /* HIP runtime error                                        */
-  FDE_EUNSUPPORTED = -6  /* valid input this build does not handle (e.g. s not 2^k)  */
+  FDE_EUNSUPPORTED = -6  /* valid input the library does not handle (e.g. s not 2^k)*/
 } fde_status;
 
 /* Built-in BVMs (Section 2.2; the paper prints no coefficients, so each is stated here):

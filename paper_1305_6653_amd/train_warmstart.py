@@ -29,7 +29,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--out", default="gpurun_out/warmstart_eval.json")
+    ap.add_argument("--out", default="warmstart_eval.json")
     ap.add_argument("--checkpoint", default="")
     ap.add_argument("--target", default="lowrank", choices=["solution", "lowrank"],
                     help="solution: predict u; lowrank: predict c = (S - M) u on the boundary rows")

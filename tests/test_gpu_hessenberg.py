@@ -47,7 +47,7 @@ def test_reduction_matches_lapack(name):
     assert np.abs(Q.T @ Q - np.eye(p.m)).max() <= 1e-13 * np.sqrt(p.m)
     # the same first reflection as LAPACK (same sign convention); later columns of two
     # backward-stable reductions may drift apart where subdiagonal entries get small, so the
-    # rest is judged by the backward error above
+    # rest is checked by the backward error above
     np.testing.assert_allclose(H[:, 0], Hr[:, 0], rtol=0, atol=1e-13 * nJ * np.sqrt(p.m))
 
 

@@ -110,7 +110,9 @@ def test_trained_warm_start_keeps_answers_and_reports_gain(target):
     # start, so a guess with a few per cent of error costs at most a few iterations
     assert np.mean(res["iters_warm"]) <= np.mean(res["iters_zero"]) + 3.0
     out = {k: (float(np.mean(v)) if isinstance(v, list) else v) for k, v in res.items()}
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(f"gpurun_out/warmstart_small_eval_{target}.json", "w") as fh:
-        json.dump(out, fh)
+    out_dir = os.environ.get("FDE_EVAL_DIR")  # optional: keep the evaluation as JSON
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"warmstart_small_eval_{target}.json"), "w") as fh:
+            json.dump(out, fh)
     print(f"warm start ({target}, 2048 training instances):", out)

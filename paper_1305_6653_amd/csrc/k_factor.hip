@@ -821,95 +821,163 @@ __device__ __forceinline__ int ts_ready(const unsigned long long *fl, int sweep,
   return *sh;
 }
 
+// Waits until *flag holds the epoch (thread 0 polls; bounded like ts_ready); uniform result.
+__device__ __forceinline__ bool ts_wait(const unsigned long long *flag, unsigned long long epoch,
+                                        int *err, int *sh) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      for (int it = 0;; ++it) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (it > TS_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicOr(err, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    *sh = ok;
+  }
+  __syncthreads();
+  return *sh != 0;
+}
+
+// One 64-row panel P of block k in one sweep: stream the off-diagonal chunks as their pieces
+// are published, subtract, multiply by the diagonal inverse, publish.  need_fwd (backward
+// sweep, panels handed out dynamically): the forward result of this panel may come from
+// another workgroup, so its flag is awaited before it is read.  Returns false if a wait was
+// abandoned.  Every thread of the workgroup calls it.
+template <typename T>
+__device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int sweep,
+                                           bool need_fwd, unsigned long long epoch, int *err,
+                                           int *ready_slot, int &calls, double2 *tmp) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
+  const int r16 = wave * 16;  // this wave's first row inside the panel
+  const int mp = d.mp, npan = d.npan;
+  const c_t<T> *dinv = (const c_t<T> *)d.dinv;
+  const c_t<T> *A = (const c_t<T> *)d.K + (size_t)k * mp * mp;
+  double2 *v = d.Vts + (size_t)k * mp;
+  unsigned long long *fl = d.tsflags + (size_t)k * npan * 2;
+  const int p0 = P * PB;
+  const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
+  // FP32: touch every 128-byte line of the diagonal inverse now, so that its read after
+  // the off-diagonal GEMV (on the dependency chain of the sweep) hits L2; the touched
+  // values enter the result as x * 0 (they are finite), which keeps the loads.  (For FP64
+  // factors the extra loads cost more than they save.)
+  constexpr int TL = sizeof(T) == 4 ? 1 : 0;  // lines per thread
+  double touch[TL > 0 ? TL : 1];
+#pragma unroll
+  for (int u = 0; u < TL; ++u)
+    touch[u] = (double)reinterpret_cast<const T *>(Di)[(size_t)(threadIdx.x * TL + u) * (128 / sizeof(T))];
+  double2 acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
+  const int nq = sweep == 0 ? P : npan - 1 - P;
+  int have = 0;  // chunks t < have are known to be published
+  for (int t = 0; t < nq; ++t) {
+    const int Q = sweep == 0 ? t : npan - 1 - t;
+    // FP32 chunks are loaded before a possible wait, so the loads are in flight meanwhile
+    // (FP64 chunks would need twice the registers and halve the co-resident workgroups)
+    constexpr bool early = sizeof(T) == 4;
+    c_t<T> a[4][4];
+    if (early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
+    if (t >= have) {
+      have = ts_ready(fl, sweep, npan, t, nq, epoch, err, &ready_slot[calls++ & 1]);
+      if (have < 0) return false;
+    }
+    if (!early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
+    // the published piece y_Q: one coherent load per lane (entry `lane`), then each lane
+    // takes its four entries from the wavefront by shuffles
+    const double2 xl = ld_coh(&v[Q * PB + lane]);
+    double2 x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int src = chunk_col<T>(j, cs);
+      x[j] = make_double2(__shfl(xl.x, src, 64), __shfl(xl.y, src, 64));
+    }
+    chunk_fma<T>(a, x, acc);
+  }
+  if (need_fwd && !ts_wait(&fl[P * 2 + 0], epoch, err, &ready_slot[calls++ & 1])) return false;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    acc[g] = sum16(acc[g]);
+    if (cs == 0) {
+      const int rr = r16 + 4 * g + rs;
+      tmp[rr] = csub(ld_coh(&v[p0 + rr]), acc[g]);
+    }
+  }
+  __syncthreads();
+  double2 x[4], b[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = tmp[chunk_col<T>(j, cs)];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < TL; ++u) b[0].x = fma(touch[u], 0.0, b[0].x);
+  chunk_gemv<T>(Di + (size_t)r16 * PB, PB, x, b);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    b[g] = sum16(b[g]);
+    if (cs == 0) st_coh(&v[p0 + r16 + 4 * g + rs], b[g]);
+  }
+  ts_publish(&fl[P * 2 + sweep], epoch);
+  return true;
+}
+
+// Two ways of handing out the panels.  Static (npan_u = 0): item (k, w), w < W, owns the panels
+// P = w, w+W, ... of block k.  Dynamic (all instances of the plan have npan_u panels): each
+// workgroup claims the next unit from a counter (reset by the time FFT that draws the epoch):
+// units run through the forward sweep level by level (panel 0 of every block, then panel 1,
+// ...), then the backward sweep from the last panel down, so a unit only waits on units
+// claimed before it, all held by running workgroups; a workgroup that is slowed (a CU shared
+// by more workgroups) simply claims fewer units, and the grid need not be a multiple of the
+// block count.
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_trsv_coop(const InstDesc *__restrict__ Dd, ItemMap map,
                                                    int items,
                                                    const unsigned long long *__restrict__ epoch_p,
-                                                   int *__restrict__ err, int first_sweep) {
+                                                   int *__restrict__ err, int first_sweep,
+                                                   ItemMap blkmap, int nblk, int npan_u) {
   __shared__ double2 tmp[PB];
   __shared__ int ready_slot[2];
+  __shared__ int claim;
   int calls = 0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, rs = lane >> 4, cs = lane & 15;
-  const int r16 = wave * 16;  // this wave's first row inside the panel
   const unsigned long long epoch =
       __hip_atomic_load(epoch_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (npan_u > 0) {
+    unsigned *ctr = reinterpret_cast<unsigned *>(const_cast<unsigned long long *>(epoch_p + 1));
+    const int U = npan_u * nblk;  // units per sweep
+    for (;;) {
+      if (threadIdx.x == 0)
+        claim = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int u = claim + first_sweep * U;
+      __syncthreads();
+      if (u >= 2 * U) break;
+      const int sweep = u / U, r = u % U, lvl = r / nblk, b = r % nblk;
+      const int q = item_slot(blkmap, b);
+      if (item_gated(blkmap, q)) continue;
+      const InstDesc &d = Dd[blkmap.ids[q]];
+      const int P = sweep == 0 ? lvl : npan_u - 1 - lvl;
+      const bool need_fwd = sweep == 1 && first_sweep == 0;
+      if (!trsv_panel<T>(d, b - blkmap.pre[q], P, sweep, need_fwd, epoch, err, ready_slot, calls,
+                         tmp))
+        return;
+    }
+    return;
+  }
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int q = item_slot(map, item);
     if (item_gated(map, q)) continue;
     const InstDesc &d = Dd[map.ids[q]];
     const int local = item - map.pre[q];
-    const int mp = d.mp, npan = d.npan, W = d.W;
+    const int npan = d.npan, W = d.W;
     const int k = local / W, w = local % W;
-    const c_t<T> *dinv = (const c_t<T> *)d.dinv;
-    const c_t<T> *A = (const c_t<T> *)d.K + (size_t)k * mp * mp;
-    double2 *v = d.Vts + (size_t)k * mp;
-    unsigned long long *fl = d.tsflags + (size_t)k * npan * 2;
     for (int sweep = first_sweep; sweep < 2; ++sweep) {
       const int Pfirst = sweep == 0 ? w : w + ((npan - 1 - w) / W) * W;
-      for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W) {
-        const int p0 = P * PB;
-        const c_t<T> *Di = dinv + ((size_t)(k * npan + P) * 2 + sweep) * PB * PB;
-        // FP32: touch every 128-byte line of the diagonal inverse now, so that its read after
-        // the off-diagonal GEMV (on the dependency chain of the sweep) hits L2; the touched
-        // values enter the result as x * 0 (they are finite), which keeps the loads.  (For FP64
-        // factors the extra loads cost more than they save.)
-        constexpr int TL = sizeof(T) == 4 ? 1 : 0;  // lines per thread
-        double touch[TL > 0 ? TL : 1];
-#pragma unroll
-        for (int u = 0; u < TL; ++u)
-          touch[u] = (double)reinterpret_cast<const T *>(Di)[(size_t)(threadIdx.x * TL + u) * (128 / sizeof(T))];
-        double2 acc[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
-        const int nq = sweep == 0 ? P : npan - 1 - P;
-        int have = 0;  // chunks t < have are known to be published
-        for (int t = 0; t < nq; ++t) {
-          const int Q = sweep == 0 ? t : npan - 1 - t;
-          // FP32 chunks are loaded before a possible wait, so the loads are in flight meanwhile
-          // (FP64 chunks would need twice the registers and halve the co-resident workgroups)
-          constexpr bool early = sizeof(T) == 4;
-          c_t<T> a[4][4];
-          if (early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
-          if (t >= have) {
-            have = ts_ready(fl, sweep, npan, t, nq, epoch, err, &ready_slot[calls++ & 1]);
-            if (have < 0) return;
-          }
-          if (!early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
-          // the published piece y_Q: one coherent load per lane (entry `lane`), then each lane
-          // takes its four entries from the wavefront by shuffles
-          const double2 xl = ld_coh(&v[Q * PB + lane]);
-          double2 x[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int src = chunk_col<T>(j, cs);
-            x[j] = make_double2(__shfl(xl.x, src, 64), __shfl(xl.y, src, 64));
-          }
-          chunk_fma<T>(a, x, acc);
-        }
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          acc[g] = sum16(acc[g]);
-          if (cs == 0) {
-            const int rr = r16 + 4 * g + rs;
-            tmp[rr] = csub(ld_coh(&v[p0 + rr]), acc[g]);
-          }
-        }
-        __syncthreads();
-        double2 x[4], b[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = tmp[chunk_col<T>(j, cs)];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < TL; ++u) b[0].x = fma(touch[u], 0.0, b[0].x);
-        chunk_gemv<T>(Di + (size_t)r16 * PB, PB, x, b);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          b[g] = sum16(b[g]);
-          if (cs == 0) st_coh(&v[p0 + r16 + 4 * g + rs], b[g]);
-        }
-        ts_publish(&fl[P * 2 + sweep], epoch);
-      }
+      for (int P = Pfirst; P >= 0 && P < npan; P += sweep == 0 ? W : -W)
+        if (!trsv_panel<T>(d, k, P, sweep, false, epoch, err, ready_slot, calls, tmp)) return;
     }
   }
 }
@@ -987,13 +1055,25 @@ int trsv_coop_capacity() {
 template <typename T>
 hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                             const unsigned long long *epoch, int *err, hipStream_t st,
-                            int first_sweep) {
+                            int first_sweep, const ItemMap *blkmap, int nblk, int npan_u) {
   if (items <= 0) return hipSuccess;
   const int cap = trsv_coop_capacity<T>();
   if (cap <= 0) return hipErrorNotSupported;
-  const int grid = items < cap ? items : cap;
-  void *args[] = {(void *)&D, (void *)&map, (void *)&items, (void *)&epoch, (void *)&err,
-                  (void *)&first_sweep};
+  int grid = items < cap ? items : cap;
+  ItemMap bm = map;
+  if (blkmap && npan_u > 0 && nblk > 0) {
+    // claimed units: any grid size works, so use whole multiples of the CU count (no CU gets
+    // one workgroup more than the others)
+    const int cus = device_cus();
+    if (grid > cus) grid -= grid % cus;
+    bm = *blkmap;
+  } else {
+    npan_u = 0;
+    nblk = 0;
+  }
+  void *args[] = {(void *)&D,           (void *)&map,  (void *)&items, (void *)&epoch,
+                  (void *)&err,         (void *)&first_sweep, (void *)&bm, (void *)&nblk,
+                  (void *)&npan_u};
   return hipLaunchCooperativeKernel((const void *)k_trsv_coop<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
@@ -1006,7 +1086,8 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                                           hipStream_t);                                         \
   template hipError_t launch_trsv<T>(const InstDesc *, const ItemMap &, int, int, hipStream_t);    \
   template hipError_t launch_trsv_coop<T>(const InstDesc *, const ItemMap &, int,                 \
-                                          const unsigned long long *, int *, hipStream_t, int);  \
+                                          const unsigned long long *, int *, hipStream_t, int,   \
+                                          const ItemMap *, int, int);                             \
   template hipError_t launch_hess_uinv<T>(const InstDesc *, const ItemMap &, int, int *,          \
                                           hipStream_t);                                         \
   template int trsv_coop_capacity<T>();

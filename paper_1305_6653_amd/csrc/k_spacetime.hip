@@ -146,15 +146,19 @@ __global__ __launch_bounds__(ST_NT) void k_rhs(const InstDesc *__restrict__ D, I
 // into LDS behind the data.
 
 // If epoch_ctr is set, the first workgroup also draws the next block-solve epoch from the
-// device-wide counter into *epoch_slot (read by the block solve that follows on the stream),
-// so a recorded launch sequence gets a fresh epoch on every replay.
+// device-wide counter into epoch_slot[0] (read by the block solve that follows on the stream),
+// so a recorded launch sequence gets a fresh epoch on every replay, and clears the block
+// solve's unit counter epoch_slot[1].
 template <int TP>
 __global__ __launch_bounds__(ST_NT) void k_time_rfft(const InstDesc *__restrict__ D, ItemMap map,
                                                      int src_sel, int src_j, int max_log2s,
                                                      unsigned long long *epoch_ctr,
                                                      unsigned long long *epoch_slot) {
   extern __shared__ double2 buf[];
-  if (epoch_ctr && blockIdx.x == 0 && threadIdx.x == 0) *epoch_slot = atomicAdd(epoch_ctr, 1ull) + 1ull;
+  if (epoch_ctr && blockIdx.x == 0 && threadIdx.x == 0) {
+    *epoch_slot = atomicAdd(epoch_ctr, 1ull) + 1ull;
+    epoch_slot[1] = 0ull;  // the block solve's unit counter
+  }
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int q = item_slot(map, item);
   if (item_gated(map, q)) return;

@@ -61,11 +61,14 @@ hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max
 // instance; flags in the descriptors hold the epoch of the last published panel; the epoch of
 // this launch is read from *epoch (device memory, written by the preceding time FFT); *err is
 // raised if a dependency wait had to be abandoned.  first_sweep = 1 runs the U sweep only (the
-// Hessenberg route, whose lower factor is applied by launch_hess_lsolve).
+// Hessenberg route, whose lower factor is applied by launch_hess_lsolve).  With blkmap (items =
+// nb per instance, nblk in all) and npan_u > 0 (every instance has npan_u panels) the panels
+// are claimed from the counter epoch[1] instead, which the preceding time FFT resets.
 template <typename T>
 hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                             const unsigned long long *epoch, int *err, hipStream_t st,
-                            int first_sweep = 0);
+                            int first_sweep = 0, const ItemMap *blkmap = nullptr, int nblk = 0,
+                            int npan_u = 0);
 // co-resident workgroups of the cooperative block solve on this device (0 if unknown)
 template <typename T>
 int trsv_coop_capacity();

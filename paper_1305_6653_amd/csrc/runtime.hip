@@ -329,6 +329,7 @@ struct SolveMaps {
   int pc = 0, route = FDE_BLOCKS_LU;
   int max_log2L = 1, max_log2s = 1, max_mp = 64;
   int tfft_cols = 16;  // spatial columns per time-FFT workgroup
+  int npan_u = 0;      // panels per block if every instance has the same count, else 0
   int prec = -1;
   double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0;
 };
@@ -1579,6 +1580,9 @@ static fde_status ensure_full_maps(Plan *P) {
   S.n_rhs = hm[4].items;
   S.n_ju0 = hm[5].items;
   S.prec = prec;
+  S.npan_u = P->hs[0]->npan;
+  for (fde_bvm *h : P->hs)
+    if (h->npan != S.npan_u) S.npan_u = 0;
   P->full = S;
   P->full_ok = true;
   return FDE_OK;
@@ -1633,8 +1637,10 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
     HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
       if (!g_coop_ok) return hipErrorNotSupported;
       return S.prec == FDE_FP64
-                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1)
-                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1);
+                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
+                                            &S.blk, S.n_blk, S.npan_u)
+                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
+                                           &S.blk, S.n_blk, S.npan_u);
     }));
     HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
@@ -1646,8 +1652,10 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
     hipError_t e = hipErrorNotSupported;
     if (g_coop_ok) {
       e = S.prec == FDE_FP64
-              ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st)
-              : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st);
+              ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 0,
+                                         &S.blk, S.n_blk, S.npan_u)
+              : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 0,
+                                        &S.blk, S.n_blk, S.npan_u);
       if (e == hipSuccess || g_capture) return e;  // a refusal while recording ends the recording
       (void)hipGetLastError();
       g_coop_ok = false;

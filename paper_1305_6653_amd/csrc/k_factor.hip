@@ -448,14 +448,39 @@ struct GemmLds {
   c_t<T> Bs[2][US][PB + 1];  // B slice: US x 64 columns
 };
 
-template <typename T, bool NEG>
+// Output layout of gemm64_lds: wave w holds the 16x16 sub-blocks (r, c), r, c < 2, at rows
+// gemm_row0(w, r) and columns gemm_col0(w, c).  TRI = 0: the wave's 32x32 quadrant.  With a
+// triangular operand the sub-blocks need different K ranges (16-wide group g: 2g + 2 of the
+// 8 slices), so each wave takes the groups {0, 3} or {1, 2} of the triangular side, 10 of 16
+// slice-groups per wave: TRI = 1, B upper triangular (column groups); TRI = 2, A lower
+// triangular (row groups).
+__device__ __forceinline__ int tri_pair(int h, int i) { return h == 0 ? 3 * i : 1 + i; }
+template <int TRI>
+__device__ __forceinline__ int gemm_row0(int wave, int r) {
+  return TRI == 2 ? 16 * tri_pair(wave >> 1, r) : (wave >> 1) * 32 + 16 * r;
+}
+template <int TRI>
+__device__ __forceinline__ int gemm_col0(int wave, int c) {
+  return TRI == 1 ? 16 * tri_pair(wave & 1, c) : (wave & 1) * 32 + 16 * c;
+}
+
+template <typename T, bool NEG, int TRI = 0>
 __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda,
                                            const c_t<T> *__restrict__ B, int ldb, int nsl,
                                            GemmLds<T> &sm, acc_t<T> (&cre)[2][2],
                                            acc_t<T> (&cim)[2][2]) {
   typedef c_t<T> C;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  // (a triangular operand skips MFMAs per wave: the wave index is made scalar so that the
+  // tests are scalar branches)
+  const int wave = TRI ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  int row0[2], col0[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    row0[i] = gemm_row0<TRI>(wave, i);
+    col0[i] = gemm_col0<TRI>(wave, i);
+  }
   // staging: A slice thread -> row tid / 4, columns 2 (tid % 4) + {0, 1};
   //          B slice thread -> row tid / 32, columns 2 (tid % 32) + {0, 1}
   const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
@@ -489,19 +514,33 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {
       C a[2], b[2];
+      if constexpr (TRI == 0) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
+        for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
+        for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][row0[r] + li][kk + lk];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][col0[c] + li];
+      }
       T bs[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
+      const int k0 = sl * US + kk;  // this step's K rows k0 .. k0+3
+      (void)k0;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const T ar_ = NEG ? -a[r].x : a[r].x, ai_ = NEG ? -a[r].y : a[r].y;
         const T as_ = ar_ + ai_;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+          // a triangular operand is zero in the whole step for this sub-block: skip it
+          if constexpr (TRI == 1)
+            if (k0 >= col0[c] + 16) continue;
+          if constexpr (TRI == 2)
+            if (k0 >= row0[r] + 16) continue;
           p1[r][c] = mfma16(ar_, b[c].x, p1[r][c]);
           p2[r][c] = mfma16(ai_, b[c].y, p2[r][c]);
           p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
@@ -544,19 +583,34 @@ __global__ __launch_bounds__(256, 3) void k_lu_panel(const InstDesc *__restrict_
   const int blk = local / (2 * nrem), t = local % (2 * nrem);
   C *Kb = (C *)d.K + (size_t)blk * mp * mp;
   const int wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   acc_t<T> cre[2][2], cim[2][2];
   const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + p) * 2 + 0) * PB * PB;
   const C *Du = Dl + PB * PB;
   C *Ct;
+  int row0[2], col0[2];
   if (t < nrem) {
     Ct = Kb + (size_t)(p + 1 + t) * PB * mp + (size_t)p * PB;
-    gemm64_lds<T, false>(Ct, mp, Du, PB, PB / US, sm, cre, cim);
+    gemm64_lds<T, false, 1>(Ct, mp, Du, PB, PB / US, sm, cre, cim);
+    for (int i = 0; i < 2; ++i) {
+      row0[i] = gemm_row0<1>(wave, i);
+      col0[i] = gemm_col0<1>(wave, i);
+    }
   } else {
     Ct = Kb + (size_t)p * PB * mp + (size_t)(p + 1 + t - nrem) * PB;
-    gemm64_lds<T, false>(Dl, PB, Ct, mp, PB / US, sm, cre, cim);
+    gemm64_lds<T, false, 2>(Dl, PB, Ct, mp, PB / US, sm, cre, cim);
+    for (int i = 0; i < 2; ++i) {
+      row0[i] = gemm_row0<2>(wave, i);
+      col0[i] = gemm_col0<2>(wave, i);
+    }
   }
-  tile_store<T>(Ct + (size_t)wr * mp + wc, mp, cre, cim);
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ct[(size_t)(row0[r] + mfma_row<T>(lk, v)) * mp + col0[c] + li] = mk<T>(cre[r][c][v], cim[r][c][v]);
 }
 
 // Trailing updates, in pairs of panel steps (p, p+1) so that the trailing matrix is read and

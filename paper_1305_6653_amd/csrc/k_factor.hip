@@ -448,6 +448,16 @@ struct GemmLds {
   c_t<T> Bs[2][US][PB + 1];  // B slice: US x 64 columns
 };
 
+// Load of a complex value through a global-address-space pointer (a global_load, counted in
+// vmcnt only; a load through a generic pointer is a flat load, counted in lgkmcnt as well).
+template <typename T>
+__device__ __forceinline__ c_t<T> ld_global(const c_t<T> *p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) const v2 gv2;
+  const v2 v = *(gv2 *)p;
+  return mk<T>(v.x, v.y);
+}
+
 // Output layout of gemm64_lds: wave w holds the 16x16 sub-blocks (r, c), r, c < 2, at rows
 // gemm_row0(w, r) and columns gemm_col0(w, c).  TRI = 0: the wave's 32x32 quadrant.  With a
 // triangular operand the sub-blocks need different K ranges (16-wide group g: 2g + 2 of the
@@ -494,7 +504,10 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
-  C ra0 = Ap[0], ra1 = Ap[1], rb0 = Bp[0], rb1 = Bp[1];  // slice 0
+  // the slices are staged with global (not flat) loads: a flat load also counts in lgkmcnt, so
+  // the wait for a slice's first LDS read would wait for the next slice's loads as well
+  C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);  // slice 0
+  C rb0 = ld_global<T>(Bp), rb1 = ld_global<T>(Bp + 1);
   sm.As[0][ar][ac] = ra0;
   sm.As[0][ar][ac + 1] = ra1;
   sm.Bs[0][br][bc] = rb0;
@@ -506,10 +519,10 @@ __device__ __forceinline__ void gemm64_lds(const c_t<T> *__restrict__ A, int lda
     const bool more = sl + 1 < nsl;
     if (more) {
       const int k1 = (sl + 1) * US;
-      ra0 = Ap[k1];
-      ra1 = Ap[k1 + 1];
-      rb0 = Bp[(size_t)k1 * ldb];
-      rb1 = Bp[(size_t)k1 * ldb + 1];
+      ra0 = ld_global<T>(Ap + k1);
+      ra1 = ld_global<T>(Ap + k1 + 1);
+      rb0 = ld_global<T>(Bp + (size_t)k1 * ldb);
+      rb1 = ld_global<T>(Bp + (size_t)k1 * ldb + 1);
     }
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {

@@ -44,36 +44,36 @@ PMC_KERNEL_GROUP = {
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
 }
-PMC_SOURCE_HASH = {"factor": "934e8dcb158e5543", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb", "hessenberg": "cf0e655e99339546"}
+PMC_SOURCE_HASH = {"factor": "c53d9b1c3810c0bd", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb", "hessenberg": "cf0e655e99339546"}
 PMC_TRAFFIC = {
     ("c2", "fp64", "assemble"): 1.0112e+09,
     ("c2", "fp64", "bccb_solve"): 9.3250e+06,
     ("c2", "fp64", "bvm_matvec"): 2.1818e+07,
     ("c2", "fp64", "lu_diag"): 6.7648e+07,
-    ("c2", "fp64", "lu_panel"): 5.7403e+08,
-    ("c2", "fp64", "lu_update"): 1.8891e+09,
+    ("c2", "fp64", "lu_panel"): 5.7406e+08,
+    ("c2", "fp64", "lu_update"): 1.8857e+09,
     ("c2", "fp64", "mgs"): 1.5971e+07,
     ("c2", "fp64", "normalize"): 8.5660e+06,
     ("c2", "fp64", "time_irfft"): 8.6140e+06,
     ("c2", "fp64", "time_rfft"): 8.9990e+06,
     ("c2", "fp64", "trsv"): 4.4729e+09,
     ("c2", "mixed", "assemble"): 5.0574e+08,
-    ("c2", "mixed", "lu_diag"): 3.3816e+07,
-    ("c2", "mixed", "lu_panel"): 2.9020e+08,
-    ("c2", "mixed", "lu_update"): 8.5512e+08,
-    ("c2", "mixed", "trsv"): 2.6341e+09,
+    ("c2", "mixed", "lu_diag"): 3.3814e+07,
+    ("c2", "mixed", "lu_panel"): 2.9044e+08,
+    ("c2", "mixed", "lu_update"): 8.5514e+08,
+    ("c2", "mixed", "trsv"): 2.6343e+09,
     ("c2h", "fp64", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "fp64", "hess_lu"): 2.2035e+09,
-    ("c2h", "fp64", "hess_reduce"): 6.8206e+09,
+    ("c2h", "fp64", "hess_lu"): 2.2026e+09,
+    ("c2h", "fp64", "hess_reduce"): 6.8204e+09,
     ("c2h", "fp64", "hess_uinv"): 4.2120e+08,
-    ("c2h", "fp64", "qgemm"): 5.2901e+07,
-    ("c2h", "fp64", "trsv"): 2.2374e+09,
+    ("c2h", "fp64", "qgemm"): 5.2862e+07,
+    ("c2h", "fp64", "trsv"): 2.2364e+09,
     ("c2h", "mixed", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "mixed", "hess_lu"): 1.1247e+09,
-    ("c2h", "mixed", "hess_reduce"): 6.8206e+09,
+    ("c2h", "mixed", "hess_lu"): 1.1253e+09,
+    ("c2h", "mixed", "hess_reduce"): 6.8204e+09,
     ("c2h", "mixed", "hess_uinv"): 2.1905e+08,
-    ("c2h", "mixed", "qgemm"): 5.2901e+07,
-    ("c2h", "mixed", "trsv"): 1.3208e+09,
+    ("c2h", "mixed", "qgemm"): 5.2862e+07,
+    ("c2h", "mixed", "trsv"): 1.3156e+09,
 }
 
 

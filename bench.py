@@ -1,12 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark: ms per all-at-once solve to true rel-res 1e-10 (reported as solves/s).
 
-One step = fde_precond_factor + fde_bvm_solve on the 1,023 x 512 GBDF3 workload
-(alpha = 1.8, seeded smooth random data, 523,776 unknowns) with u0 and f already
+One step = fde_precond_factor + fde_bvm_solve on the 4,095 x 256 GBDF3 workload
+(alpha = 1.3, seeded smooth random data, 1,048,320 unknowns) with u0 and f already
 resident in HBM.  Prints ONE JSON line.  The plain FP64 form is the headline value;
 the mixed form (complex-FP32 blocks inside flexible GMRES) is reported beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4|ex41]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -160,7 +161,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "ex41"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "ex41"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-hessenberg", action="store_true",
@@ -176,10 +177,22 @@ def parse():
 def workload(name):
     import workloads as W
     if name == "c1":
-        return W.manufactured_c1(), "fp64"
-    if name == "c3":
-        return W.smooth_c3(), "mixed"
-    return W.smooth_c2(), "fp64"
+        return W.manufactured_c1()
+    if name == "c2":
+        return W.smooth_c2()
+    return W.smooth_c3()
+
+
+def workload_alt(name):
+    """A second right-hand side of the same recipe and sizes (another seed)."""
+    import workloads as W
+    p = workload(name)
+    if name == "c1":   # analytic: the same source with a scaled initial value
+        q = W.manufactured_c1()
+        q.u0 = 0.5 * q.u0
+        q.name = p.name + "_u0x0.5"
+        return q
+    return W.smooth_random(p.m, p.s, p.alpha, {"c2": 2, "c3": 3}[name] + 100)
 
 
 def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
@@ -257,38 +270,106 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
     return out
 
 
-def cpu_baseline(p):
-    """The oracle (scipy/numpy FP64, textbook GMRES) timed on the host cores: whole solves of the
-    same workload (all s/2+1 LAPACK block LUs plus the preconditioned GMRES iterations), repeated
-    at least three times and until 10 s of work (30 s at most); the median solve time is used."""
+def _median_time(fn, reps=3):
     import numpy as np
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    times, t_all = [], time.perf_counter()
-    while True:
+    ts = []
+    for _ in range(reps):
         t0 = time.perf_counter()
-        res = O.solve_gmres(p, tol=1e-10)
-        times.append(time.perf_counter() - t0)
-        spent = time.perf_counter() - t_all
-        if (len(times) >= 3 and spent >= 10.0) or spent >= 30.0:
-            break
-    dt = float(np.median(times))
-    sample = (f"{len(times)} full oracle solves of the same workload (m={p.m}, s={p.s}, {p.bvm}): "
-              f"{p.s // 2 + 1} LAPACK block LUs + {res.iters} GMRES iterations each, tol 1e-10; "
-              f"median time per solve")
-    model = ""
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _oracle_pieces(p, nblk, reps):
+    """Times of the oracle's own operations on this workload.  Block factorization: the
+    expression StrangPreconditioner evaluates per block, scipy lu_factor(lambda_k I - tau mu_k J),
+    on nblk blocks spread over the spectrum (mean of their medians); block solve: its lu_solve,
+    taken in turn over the nblk factors so that each solve reads its factor from memory as an
+    apply over all blocks does; plus the time rfft + irfft of an apply, the dense-J product
+    apply_M and one dot + axpy pair of the Arnoldi step (medians of `reps`)."""
+    import numpy as np
+    import scipy.linalg
+    import oracle as O
+    J, F, tau, _ = O.problem_matrices(p)
+    A, B, _, _, _ = O.s_form(F, p.s)
+    lam, mu = O.strang_eigs(F, p.s)
+    nb = p.s // 2 + 1
+    ks = sorted({int(round(i * (nb - 1) / max(1, nblk - 1))) for i in range(nblk)})
+    rng = np.random.default_rng(0)
+    n = p.s * p.m
+    eye = np.eye(p.m)
+    t_lu, lus = [], []
+    for k in ks:
+        box = [None]
+
+        def fac():
+            box[0] = scipy.linalg.lu_factor(lam[k] * eye - tau * mu[k] * J, check_finite=False)
+        t_lu.append(_median_time(fac, reps))
+        lus.append(box[0])
+    rhs = rng.standard_normal((len(ks), p.m)) + 1j * rng.standard_normal((len(ks), p.m))
+    t_sol = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for lu, r in zip(lus, rhs):
+            scipy.linalg.lu_solve(lu, r, check_finite=False)
+        t_sol.append((time.perf_counter() - t0) / len(ks))
+    del lus
+    V = rng.standard_normal((p.s, p.m))
+    t_fft = _median_time(lambda: np.fft.irfft(np.fft.rfft(V, axis=0), n=p.s, axis=0), reps)
+    t_mv = _median_time(lambda: O.apply_M(J, A, B, tau, V), reps)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    t_mgs = _median_time(lambda: y - (x @ y) * x, reps)
+    return float(np.mean(t_lu)), float(np.median(t_sol)), t_fft, t_mv, t_mgs, len(ks)
+
+
+def cpu_baseline(p, iters, restarts):
+    """The oracle (scipy/numpy FP64, textbook GMRES with LAPACK block solves) on the host cores,
+    on a bounded sample of the same workload scaled to one whole solve: its per-block LU and
+    block solve timed on a sample of the s/2+1 blocks, its time FFTs, dense-J product and Arnoldi
+    vector operations timed in full (median of 3 each), combined as one solve takes them:
+    (s/2+1) block LUs, then per GMRES iteration one preconditioner apply (time FFT pair and
+    s/2+1 block solves), one product with M and j dot/axpy pairs at step j, plus one product
+    with M per restart for the true residual.  `iters` is the GPU's FP64 count (equal to the
+    oracle's within one, tested).  Also the same at one BLAS thread (one sampled block)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    nb = p.s // 2 + 1
+    R = 20
+    steps = sum((j % R) + 1 for j in range(iters))   # Arnoldi step j (in its cycle) has j+1 pairs
+
+    def model(t):
+        t_lu, t_sol, t_fft, t_mv, t_mgs = t
+        return nb * t_lu + iters * (t_fft + nb * t_sol + t_mv) + steps * t_mgs + (restarts + 1) * t_mv
+
+    # enough sampled blocks that their factors (16 m^2 bytes each) exceed 1 GB, or all of them
+    nblk = min(nb, max(3, -(-10 ** 9 // (16 * p.m * p.m))))
+    t_all = time.perf_counter()
+    pieces = _oracle_pieces(p, nblk, 3)
+    full = model(pieces[:5])
+    t_sample = time.perf_counter() - t_all
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        pieces1 = _oracle_pieces(p, 1 if p.m > 2048 else 3, 1)
+        t_sample1 = time.perf_counter() - t1
+    one = model(pieces1[:5])
+    model_name = ""
     try:
         with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+            model_name = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 4), "repeats": len(times), "iters": res.iters,
-            "cpu_model": model, "logical_cpus": os.cpu_count()}, res.x
+    sample = (f"oracle pieces of the m={p.m}, s={p.s} {p.bvm} workload, median of 3 each: LAPACK "
+              f"block LU and block solve on {pieces[5]} of the {nb} blocks, time rfft+irfft, dense-J "
+              f"product with M, Arnoldi dot/axpy; scaled to one solve of {iters} iterations, "
+              f"{restarts + 1} true residuals ({t_sample:.1f} s of sampling)")
+    return {"value": round(1.0 / full, 5), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": sample, "seconds_per_solve": round(full, 3),
+            "factor_seconds": round(nb * pieces[0], 3),
+            "one_thread": {"value": round(1.0 / one, 6), "seconds_per_solve": round(one, 2), "cores": 1,
+                           "sample": f"as above at one BLAS thread, {pieces1[5]} sampled block(s), one "
+                                     f"timing each ({t_sample1:.1f} s of sampling)"},
+            "cpu_model": model_name, "logical_cpus": os.cpu_count()}
 
 
 def bench_batch(args):
@@ -445,10 +526,12 @@ def main():
     from paper_1305_6653_amd import BvmSolver, autotune_report
     from paper_1305_6653_amd import _native as N
 
-    p, prec = workload(args.workload)
+    p = workload(args.workload)
+    prec = "fp64"
+    fp64_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     dev = torch.device("cuda:0")
-    u0 = torch.from_numpy(np.ascontiguousarray(p.u0)).to(dev)
-    f = torch.from_numpy(np.ascontiguousarray(p.f)).to(dev)
+    u0 = fp64_dev(p.u0)
+    f = fp64_dev(p.f)
     out = torch.empty((p.s, p.m), dtype=torch.float64, device=dev)
     S = BvmSolver(p)
     S.set_stream(torch.cuda.current_stream())
@@ -459,13 +542,13 @@ def main():
     result = {
         "metric": METRIC, "value": round(1000.0 / ms, 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "c32+f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded smooth random Fourier modes, workloads module)",
         "config": {"workload": p.name, "m": p.m, "s": p.s, "bvm": p.bvm, "alpha": p.alpha,
                    "unknowns": p.m * p.s, "precision": prec, "rtol": 1e-10, "restart": 20,
                    "step": "fde_precond_factor + fde_bvm_solve"},
-        "iters": infos[-1]["iters"], "true_relres": infos[-1]["true_relres"],
+        "iters": infos[-1]["iters"], "restarts": infos[-1]["restarts"],
+        "true_relres": infos[-1]["true_relres"],
         "t_factor_ms": round(infos[-1]["t_factor_ms"], 3),
         "t_solve_ms": round(infos[-1]["t_solve_ms"], 3),
         "profiled_ms_per_step": round(ms_prof, 4),
@@ -473,7 +556,24 @@ def main():
         "roofline": roofline(prof, prec, args.workload, read_peak),
         "autotuned": autotune_report(),
     }
-    if not args.no_mixed and prec == "fp64":
+    # Every solve of a handle sizes its first stretch of Arnoldi steps from its previous solve;
+    # with a right-hand side that changes from step to step that guess is not exact.  Same
+    # steps, alternating between two seeded right-hand sides of the same recipe.
+    q = workload_alt(args.workload)
+    rhs = [(u0, f), (fp64_dev(q.u0), fp64_dev(q.f))]
+    for k in range(2):
+        S.factor(prec)
+        S.solve(*rhs[k % 2], out=out, rtol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        S.factor(prec)
+        S.solve(*rhs[k % 2], out=out, rtol=1e-10)
+    torch.cuda.synchronize()
+    ms_alt = (time.perf_counter() - t0) * 1e3 / args.steps
+    result["changed_rhs"] = {"ms_per_step": round(ms_alt, 4), "value": round(1000.0 / ms_alt, 4),
+                             "rhs": f"alternating {p.name} and {q.name}'s u0, f"}
+    if not args.no_mixed:
         ms2, _, infos2, prof2 = timed_steps(S, u0, f, out, "mixed", args.steps, args.warmup)
         u_mixed = out.cpu().numpy()
         result["mixed"] = {
@@ -482,29 +582,20 @@ def main():
             "t_factor_ms": round(infos2[-1]["t_factor_ms"], 3),
             "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
+            "speedup_vs_fp64": round(ms / ms2, 3),
             "kernels": kernel_table(prof2, args.steps, "mixed"),
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
-    if not args.no_mixed and prec == "mixed":
-        # the plain FP64 form of the same workload, for the mixed-vs-FP64 comparison
-        ms2, _, infos2, prof2 = timed_steps(S, u0, f, out, "fp64", args.steps, args.warmup)
-        u_fp64 = out.cpu().numpy()
-        result["fp64"] = {
-            "ms_per_step": round(ms2, 4), "value": round(1000.0 / ms2, 4), "iters": infos2[-1]["iters"],
-            "true_relres": infos2[-1]["true_relres"],
-            "t_factor_ms": round(infos2[-1]["t_factor_ms"], 3),
-            "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
-            "rel_diff_vs_mixed": float(np.linalg.norm(u_fp64 - u_main) / np.linalg.norm(u_main)),
-            "mixed_speedup": round(ms2 / ms, 3),
-            "kernels": kernel_table(prof2, args.steps, "fp64"),
-            "roofline": roofline(prof2, "fp64", args.workload, read_peak),
-        }
-    if not args.no_hessenberg and prec == "fp64":
+    if not args.no_hessenberg:
         # the same preconditioner S with its blocks through one Hessenberg form of J
         result["hessenberg"] = {}
         for form in ("fp64", "mixed"):
             S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_HESSENBERG)
-            ms4, _, infos4, prof4 = timed_steps(S, u0, f, out, form, args.steps, args.warmup)
+            try:
+                ms4, _, infos4, prof4 = timed_steps(S, u0, f, out, form, args.steps, args.warmup)
+            except N.FdeError as e:
+                result["hessenberg"][form] = {"unsupported": str(e)}
+                continue
             u4 = out.cpu().numpy()
             result["hessenberg"][form] = {
                 "ms_per_step": round(ms4, 4), "value": round(1000.0 / ms4, 4),
@@ -516,7 +607,7 @@ def main():
                 "roofline": roofline(prof4, form, args.workload + "h", read_peak),
             }
         S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_LU)
-    if not args.no_bccb and prec == "fp64":
+    if not args.no_bccb and args.workload == "c2":
         # the paper's other preconditioners on the same system (Section 3.1): S2 = s(A) x I -
         # tau s(B) x s(J) and its shifted form, each a 2-D FFT diagonal solve per iteration
         result["bccb"] = {}
@@ -536,13 +627,12 @@ def main():
                                         / (prof3["bccb_solve"]["total_ms"] * 1e-3) / 1e9, 1)
                 if "bccb_solve" in prof3 else None,
             }
+    S.close()
     if not args.no_cpu_baseline:
-        cb, u_ref = cpu_baseline(p)
-        result["cpu_baseline"] = cb
-        result["rel_diff_vs_oracle"] = float(np.linalg.norm(u_main - u_ref) / np.linalg.norm(u_ref))
+        result["cpu_baseline"] = cpu_baseline(p, result["iters"], result["restarts"])
+        result["vs_cpu_baseline"] = round(result["value"] / result["cpu_baseline"]["value"], 1)
     else:
         result["cpu_baseline"] = None
-    S.close()
     calib_copy(args.calib_copy_mib)
     print(json.dumps(result), flush=True)
 

@@ -28,7 +28,10 @@
  * Errors.  Status codes only (no exceptions, no abort across the ABI); the message of
  *   the last failure on the calling thread is returned by fde_last_error().
  * Streams.  Work is enqueued on the handle's stream (fde_set_stream, default: a stream
- *   the library creates) and every call returns after that stream is synchronised.
+ *   the library creates, which does not synchronise with the null stream) and every call
+ *   returns after that stream is synchronised.  FDE_MEM_DEVICE inputs are read on the
+ *   handle's stream: work that produces them on another stream must be complete, or
+ *   ordered before the call by passing the producer's stream to fde_set_stream.
  *   A handle is not thread-safe; distinct handles may be used from distinct threads.
  */
 #ifndef FDEBVM_H
@@ -256,6 +259,21 @@ fde_status fde_read_bandwidth_probe(size_t bytes, int reps, double *gbs);
  * of the blocked LU) on every SIMD, in TFLOP/s: the matrix-core rate MFMA-bound kernels can
  * practically reach on the current device.  FDE_EINVAL for reps < 1 or a null tflops. */
 fde_status fde_mfma_peak_probe(int fp64, int reps, double *tflops);
+
+/* ---- device buffers ------------------------------------------------------------------
+ * For callers that hold no device allocator of their own (a C program, or a Python process
+ * that must not load a second HIP runtime, e.g. under a profiler that preloads the system
+ * one): plain device memory on the current device, usable wherever FDE_MEM_DEVICE pointers
+ * are accepted.  fde_device_alloc returns FDE_EINVAL for bytes == 0 and FDE_ENOMEM when the
+ * allocation fails (*ptr is then NULL); fde_device_free(NULL) is a no-op.  fde_memcpy is
+ * synchronous (it returns after the copy has completed on the device); kind is one of
+ * FDE_COPY_H2D, FDE_COPY_D2H, FDE_COPY_D2D.  fde_device_synchronize waits for all work on
+ * the current device, every stream included. */
+typedef enum { FDE_COPY_H2D = 0, FDE_COPY_D2H = 1, FDE_COPY_D2D = 2 } fde_copy_kind;
+fde_status fde_device_alloc(size_t bytes, void **ptr);
+fde_status fde_device_free(void *ptr);
+fde_status fde_memcpy(void *dst, const void *src, size_t bytes, int kind);
+fde_status fde_device_synchronize(void);
 
 /* ---- the individual steps of the path, for per-kernel checks ----------------------- */
 /* b = right-hand side of eq. (1.10) in s-form, [s][m]. */

@@ -299,15 +299,18 @@ class StrangPreconditioner:
     pivoting) for k = 0..floor(s/2); K_{s-k} = conj(K_k) because J, A and B are real.
     """
 
-    def __init__(self, J: np.ndarray, F: Formula, s: int, tau: float):
+    def __init__(self, J: np.ndarray, F: Formula, s: int, tau: float, progress=None):
         self.s = s
         self.m = J.shape[0]
         lam, mu = strang_eigs(F, s)
         self.lam = lam[: s // 2 + 1]
         self.mu = mu[: s // 2 + 1]
         eye = np.eye(self.m)
-        self.factors = [scipy.linalg.lu_factor(lk * eye - tau * mk * J, check_finite=False)
-                        for lk, mk in zip(self.lam, self.mu)]
+        self.factors = []
+        for k, (lk, mk) in enumerate(zip(self.lam, self.mu)):
+            self.factors.append(scipy.linalg.lu_factor(lk * eye - tau * mk * J, check_finite=False))
+            if progress and (k + 1) % 16 == 0:
+                progress(f"oracle: {k + 1} of {len(self.lam)} blocks factored")
 
     def block(self, k: int, J: np.ndarray, tau: float) -> np.ndarray:
         return self.lam[k] * np.eye(self.m) - tau * self.mu[k] * J
@@ -470,7 +473,7 @@ class GmresResult:
 
 def gmres(matvec: Callable, precond: Optional[Callable], b: np.ndarray, x0: Optional[np.ndarray] = None,
           tol: float = 1e-10, restart: int = 20, maxit: int = 1000,
-          side: str = "right") -> GmresResult:
+          side: str = "right", progress=None) -> GmresResult:
     """Restarted GMRES(restart) with right preconditioning, as flexible GMRES (the
     preconditioned directions z_j are kept), modified Gram-Schmidt Arnoldi and Givens
     rotations for the small least-squares problem.  Convergence is declared only on
@@ -533,6 +536,8 @@ def gmres(matvec: Callable, precond: Optional[Callable], b: np.ndarray, x0: Opti
             g[j] = cs[j] * g[j]
             k = j + 1
             history.append(abs(g[j + 1]) / bnorm)
+            if progress:
+                progress(f"oracle: GMRES iteration {its}, estimate {history[-1]:.2e}")
             if abs(g[j + 1]) <= tol * bnorm or its >= maxit:
                 break
         y = scipy.linalg.solve_triangular(H[:k, :k], g[:k])
@@ -602,10 +607,11 @@ def true_relres(p, U: np.ndarray) -> float:
 
 def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
                 x0: Optional[np.ndarray] = None, preconditioned: bool = True,
-                precond: str = "strang", side: str = "right") -> GmresResult:
+                precond: str = "strang", side: str = "right", progress=None) -> GmresResult:
     """O2: preconditioned GMRES(restart) on the s-form system of a Problem; precond is
     "strang" (S, eq. (1.11)), "bccb" (S2, eq. (x1)), "bccb_shifted" (S2~, eq. (xc)) or
-    "none" (the unpreconditioned column I of Tables 1-2)."""
+    "none" (the unpreconditioned column I of Tables 1-2).  progress, if given, is called with a
+    line of text as the long steps finish (every 16 block factorizations, every iteration)."""
     J, F, tau, _ = problem_matrices(p)
     A, B, a0, b0, Bfull = s_form(F, p.s)
     b = (tau * (Bfull @ p.f) - np.outer(a0, p.u0) + tau * np.outer(b0, J @ p.u0)).reshape(-1)
@@ -613,7 +619,7 @@ def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
     if not preconditioned or precond == "none":
         pc = None
     elif precond == "strang":
-        pc = StrangPreconditioner(J, F, p.s, tau).apply
+        pc = StrangPreconditioner(J, F, p.s, tau, progress).apply
     elif precond == "strang_hessenberg":
         pc = HessenbergPreconditioner(J, F, p.s, tau).apply
     elif precond in ("bccb", "bccb_shifted"):
@@ -621,6 +627,6 @@ def solve_gmres(p, tol: float = 1e-13, restart: int = 20, maxit: int = 2000,
     else:
         raise ValueError(f"unknown preconditioner {precond!r}")
     res = gmres(mv, (lambda v: pc(v).reshape(-1)) if pc else None, b, x0, tol, restart, maxit,
-                side)
+                side, progress if side == "right" else None)
     res.x = res.x.reshape(p.s, p.m)
     return res

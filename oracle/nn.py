@@ -78,8 +78,14 @@ def features(cfg: NetConfig, f: np.ndarray, d_plus: np.ndarray, d_minus: np.ndar
     return X, r
 
 
-def conv_forward(X: np.ndarray, W: np.ndarray, b: np.ndarray, lout: int) -> np.ndarray:
-    """out[o][co] = b[co] + sum_{t<5} sum_c X[2o + t - 2][c] W[t*C + c][co] (X zero outside)."""
+def _id(x):
+    return x
+
+
+def conv_forward(X: np.ndarray, W: np.ndarray, b: np.ndarray, lout: int, q=_id) -> np.ndarray:
+    """out[o][co] = b[co] + sum_{t<5} sum_c X[2o + t - 2][c] W[t*C + c][co] (X zero outside).
+    q rounds the operands of every product (identity: exact FP64)."""
+    X, W = q(X), q(W)
     L, C = X.shape
     out = np.tile(b, (lout, 1)).astype(np.float64)
     for t in range(5):
@@ -89,8 +95,11 @@ def conv_forward(X: np.ndarray, W: np.ndarray, b: np.ndarray, lout: int) -> np.n
     return out
 
 
-def conv_backward(X: np.ndarray, W: np.ndarray, dOut: np.ndarray):
-    """Gradients of conv_forward w.r.t. W, b and X."""
+def conv_backward(X: np.ndarray, W: np.ndarray, dOut: np.ndarray, q=_id):
+    """Gradients of conv_forward w.r.t. W, b and X (q as in conv_forward; the bias gradient
+    sums the unrounded dOut)."""
+    db = dOut.sum(axis=0)
+    X, W, dOut = q(X), q(W), q(dOut)
     L, C = X.shape
     lout = dOut.shape[0]
     dW = np.zeros_like(W)
@@ -100,28 +109,30 @@ def conv_backward(X: np.ndarray, W: np.ndarray, dOut: np.ndarray):
         ok = (src >= 0) & (src < L)
         dW[t * C:(t + 1) * C] += X[src[ok]].T @ dOut[ok]
         np.add.at(dX, src[ok], dOut[ok] @ W[t * C:(t + 1) * C].T)
-    return dW, dOut.sum(axis=0), dX
+    return dW, db, dX
 
 
-def forward(cfg: NetConfig, theta: np.ndarray, X: np.ndarray):
-    """U [s*m] for one instance's features X; also returns the cached activations."""
+def forward(cfg: NetConfig, theta: np.ndarray, X: np.ndarray, q=_id):
+    """U [s*m] for one instance's features X; also returns the cached activations.  q rounds
+    the operands of every matrix product (identity: exact FP64; a bf16 rounding reproduces a
+    network that multiplies bf16 operands)."""
     params = unpack(cfg, theta)
     shapes = cfg.layer_shapes()
     acts = [X]
     h = X
     for (W, b), (kin, kout, conv, relu, lin, lout, cin) in zip(params, shapes):
         if conv:
-            z = conv_forward(h, W, b, lout)
+            z = conv_forward(h, W, b, lout, q)
         else:
-            z = h.reshape(-1) @ W + b
+            z = q(h.reshape(-1)) @ q(W) + b
         h = np.maximum(z, 0.0) if relu else z
         acts.append(h)
-    U = acts[-1] @ synthesis_basis(cfg)
+    U = q(acts[-1]) @ q(synthesis_basis(cfg))
     return U, acts
 
 
-def loss_and_grad(cfg: NetConfig, theta: np.ndarray, Xs, Ts, rs):
-    """Mean relative MSE over the batch and its gradient w.r.t. theta."""
+def loss_and_grad(cfg: NetConfig, theta: np.ndarray, Xs, Ts, rs, q=_id):
+    """Mean relative MSE over the batch and its gradient w.r.t. theta (q as in forward)."""
     B = len(Xs)
     Bsyn = synthesis_basis(cfg)
     params = unpack(cfg, theta)
@@ -130,12 +141,12 @@ def loss_and_grad(cfg: NetConfig, theta: np.ndarray, Xs, Ts, rs):
     gparts = unpack(cfg, grad)  # views into grad
     total = 0.0
     for X, T, r in zip(Xs, Ts, rs):
-        U, acts = forward(cfg, theta, X)
+        U, acts = forward(cfg, theta, X, q)
         tv = T / r
         den = float(tv @ tv)
         total += float((U - tv) @ (U - tv)) / den
         dU = 2.0 * (U - tv) / (den * B)
-        d = Bsyn @ dU
+        d = q(Bsyn) @ q(dU)
         for li in range(5, -1, -1):
             W, b = params[li]
             kin, kout, conv, relu, lin, lout, cin = shapes[li]
@@ -145,12 +156,12 @@ def loss_and_grad(cfg: NetConfig, theta: np.ndarray, Xs, Ts, rs):
             hin = acts[li]
             gW, gb = gparts[li]
             if conv:
-                dW, db, dX = conv_backward(hin, W, d)
+                dW, db, dX = conv_backward(hin, W, d, q)
                 gW += dW
                 gb += db
                 d = dX
             else:
-                gW += np.outer(hin.reshape(-1), d)
+                gW += np.outer(q(hin.reshape(-1)), q(d))
                 gb += d
-                d = (W @ d).reshape(hin.shape)
+                d = (q(W) @ q(d)).reshape(hin.shape)
     return total / B, grad

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "FDE_OK", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -3: "FDE_ESINGU
 FDE_BVM_TRAPEZOIDAL, FDE_BVM_GBDF3, FDE_BVM_CUSTOM, FDE_BVM_GAM5 = 0, 1, 2, 3
 FDE_FP64, FDE_MIXED_C32 = 0, 1
 FDE_MEM_HOST, FDE_MEM_DEVICE = 0, 1
+FDE_COPY_H2D, FDE_COPY_D2H, FDE_COPY_D2D = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 
@@ -94,6 +95,10 @@ SIGNATURES = [
     ("fde_bvm_set_option", C.c_int, [_VP, C.c_int, C.c_int]),
     ("fde_bvm_get_option", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int)]),
     ("fde_autotune_report", C.c_int, [C.c_char_p, C.c_int]),
+    ("fde_device_alloc", C.c_int, [C.c_size_t, C.POINTER(_VP)]),
+    ("fde_device_free", C.c_int, [_VP]),
+    ("fde_memcpy", C.c_int, [_VP, _VP, C.c_size_t, C.c_int]),
+    ("fde_device_synchronize", C.c_int, []),
     ("fde_read_bandwidth_probe", C.c_int, [C.c_size_t, C.c_int, _dp]),
     ("fde_mfma_peak_probe", C.c_int, [C.c_int, C.c_int, _dp]),
     ("fde_build_rhs", C.c_int, [_VP, _VP, _VP, _VP, C.c_int]),
@@ -130,18 +135,23 @@ SIGNATURES = [
 _lib = None
 
 
-def _preload_torch_hip_runtime():
-    """Bind the process to ONE HIP runtime.  torch ships its own libamdhip64.so with the same
-    SONAME as ROCm's; if ours were loaded first, torch would later map a second runtime that
-    sees no GPU.  Loading torch's copy first (by path, RTLD_GLOBAL) makes libfdebvm.so bind to
-    it, so torch tensors, streams and this library share a runtime."""
-    import importlib.util
-    spec = importlib.util.find_spec("torch")
-    if spec is None or not spec.origin:
+def _bind_runtime_first():
+    """Make the HIP runtime that torch ships the only one in the process.
+
+    torch's libamdhip64.so carries the same SONAME (libamdhip64.so.7) as the system ROCm
+    runtime this library is linked against, and torch resolves its own copy through its
+    RPATH, so the first of the two to be loaded decides which runtime this library binds
+    to.  Importing torch first maps torch's runtime (and its HSA runtime) once; this library
+    then binds to it by SONAME and no second runtime is ever mapped.  With FDE_NO_TORCH=1
+    torch is not imported and the library binds to the system runtime instead (a process
+    that must not map torch's copy, e.g. one whose profiler preloads the system runtime);
+    torch must then not be imported later in that process."""
+    if os.environ.get("FDE_NO_TORCH", "0") == "1":
         return
-    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
-    if os.path.exists(path):
-        C.CDLL(path, mode=C.RTLD_GLOBAL)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
 
 
 def lib():
@@ -149,7 +159,7 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    _preload_torch_hip_runtime()
+    _bind_runtime_first()
     if not os.path.exists(LIB_PATH):
         raise NativeLibraryMissing(
             f"{LIB_PATH} is not built; run `python -m paper_1305_6653_amd.build` (hipcc, gfx950)")

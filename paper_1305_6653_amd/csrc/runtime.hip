@@ -1219,6 +1219,38 @@ extern "C" fde_status fde_mfma_peak_probe(int fp64, int reps, double *tflops) {
   return st;
 }
 
+// ---- device buffers for callers without a device allocator of their own ------------------
+extern "C" fde_status fde_device_alloc(size_t bytes, void **ptr) {
+  if (!ptr) return fail(FDE_EINVAL, "ptr is NULL");
+  *ptr = nullptr;
+  if (bytes == 0) return fail(FDE_EINVAL, "bytes must be positive");
+  return dalloc_raw(ptr, bytes);
+}
+
+extern "C" fde_status fde_device_free(void *ptr) {
+  if (ptr) HIPCHK(hipFree(ptr));
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_memcpy(void *dst, const void *src, size_t bytes, int kind) {
+  if (bytes == 0) return FDE_OK;
+  if (!dst || !src) return fail(FDE_EINVAL, "NULL pointer");
+  hipMemcpyKind k;
+  switch (kind) {
+    case FDE_COPY_H2D: k = hipMemcpyHostToDevice; break;
+    case FDE_COPY_D2H: k = hipMemcpyDeviceToHost; break;
+    case FDE_COPY_D2D: k = hipMemcpyDeviceToDevice; break;
+    default: return fail(FDE_EINVAL, "unknown copy kind %d", kind);
+  }
+  HIPCHK(hipMemcpy(dst, src, bytes, k));
+  return FDE_OK;
+}
+
+extern "C" fde_status fde_device_synchronize(void) {
+  HIPCHK(hipDeviceSynchronize());
+  return FDE_OK;
+}
+
 extern "C" fde_status fde_autotune_report(char *buf, int len) {
   if (!buf || len < 1) return fail(FDE_EINVAL, "invalid buffer");
   const std::string r = tuned_summary();

@@ -6,12 +6,16 @@ happens in the HIP library; nothing here does arithmetic on the data.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from typing import Optional
 
 import numpy as np
 
 from . import _native as N
+from .devmem import DeviceArray
 
 _KINDS = {"trapezoidal": N.FDE_BVM_TRAPEZOIDAL, "gbdf3": N.FDE_BVM_GBDF3, "gam5": N.FDE_BVM_GAM5}
 _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
@@ -21,12 +25,43 @@ _SIDE = {"right": N.FDE_SIDE_RIGHT, "left": N.FDE_SIDE_LEFT}
 _BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG}
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    """Destroy the handles still open at interpreter exit while the HIP runtime is fully up
+    (a destructor run during interpreter teardown could free device memory after the
+    runtime's own exit handlers)."""
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 def _is_torch_cuda(x) -> bool:
-    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+    return hasattr(x, "is_cuda") and bool(x.is_cuda) and not isinstance(x, DeviceArray)
+
+
+def _sync_torch_producers(stream_ptr, *arrays):
+    """Device tensors are read on the library's stream.  Unless that stream is torch's current
+    one, wait until torch's current stream has finished the work that produced them."""
+    if not any(_is_torch_cuda(a) for a in arrays if a is not None):
+        return
+    import torch
+    cs = torch.cuda.current_stream()
+    if not (stream_ptr and stream_ptr == cs.cuda_stream):
+        cs.synchronize()
 
 
 def _arg(x, count: int, name: str, writable: bool = False):
-    """Return (pointer, mem_space, keepalive) for a host numpy or device torch FP64 array."""
+    """Return (pointer, mem_space, keepalive) for a host numpy array or a device FP64 array
+    (torch CUDA tensor or ``DeviceArray``)."""
+    if isinstance(x, DeviceArray):
+        if x.numel() != count:
+            raise ValueError(f"{name}: expected {count} elements, got {x.numel()}")
+        return C.c_void_p(x.data_ptr()), N.FDE_MEM_DEVICE, x
     if _is_torch_cuda(x):
         import torch
         if x.dtype != torch.float64 or not x.is_contiguous():
@@ -59,7 +94,10 @@ class BvmSolver:
     and optional xL, xR, t0, T (a ``workloads.Problem`` works).
     """
 
-    def __init__(self, problem, stream=None):
+    def __init__(self, problem, stream=None, formula=None):
+        """formula: a custom mu-step BVM (FDE_BVM_CUSTOM) given as any object with nu, mu,
+        alpha, beta [mu+1], alpha_init, beta_init [nu-1][mu+1] and alpha_fin, beta_fin
+        [mu-nu][mu+1]; it replaces the problem's named BVM."""
         L = N.lib()
         self.m = int(problem.m)
         self.s = int(problem.s)
@@ -68,13 +106,19 @@ class BvmSolver:
         if self._dp.size != self.m or self._dm.size != self.m:
             raise ValueError("d_plus and d_minus must have m entries")
         kind = getattr(problem, "bvm", "gbdf3")
-        if kind not in _KINDS:
+        custom = None
+        if formula is not None:
+            custom = self._custom_formula(formula)
+            code = N.FDE_BVM_CUSTOM
+        elif kind in _KINDS:
+            code = _KINDS[kind]
+        else:
             raise ValueError(f"unknown BVM {kind!r}")
         p = N.FdeProblem(float(problem.alpha), float(getattr(problem, "xL", 0.0)),
                          float(getattr(problem, "xR", 2.0)), float(getattr(problem, "t0", 0.0)),
                          float(getattr(problem, "T", 1.0)), self.m, self.s,
                          self._dp.ctypes.data_as(N._dp), self._dm.ctypes.data_as(N._dp),
-                         _KINDS[kind], None)
+                         code, C.pointer(custom) if custom is not None else None)
         h = C.c_void_p()
         N.check(L.fde_bvm_setup(C.byref(p), C.byref(h)))
         self._h = h
@@ -82,8 +126,26 @@ class BvmSolver:
         N.check(L.fde_get_dims(h, dims))
         self.mu, self.nu, self.nb, self.mp = dims[2], dims[3], dims[4], dims[5]
         self.n = self.m * self.s
+        self._stream_ptr = 0
+        _LIVE.add(self)
         if stream is not None:
             self.set_stream(stream)
+
+    def _custom_formula(self, F):
+        nu, mu = int(F.nu), int(F.mu)
+        arrs = []
+
+        def dp(x, rows):
+            if rows == 0:
+                return None
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(rows, mu + 1))
+            arrs.append(a)
+            return a.ctypes.data_as(N._dp)
+        f = N.FdeBvmFormula(nu, mu - nu, dp(F.alpha, 1), dp(F.beta, 1),
+                            dp(F.alpha_init, nu - 1), dp(F.beta_init, nu - 1),
+                            dp(F.alpha_fin, mu - nu), dp(F.beta_fin, mu - nu))
+        self._formula_keep = arrs  # the library copies the tables during setup
+        return f
 
     # ---- lifecycle
     def close(self):
@@ -92,6 +154,8 @@ class BvmSolver:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -112,6 +176,7 @@ class BvmSolver:
     def set_stream(self, stream):
         ptr = getattr(stream, "cuda_stream", stream)
         N.check(N.lib().fde_set_stream(self._h, C.c_void_p(ptr or 0)))
+        self._stream_ptr = int(ptr or 0)
 
     # ---- the three calls
     def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None,
@@ -149,6 +214,7 @@ class BvmSolver:
             out = self._alloc_like(space, (self.s, self.m), u0)
         pu, so, k4 = _arg(out, self.n, "out", writable=True)
         _same_space(space, so)
+        _sync_torch_producers(self._stream_ptr, u0, f, x0, out)
         opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), px0, space, int(x0_kind))
         info = N.FdeSolveInfo()
         st = N.lib().fde_bvm_solve(self._h, pu0, pf, pu, C.byref(opts), C.byref(info))
@@ -163,6 +229,7 @@ class BvmSolver:
         space = _same_space(s1, s2)
         out = self._alloc_like(space, (self.s, self.m), u0) if out is None else out
         pb, _, _c = _arg(out, self.n, "out", writable=True)
+        _sync_torch_producers(self._stream_ptr, u0, f, out)
         N.check(N.lib().fde_build_rhs(self._h, pu0, pf, pb, space))
         return out
 
@@ -170,6 +237,7 @@ class BvmSolver:
         pz, space, _a = _arg(z, self.n, "z")
         out = self._alloc_like(space, (self.s, self.m), z) if out is None else out
         pw, _, _b = _arg(out, self.n, "out", writable=True)
+        _sync_torch_producers(self._stream_ptr, z, out)
         N.check(N.lib().fde_apply_matvec(self._h, pz, pw, space))
         return out
 
@@ -185,6 +253,7 @@ class BvmSolver:
         pz, space, _a = _arg(z, self.n, "z")
         out = self._alloc_like(space, (self.s, self.m), z) if out is None else out
         pw, _, _b = _arg(out, self.n, "out", writable=True)
+        _sync_torch_producers(self._stream_ptr, z, out)
         N.check(fn(self._h, pz, pw, space))
         return out
 
@@ -198,6 +267,7 @@ class BvmSolver:
         pv, space, _a = _arg(v, self.n, "v")
         out = self._alloc_like(space, (self.s, self.m), v) if out is None else out
         pz, _, _b = _arg(out, self.n, "out", writable=True)
+        _sync_torch_producers(self._stream_ptr, v, out)
         N.check(N.lib().fde_apply_precond(self._h, pv, pz, space))
         return out
 
@@ -240,6 +310,8 @@ class BvmSolver:
 
     @staticmethod
     def _alloc_like(space, shape, like):
+        if isinstance(like, DeviceArray):
+            return DeviceArray(shape)
         if space == N.FDE_MEM_DEVICE:
             import torch
             return torch.empty(shape, dtype=torch.float64, device=like.device)
@@ -287,6 +359,7 @@ def solve_batch(solvers, u0s, fs, rtol: float = 1e-10, restart: int = 20, maxit:
             spaces.append(sd)
             px0[i] = d
     space = _same_space(*spaces)
+    _sync_torch_producers(solvers[0]._stream_ptr if count else 0, *keep)
     opts = N.FdeSolveOpts(float(rtol), int(restart), int(maxit), None, space, int(x0_kind))
     infos = (N.FdeSolveInfo * count)()
     if x0s is None:

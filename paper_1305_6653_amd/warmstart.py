@@ -40,6 +40,9 @@ class WarmStartNet:
             self._h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -1,6 +1,8 @@
 """Batched form: many uneven instances factored and solved with one launch per phase.
 Each instance's arithmetic is independent of its batch-mates, so a batched result must be
 bitwise equal to solving the instance alone; both must match the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -59,23 +61,53 @@ def test_batch_warm_start_x0():
         assert i["iters"] == 0 and _rel(b, a) <= 1e-12
 
 
-@pytest.mark.slow
-def test_uneven_64_instance_batch_mixed():
-    """The 64-instance uneven batch (m in 127..2047, s in 64..512, seeds 4000+i), mixed
-    precision: every instance reaches true relative residual 1e-10, re-checked on the CPU
-    in FP64 with the oracle's dense-J product; a sample of small instances is compared
-    with the oracle's solution."""
+def _batch64_mixed():
     ps = W.batch_c4(64)
     batch = [BvmSolver(p) for p in ps]
     factor_batch(batch, "mixed")
     outs, infos = solve_batch(batch, [p.u0 for p in ps], [p.f for p in ps])
+    for S in batch:
+        S.close()
+    return ps, outs, infos
+
+
+def _compare_with_oracle(p, u):
+    ref = O.solve_gmres(p, tol=1e-12, progress=lambda t: print(t, flush=True))
+    err = np.abs(u - ref.x).max() / np.abs(ref.x).max()
+    assert _rel(u, ref.x) <= 1e-8 and err <= 1e-8, (p.name, _rel(u, ref.x), err)
+    print(f"oracle solution of {p.name} compared: {_rel(u, ref.x):.2e} norm-wise, {err:.2e} worst entry",
+          flush=True)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_uneven_64_instance_batch_mixed():
+    """The 64-instance uneven batch (m in 127..2047, s in 64..512, seeds 4000+i), mixed
+    precision: every instance reaches true relative residual 1e-10, re-checked on the CPU
+    in FP64 with the oracle's dense-J product for all 64; the four smallest instances and the
+    largest with m <= 1023 are compared with the oracle's solution, norm-wise and entry by
+    entry (the largest, m = 2047, in the heavy test below)."""
+    ps, outs, infos = _batch64_mixed()
     assert all(i["converged"] == 1 for i in infos)
     order = sorted(range(64), key=lambda i: ps[i].m * ps[i].s)
-    for i in order[:40]:
+    for i in order:
         assert O.true_relres(ps[i], outs[i]) <= 1.5e-10, ps[i].name
-    for i in order[:4]:
-        ref = O.solve_gmres(ps[i], tol=1e-12)
-        assert _rel(outs[i], ref.x) <= 1e-8, ps[i].name
+    print("64 true residuals checked", flush=True)
+    mid = [i for i in order if ps[i].m <= 1023][-1]
+    for i in order[:4] + [mid]:
+        _compare_with_oracle(ps[i], outs[i])
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1800)
+@pytest.mark.skipif(os.environ.get("FDE_HEAVY_TESTS") != "1",
+                    reason="the oracle's solve of an m = 2047, s = 512 instance takes several minutes "
+                           "(257 LAPACK LUs of order 2047, 17 GB of factors); FDE_HEAVY_TESTS=1 runs it")
+def test_uneven_64_instance_batch_largest_against_the_oracle():
+    ps, outs, infos = _batch64_mixed()
+    i = max(range(64), key=lambda i: ps[i].m * ps[i].s)
+    assert infos[i]["converged"] == 1
+    _compare_with_oracle(ps[i], outs[i])
 
 
 @pytest.mark.parametrize("count", [5, 9])

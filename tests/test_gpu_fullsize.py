@@ -3,10 +3,13 @@
 * 1023 x 512 GBDF3 (seed 2): the FP64 and the mixed-form solutions against the oracle's
   (textbook preconditioned GMRES to 1e-11 with LAPACK block solves, ~10-20 s), plus the
   true residual with the oracle's dense operator, and sampled factor blocks.
-* 4095 x 256 GBDF3 (seed 3, mixed form): the oracle's whole solve takes about a minute, so the
-  checks are the properties that hold at any size: the true residual of the GPU solution with
-  the oracle's dense operator, and sampled FP32 factor blocks against the oracle's K_k by
-  products with random vectors."""
+* 4095 x 256 GBDF3 (seed 3), FP64 and mixed form: the solutions against the oracle's (about a
+  minute of host LAPACK work and 35 GB of host memory for its block factors), plus the true
+  residual with the oracle's dense operator and sampled factor blocks against the oracle's K_k
+  by products with random vectors.
+
+Solutions are compared norm-wise and entry by entry (the worst entry relative to the
+solution's largest)."""
 import numpy as np
 import pytest
 
@@ -21,6 +24,10 @@ def _rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _elem(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max()
 
 
 def _factor_product_error(S, p, k, rng):
@@ -39,7 +46,8 @@ def _factor_product_error(S, p, k, rng):
 def test_m1023_s512_fp64_and_mixed_match_the_oracle():
     p = W.smooth_c2()
     S = BvmSolver(p)
-    ref = O.solve_gmres(p, tol=1e-11, maxit=200)  # true rel-res ~4e-12
+    ref = O.solve_gmres(p, tol=1e-11, maxit=200,  # true rel-res ~4e-12
+                        progress=lambda t: print(t, flush=True))
     rng = np.random.default_rng(5)
     nb = p.s // 2 + 1
     for prec, tol, ftol in (("fp64", 1e-9, 1e-12), ("mixed", 1e-8, 1e-5)):
@@ -47,6 +55,7 @@ def test_m1023_s512_fp64_and_mixed_match_the_oracle():
         u, info = S.solve(p.u0, p.f, rtol=1e-10)
         assert info["converged"] == 1 and info["true_relres"] <= 1e-10
         assert _rel(u, ref.x) <= tol, (prec, _rel(u, ref.x))
+        assert _elem(u, ref.x) <= tol, (prec, _elem(u, ref.x))
         assert O.true_relres(p, u) <= 1.5e-10
         for k in (0, 1, nb // 2, nb - 1):
             e = _factor_product_error(S, p, k, rng)
@@ -54,16 +63,28 @@ def test_m1023_s512_fp64_and_mixed_match_the_oracle():
     S.close()
 
 
-def test_m4095_s256_mixed_full_size_properties():
+@pytest.fixture(scope="module")
+def c3_oracle():
     p = W.smooth_c3()
+    print("oracle solve of the 4095 x 256 workload (about a minute)", flush=True)
+    return p, O.solve_gmres(p, tol=1e-11, maxit=200, progress=lambda t: print(t, flush=True))
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,tol,ftol", [("fp64", 1e-9, 1e-12), ("mixed", 1e-8, 1e-4)])
+def test_m4095_s256_matches_the_oracle(c3_oracle, prec, tol, ftol):
+    p, ref = c3_oracle
+    assert ref.converged
     S = BvmSolver(p)
-    S.factor("mixed")
+    S.factor(prec)
     u, info = S.solve(p.u0, p.f, rtol=1e-10)
     assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+    assert _rel(u, ref.x) <= tol, (prec, _rel(u, ref.x))
+    assert _elem(u, ref.x) <= tol, (prec, _elem(u, ref.x))
     assert O.true_relres(p, u) <= 1.5e-10
     rng = np.random.default_rng(6)
     nb = p.s // 2 + 1
     for k in (0, 1, nb // 2, nb - 1):
         e = _factor_product_error(S, p, k, rng)
-        assert e <= 1e-4, (k, e)
+        assert e <= ftol, (prec, k, e)
     S.close()

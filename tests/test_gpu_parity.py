@@ -35,6 +35,13 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def _elem(a, b):
+    """max_i |a_i - b_i| / max_i |b_i|: the worst single entry, relative to the solution's scale."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
 @pytest.mark.parametrize("name", SMALL)
 def test_toeplitz_matvec_vs_dense(name):
     p, S = _setup(name)
@@ -129,6 +136,7 @@ def test_solve_vs_oracle(name, prec, tol):
     ref = O.solve_gmres(p, tol=1e-12)   # 1e-13 is below the FP64 floor of some cases
     assert ref.converged
     assert _rel(u, ref.x) <= tol, _rel(u, ref.x)
+    assert _elem(u, ref.x) <= tol, _elem(u, ref.x)
     assert O.true_relres(p, u) <= 1.5e-10
     if prec == "fp64":
         ref10 = O.solve_gmres(p, tol=1e-10)
@@ -176,11 +184,6 @@ def test_errors_and_noconv():
     assert e.value.status == N.FDE_ENOCONV
 
 
-@pytest.mark.skip(reason="a full GPU-suite run ended in a segmentation fault of the host "
-                  "process inside this test's first `import torch`, after 149 tests had used the "
-                  "library; no cause found yet (every host-side copy of the library is "
-                  "synchronized before it returns, no kernel writes host-mapped memory), so the "
-                  "case is off until one is shown")
 def test_device_pointers_match_host():
     import torch
     p, S = _setup("gbdf3_m200_s32")
@@ -192,6 +195,95 @@ def test_device_pointers_match_host():
     ud, info = S.solve(u0, f)
     torch.cuda.synchronize()
     assert np.array_equal(ud.cpu().numpy(), uh)
+
+
+def test_device_inputs_produced_just_before_the_call():
+    """Device inputs written by torch work still queued on torch's current stream (a long
+    product first, then the copies that fill f and u0) are read only after that work: the
+    binding orders the library's stream after torch's producers."""
+    import torch
+    p, S = _setup("gbdf3_m200_s32")
+    S.factor("fp64")
+    uh, _ = S.solve(p.u0, p.f)
+    dev = torch.device("cuda:0")
+    a = torch.randn(4096, 4096, device=dev)
+    f = torch.zeros((p.s + 1, p.m), dtype=torch.float64, device=dev)
+    u0 = torch.zeros(p.m, dtype=torch.float64, device=dev)
+    fh = torch.from_numpy(np.ascontiguousarray(p.f)).pin_memory()
+    u0h = torch.from_numpy(np.ascontiguousarray(p.u0)).pin_memory()
+    torch.cuda.synchronize()
+    for _ in range(8):
+        a = a @ a / 64.0          # queued ahead of the copies
+    f.copy_(fh, non_blocking=True)
+    u0.copy_(u0h, non_blocking=True)
+    ud, info = S.solve(u0, f)
+    torch.cuda.synchronize()
+    assert np.array_equal(ud.cpu().numpy(), uh)
+    w = S.matvec(ud)
+    torch.cuda.synchronize()
+    assert np.array_equal(w.cpu().numpy(), S.matvec(uh))
+
+
+def test_device_array_inputs_match_host():
+    """Device buffers from the library's own allocator (no torch) give the host result."""
+    from paper_1305_6653_amd.devmem import DeviceArray
+    p, S = _setup("trap_m130_s16")
+    S.factor("fp64")
+    uh, _ = S.solve(p.u0, p.f)
+    u0, f = DeviceArray.from_numpy(p.u0), DeviceArray.from_numpy(p.f)
+    ud, _ = S.solve(u0, f)
+    assert isinstance(ud, DeviceArray) and np.array_equal(ud.numpy(), uh)
+    for a in (u0, f, ud):
+        a.free()
+
+
+@pytest.mark.parametrize("where", ["f", "u0"])
+def test_non_finite_input_is_rejected(where):
+    """A NaN in f or u0 makes the right-hand side non-finite: FDE_EINVAL, nothing solved."""
+    p, S = _setup("gbdf3_m7_s8")
+    S.factor("fp64")
+    f, u0 = p.f.copy(), p.u0.copy()
+    if where == "f":
+        f[1, 3] = np.nan
+    else:
+        u0[3] = np.nan
+    with pytest.raises(FdeError) as e:
+        S.solve(u0, f)
+    assert e.value.status == N.FDE_EINVAL
+
+
+def test_custom_formula_equals_the_built_in_one():
+    """FDE_BVM_CUSTOM carrying the third-order GBDF's coefficients (eq. (1.7)-(1.9)) gives the
+    built-in GBDF3 solve bit for bit: same tables, same kernels."""
+    p = CASES["gbdf3_m200_s32"]()
+    S1, S2 = BvmSolver(p), BvmSolver(p, formula=O.gbdf3())
+    for prec in ("fp64", "mixed"):
+        S1.factor(prec)
+        S2.factor(prec)
+        u1, i1 = S1.solve(p.u0, p.f)
+        u2, i2 = S2.solve(p.u0, p.f)
+        assert np.array_equal(u1, u2) and i1["iters"] == i2["iters"], prec
+    S1.close()
+    S2.close()
+
+
+def test_zero_pivot_returns_esingular():
+    """A consistent custom formula with sigma = 0 and a double root of rho at 1
+    (u_{n+1} - 2 u_n + u_{n-1} = 0) makes the zero-frequency block K_0 = rho(1) I = 0: the
+    factorization reports FDE_ESINGULAR and leaves the handle unfactored."""
+    import types
+    p = W.tiny(20, 8, 1.5, 9, "gbdf3")
+    F = types.SimpleNamespace(nu=1, mu=2, alpha=[1.0, -2.0, 1.0], beta=[0.0, 0.0, 0.0],
+                              alpha_init=[], beta_init=[], alpha_fin=[1.0, -2.0, 1.0],
+                              beta_fin=[0.0, 0.0, 0.0])
+    S = BvmSolver(p, formula=F)
+    with pytest.raises(FdeError) as e:
+        S.factor("fp64")
+    assert e.value.status == N.FDE_ESINGULAR
+    with pytest.raises(FdeError) as e:
+        S.solve(p.u0, p.f)
+    assert e.value.status == N.FDE_EINVAL
+    S.close()
 
 
 def test_batch_equals_single():

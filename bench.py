@@ -143,17 +143,71 @@ def measured_read_peak():
     return round(v.value, 1)
 
 
-def calib_copy(mib):
-    """One plain device-to-device copy of mib MiB (a blit dispatch) outside the timed region."""
-    import torch
-    if mib <= 0:
-        return
-    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0")
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    b.copy_(a)
-    torch.cuda.synchronize()
-    del a, b
+class DeviceMemory:
+    """Where the benchmark keeps its device arrays: torch CUDA tensors (default), or the
+    library's own device buffers (``library``: no torch in the process, so a profiler that
+    preloads the system HIP runtime sees the only runtime the process maps)."""
+
+    def __init__(self, kind):
+        self.kind = kind
+        if kind == "library":
+            os.environ["FDE_NO_TORCH"] = "1"
+
+    def put(self, a):
+        import numpy as np
+        if self.kind == "library":
+            from paper_1305_6653_amd.devmem import DeviceArray
+            return DeviceArray.from_numpy(a)
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+    def empty(self, shape):
+        if self.kind == "library":
+            from paper_1305_6653_amd.devmem import DeviceArray
+            return DeviceArray(shape)
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device="cuda:0")
+
+    def get(self, d):
+        return d.numpy().copy() if self.kind == "library" else d.cpu().numpy().copy()
+
+    def sync(self):
+        if self.kind == "library":
+            from paper_1305_6653_amd.devmem import synchronize
+            synchronize()
+        else:
+            import torch
+            torch.cuda.synchronize()
+
+    def stream(self):
+        if self.kind == "library":
+            return None
+        import torch
+        return torch.cuda.current_stream()
+
+    def calib_copy(self, mib):
+        """One plain device-to-device copy of mib MiB (a blit dispatch) outside the timed region."""
+        if mib <= 0:
+            return
+        if self.kind == "library":
+            from paper_1305_6653_amd.devmem import DeviceArray
+            a, b = DeviceArray(mib << 17), DeviceArray(mib << 17)   # 8-byte elements
+            self.sync()
+            b.copy_from(a)
+            self.sync()
+            a.free()
+            b.free()
+            return
+        import torch
+        a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+
+DEV = DeviceMemory("torch")
 
 
 def parse():
@@ -168,6 +222,9 @@ def parse():
                     help="skip the solves with the blocks factored through a Hessenberg form of J")
     ap.add_argument("--no-bccb", action="store_true",
                     help="skip the BCCB-preconditioned solves reported beside the main one")
+    ap.add_argument("--device-memory", default="torch", choices=["torch", "library"],
+                    help="hold the device arrays in torch tensors or in the library's own buffers "
+                         "(library: torch is not imported)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this many MiB "
                          "(the reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -199,26 +256,25 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     """W warmup steps, then K timed steps (the value), then the same K steps again with every
     launch bracketed by HIP events on the library's stream (the per-kernel profile: the
     events cost a few microseconds per launch, so they are kept out of the first pass)."""
-    import torch
     for _ in range(warmup):
         S.factor(prec, pc)
         S.solve(u0, f, out=out, rtol=1e-10)
-    torch.cuda.synchronize()
+    DEV.sync()
     infos = []
     t0 = time.perf_counter()
     for _ in range(steps):
         S.factor(prec, pc)
         _, info = S.solve(u0, f, out=out, rtol=1e-10)
         infos.append(info)
-    torch.cuda.synchronize()
+    DEV.sync()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     S.profile(True)
-    torch.cuda.synchronize()
+    DEV.sync()
     t0 = time.perf_counter()
     for _ in range(steps):
         S.factor(prec, pc)
         S.solve(u0, f, out=out, rtol=1e-10)
-    torch.cuda.synchronize()
+    DEV.sync()
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
@@ -444,7 +500,7 @@ def bench_batch(args):
         "kernels": kernel_table(prof, args.steps, "mixed"),
         "roofline": roofline(prof, "mixed", "c4"), "cpu_baseline": None,
     }
-    calib_copy(args.calib_copy_mib)
+    DEV.calib_copy(args.calib_copy_mib)
     for S in Ss:
         S.close()
     print(json.dumps(result), flush=True)
@@ -504,7 +560,9 @@ def bench_example41(args):
 
 
 def main():
+    global DEV
     args = parse()
+    DEV = DeviceMemory(args.device_memory)
     if args.workload == "ex41":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -522,23 +580,22 @@ def main():
               "GPUs by frequency block, which this library does not run", file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    import torch
     from paper_1305_6653_amd import BvmSolver, autotune_report
     from paper_1305_6653_amd import _native as N
 
     p = workload(args.workload)
     prec = "fp64"
-    fp64_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    dev = torch.device("cuda:0")
+    fp64_dev = DEV.put
     u0 = fp64_dev(p.u0)
     f = fp64_dev(p.f)
-    out = torch.empty((p.s, p.m), dtype=torch.float64, device=dev)
+    out = DEV.empty((p.s, p.m))
     S = BvmSolver(p)
-    S.set_stream(torch.cuda.current_stream())
+    if DEV.stream() is not None:
+        S.set_stream(DEV.stream())
 
     ms, ms_prof, infos, prof = timed_steps(S, u0, f, out, prec, args.steps, args.warmup)
     read_peak = measured_read_peak()
-    u_main = out.cpu().numpy().copy()
+    u_main = DEV.get(out)
     result = {
         "metric": METRIC, "value": round(1000.0 / ms, 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -564,18 +621,18 @@ def main():
     for k in range(2):
         S.factor(prec)
         S.solve(*rhs[k % 2], out=out, rtol=1e-10)
-    torch.cuda.synchronize()
+    DEV.sync()
     t0 = time.perf_counter()
     for k in range(args.steps):
         S.factor(prec)
         S.solve(*rhs[k % 2], out=out, rtol=1e-10)
-    torch.cuda.synchronize()
+    DEV.sync()
     ms_alt = (time.perf_counter() - t0) * 1e3 / args.steps
     result["changed_rhs"] = {"ms_per_step": round(ms_alt, 4), "value": round(1000.0 / ms_alt, 4),
                              "rhs": f"alternating {p.name} and {q.name}'s u0, f"}
     if not args.no_mixed:
         ms2, _, infos2, prof2 = timed_steps(S, u0, f, out, "mixed", args.steps, args.warmup)
-        u_mixed = out.cpu().numpy()
+        u_mixed = DEV.get(out)
         result["mixed"] = {
             "ms_per_step": round(ms2, 4), "value": round(1000.0 / ms2, 4), "iters": infos2[-1]["iters"],
             "true_relres": infos2[-1]["true_relres"],
@@ -596,7 +653,7 @@ def main():
             except N.FdeError as e:
                 result["hessenberg"][form] = {"unsupported": str(e)}
                 continue
-            u4 = out.cpu().numpy()
+            u4 = DEV.get(out)
             result["hessenberg"][form] = {
                 "ms_per_step": round(ms4, 4), "value": round(1000.0 / ms4, 4),
                 "iters": infos4[-1]["iters"], "true_relres": infos4[-1]["true_relres"],
@@ -614,7 +671,7 @@ def main():
         for pc in ("bccb", "bccb_shifted"):
             ms3, _, infos3, prof3 = timed_steps(S, u0, f, out, "fp64", max(1, args.steps // 2),
                                                 1, pc)
-            u3 = out.cpu().numpy()
+            u3 = DEV.get(out)
             result["bccb"][pc] = {
                 "ms_per_step": round(ms3, 4), "value": round(1000.0 / ms3, 4),
                 "iters": infos3[-1]["iters"], "true_relres": infos3[-1]["true_relres"],
@@ -633,7 +690,7 @@ def main():
         result["vs_cpu_baseline"] = round(result["value"] / result["cpu_baseline"]["value"], 1)
     else:
         result["cpu_baseline"] = None
-    calib_copy(args.calib_copy_mib)
+    DEV.calib_copy(args.calib_copy_mib)
     print(json.dumps(result), flush=True)
 
 

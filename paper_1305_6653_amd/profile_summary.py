@@ -11,6 +11,10 @@ by a reference copy dispatch of known size (the largest dispatch whose name matc
 
     python -m paper_1305_6653_amd.profile_summary pmc <fetch.csv> <write.csv> --copy-bytes N \
         [--split NAME_SUBSTRING:KiB ...]
+
+Any counters (e.g. SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES): per-kernel averages:
+
+    python -m paper_1305_6653_amd.profile_summary counters <counter_collection.csv> [--key C]
 """
 import argparse
 import csv
@@ -192,6 +196,42 @@ def pmc_main(a):
         print(f"{name[:44]:44s} {max(nf, nw):6d} {fa:15.1f} {wa:15.1f} {rb:13.3f} {wb:13.3f} {rb + wb:12.3f}")
 
 
+def counters_main(a):
+    """Per kernel: dispatches and the average of every counter in the CSV (dispatches whose key
+    counter is below 5% of the kernel's median are left out, as gated-off launches)."""
+    tabs = {}
+    with open(a.csv, newline="") as fh:
+        rd = csv.reader(fh)
+        header = next(rd)
+        ik = _col(header, "Kernel_Name", "Kernel-Name", "KernelName")
+        ic = _col(header, "Counter_Name", "Counter-Name")
+        iv = _col(header, "Counter_Value", "Counter-Value")
+        idd = _col(header, "Dispatch_Id", "Dispatch-Id", "Correlation_Id")
+        for row in rd:
+            d, c = row[idd], row[ic].strip()
+            e = tabs.setdefault(d, [row[ik], {}])
+            e[1][c] = e[1].get(c, 0.0) + float(row[iv])
+    names = sorted({c for _, cs in tabs.values() for c in cs})
+    first = names[0] if not a.key else a.key
+    by = defaultdict(list)
+    for n, cs in tabs.values():
+        by[short_name(n)].append(cs)
+    if a.title:
+        print(a.title)
+    for c in a.command or []:
+        print(f"command: {c}")
+    print(f"{'kernel':44s} {'disp':>6s} " + " ".join(f"{c:>28s}" for c in names))
+    rows = []
+    for n, lst in by.items():
+        med = sorted(x.get(first, 0.0) for x in lst)[len(lst) // 2]
+        act = [x for x in lst if x.get(first, 0.0) >= 0.05 * med] or lst
+        avg = {c: sum(x.get(c, 0.0) for x in act) / len(act) for c in names}
+        rows.append((n, len(act), avg))
+    rows.sort(key=lambda r: -r[2].get(first, 0.0) * r[1])
+    for n, k, avg in rows[:a.top]:
+        print(f"{n[:44]:44s} {k:6d} " + " ".join(f"{avg[c]:28.4g}" for c in names))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -211,8 +251,14 @@ def main():
     p.add_argument("--top", type=int, default=25)
     p.add_argument("--split", action="append",
                    help="NAME_SUBSTRING:KiB: report a kernel's dispatches below and above KiB apart")
+    g = sub.add_parser("counters")
+    g.add_argument("csv")
+    g.add_argument("--key", default="", help="counter that orders the rows and sets the gated-off cut")
+    g.add_argument("--title", default="")
+    g.add_argument("--command", action="append")
+    g.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
-    trace_main(a) if a.mode == "trace" else pmc_main(a)
+    {"trace": trace_main, "pmc": pmc_main, "counters": counters_main}[a.mode](a)
 
 
 if __name__ == "__main__":

@@ -288,6 +288,22 @@ fde_status fde_toeplitz_apply(fde_bvm *h, const double *x, double *y, int count,
 fde_status fde_time_rfft(fde_bvm *h, const double *v, double *vhat, int mem_space);
 /* z = S^{-1} v (time DFT, block solves with the stored factors, inverse DFT), [s][m]. */
 fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, int mem_space);
+/* z = S^{-1} v like fde_apply_precond, allocating nothing: for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  v and z are DEVICE pointers ([s][m]); the handle must have been factored with
+ * the Strang preconditioner and block LU factors (the default).  The working memory of the
+ * call (the frequency-domain vector, the block-solve flags and counters, the launch
+ * descriptor) is one fixed static device array of FDE_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; its address is looked up once per device at fde_bvm_setup.  Every
+ * call on a GPU shares that array: calls that overlap on one GPU (from other threads or on
+ * other streams) race, so a caller serialises them.  The result equals fde_apply_precond's
+ * bit for bit (same kernels, same launch shapes).  Errors: FDE_EINVAL for NULL arguments or an
+ * unfactored handle; FDE_EUNSUPPORTED when (s/2+1) * mp * 16 bytes of frequency vector (mp =
+ * m rounded up to 64) plus its flags exceed the array (m = 4095 fits up to s = 256, m = 1023
+ * up to s = 1024), or for another preconditioner or block solver; FDE_EDEVICE if the block
+ * solve had to abandon a dependency wait. */
+#define FDE_NOALLOC_SCRATCH_BYTES (16u << 20)
+fde_status fde_apply_precond_noalloc(fde_bvm *h, const double *v, double *z);
 /* Copies the stored LU factors of block k (unit-lower L below the diagonal, U on and above
  * it, complex interleaved, [m][m] row-major, widened to FP64) to the host array out. */
 fde_status fde_get_factor_block(fde_bvm *h, int k, double *out);

@@ -106,6 +106,7 @@ SIGNATURES = [
     ("fde_toeplitz_apply", C.c_int, [_VP, _VP, _VP, C.c_int, C.c_int]),
     ("fde_time_rfft", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("fde_apply_precond", C.c_int, [_VP, _VP, _VP, C.c_int]),
+    ("fde_apply_precond_noalloc", C.c_int, [_VP, _VP, _VP]),
     ("fde_get_factor_block", C.c_int, [_VP, C.c_int, _VP]),
     ("fde_get_hessenberg", C.c_int, [_VP, _VP, _VP]),
     ("fde_profile_enable", C.c_int, [_VP, C.c_int]),

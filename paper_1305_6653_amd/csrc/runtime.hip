@@ -201,6 +201,8 @@ struct fde_bvm {
 // ====================================================================================
 // device memory helpers
 // ====================================================================================
+static fde_status noalloc_scratch(void **out);
+
 static fde_status dalloc_raw(void **p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
@@ -986,6 +988,11 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
     return bail(fail(FDE_EDEVICE, "hipStreamCreate failed"));
   }
   h->stream = h->own_stream;
+  {
+    void *na = nullptr;  // the allocation-free apply's array: address looked up once per device
+    fde_status sst = noalloc_scratch(&na);
+    if (sst != FDE_OK) return bail(sst);
+  }
   const int m = h->m, s = h->s, mu1 = h->mu + 1, nb = h->nb, L = h->L;
   const size_t n = h->n();
   fde_status st = FDE_OK;
@@ -2313,6 +2320,110 @@ extern "C" fde_status fde_apply_precond(fde_bvm *h, const double *v, double *z, 
   STCHK(copy_out(h, z, h->d_tmp, h->n(), mem_space));
   STCHK(sync_and_flush(h));
   return check_trsv_err(h->self);
+}
+
+// ---- allocation-free preconditioner apply --------------------------------------------------
+// Working memory of fde_apply_precond_noalloc: one file-scope device array per GPU, held until
+// the process ends.  Layout: the launch head (descriptor, item maps, epoch counter and slots,
+// error flag) in the first NA_HEAD bytes, the block-solve flags [nb][npan][2] in the next
+// NA_FLAGS bytes (a region of their own, so no other use of the array ever overwrites them:
+// every apply draws a larger epoch from the array's own counter, and flags only ever hold
+// earlier epochs), then the frequency-domain vector [nb][mp] complex FP64.
+static constexpr size_t NA_BYTES = (size_t)FDE_NOALLOC_SCRATCH_BYTES;
+static constexpr size_t NA_HEAD = 4096;
+static constexpr size_t NA_FLAGS = 512u << 10;
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+struct NoallocHead {
+  InstDesc desc;
+  int ids[1];
+  int pre_tfft[2], pre_trsv[2], pre_blk[2];
+  int err;
+  unsigned long long ctr;       // epochs drawn by the applies that used this array
+  unsigned long long epoch[2];  // epoch of the current apply, claimed-unit counter
+};
+static_assert(sizeof(NoallocHead) <= NA_HEAD, "launch head exceeds its region");
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+// Device address of this GPU's array (the name `scratch` is a host-side stand-in): looked up
+// once per device, with that device current, and kept.
+static fde_status noalloc_scratch(void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(FDE_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FDE_OK;
+}
+
+// Writes the launch head of one apply (the counter is left as it is); the block solve's error
+// flag starts at zero.
+__global__ void k_noalloc_head(NoallocHead *hd, InstDesc d, int n_tfft, int n_trsv, int n_blk) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  hd->desc = d;
+  hd->ids[0] = 0;
+  hd->pre_tfft[0] = 0;
+  hd->pre_tfft[1] = n_tfft;
+  hd->pre_trsv[0] = 0;
+  hd->pre_trsv[1] = n_trsv;
+  hd->pre_blk[0] = 0;
+  hd->pre_blk[1] = n_blk;
+  hd->err = 0;
+}
+
+extern "C" fde_status fde_apply_precond_noalloc(fde_bvm *h, const double *v, double *z) {
+  if (!h || !v || !z) return fail(FDE_EINVAL, "NULL argument");
+  const size_t flag_bytes = (size_t)h->nb * h->npan * 2 * sizeof(unsigned long long);
+  const size_t vh_bytes = (size_t)h->nb * h->mp * sizeof(double2);
+  if (flag_bytes > NA_FLAGS || vh_bytes > NA_BYTES - NA_HEAD - NA_FLAGS)
+    return fail(FDE_EUNSUPPORTED,
+                "m = %d, s = %d needs %zu bytes of working memory; the allocation-free apply has %zu",
+                h->m, h->s, NA_HEAD + NA_FLAGS + vh_bytes, NA_BYTES);
+  if (h->prec < 0) return fail(FDE_EINVAL, "fde_precond_factor must succeed first");
+  if (h->pc != FDE_PC_STRANG || h->blk_route != FDE_BLOCKS_LU)
+    return fail(FDE_EUNSUPPORTED, "the allocation-free apply takes the Strang preconditioner with block LU factors");
+  void *base = nullptr;
+  STCHK(noalloc_scratch(&base));
+  unsigned char *b = (unsigned char *)base;
+  NoallocHead *hd = (NoallocHead *)b;
+  // launch shapes as the handle's own apply takes them (same kernels, same bits)
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int cols = time_fft_cols_per_item(h->mp, std::max(cus, 1));
+  const int W = trsv_workgroups(h->self, h, h->prec);
+  const int n_tfft = h->mp / cols, n_trsv = h->nb * W, n_blk = h->nb;
+  InstDesc d = make_desc(h);
+  d.W = W;
+  d.sio = const_cast<double *>(v);  // read by the time FFT
+  d.tmp = z;                        // written by the inverse time FFT
+  d.tsflags = (unsigned long long *)(b + NA_HEAD);
+  d.Vh = (double2 *)(b + NA_HEAD + NA_FLAGS);
+  d.Vts = d.Vh;
+  hipStream_t st = h->stream;
+  hipLaunchKernelGGL(k_noalloc_head, dim3(1), dim3(64), 0, st, hd, d, n_tfft, n_trsv, n_blk);
+  HIPCHK(hipGetLastError());
+  const InstDesc *D = &hd->desc;
+  const ItemMap tfft{hd->ids, hd->pre_tfft, 1, nullptr};
+  const ItemMap trsv{hd->ids, hd->pre_trsv, 1, nullptr};
+  const ItemMap blk{hd->ids, hd->pre_blk, 1, nullptr};
+  HIPCHK(launch_time_rfft(D, tfft, n_tfft, h->log2s, cols, VS_SIO, 0, st, &hd->ctr, hd->epoch));
+  HIPCHK(h->prec == FDE_FP64
+             ? launch_trsv_coop<double>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan)
+             : launch_trsv_coop<float>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan));
+  HIPCHK(launch_time_irfft(D, tfft, n_tfft, h->log2s, cols, VS_TMP, 0, st));
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, &hd->err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (err) return fail(FDE_EDEVICE, "block solve abandoned a dependency wait");
+  return FDE_OK;
 }
 
 extern "C" fde_status fde_time_rfft(fde_bvm *h, const double *v, double *vhat, int mem_space) {

@@ -34,6 +34,7 @@ PMC_GROUPS = {
     "spacetime": ("k_spacetime.hip", "fft_lds.hpp", "common.hpp", "batch.hpp"),
     "krylov": ("k_krylov.hip", "common.hpp", "batch.hpp"),
     "hessenberg": ("k_hessenberg.hip", "common.hpp", "batch.hpp"),
+    "band": ("k_band.hip", "common.hpp", "batch.hpp"),
 }
 PMC_KERNEL_GROUP = {
     "assemble": "factor", "lu_diag": "factor", "lu_panel": "factor", "lu_update": "factor",
@@ -44,6 +45,7 @@ PMC_KERNEL_GROUP = {
     "update_x": "krylov", "dot": "krylov",
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
+    "band_reduce": "band", "band_lu_panel": "factor", "band_lu_rows": "factor", "band_lsolve": "factor",
 }
 PMC_SOURCE_HASH = {"factor": "c53d9b1c3810c0bd", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb", "hessenberg": "cf0e655e99339546"}
 PMC_TRAFFIC = {
@@ -109,7 +111,8 @@ def measured_mfma_peak(prec):
     return _MFMA_PEAK[prec]
 
 
-FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "hess_uinv")
+FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "hess_uinv",
+                "band_reduce", "band_lu_panel", "band_lu_rows")
 
 
 def kernel_table(prof, steps, prec):
@@ -123,7 +126,8 @@ def kernel_table(prof, steps, prec):
         if v.get("work") and v["total_ms"] > 0:
             rate = v["work"] / (v["total_ms"] * 1e-3)
             if k in FLOP_KERNELS:
-                peak = PEAK_FP32_TFLOPS if (prec == "mixed" and k in ("lu_panel", "lu_update")) else PEAK_FP64_TFLOPS
+                peak = PEAK_FP32_TFLOPS if (prec == "mixed" and k in ("lu_panel", "lu_update", "band_lu_rows")) \
+                    else PEAK_FP64_TFLOPS
                 row["TFLOPs"] = round(rate / 1e12, 3)
                 row["frac"] = round(rate / 1e12 / peak, 4)
             else:
@@ -279,7 +283,8 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
               "time_irfft", "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot",
-              "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve"):
+              "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve",
+              "band_reduce", "band_lu_panel", "band_lu_rows", "band_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
             prof[k] = q
@@ -300,14 +305,15 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
                 "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
                 "work_per_launch": q["work"] / q["count"]}
-    if name.startswith("lu_"):
+    if name.startswith("lu_") or name.startswith("band_"):
         achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+        # the band reduction is FP64 in either form; the band LU runs in the factor precision
+        peak = PEAK_FP64_TFLOPS if (prec == "fp64" or name == "band_reduce") else PEAK_FP32_TFLOPS
         out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
                "work_per_launch": q["work"] / q["count"]}
-        if name in ("lu_update", "lu_panel"):
+        if name in ("lu_update", "lu_panel", "band_lu_rows"):
             # the work is counted as 8 real flops per complex multiply-add; the 3M form of the
             # complex GEMM issues 3 real MFMA products per complex one, i.e. 6 of those 8 flops
             out["mfma_executed_frac"] = round(0.75 * achieved / peak, 4)
@@ -644,25 +650,28 @@ def main():
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
     if not args.no_hessenberg:
-        # the same preconditioner S with its blocks through one Hessenberg form of J
-        result["hessenberg"] = {}
-        for form in ("fp64", "mixed"):
-            S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_HESSENBERG)
-            try:
-                ms4, _, infos4, prof4 = timed_steps(S, u0, f, out, form, args.steps, args.warmup)
-            except N.FdeError as e:
-                result["hessenberg"][form] = {"unsupported": str(e)}
-                continue
-            u4 = DEV.get(out)
-            result["hessenberg"][form] = {
-                "ms_per_step": round(ms4, 4), "value": round(1000.0 / ms4, 4),
-                "iters": infos4[-1]["iters"], "true_relres": infos4[-1]["true_relres"],
-                "t_factor_ms": round(infos4[-1]["t_factor_ms"], 3),
-                "t_solve_ms": round(infos4[-1]["t_solve_ms"], 3),
-                "rel_diff_vs_lu": float(np.linalg.norm(u4 - u_main) / np.linalg.norm(u_main)),
-                "kernels": kernel_table(prof4, args.steps, form),
-                "roofline": roofline(prof4, form, args.workload + "h", read_peak),
-            }
+        # the same preconditioner S with its blocks through one Hessenberg form of J (m <= 1024)
+        # and through one band form of J (any m)
+        for key, route in (("hessenberg", N.FDE_BLOCKS_HESSENBERG), ("band", N.FDE_BLOCKS_BAND)):
+            result[key] = {}
+            for form in ("fp64", "mixed"):
+                S.set_option(N.FDE_OPT_BLOCKS, route)
+                try:
+                    ms4, _, infos4, prof4 = timed_steps(S, u0, f, out, form, args.steps, args.warmup)
+                except N.FdeError as e:
+                    result[key][form] = {"unsupported": str(e)}
+                    continue
+                u4 = DEV.get(out)
+                result[key][form] = {
+                    "ms_per_step": round(ms4, 4), "value": round(1000.0 / ms4, 4),
+                    "iters": infos4[-1]["iters"], "true_relres": infos4[-1]["true_relres"],
+                    "t_factor_ms": round(infos4[-1]["t_factor_ms"], 3),
+                    "t_solve_ms": round(infos4[-1]["t_solve_ms"], 3),
+                    "rel_diff_vs_lu": float(np.linalg.norm(u4 - u_main) / np.linalg.norm(u_main)),
+                    "speedup_vs_lu_fp64": round(ms / ms4, 3),
+                    "kernels": kernel_table(prof4, args.steps, form),
+                    "roofline": roofline(prof4, form, args.workload + key[0], read_peak),
+                }
         S.set_option(N.FDE_OPT_BLOCKS, N.FDE_BLOCKS_LU)
     if not args.no_bccb and args.workload == "c2":
         # the paper's other preconditioners on the same system (Section 3.1): S2 = s(A) x I -

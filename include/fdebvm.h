@@ -237,8 +237,14 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
  *                          and i+1 compete in step i).  An apply is Q^T v_k, the exchanges and
  *                          eliminations, U^{-1}, Q: the solves read only the U factors (half the
  *                          bytes).  Not in the paper.  m <= 1024 (FDE_EUNSUPPORTED beyond);
- *                          needs cooperative launches. */
-typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1 } fde_block_solver;
+ *                          needs cooperative launches.
+ *   FDE_BLOCKS_BAND        as FDE_BLOCKS_HESSENBERG with H of lower bandwidth 64 instead of 1:
+ *                          a blocked Householder reduction J = Q H Q^T whose O(m^3) work runs
+ *                          as matrix products (FP64), then per block an LU of lambda_k I -
+ *                          tau mu_k H with partial pivoting among the 128 rows of each 64-column
+ *                          panel (O(64 m^2)); the solves read U and the band of L.  Any m the
+ *                          library takes; needs cooperative launches.  Not in the paper. */
+typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2 } fde_block_solver;
 /* FDE_OPT_ORTHO selects the Arnoldi orthogonalisation (FP64 either way):
  *   FDE_ORTHO_MGS   (default) modified Gram-Schmidt, j + 2 dependent launches at step j.
  *   FDE_ORTHO_CGS2  classical Gram-Schmidt applied twice: three launches per step whatever j;

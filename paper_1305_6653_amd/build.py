@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfdebvm.so")
-SOURCES = ["k_spacetime.hip", "k_factor.hip", "k_krylov.hip", "k_gmres.hip", "k_probe.hip", "k_hessenberg.hip", "runtime.hip", "nn.hip"]
+SOURCES = ["k_spacetime.hip", "k_factor.hip", "k_krylov.hip", "k_gmres.hip", "k_probe.hip", "k_hessenberg.hip", "k_band.hip", "runtime.hip", "nn.hip"]
 ARCH = os.environ.get("FDE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,0 +1,426 @@
+// The blocks of the Strang preconditioner through one band form of J (not in the paper).
+//
+// Every block K_k = lambda_k I - tau mu_k J (Section 3.2) is a shift of the same real matrix J.
+// An orthogonal similarity J = Q H Q^T with H of lower bandwidth 64 (H[i][j] = 0 for
+// i > j + 64: a block upper Hessenberg matrix with 64 x 64 blocks whose subdiagonal blocks are
+// upper triangular) turns every block into C_k = lambda_k I - tau mu_k H = Q^T K_k Q.  Gaussian
+// elimination with partial pivoting confined to the 128 rows of each 64-column panel factors
+// C_k in O(64 m^2) operations instead of the O(m^3) of a dense LU (k_factor.hip), and the
+// solves read L only inside the band.
+//
+// The reduction here is blocked so that its O(m^3) work runs as matrix products on the matrix
+// cores.  For panel p (columns 64p .. 64p+63, c = 64(p+1), w = mp - c):
+//   k_band_panel   the w x 64 block A[c:, 64p:c] is reduced to upper triangular form by 64
+//                  Householder reflections H_j = I - beta_j v_j v_j^T (the sign choice of the
+//                  textbook reflector, alpha = -sign(x_0) |x|), accumulated in compact WY form
+//                  H_0 ... H_63 = I - V T V^T (T upper triangular, by the forward recurrence
+//                  T[0:j, j] = -beta_j T[0:j, 0:j] V[:, 0:j]^T v_j).  Cooperative: workgroup g
+//                  holds 128 rows of the block in LDS; per reflection one grid-wide exchange of
+//                  the column dot products x^T a (all of them at once, before the reflector is
+//                  known: v^T a = x^T a - alpha a_0 and v^T v = 2 (x^T x - alpha x_0)).
+//   right update   [A; Q][:, c:] -= ([A; Q][:, c:] V) T V^T   (A and Q stacked: one product)
+//   left update    A[c:, c:] -= V T^T (V^T A[c:, c:])
+// with FP64 MFMA products (k_dgemm; the long inner products are split over the K dimension
+// into partial outputs that k_band_w2 / k_band_y2 sum in a fixed order together with the
+// multiplication by T).  Q starts as I, so at the end Q H Q^T = J with H = A.
+#include <algorithm>
+
+#include "batch.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fde {
+
+static constexpr int BW = 64;           // bandwidth = panel width
+static constexpr int BP_ROWS = 128;     // rows of the panel per workgroup
+static constexpr int BP_SPIN_MAX = 1 << 21;
+
+__device__ __forceinline__ void bst(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double bld(const double *p) {
+  return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Grid barrier number b: workgroup g raises arrive[g] to b (after its coherent stores have
+// completed), then one wavefront polls all entries until each has reached b.  Bounded: after
+// BP_SPIN_MAX polls, or once any workgroup has raised *err, the wait is abandoned (uniform
+// false) and the kernel winds down.
+__device__ __forceinline__ bool band_barrier(unsigned *arrive, int G, unsigned b, int *err, int *sh) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) __hip_atomic_store(arrive + blockIdx.x, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    for (int it = 0;; ++it) {
+      bool done = true;
+      for (int q = lane; q < G; q += 64)
+        done = done && __hip_atomic_load(arrive + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
+      if (__all(done)) break;
+      if (it > BP_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (lane == 0) atomicOr(err, 1);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) *sh = ok;
+  }
+  __syncthreads();
+  const bool ok = *sh != 0;
+  __syncthreads();
+  return ok;
+}
+
+// ---- [A; Q] = [J padded with I; I] -------------------------------------------------------
+// J[i][j] = dx^{-a} (d+_i g_{i-j+1} + d-_i g_{j-i+1}) (eq. (1.4)-(1.5)); the pad rows and
+// columns (i or j >= m) carry the unit diagonal, which the reduction leaves untouched.
+__global__ __launch_bounds__(256) void k_band_init(const InstDesc *__restrict__ Dd, int inst,
+                                                   double *__restrict__ AQ) {
+  const InstDesc &d = Dd[inst];
+  const int mp = d.mp, m = d.m;
+  const int i = blockIdx.y;  // row of [A; Q]
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= mp) return;
+  double v;
+  if (i < mp) {
+    if (i < m && j < m) {
+      const int dd = i - j;
+      const double gp = (dd >= -1 && dd + 1 <= m) ? d.g[dd + 1] : 0.0;
+      const double gm = (dd <= 1 && 1 - dd <= m) ? d.g[1 - dd] : 0.0;
+      v = d.scale * fma(d.dp[i], gp, d.dm[i] * gm);
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+  } else {
+    v = (i - mp == j) ? 1.0 : 0.0;
+  }
+  AQ[(size_t)i * mp + j] = v;
+}
+
+__global__ void k_band_zero_u32(unsigned *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---- panel reduction (cooperative) ---------------------------------------------------------
+// Workgroup g holds panel rows [128 g, 128 g + 128) (local to the panel: row r is row c + r of
+// A) in LDS; thread t works on column t % 64 and rows t / 64 + 4 i.  Barrier numbers b0 + 1 ..
+// b0 + 65 (the arrive array is cleared before the first panel of a reduction).
+struct BandPanelArgs {
+  double *AQ;           // [2 mp][mp]
+  double *V;            // [w][64]: the Householder vectors (zero above the diagonal)
+  double *T;            // [64][64]: the compact-WY factor (zero below the diagonal)
+  double *xpart;        // [2][G][64]: per-workgroup column dot products, two steps in flight
+  double *xtop;         // [2][64]: row j of the panel at step j
+  double *gpart;        // [G][64][64]: per-workgroup parts of V^T V
+  unsigned *arrive;     // [G]
+  int *err;
+  int mp, p;
+  unsigned b0;
+};
+
+__global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
+  __shared__ double S[BP_ROWS][BW + 1];
+  __shared__ double red[4][BW];
+  __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
+  __shared__ int sh;
+  const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
+  const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
+  const int rbase = g * BP_ROWS;  // first panel row of this workgroup
+  for (int i = 0; i < BP_ROWS / 4; ++i) {
+    const int sr = rg + 4 * i, r = rbase + sr;
+    S[sr][col] = r < w ? a.AQ[(size_t)(c + r) * mp + pc] : 0.0;
+  }
+  __syncthreads();
+  unsigned bno = a.b0;
+  bool ok = true;
+  for (int j = 0; j < BW && ok; ++j) {
+    // column dot products of step j over this workgroup's rows r >= j: x^T a for every column
+    double s = 0.0;
+    for (int i = 0; i < BP_ROWS / 4; ++i) {
+      const int sr = rg + 4 * i;
+      if (rbase + sr >= j) s = fma(S[sr][j], S[sr][col], s);
+    }
+    red[rg][col] = s;
+    __syncthreads();
+    if (t < BW) {
+      bst(&a.xpart[((size_t)(j & 1) * G + g) * BW + t], ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t]);
+      if (g == 0) bst(&a.xtop[(j & 1) * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 128)
+    }
+    ok = band_barrier(a.arrive, G, ++bno, a.err, &sh);
+    if (!ok) break;
+    if (t < BW) {
+      double q = 0.0;
+      for (int h = 0; h < G; ++h) q += bld(&a.xpart[((size_t)(j & 1) * G + h) * BW + t]);
+      sx[t] = q;
+      tp[t] = bld(&a.xtop[(j & 1) * BW + t]);
+    }
+    __syncthreads();
+    const double sxx = sx[j], x0 = tp[j];
+    const double nrm = sqrt(sxx);
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double vtv = 2.0 * (sxx - alpha * x0);  // (x0 - alpha)^2 + sum_{r > j} x_r^2
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    const double v0 = x0 - alpha;
+    if (col > j) {
+      const double f = beta * (sx[col] - alpha * tp[col]);  // beta v^T a
+      for (int i = 0; i < BP_ROWS / 4; ++i) {
+        const int sr = rg + 4 * i, r = rbase + sr;
+        if (r >= j) {
+          const double v = r == j ? v0 : S[sr][j];
+          S[sr][col] = fma(-f, v, S[sr][col]);
+        }
+      }
+    }
+    if (t == 0) {
+      rd[j] = beta > 0.0 ? alpha : x0;  // R[j][j] (a zero column below j keeps x0)
+      bt[j] = beta;
+    }
+    __syncthreads();
+    if (g == 0 && t == 0) S[j][j] = beta > 0.0 ? v0 : 0.0;  // v_j's first entry
+    __syncthreads();
+  }
+  if (!ok) return;
+  // V (zero above the diagonal, and the whole column when beta_j = 0) and the reduced panel:
+  // R on and above the diagonal, zeros below
+  for (int i = 0; i < BP_ROWS / 4; ++i) {
+    const int sr = rg + 4 * i, r = rbase + sr;
+    if (r >= w) continue;
+    const double x = S[sr][col];
+    const double vv = (r >= col && bt[col] > 0.0) ? x : 0.0;
+    a.V[(size_t)r * BW + col] = vv;
+    a.AQ[(size_t)(c + r) * mp + pc] = r < col ? x : (r == col ? rd[col] : 0.0);
+    S[sr][col] = vv;
+  }
+  __syncthreads();
+  // this workgroup's part of V^T V: entry (u, v) for u = t / 4 ... 16 entries per thread
+  for (int e = t; e < BW * BW; e += 256) {
+    const int u = e >> 6, v = e & 63;
+    double q = 0.0;
+    for (int sr = 0; sr < BP_ROWS; ++sr) q = fma(S[sr][u], S[sr][v], q);
+    bst(&a.gpart[(size_t)g * BW * BW + e], q);
+  }
+  ok = band_barrier(a.arrive, G, ++bno, a.err, &sh);
+  if (!ok || g != 0) return;
+  // T by the forward recurrence, in workgroup 0: Gm = V^T V summed over the workgroups in
+  // order, then column j of T from columns 0 .. j-1
+  double(*Gm)[BW + 1] = S;  // rows 0..63 of the slab buffer
+  for (int e = t; e < BW * BW; e += 256) {
+    double q = 0.0;
+    for (int h = 0; h < G; ++h) q += bld(&a.gpart[(size_t)h * BW * BW + e]);
+    Gm[e >> 6][e & 63] = q;
+  }
+  double(*Tm)[BW + 1] = S + BW;  // rows 64..127
+  for (int e = t; e < BW * BW; e += 256) Tm[e >> 6][e & 63] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < BW; ++j) {
+    if (t < j) {
+      double q = 0.0;
+      for (int l = t; l < j; ++l) q = fma(Tm[t][l], Gm[l][j], q);
+      Tm[t][j] = -bt[j] * q;
+    } else if (t == j) {
+      Tm[j][j] = bt[j];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < BW * BW; e += 256) a.T[e] = Tm[e >> 6][e & 63];
+}
+
+// ---- FP64 matrix products on MFMA -----------------------------------------------------------
+// C (M x N) = alpha op(A) op(B) over the K range of split z = blockIdx.z (kc per split):
+//   MODE 0: store the partial product at C + z M N (row-major, leading dimension N);
+//   MODE 1: C[i][j] += alpha * product (one split).
+// op(A)(i, k) = TA ? A[k lda + i] : A[i lda + k];  op(B)(k, j) = TB ? B[j ldb + k] : B[k ldb + j].
+// M, N multiples of 64 and kc of 16.  64 x 64 tile per workgroup; wavefront w computes the 32 x 32
+// quarter (w / 2, w % 2) as 2 x 2 products of v_mfma_f64_16x16x4f64 from 16-deep K slices
+// staged in LDS.  Fixed summation order (deterministic).
+static constexpr int DG_KS = 16;
+
+template <bool TA, bool TB, int MODE>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int kc, int K, const double *__restrict__ A,
+                                               int lda, const double *__restrict__ B, int ldb,
+                                               double *__restrict__ C, int ldc, double alpha) {
+  __shared__ double As[DG_KS][64 + 1];  // As[k][i]
+  __shared__ double Bs[DG_KS][64 + 1];  // Bs[k][j]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += DG_KS) {
+    // stage op(A)[row0 .. +64][k0 .. +16] and op(B)[k0 .. +16][col0 .. +64], 4 doubles per thread each
+    if (!TA) {
+      const int i = tid >> 2, k4 = (tid & 3) * 4;
+      const double *p = A + (size_t)(row0 + i) * lda + k0 + k4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) As[k4 + u][i] = p[u];
+    } else {
+      const int k = tid >> 4, i4 = (tid & 15) * 4;
+      const double *p = A + (size_t)(k0 + k) * lda + row0 + i4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) As[k][i4 + u] = p[u];
+    }
+    if (!TB) {
+      const int k = tid >> 4, j4 = (tid & 15) * 4;
+      const double *p = B + (size_t)(k0 + k) * ldb + col0 + j4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Bs[k][j4 + u] = p[u];
+    } else {
+      const int j = tid >> 2, k4 = (tid & 3) * 4;
+      const double *p = B + (size_t)(col0 + j) * ldb + k0 + k4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Bs[k4 + u][j] = p[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < DG_KS; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) av[r] = As[kk + lk][wr + 16 * r + li];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = Bs[kk + lk][wc + 16 * c + li];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[r][c] = mfma16(av[r], bv[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + wr + 16 * r + mfma_row<double>(lk, v), j = col0 + wc + 16 * c + li;
+        if (MODE == 0) {
+          C[(size_t)blockIdx.z * M * N + (size_t)i * N + j] = acc[r][c][v];
+        } else {
+          double *e = C + (size_t)i * ldc + j;
+          *e = fma(alpha, acc[r][c][v], *e);
+        }
+      }
+}
+
+// W2[i][:] = (sum_z P[z][i][:]) T for rows i < M (P: [nsplit][M][64]; T upper triangular).
+__global__ __launch_bounds__(256) void k_band_w2(const double *__restrict__ P, int nsplit, int M,
+                                                 const double *__restrict__ T, double *__restrict__ W2) {
+  __shared__ double Ts[BW][BW + 1];
+  __shared__ double rs[4][BW];
+  const int t = threadIdx.x, col = t & 63, rr = t >> 6, i = blockIdx.x * 4 + rr;
+  for (int e = t; e < BW * BW; e += 256) Ts[e >> 6][e & 63] = T[e];
+  double q = 0.0;
+  for (int z = 0; z < nsplit; ++z) q += P[((size_t)z * M + i) * BW + col];
+  rs[rr][col] = q;
+  __syncthreads();
+  double o = 0.0;
+  for (int k = 0; k <= col; ++k) o = fma(rs[rr][k], Ts[k][col], o);
+  W2[(size_t)i * BW + col] = o;
+}
+
+// Y2[:, j] = T^T (sum_z P[z][:, j]) for columns j < N (P: [nsplit][64][N]).
+__global__ __launch_bounds__(256) void k_band_y2(const double *__restrict__ P, int nsplit, int N,
+                                                 const double *__restrict__ T, double *__restrict__ Y2) {
+  __shared__ double Ts[BW][BW + 1];
+  __shared__ double ys[BW][4 + 1];
+  const int t = threadIdx.x, a = t & 63, cc = t >> 6, j = blockIdx.x * 4 + cc;
+  for (int e = t; e < BW * BW; e += 256) Ts[e >> 6][e & 63] = T[e];
+  double q = 0.0;
+  for (int z = 0; z < nsplit; ++z) q += P[((size_t)z * BW + a) * N + j];
+  ys[a][cc] = q;
+  __syncthreads();
+  double o = 0.0;
+  for (int k = 0; k <= a; ++k) o = fma(Ts[k][a], ys[k][cc], o);
+  Y2[(size_t)a * N + j] = o;
+}
+
+// Qt = Q^T ([mp][mp], 64 x 64 tiles through LDS).
+__global__ __launch_bounds__(256) void k_band_transpose(const double *__restrict__ Q, double *__restrict__ Qt,
+                                                        int mp) {
+  __shared__ double tl[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, t = threadIdx.x;
+  for (int e = t; e < 64 * 64; e += 256) tl[e >> 6][e & 63] = Q[(size_t)(r0 + (e >> 6)) * mp + c0 + (e & 63)];
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) Qt[(size_t)(c0 + (e >> 6)) * mp + r0 + (e & 63)] = tl[e & 63][e >> 6];
+}
+
+// ---- host side -------------------------------------------------------------------------------
+int band_panel_groups(int mp) { return (mp - BW + BP_ROWS - 1) / BP_ROWS; }
+
+static int dg_splits(int tiles, int K) {
+  // enough workgroups to fill the device twice over, each with at least 256 of the K range
+  int z = 1;
+  while (tiles * z < 512 && K / (2 * z) >= 256) z *= 2;
+  return z;
+}
+
+size_t band_work_doubles(int mp) {
+  const int G = band_panel_groups(mp);
+  const size_t w2 = (size_t)2 * mp * BW * 16;  // W partials: up to 16 splits of [2 mp][64]
+  const size_t y1 = (size_t)BW * mp * 16;      // Y partials
+  return (size_t)mp * BW      // V
+         + BW * BW             // T
+         + (size_t)2 * G * BW  // xpart
+         + 2 * BW              // xtop
+         + (size_t)G * BW * BW  // gpart
+         + std::max(w2, y1)    // partial products
+         + (size_t)2 * mp * BW  // W2
+         + (size_t)BW * mp;     // Y2
+}
+
+template <bool TA, bool TB, int MODE>
+static hipError_t dgemm(int M, int N, int K, int splits, const double *A, int lda, const double *B, int ldb,
+                        double *C, int ldc, double alpha, hipStream_t st) {
+  const int kc = ((K / splits + DG_KS - 1) / DG_KS) * DG_KS;
+  hipLaunchKernelGGL((k_dgemm<TA, TB, MODE>), dim3(M / 64, N / 64, splits), dim3(256), 0, st, M, N, kc, K, A,
+                     lda, B, ldb, C, ldc, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
+                              unsigned *arrive, int *err, hipStream_t st) {
+  const int G = band_panel_groups(mp);
+  double *V = work, *T = V + (size_t)mp * BW, *xpart = T + BW * BW, *xtop = xpart + (size_t)2 * G * BW;
+  double *gpart = xtop + 2 * BW, *part = gpart + (size_t)G * BW * BW;
+  const size_t w2 = (size_t)2 * mp * BW * 16, y1 = (size_t)BW * mp * 16;
+  double *W2 = part + std::max(w2, y1), *Y2 = W2 + (size_t)2 * mp * BW;
+  hipLaunchKernelGGL(k_band_init, dim3((mp + 255) / 256, 2 * mp), dim3(256), 0, st, D, inst, AQ);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_zero_u32, dim3(1), dim3(256), 0, st, arrive, G);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int np = mp / BW;
+  for (int p = 0; p + 1 < np; ++p) {
+    const int c = (p + 1) * BW, w = mp - c;
+    const int g = (w + BP_ROWS - 1) / BP_ROWS;
+    BandPanelArgs pa{AQ, V, T, xpart, xtop, gpart, arrive, err, mp, p, (unsigned)(p * (BW + 1))};
+    void *args[] = {(void *)&pa};
+    if ((e = hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(256), args, 0, st)) != hipSuccess)
+      return e;
+    // right update of [A; Q] (2 mp rows): W = [A; Q][:, c:] V, W2 = W T, [A; Q][:, c:] -= W2 V^T
+    const int zr = dg_splits(2 * mp / 64, w);
+    if ((e = dgemm<false, false, 0>(2 * mp, BW, w, zr, AQ + c, mp, V, BW, part, BW, 1.0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_w2, dim3(2 * mp / 4), dim3(256), 0, st, part, zr, 2 * mp, T, W2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = dgemm<false, true, 1>(2 * mp, w, BW, 1, W2, BW, V, BW, AQ + c, mp, -1.0, st)) != hipSuccess) return e;
+    // left update of A[c:, c:]: Y = V^T A[c:, c:], Y2 = T^T Y, A[c:, c:] -= V Y2
+    const int zl = dg_splits(w / 64, w);
+    double *Ac = AQ + (size_t)c * mp + c;
+    if ((e = dgemm<true, false, 0>(BW, w, w, zl, V, BW, Ac, mp, part, w, 1.0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_y2, dim3(w / 4), dim3(256), 0, st, part, zl, w, T, Y2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = dgemm<false, false, 1>(w, w, BW, 1, V, BW, Y2, w, Ac, mp, -1.0, st)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_band_transpose, dim3(mp / 64, mp / 64), dim3(256), 0, st, AQ + (size_t)mp * mp, Qt, mp);
+  return hipGetLastError();
+}
+
+}  // namespace fde

@@ -1076,6 +1076,320 @@ __global__ __launch_bounds__(256, 4) void k_trsv_coop(const InstDesc *__restrict
 }
 
 // ------------------------------------------------------------------------------------
+// The band route (k_band.hip reduces J to H of lower bandwidth 64, J = Q H Q^T): LU with
+// partial pivoting of C_k = lambda_k I - tau mu_k H, one 64-column panel per step.  At step j
+// only block rows j and j + 1 hold entries in block column j (block row j carries the updates
+// of step j - 1; block row j + 1 is still C_k's own and is formed from H when first read), so
+// the pivots are chosen among those 128 rows and the step changes only those two block rows:
+//   k_band_lu_panel  P_j [C_j; C_{j+1}][:, block j] = [L11; L21] U11 in LDS; L11 \ U11 into K
+//                    block (j, j), L21 into K block (j + 1, j), the row order after the
+//                    exchanges into the permutation array (row i of the window came from row
+//                    perm[i]), the inverses of L11 and U11 into dinv[..][0] and [1];
+//   k_band_lu_rows   per 64-column tile of the trailing width: the window's rows reordered,
+//                    U12 = L11^{-1} top -> K block row j, bottom - L21 U12 -> K block row j+1;
+//   k_band_lsolve    y <- L11^{-1} (P_j y)_top, then (P_j y)_bottom - L21 (that), step by step
+//                    on the frequency vectors (U^{-1} is the backward sweep of k_trsv_coop).
+// Pivot: the largest |re| + |im| of the column (the lowest row on ties).
+template <typename T>
+__device__ __forceinline__ c_t<T> band_entry(const double *__restrict__ H, int mp, int m, double2 lam,
+                                             double2 mu, double tau, int r, int c) {
+  if (r >= m || c >= m) return mk<T>((T)(r == c ? 1.0 : 0.0), (T)0);
+  const double h = H[(size_t)r * mp + c];
+  double re = -tau * mu.x * h, im = -tau * mu.y * h;
+  if (r == c) {
+    re += lam.x;
+    im += lam.y;
+  }
+  return mk<T>((T)re, (T)im);
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map, int j,
+                                                       int *__restrict__ flag) {
+  typedef c_t<T> C;
+  constexpr int NT = 512;
+  __shared__ C a[2 * PB][PB + 1];
+  __shared__ int perm[2 * PB];
+  __shared__ T wmax[2];
+  __shared__ int widx[2];
+  __shared__ int spiv;
+  __shared__ C srec;
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = Dd[map.ids[q]];
+  const int blk = blockIdx.x - map.pre[q], tid = threadIdx.x;
+  const int mp = d.mp, npan = d.npan, m = d.m, r0 = j * PB;
+  const int nr = j + 1 < npan ? 2 * PB : PB;
+  C *K = (C *)d.K + (size_t)blk * mp * mp;
+  const double2 lam = d.lam[blk], mu = d.mu[blk];
+  for (int e = tid; e < nr * PB; e += NT) {
+    const int r = e / PB, c = e % PB;
+    a[r][c] = (r < PB && j > 0) ? K[(size_t)(r0 + r) * mp + r0 + c]
+                                : band_entry<T>(d.hH, mp, m, lam, mu, d.tau, r0 + r, r0 + c);
+  }
+  if (tid < 2 * PB) perm[tid] = tid;
+  __syncthreads();
+  int bad = 0;
+  for (int k = 0; k < PB; ++k) {
+    if (tid < 2 * PB) {  // waves 0 and 1: the candidates' magnitudes, arg-max per wave
+      T v = (T)-1;
+      if (tid >= k && tid < nr) v = fabs(a[tid][k].x) + fabs(a[tid][k].y);
+      int ix = tid;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(ix, o, 64);
+        if (ov > v || (ov == v && oi < ix)) {
+          v = ov;
+          ix = oi;
+        }
+      }
+      if ((tid & 63) == 0) {
+        wmax[tid >> 6] = v;
+        widx[tid >> 6] = ix;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int p = wmax[1] > wmax[0] ? widx[1] : widx[0];
+      spiv = p;
+      const int t0 = perm[k];
+      perm[k] = perm[p];
+      perm[p] = t0;
+    }
+    __syncthreads();
+    const int p = spiv;
+    if (p != k && tid < PB) {
+      const C t0 = a[k][tid];
+      a[k][tid] = a[p][tid];
+      a[p][tid] = t0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      bool ok;
+      srec = recip_checked<T>(a[k][k], ok);
+      bad |= ok ? 0 : 1;
+    }
+    __syncthreads();
+    const C rp = srec;
+    if (tid > k && tid < nr) a[tid][k] = tmul<T>(a[tid][k], rp);
+    __syncthreads();
+    const int rows = nr - k - 1, cols = PB - k - 1;
+    for (int e = tid; e < rows * cols; e += NT) {
+      const int r = k + 1 + e / cols, c = k + 1 + e % cols;
+      a[r][c] = tsub<T>(a[r][c], tmul<T>(a[r][k], a[k][c]));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nr * PB; e += NT) {
+    const int r = e / PB, c = e % PB;
+    K[(size_t)(r0 + r) * mp + r0 + c] = a[r][c];
+  }
+  if (tid < nr) d.hpiv[((size_t)blk * npan + j) * 2 * PB + tid] = perm[tid];
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  if (tid < PB) {
+    bool ok;
+    a[tid][tid] = recip_checked<T>(a[tid][tid], ok);
+  }
+  __syncthreads();
+  tri_inv_doubling<T, NT, true>(a);
+  C *Dl = (C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB;
+  C *Du = Dl + PB * PB;
+  const C zero = mk<T>((T)0, (T)0), one = mk<T>((T)1, (T)0);
+  for (int e = tid; e < PB * PB; e += NT) {
+    const int r = e / PB, c = e % PB;
+    const C v = a[r][c];
+    Dl[e] = csel<T>(r > c, v, csel<T>(r == c, one, zero));
+    Du[e] = csel<T>(r <= c, v, zero);
+  }
+}
+
+// 64x64 complex product on one workgroup with A (64 x 64, row stride lda) streamed from global
+// memory in slices through LDS and B (64 x 64) already in LDS; (cre, cim) = (+/-) A B in the
+// layout of tile_load, 3M form as gemm64_lds.  Every read of Bt completes before it returns.
+template <typename T>
+struct GemmLdsA {
+  c_t<T> As[2][PB][US + 1];
+};
+
+template <typename T, bool NEG>
+__device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda, c_t<T> (*Bt)[PB + 1],
+                                          GemmLdsA<T> &sm, acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
+  typedef c_t<T> C;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wave = tid >> 6, wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int ar = tid >> 2, ac = (tid & 3) * 2;
+  const C *Ap = A + (size_t)ar * lda + ac;
+  acc_t<T> p1[2][2], p2[2][2], p3[2][2];
+  tile_zero<T>(p1, p2);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
+  C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);
+  sm.As[0][ar][ac] = ra0;
+  sm.As[0][ar][ac + 1] = ra1;
+  __syncthreads();
+  constexpr int nsl = PB / US;
+#pragma unroll 1
+  for (int sl = 0; sl < nsl; ++sl) {
+    const int buf = sl & 1;
+    const bool more = sl + 1 < nsl;
+    if (more) {
+      const int k1 = (sl + 1) * US;
+      ra0 = ld_global<T>(Ap + k1);
+      ra1 = ld_global<T>(Ap + k1 + 1);
+    }
+#pragma unroll
+    for (int kk = 0; kk < US; kk += 4) {
+      C a[2], b[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) b[c] = Bt[sl * US + kk + lk][wc + c * 16 + li];
+      T bs[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const T ar_ = NEG ? -a[r].x : a[r].x, ai_ = NEG ? -a[r].y : a[r].y;
+        const T as_ = ar_ + ai_;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          p1[r][c] = mfma16(ar_, b[c].x, p1[r][c]);
+          p2[r][c] = mfma16(ai_, b[c].y, p2[r][c]);
+          p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
+        }
+      }
+    }
+    if (more) {
+      sm.As[buf ^ 1][ar][ac] = ra0;
+      sm.As[buf ^ 1][ar][ac + 1] = ra1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cre[r][c][v] = p1[r][c][v] - p2[r][c][v];
+        cim[r][c][v] = p3[r][c][v] - p1[r][c][v] - p2[r][c][v];
+      }
+}
+
+// Item = (instance, block, tile t < npan - j - 1): columns c0 = 64 (j + 1 + t) ..
+template <typename T>
+__global__ __launch_bounds__(256, 1) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j) {
+  typedef c_t<T> C;
+  __shared__ C Tt[PB][PB + 1];  // top rows of the reordered window, then U12
+  __shared__ C Tb[PB][PB + 1];  // bottom rows of the reordered window
+  __shared__ GemmLdsA<T> sm;
+  const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
+  const int q = item_slot(map, item);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = Dd[map.ids[q]];
+  const int mp = d.mp, npan = d.npan, m = d.m, nrem = npan - j - 1;
+  const int local = item - map.pre[q];
+  const int blk = local / nrem, tt = local % nrem;
+  const int r0 = j * PB, c0 = (j + 1 + tt) * PB, tid = threadIdx.x;
+  C *K = (C *)d.K + (size_t)blk * mp * mp;
+  const int *perm = d.hpiv + ((size_t)blk * npan + j) * 2 * PB;
+  const double2 lam = d.lam[blk], mu = d.mu[blk];
+  for (int e = tid; e < 2 * PB * PB; e += 256) {
+    const int i = e / PB, c = e % PB, sr = perm[i];
+    const C v = (sr < PB && j > 0) ? K[(size_t)(r0 + sr) * mp + c0 + c]
+                                   : band_entry<T>(d.hH, mp, m, lam, mu, d.tau, r0 + sr, c0 + c);
+    if (i < PB) Tt[i][c] = v;
+    else Tb[i - PB][c] = v;
+  }
+  __syncthreads();
+  const int lane = tid & 63, li = lane & 15, lk = lane >> 4, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  acc_t<T> cre[2][2], cim[2][2];
+  const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB;
+  gemm64_bl<T, false>(Dl, PB, Tt, sm, cre, cim);  // U12 = L11^{-1} top
+  tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tt[wr + r * 16 + mfma_row<T>(lk, v)][wc + c * 16 + li] = mk<T>(cre[r][c][v], cim[r][c][v]);
+  __syncthreads();
+  gemm64_bl<T, true>(K + (size_t)(r0 + PB) * mp + r0, mp, Tt, sm, cre, cim);  // -L21 U12
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const C z = Tb[wr + r * 16 + mfma_row<T>(lk, v)][wc + c * 16 + li];
+        cre[r][c][v] += z.x;
+        cim[r][c][v] += z.y;
+      }
+  tile_store<T>(K + (size_t)(r0 + PB + wr) * mp + c0 + wc, mp, cre, cim);
+}
+
+// One workgroup per block: the window [top; bottom] of step j (the top carried from step j-1,
+// the bottom read from the vector), reordered, top <- L11^{-1} top (final), bottom <- bottom -
+// L21 top (the next step's top).  Thread t: row t / 4, columns 16 (t % 4) .. + 16.
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
+  typedef c_t<T> C;
+  __shared__ double2 ys[2 * PB];  // the window before the exchanges
+  __shared__ double2 y[2 * PB];   // after them
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = Dd[map.ids[q]];
+  const int blk = blockIdx.x - map.pre[q], tid = threadIdx.x;
+  const int mp = d.mp, npan = d.npan;
+  double2 *v = d.Vts + (size_t)blk * mp;
+  const C *K = (const C *)d.K + (size_t)blk * mp * mp;
+  const C *dinv = (const C *)d.dinv;
+  const int *perm = d.hpiv + (size_t)blk * npan * 2 * PB;
+  const int i = tid >> 2, qq = tid & 3;
+  if (tid < PB) ys[tid] = v[tid];
+  for (int j = 0; j < npan; ++j) {
+    const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
+    if (tid >= PB && tid < nr) ys[tid] = v[r0 + tid];
+    __syncthreads();
+    if (tid < nr) y[tid] = ys[perm[(size_t)j * 2 * PB + tid]];
+    __syncthreads();
+    const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq * 16;
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll 4
+    for (int c = 0; c < 16; ++c) s = cfma(widen(Li[c]), y[qq * 16 + c], s);
+    s.x += __shfl_xor(s.x, 1, 64);
+    s.y += __shfl_xor(s.y, 1, 64);
+    s.x += __shfl_xor(s.x, 2, 64);
+    s.y += __shfl_xor(s.y, 2, 64);
+    __syncthreads();  // every read of y[0:64] done
+    if (qq == 0) {
+      y[i] = s;
+      v[r0 + i] = s;
+    }
+    __syncthreads();
+    if (nr == 2 * PB) {
+      const C *L21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 16;
+      double2 t = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int c = 0; c < 16; ++c) t = cfma(widen(L21[c]), y[qq * 16 + c], t);
+      t.x += __shfl_xor(t.x, 1, 64);
+      t.y += __shfl_xor(t.y, 1, 64);
+      t.x += __shfl_xor(t.x, 2, 64);
+      t.y += __shfl_xor(t.y, 2, 64);
+      if (qq == 0) ys[i] = csub(y[PB + i], t);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
 static constexpr int ASM_KCHUNK = 8;
 int assemble_items(int mp, int nb) { return mp * ((nb + ASM_KCHUNK - 1) / ASM_KCHUNK); }
 int assemble_lead() { return ASM_LEAD; }
@@ -1123,6 +1437,28 @@ hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_trsv<T>, dim3(items), dim3(TS_NT), lds, st, D, map);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items, int j, int *flag,
+                                hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_lu_panel<T>, dim3(items), dim3(512), 0, st, D, map, j, flag);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_lsolve(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_lsolve<T>, dim3(items), dim3(256), 0, st, D, map);
   return hipGetLastError();
 }
 
@@ -1183,6 +1519,11 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                                           const ItemMap *, int, int);                             \
   template hipError_t launch_hess_uinv<T>(const InstDesc *, const ItemMap &, int, int *,          \
                                           hipStream_t);                                         \
+  template hipError_t launch_band_lu_panel<T>(const InstDesc *, const ItemMap &, int, int, int *,  \
+                                              hipStream_t);                                     \
+  template hipError_t launch_band_lu_rows<T>(const InstDesc *, const ItemMap &, int, int,          \
+                                             hipStream_t);                                      \
+  template hipError_t launch_band_lsolve<T>(const InstDesc *, const ItemMap &, int, hipStream_t);   \
   template int trsv_coop_capacity<T>();
 FDE_INST(double)
 FDE_INST(float)

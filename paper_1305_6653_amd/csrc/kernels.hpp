@@ -135,6 +135,23 @@ hipError_t launch_hess_lu(const InstDesc *D, const ItemMap &map, int items, int 
 template <typename T>
 hipError_t launch_hess_uinv(const InstDesc *D, const ItemMap &map, int items, int *flag,
                             hipStream_t st);
+// ---- the band route: J = Q H Q^T with H of lower bandwidth 64 (k_band.hip) ----
+int band_panel_groups(int mp);    // workgroups of the first panel reduction
+size_t band_work_doubles(int mp);  // workspace of launch_band_reduce
+// [A; Q] ([2 mp][mp]) <- [H; Q] from J of instance `inst`, Qt <- Q^T; arrive [band_panel_groups],
+// err set if a grid barrier had to be abandoned
+hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
+                              unsigned *arrive, int *err, hipStream_t st);
+// step j of the pivoted band LU: item = (instance, block) for the panel, (instance, block, tile)
+// with npan - j - 1 tiles per block for the rows; permutations in hpiv [nb][npan][128]
+template <typename T>
+hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items, int j, int *flag,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st);
+// item = (instance, block): y <- L^{-1} P y on Vts in place
+template <typename T>
+hipError_t launch_band_lsolve(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);
 // item = (instance, block): the exchanges and eliminations applied to Vts in place
 hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, int max_mp,
                               hipStream_t st);

@@ -176,6 +176,12 @@ struct fde_bvm {
   double2 *d_hl = nullptr, *d_Vh2 = nullptr;
   int *d_hpiv = nullptr;
   HessWork hwk{};
+  // ---- band route to the blocks (allocated when first factored that way): [H; Q] [2 mp][mp]
+  // of J = Q H Q^T (H of lower bandwidth 64), Q^T [mp][mp], the row orders of the pivoted band
+  // LU [nb][npan][128], the reduction's workspace, grid-barrier counters and error flag
+  double *d_bAQ = nullptr, *d_bQt = nullptr, *d_bwork = nullptr;
+  int *d_bpiv = nullptr, *d_berr = nullptr;
+  unsigned *d_barrive = nullptr;
   // ---- BCCB preconditioner tables (allocated when a BCCB preconditioner is factored)
   double2 *d_chirp = nullptr, *d_bh = nullptr, *d_lamx = nullptr;
   double lam0s = 0.0;
@@ -333,7 +339,7 @@ struct SolveMaps {
   int tfft_cols = 16;  // spatial columns per time-FFT workgroup
   int npan_u = 0;      // panels per block if every instance has the same count, else 0
   int prec = -1;
-  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0;
+  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0, band_l_bytes = 0;
 };
 
 // The same maps with their items skipped for instances whose gate entry is zero.
@@ -507,12 +513,19 @@ static InstDesc make_desc(fde_bvm *h) {
   d.Ju0 = h->d_Ju0;
   d.Vh = h->d_Vh;
   d.blk = h->blk_route;
-  d.hH = h->d_hH;
-  d.hQ = h->d_hQ;
-  d.hQt = h->d_hQt;
+  if (h->blk_route == FDE_BLOCKS_BAND) {
+    d.hH = h->d_bAQ;
+    d.hQ = h->d_bAQ ? h->d_bAQ + (size_t)h->mp * h->mp : nullptr;
+    d.hQt = h->d_bQt;
+    d.hpiv = h->d_bpiv;
+  } else {
+    d.hH = h->d_hH;
+    d.hQ = h->d_hQ;
+    d.hQt = h->d_hQt;
+    d.hpiv = h->d_hpiv;
+  }
   d.hl = h->d_hl;
-  d.hpiv = h->d_hpiv;
-  d.Vts = h->blk_route == FDE_BLOCKS_HESSENBERG ? h->d_Vh2 : h->d_Vh;
+  d.Vts = h->blk_route != FDE_BLOCKS_LU ? h->d_Vh2 : h->d_Vh;
   d.pc = h->pc;
   d.lam0s = h->lam0s;
   d.chirp = h->d_chirp;
@@ -548,6 +561,7 @@ static std::map<std::string, int> g_tuned_w;
 static std::string plan_shape_key(const Plan *P, int prec) {
   std::string k = prec == FDE_FP64 ? "f64" : "c32";
   if (!P->hs.empty() && P->hs[0]->blk_route == FDE_BLOCKS_HESSENBERG) k += "h";
+  if (!P->hs.empty() && P->hs[0]->blk_route == FDE_BLOCKS_BAND) k += "b";
   char buf[32];
   for (const fde_bvm *h : P->hs) {
     snprintf(buf, sizeof buf, ":%dx%d", h->m, h->s);
@@ -1134,8 +1148,8 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
       h->opt_ortho = value;
       return FDE_OK;
     case FDE_OPT_BLOCKS:
-      if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG)
-        return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU or FDE_BLOCKS_HESSENBERG");
+      if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG && value != FDE_BLOCKS_BAND)
+        return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU, FDE_BLOCKS_HESSENBERG or FDE_BLOCKS_BAND");
       if (value != h->opt_blocks) h->prec = -1;  // factor again before the next solve
       h->opt_blocks = value;
       return FDE_OK;
@@ -1425,6 +1439,71 @@ static fde_status hess_alloc(fde_bvm *h) {
   return FDE_OK;
 }
 
+// The band route: J = Q H Q^T with H of lower bandwidth 64 per instance (blocked Householder
+// reduction, k_band.hip), then the pivoted band LU of every block, one panel step at a time
+// (a panel launch over the blocks of all instances, then a launch over their row tiles).
+static fde_status band_alloc(fde_bvm *h) {
+  if (h->d_bAQ) return FDE_OK;
+  const size_t mp = h->mp, nb = h->nb, G = band_panel_groups(h->mp);
+  STCHK(dalloc_t(h, &h->d_bAQ, 2 * mp * mp));
+  STCHK(dalloc_t(h, &h->d_bQt, mp * mp));
+  STCHK(dalloc_t(h, &h->d_bpiv, nb * mp * 2));
+  STCHK(dalloc_t(h, &h->d_bwork, band_work_doubles(h->mp)));
+  STCHK(dalloc_t(h, &h->d_barrive, G + 64));
+  h->d_berr = (int *)(h->d_barrive + G + 32);
+  HIPCHK(hipMemsetAsync(h->d_barrive, 0, (G + 64) * sizeof(unsigned), h->stream));
+  if (!h->d_Vh2) {
+    STCHK(dalloc_t(h, &h->d_Vh2, nb * mp));
+    HIPCHK(hipMemsetAsync(h->d_Vh2, 0, nb * mp * sizeof(double2), h->stream));
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status band_factor(Plan *P) {
+  fde_bvm *L = P->lead;
+  const int count = (int)P->hs.size();
+  hipStream_t st = L->stream;
+  int maxpan = 0;
+  for (int i = 0; i < count; ++i) {
+    fde_bvm *h = P->hs[i];
+    maxpan = std::max(maxpan, h->npan);
+    // algorithmic flops of the reduction: 10/3 m^3 for H, 4/3 m^3 for Q (Householder)
+    const double m = h->m;
+    HIPCHK(run(L, "band_reduce", 14.0 / 3.0 * m * m * m, [&] {
+      return launch_band_reduce(P->d_desc, i, h->mp, h->d_bAQ, h->d_bQt, h->d_bwork, h->d_barrive, h->d_berr, st);
+    }));
+  }
+  std::vector<int> slots(count), it(count);
+  for (int i = 0; i < count; ++i) slots[i] = i;
+  std::vector<HostMap> hm;
+  for (int j = 0; j < maxpan; ++j) {
+    for (int i = 0; i < count; ++i) it[i] = j < P->hs[i]->npan ? P->hs[i]->nb : 0;
+    hm.push_back(make_map(slots, it));  // panel j
+    for (int i = 0; i < count; ++i) it[i] = std::max(0, P->hs[i]->npan - j - 1) * P->hs[i]->nb;
+    hm.push_back(make_map(slots, it));  // row tiles j
+  }
+  std::vector<ItemMap> dm;
+  STCHK(upload_maps(P, hm, dm));
+  for (int j = 0; j < maxpan; ++j) {
+    // algorithmic flops (complex multiply-add = 8 real flops): the 128 x 64 panel LU, and per
+    // tile of the trailing width the two 64 x 64 x 64 products
+    double wp = 0.0, wr = 0.0;
+    for (fde_bvm *h : P->hs) {
+      if (j >= h->npan) continue;
+      const double nr = j + 1 < h->npan ? 128.0 : 64.0;
+      wp += h->nb * 8.0 * 64.0 * 64.0 * (nr - 64.0 / 3.0) / 2.0;
+      wr += h->nb * std::max(0, h->npan - j - 1) * 2.0 * 8.0 * 64.0 * 64.0 * 64.0;
+    }
+    const size_t ip = 2 * j, ir = 2 * j + 1;
+    if (hm[ip].items > 0)
+      HIPCHK(run(L, "band_lu_panel", wp, [&] { return launch_band_lu_panel<T>(P->d_desc, dm[ip], hm[ip].items, j, P->d_flag, st); }));
+    if (hm[ir].items > 0)
+      HIPCHK(run(L, "band_lu_rows", wr, [&] { return launch_band_lu_rows<T>(P->d_desc, dm[ir], hm[ir].items, j, st); }));
+  }
+  return FDE_OK;
+}
+
 static fde_status bccb_prepare(fde_bvm *h);
 
 static fde_status factor_plan(Plan *P, fde_precision prec) {
@@ -1469,6 +1548,7 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
     if (h->blk_route != route && h->self) h->self->desc_dirty = true;
     h->blk_route = route;
     if (route == FDE_BLOCKS_HESSENBERG) STCHK(hess_alloc(h));
+    if (route == FDE_BLOCKS_BAND) STCHK(band_alloc(h));
   }
   const size_t esz = prec == FDE_FP64 ? sizeof(double2) : sizeof(float2);
   for (fde_bvm *h : P->hs) {
@@ -1494,6 +1574,8 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   HIPCHK(hipEventRecord(e0, L->stream));
   if (route == FDE_BLOCKS_HESSENBERG)
     STCHK(prec == FDE_FP64 ? hess_factor<double>(P) : hess_factor<float>(P));
+  else if (route == FDE_BLOCKS_BAND)
+    STCHK(prec == FDE_FP64 ? band_factor<double>(P) : band_factor<float>(P));
   else
     STCHK(prec == FDE_FP64 ? factor_plan_impl<double>(P) : factor_plan_impl<float>(P));
   HIPCHK(hipEventRecord(e1, L->stream));
@@ -1503,9 +1585,15 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   if (route == FDE_BLOCKS_HESSENBERG)
     for (size_t i = 0; i < P->hs.size(); ++i)
       HIPCHK(hipMemcpyAsync(&herr[i], P->hs[i]->hwk.err, sizeof(int), hipMemcpyDeviceToHost, L->stream));
+  if (route == FDE_BLOCKS_BAND)
+    for (size_t i = 0; i < P->hs.size(); ++i)
+      HIPCHK(hipMemcpyAsync(&herr[i], P->hs[i]->d_berr, sizeof(int), hipMemcpyDeviceToHost, L->stream));
   STCHK(sync_and_flush(L));
   for (size_t i = 0; i < herr.size(); ++i)
-    if (herr[i]) return fail(FDE_EDEVICE, "the Hessenberg reduction of instance %zu did not complete", i);
+    if (herr[i]) {
+      if (route == FDE_BLOCKS_BAND) (void)hipMemset(P->hs[i]->d_berr, 0, sizeof(int));
+      return fail(FDE_EDEVICE, "the Hessenberg or band reduction of instance %zu did not complete", i);
+    }
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   L->evpool.push_back(e0);
@@ -1561,13 +1649,15 @@ static fde_status ensure_full_maps(Plan *P) {
     S.max_mp = std::max(S.max_mp, h->mp);
     qq[q] = qgemm_items(h->nb, h->mp);
     const double esz = h->prec == FDE_FP64 ? 16.0 : 8.0;
-    const double fac = h->blk_route == FDE_BLOCKS_HESSENBERG ? 0.5 * h->m * (h->m + 1.0)
+    const double fac = h->blk_route != FDE_BLOCKS_LU ? 0.5 * h->m * (h->m + 1.0)
                                                              : (double)h->m * h->m;
     S.trsv_bytes += (double)h->nb * fac * esz + 32.0 * h->nb * h->m;
     S.qg_bytes += 8.0 * h->m * h->m + 32.0 * h->nb * h->m;  // Q once, X in and Y out
     S.vec_bytes += 8.0 * h->n();
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
     S.bccb_bytes += 32.0 * h->nb * h->m;  // one complex read and write per (frequency, node)
+    // band L solve: the band's L11^{-1} and L21 pieces (2 x 64 x 64 per panel) and the vector
+    S.band_l_bytes += (double)h->nb * h->npan * 2.0 * 64.0 * 64.0 * esz + 32.0 * h->nb * h->m;
   }
   const std::vector<HostMap> hm = {make_map(slots, a), make_map(slots, b), make_map(slots, c),
                                    make_map(slots, d), make_map(slots, e), make_map(slots, f),
@@ -1666,6 +1756,27 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
   HIPCHK(run(L, "time_rfft", S.tfft_bytes, [&] {
     return launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, src, sj, st, ctr, P->d_epoch);
   }));
+  if (S.route == FDE_BLOCKS_BAND) {
+    // Q^T v_k (the frequency vectors are rows: the row v_k^T Q), the band L solve, U^{-1}, Q
+    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
+    HIPCHK(run(L, "band_lsolve", S.band_l_bytes, [&] {
+      return S.prec == FDE_FP64 ? launch_band_lsolve<double>(P->d_desc, S.blk, S.n_blk, st)
+                                : launch_band_lsolve<float>(P->d_desc, S.blk, S.n_blk, st);
+    }));
+    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
+      if (!g_coop_ok) return hipErrorNotSupported;
+      return S.prec == FDE_FP64
+                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
+                                            &S.blk, S.n_blk, S.npan_u)
+                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
+                                           &S.blk, S.n_blk, S.npan_u);
+    }));
+    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
+    HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
+      return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
+    }));
+    return FDE_OK;
+  }
   if (S.route == FDE_BLOCKS_HESSENBERG) {
     // Q^T v_k, the row exchanges and eliminations, U^{-1}, then Q (the frequency vectors are
     // rows, so Q^T v_k is the row v_k^T Q)
@@ -2461,12 +2572,15 @@ extern "C" fde_status fde_toeplitz_apply(fde_bvm *h, const double *x, double *y,
 
 extern "C" fde_status fde_get_hessenberg(fde_bvm *h, double *H, double *Q) {
   if (!h || !H || !Q) return fail(FDE_EINVAL, "NULL argument");
-  if (h->prec < 0 || h->blk_route != FDE_BLOCKS_HESSENBERG || !h->d_hH)
-    return fail(FDE_EINVAL, "no Hessenberg factorization stored");
+  const bool band = h->blk_route == FDE_BLOCKS_BAND;
+  if (h->prec < 0 || h->blk_route == FDE_BLOCKS_LU || !(band ? (void *)h->d_bAQ : (void *)h->d_hH))
+    return fail(FDE_EINVAL, "no Hessenberg or band factorization stored");
   const size_t m = h->m, mp = h->mp;
-  HIPCHK(hipMemcpy2DAsync(H, m * sizeof(double), h->d_hH, mp * sizeof(double), m * sizeof(double), m,
+  const double *dH = band ? h->d_bAQ : h->d_hH;
+  const double *dQ = band ? h->d_bAQ + mp * mp : h->d_hQ;
+  HIPCHK(hipMemcpy2DAsync(H, m * sizeof(double), dH, mp * sizeof(double), m * sizeof(double), m,
                           hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpy2DAsync(Q, m * sizeof(double), h->d_hQ, mp * sizeof(double), m * sizeof(double), m,
+  HIPCHK(hipMemcpy2DAsync(Q, m * sizeof(double), dQ, mp * sizeof(double), m * sizeof(double), m,
                           hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return FDE_OK;

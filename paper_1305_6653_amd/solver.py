@@ -22,7 +22,7 @@ _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
 _PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED,
        "none": N.FDE_PC_NONE}
 _SIDE = {"right": N.FDE_SIDE_RIGHT, "left": N.FDE_SIDE_LEFT}
-_BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG}
+_BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG, "band": N.FDE_BLOCKS_BAND}
 
 
 _LIVE = weakref.WeakSet()

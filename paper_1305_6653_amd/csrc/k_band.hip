@@ -15,7 +15,7 @@
 //                  textbook reflector, alpha = -sign(x_0) |x|), accumulated in compact WY form
 //                  H_0 ... H_63 = I - V T V^T (T upper triangular, by the forward recurrence
 //                  T[0:j, j] = -beta_j T[0:j, 0:j] V[:, 0:j]^T v_j).  Cooperative: workgroup g
-//                  holds 128 rows of the block in LDS; per reflection one grid-wide exchange of
+//                  holds 256 rows of the block in LDS; per reflection one grid-wide exchange of
 //                  the column dot products x^T a (all of them at once, before the reflector is
 //                  known: v^T a = x^T a - alpha a_0 and v^T v = 2 (x^T x - alpha x_0)).
 //   right update   [A; Q][:, c:] -= ([A; Q][:, c:] V) T V^T   (A and Q stacked: one product)
@@ -32,7 +32,8 @@
 namespace fde {
 
 static constexpr int BW = 64;           // bandwidth = panel width
-static constexpr int BP_ROWS = 128;     // rows of the panel per workgroup
+static constexpr int BP_ROWS = 256;     // rows of the panel per workgroup
+static constexpr int BP_MAXG = 16;      // workgroups of a panel reduction (mp <= 4096)
 static constexpr int BP_SPIN_MAX = 1 << 21;
 
 __device__ __forceinline__ void bst(double *p, double v) {
@@ -107,9 +108,12 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 }
 
 // ---- panel reduction (cooperative) ---------------------------------------------------------
-// Workgroup g holds panel rows [128 g, 128 g + 128) (local to the panel: row r is row c + r of
-// A) in LDS; thread t works on column t % 64 and rows t / 64 + 4 i.  Barrier numbers b0 + 1 ..
-// b0 + 65 (the arrive array is cleared before the first panel of a reduction).
+// Workgroup g holds panel rows [256 g, 256 g + 256) (local to the panel: row r is row c + r of
+// A) in LDS; thread t works on column t % 64 and rows t / 64 + 8 i.  Barrier numbers b0 + 1 ..
+// b0 + 65 (the arrive array is cleared before the first panel of a reduction).  After a barrier
+// every thread fetches one exchanged partial (all 512 at once), then the sums run over LDS in
+// workgroup order.
+static constexpr int BP_NT = 512, BP_RG = BP_NT / BW;  // threads, row groups
 struct BandPanelArgs {
   double *AQ;           // [2 mp][mp]
   double *V;            // [w][64]: the Householder vectors (zero above the diagonal)
@@ -123,16 +127,17 @@ struct BandPanelArgs {
   unsigned b0;
 };
 
-__global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
+__global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   __shared__ double S[BP_ROWS][BW + 1];
-  __shared__ double red[4][BW];
+  __shared__ double red[BP_RG][BW];
+  __shared__ double xch[BP_MAXG][BW];
   __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
   __shared__ int sh;
   const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
   const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
   const int rbase = g * BP_ROWS;  // first panel row of this workgroup
-  for (int i = 0; i < BP_ROWS / 4; ++i) {
-    const int sr = rg + 4 * i, r = rbase + sr;
+  for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+    const int sr = rg + BP_RG * i, r = rbase + sr;
     S[sr][col] = r < w ? a.AQ[(size_t)(c + r) * mp + pc] : 0.0;
   }
   __syncthreads();
@@ -141,23 +146,27 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
   for (int j = 0; j < BW && ok; ++j) {
     // column dot products of step j over this workgroup's rows r >= j: x^T a for every column
     double s = 0.0;
-    for (int i = 0; i < BP_ROWS / 4; ++i) {
-      const int sr = rg + 4 * i;
+    for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+      const int sr = rg + BP_RG * i;
       if (rbase + sr >= j) s = fma(S[sr][j], S[sr][col], s);
     }
     red[rg][col] = s;
     __syncthreads();
     if (t < BW) {
-      bst(&a.xpart[((size_t)(j & 1) * G + g) * BW + t], ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t]);
-      if (g == 0) bst(&a.xtop[(j & 1) * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 128)
+      double q = 0.0;
+      for (int h = 0; h < BP_RG; ++h) q += red[h][t];
+      bst(&a.xpart[((size_t)(j & 1) * G + g) * BW + t], q);
+      if (g == 0) bst(&a.xtop[(j & 1) * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 256)
     }
     ok = band_barrier(a.arrive, G, ++bno, a.err, &sh);
     if (!ok) break;
+    for (int h = rg; h < G; h += BP_RG) xch[h][col] = bld(&a.xpart[((size_t)(j & 1) * G + h) * BW + col]);
+    if (t < BW) tp[t] = bld(&a.xtop[(j & 1) * BW + t]);
+    __syncthreads();
     if (t < BW) {
       double q = 0.0;
-      for (int h = 0; h < G; ++h) q += bld(&a.xpart[((size_t)(j & 1) * G + h) * BW + t]);
+      for (int h = 0; h < G; ++h) q += xch[h][t];
       sx[t] = q;
-      tp[t] = bld(&a.xtop[(j & 1) * BW + t]);
     }
     __syncthreads();
     const double sxx = sx[j], x0 = tp[j];
@@ -168,8 +177,8 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
     const double v0 = x0 - alpha;
     if (col > j) {
       const double f = beta * (sx[col] - alpha * tp[col]);  // beta v^T a
-      for (int i = 0; i < BP_ROWS / 4; ++i) {
-        const int sr = rg + 4 * i, r = rbase + sr;
+      for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+        const int sr = rg + BP_RG * i, r = rbase + sr;
         if (r >= j) {
           const double v = r == j ? v0 : S[sr][j];
           S[sr][col] = fma(-f, v, S[sr][col]);
@@ -187,8 +196,8 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
   if (!ok) return;
   // V (zero above the diagonal, and the whole column when beta_j = 0) and the reduced panel:
   // R on and above the diagonal, zeros below
-  for (int i = 0; i < BP_ROWS / 4; ++i) {
-    const int sr = rg + 4 * i, r = rbase + sr;
+  for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+    const int sr = rg + BP_RG * i, r = rbase + sr;
     if (r >= w) continue;
     const double x = S[sr][col];
     const double vv = (r >= col && bt[col] > 0.0) ? x : 0.0;
@@ -197,8 +206,8 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
     S[sr][col] = vv;
   }
   __syncthreads();
-  // this workgroup's part of V^T V: entry (u, v) for u = t / 4 ... 16 entries per thread
-  for (int e = t; e < BW * BW; e += 256) {
+  // this workgroup's part of V^T V
+  for (int e = t; e < BW * BW; e += BP_NT) {
     const int u = e >> 6, v = e & 63;
     double q = 0.0;
     for (int sr = 0; sr < BP_ROWS; ++sr) q = fma(S[sr][u], S[sr][v], q);
@@ -209,13 +218,13 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
   // T by the forward recurrence, in workgroup 0: Gm = V^T V summed over the workgroups in
   // order, then column j of T from columns 0 .. j-1
   double(*Gm)[BW + 1] = S;  // rows 0..63 of the slab buffer
-  for (int e = t; e < BW * BW; e += 256) {
+  for (int e = t; e < BW * BW; e += BP_NT) {
     double q = 0.0;
     for (int h = 0; h < G; ++h) q += bld(&a.gpart[(size_t)h * BW * BW + e]);
     Gm[e >> 6][e & 63] = q;
   }
   double(*Tm)[BW + 1] = S + BW;  // rows 64..127
-  for (int e = t; e < BW * BW; e += 256) Tm[e >> 6][e & 63] = 0.0;
+  for (int e = t; e < BW * BW; e += BP_NT) Tm[e >> 6][e & 63] = 0.0;
   __syncthreads();
   for (int j = 0; j < BW; ++j) {
     if (t < j) {
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(256) void k_band_panel(BandPanelArgs a) {
     }
     __syncthreads();
   }
-  for (int e = t; e < BW * BW; e += 256) a.T[e] = Tm[e >> 6][e & 63];
+  for (int e = t; e < BW * BW; e += BP_NT) a.T[e] = Tm[e >> 6][e & 63];
 }
 
 // ---- FP64 matrix products on MFMA -----------------------------------------------------------
@@ -403,7 +412,7 @@ hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, d
     const int g = (w + BP_ROWS - 1) / BP_ROWS;
     BandPanelArgs pa{AQ, V, T, xpart, xtop, gpart, arrive, err, mp, p, (unsigned)(p * (BW + 1))};
     void *args[] = {(void *)&pa};
-    if ((e = hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(256), args, 0, st)) != hipSuccess)
+    if ((e = hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(BP_NT), args, 0, st)) != hipSuccess)
       return e;
     // right update of [A; Q] (2 mp rows): W = [A; Q][:, c:] V, W2 = W T, [A; Q][:, c:] -= W2 V^T
     const int zr = dg_splits(2 * mp / 64, w);

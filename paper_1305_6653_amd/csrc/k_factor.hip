@@ -1082,13 +1082,15 @@ __global__ __launch_bounds__(256, 4) void k_trsv_coop(const InstDesc *__restrict
 // of step j - 1; block row j + 1 is still C_k's own and is formed from H when first read), so
 // the pivots are chosen among those 128 rows and the step changes only those two block rows:
 //   k_band_lu_panel  P_j [C_j; C_{j+1}][:, block j] = [L11; L21] U11 in LDS; L11 \ U11 into K
-//                    block (j, j), L21 into K block (j + 1, j), the row order after the
-//                    exchanges into the permutation array (row i of the window came from row
-//                    perm[i]), the inverses of L11 and U11 into dinv[..][0] and [1];
-//   k_band_lu_rows   per 64-column tile of the trailing width: the window's rows reordered,
-//                    U12 = L11^{-1} top -> K block row j, bottom - L21 U12 -> K block row j+1;
-//   k_band_lsolve    y <- L11^{-1} (P_j y)_top, then (P_j y)_bottom - L21 (that), step by step
-//                    on the frequency vectors (U^{-1} is the backward sweep of k_trsv_coop).
+//                    block (j, j), M21 = L21 L11^{-1} into K block (j + 1, j), the row order
+//                    after the exchanges into the permutation array (row i of the window came
+//                    from row perm[i]), the inverses of L11 and U11 into dinv[..][0] and [1];
+//   k_band_lu_rows   per 64-column tile of the trailing width, from the window's reordered top
+//                    rows W: block row j + 1 <- bottom - M21 W, then block row j <- L11^{-1} W
+//                    (= U12); bottom - L21 U12 = bottom - M21 W, so neither waits for the other;
+//   k_band_lsolve    per step, from the reordered window y: y_top <- L11^{-1} y_top (final) and
+//                    y_bottom <- y_bottom - M21 y_top (U^{-1} is the backward sweep of
+//                    k_trsv_coop).
 // Pivot: the largest |re| + |im| of the column (the lowest row on ties).
 template <typename T>
 __device__ __forceinline__ c_t<T> band_entry(const double *__restrict__ H, int mp, int m, double2 lam,
@@ -1181,7 +1183,7 @@ __global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restric
     }
     __syncthreads();
   }
-  for (int e = tid; e < nr * PB; e += NT) {
+  for (int e = tid; e < PB * PB; e += NT) {
     const int r = e / PB, c = e % PB;
     K[(size_t)(r0 + r) * mp + r0 + c] = a[r][c];
   }
@@ -1203,23 +1205,48 @@ __global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restric
     Dl[e] = csel<T>(r > c, v, csel<T>(r == c, one, zero));
     Du[e] = csel<T>(r <= c, v, zero);
   }
+  // M21 = L21 L11^{-1} into K block (j + 1, j): the bottom rows then need only the window's
+  // top rows before their update (bottom - L21 U12 = bottom - M21 top), so the two block rows
+  // of a step are computed independently
+  if (nr == 2 * PB) {
+    for (int e = tid; e < PB * PB; e += NT) {
+      const int r = e / PB, c = e % PB;
+      C acc = a[PB + r][c];  // L11^{-1}[c][c] = 1
+      for (int k = c + 1; k < PB; ++k) acc = tfma<T>(a[PB + r][k], a[k][c], acc);
+      K[(size_t)(r0 + PB + r) * mp + r0 + c] = acc;
+    }
+  }
 }
 
-// 64x64 complex product on one workgroup with A (64 x 64, row stride lda) streamed from global
-// memory in slices through LDS and B (64 x 64) already in LDS; (cre, cim) = (+/-) A B in the
-// layout of tile_load, 3M form as gemm64_lds.  Every read of Bt completes before it returns.
+// Rows of the step-j window [C_j; C_{j+1}] (block rows j and j + 1, 128 rows) after the row
+// exchanges: row i is row perm[i] of the window, whose top half is K's block row j (j > 0; the
+// entries of step j - 1's update) and whose bottom half is still C_k's own, formed from H.
 template <typename T>
-struct GemmLdsA {
-  c_t<T> As[2][PB][US + 1];
+struct BandWin {
+  const c_t<T> *Ktop;  // K block row j (row stride mp)
+  const double *H;
+  const int *perm;
+  double2 lam, mu;
+  double tau;
+  int mp, m, r0;
+  bool top_from_K;
+  __device__ __forceinline__ c_t<T> get(int i, int c) const {
+    const int sr = perm[i];
+    return (sr < PB && top_from_K) ? Ktop[(size_t)sr * mp + c]
+                                   : band_entry<T>(H, mp, m, lam, mu, tau, r0 + sr, c);
+  }
 };
 
+// (cre, cim) = (+/-) A W for A 64 x 64 (row stride lda, streamed in slices) and W the window's
+// reordered top rows 0..63, columns c0 .. c0 + 63, staged in slices as they are gathered; 3M
+// form and double buffering as gemm64_lds.  Every read completes before it returns.
 template <typename T, bool NEG>
-__device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda, c_t<T> (*Bt)[PB + 1],
-                                          GemmLdsA<T> &sm, acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
+__device__ __forceinline__ void gemm64_win(const c_t<T> *__restrict__ A, int lda, const BandWin<T> &win, int c0,
+                                           GemmLds<T> &sm, acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
   typedef c_t<T> C;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const int wave = tid >> 6, wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int ar = tid >> 2, ac = (tid & 3) * 2;
+  const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
   const C *Ap = A + (size_t)ar * lda + ac;
   acc_t<T> p1[2][2], p2[2][2], p3[2][2];
   tile_zero<T>(p1, p2);
@@ -1230,8 +1257,11 @@ __device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda,
 #pragma unroll
       for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
   C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);
+  C rb0 = win.get(br, c0 + bc), rb1 = win.get(br, c0 + bc + 1);
   sm.As[0][ar][ac] = ra0;
   sm.As[0][ar][ac + 1] = ra1;
+  sm.Bs[0][br][bc] = rb0;
+  sm.Bs[0][br][bc + 1] = rb1;
   __syncthreads();
   constexpr int nsl = PB / US;
 #pragma unroll 1
@@ -1242,6 +1272,8 @@ __device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda,
       const int k1 = (sl + 1) * US;
       ra0 = ld_global<T>(Ap + k1);
       ra1 = ld_global<T>(Ap + k1 + 1);
+      rb0 = win.get(k1 + br, c0 + bc);
+      rb1 = win.get(k1 + br, c0 + bc + 1);
     }
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {
@@ -1249,7 +1281,7 @@ __device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda,
 #pragma unroll
       for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = Bt[sl * US + kk + lk][wc + c * 16 + li];
+      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
       T bs[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
@@ -1268,6 +1300,8 @@ __device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda,
     if (more) {
       sm.As[buf ^ 1][ar][ac] = ra0;
       sm.As[buf ^ 1][ar][ac + 1] = ra1;
+      sm.Bs[buf ^ 1][br][bc] = rb0;
+      sm.Bs[buf ^ 1][br][bc + 1] = rb1;
     }
     __syncthreads();
   }
@@ -1282,53 +1316,53 @@ __device__ __forceinline__ void gemm64_bl(const c_t<T> *__restrict__ A, int lda,
       }
 }
 
-// Item = (instance, block, tile t < npan - j - 1): columns c0 = 64 (j + 1 + t) ..
+// Item = (instance, block, tile t < npan - j - 1): columns c0 = 64 (j + 1 + t) .. of the window.
+//   half 1 (launched first): block row j + 1 <- bottom - M21 top       (K block row j + 1)
+//   half 0:                  block row j     <- L11^{-1} top = U12      (K block row j, in place)
+// Half 1 reads block row j before half 0 replaces it; within half 0 each workgroup reads its
+// own tile completely before it stores it.
 template <typename T>
-__global__ __launch_bounds__(256, 1) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j) {
+__global__ __launch_bounds__(256, 3) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j,
+                                                         int half) {
   typedef c_t<T> C;
-  __shared__ C Tt[PB][PB + 1];  // top rows of the reordered window, then U12
-  __shared__ C Tb[PB][PB + 1];  // bottom rows of the reordered window
-  __shared__ GemmLdsA<T> sm;
+  __shared__ GemmLds<T> sm;
   const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
   const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
-  const int mp = d.mp, npan = d.npan, m = d.m, nrem = npan - j - 1;
+  const int mp = d.mp, npan = d.npan, nrem = npan - j - 1;
   const int local = item - map.pre[q];
   const int blk = local / nrem, tt = local % nrem;
   const int r0 = j * PB, c0 = (j + 1 + tt) * PB, tid = threadIdx.x;
   C *K = (C *)d.K + (size_t)blk * mp * mp;
-  const int *perm = d.hpiv + ((size_t)blk * npan + j) * 2 * PB;
-  const double2 lam = d.lam[blk], mu = d.mu[blk];
-  for (int e = tid; e < 2 * PB * PB; e += 256) {
-    const int i = e / PB, c = e % PB, sr = perm[i];
-    const C v = (sr < PB && j > 0) ? K[(size_t)(r0 + sr) * mp + c0 + c]
-                                   : band_entry<T>(d.hH, mp, m, lam, mu, d.tau, r0 + sr, c0 + c);
-    if (i < PB) Tt[i][c] = v;
-    else Tb[i - PB][c] = v;
-  }
-  __syncthreads();
+  BandWin<T> win;
+  win.Ktop = K + (size_t)r0 * mp;
+  win.H = d.hH;
+  win.perm = d.hpiv + ((size_t)blk * npan + j) * 2 * PB;
+  win.lam = d.lam[blk];
+  win.mu = d.mu[blk];
+  win.tau = d.tau;
+  win.mp = mp;
+  win.m = d.m;
+  win.r0 = r0;
+  win.top_from_K = j > 0;
   const int lane = tid & 63, li = lane & 15, lk = lane >> 4, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   acc_t<T> cre[2][2], cim[2][2];
-  const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB;
-  gemm64_bl<T, false>(Dl, PB, Tt, sm, cre, cim);  // U12 = L11^{-1} top
-  tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Tt[wr + r * 16 + mfma_row<T>(lk, v)][wc + c * 16 + li] = mk<T>(cre[r][c][v], cim[r][c][v]);
-  __syncthreads();
-  gemm64_bl<T, true>(K + (size_t)(r0 + PB) * mp + r0, mp, Tt, sm, cre, cim);  // -L21 U12
+  if (half == 0) {
+    const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB;
+    gemm64_win<T, false>(Dl, PB, win, c0, sm, cre, cim);
+    tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
+    return;
+  }
+  gemm64_win<T, true>(K + (size_t)(r0 + PB) * mp + r0, mp, win, c0, sm, cre, cim);  // -M21 top
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const C z = Tb[wr + r * 16 + mfma_row<T>(lk, v)][wc + c * 16 + li];
+        const C z = win.get(PB + wr + r * 16 + mfma_row<T>(lk, v), c0 + wc + c * 16 + li);
         cre[r][c][v] += z.x;
         cim[r][c][v] += z.y;
       }
@@ -1336,8 +1370,9 @@ __global__ __launch_bounds__(256, 1) void k_band_lu_rows(const InstDesc *__restr
 }
 
 // One workgroup per block: the window [top; bottom] of step j (the top carried from step j-1,
-// the bottom read from the vector), reordered, top <- L11^{-1} top (final), bottom <- bottom -
-// L21 top (the next step's top).  Thread t: row t / 4, columns 16 (t % 4) .. + 16.
+// the bottom read from the vector), reordered; then top <- L11^{-1} top (final) and bottom <-
+// bottom - M21 top (the next step's top), both from the reordered top.  Thread t: row t / 4,
+// columns 16 (t % 4) .. + 16.
 template <typename T>
 __global__ __launch_bounds__(256) void k_band_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
   typedef c_t<T> C;
@@ -1361,29 +1396,29 @@ __global__ __launch_bounds__(256) void k_band_lsolve(const InstDesc *__restrict_
     if (tid < nr) y[tid] = ys[perm[(size_t)j * 2 * PB + tid]];
     __syncthreads();
     const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq * 16;
-    double2 s = make_double2(0.0, 0.0);
-#pragma unroll 4
-    for (int c = 0; c < 16; ++c) s = cfma(widen(Li[c]), y[qq * 16 + c], s);
-    s.x += __shfl_xor(s.x, 1, 64);
-    s.y += __shfl_xor(s.y, 1, 64);
-    s.x += __shfl_xor(s.x, 2, 64);
-    s.y += __shfl_xor(s.y, 2, 64);
-    __syncthreads();  // every read of y[0:64] done
-    if (qq == 0) {
-      y[i] = s;
-      v[r0 + i] = s;
-    }
-    __syncthreads();
+    double2 s = make_double2(0.0, 0.0), t = make_double2(0.0, 0.0);
     if (nr == 2 * PB) {
-      const C *L21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 16;
-      double2 t = make_double2(0.0, 0.0);
+      const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 16;
 #pragma unroll 4
-      for (int c = 0; c < 16; ++c) t = cfma(widen(L21[c]), y[qq * 16 + c], t);
-      t.x += __shfl_xor(t.x, 1, 64);
-      t.y += __shfl_xor(t.y, 1, 64);
-      t.x += __shfl_xor(t.x, 2, 64);
-      t.y += __shfl_xor(t.y, 2, 64);
-      if (qq == 0) ys[i] = csub(y[PB + i], t);
+      for (int c = 0; c < 16; ++c) {
+        const double2 yc = y[qq * 16 + c];
+        s = cfma(widen(Li[c]), yc, s);
+        t = cfma(widen(M21[c]), yc, t);
+      }
+    } else {
+#pragma unroll 4
+      for (int c = 0; c < 16; ++c) s = cfma(widen(Li[c]), y[qq * 16 + c], s);
+    }
+#pragma unroll
+    for (int o = 1; o <= 2; o <<= 1) {
+      s.x += __shfl_xor(s.x, o, 64);
+      s.y += __shfl_xor(s.y, o, 64);
+      t.x += __shfl_xor(t.x, o, 64);
+      t.y += __shfl_xor(t.y, o, 64);
+    }
+    if (qq == 0) {
+      v[r0 + i] = s;
+      if (nr == 2 * PB) ys[i] = csub(y[PB + i], t);
     }
     __syncthreads();
   }
@@ -1451,7 +1486,10 @@ hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items
 template <typename T>
 hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j);
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 0);
   return hipGetLastError();
 }
 

@@ -15,9 +15,10 @@
 //                  textbook reflector, alpha = -sign(x_0) |x|), accumulated in compact WY form
 //                  H_0 ... H_63 = I - V T V^T (T upper triangular, by the forward recurrence
 //                  T[0:j, j] = -beta_j T[0:j, 0:j] V[:, 0:j]^T v_j).  Cooperative: workgroup g
-//                  holds 256 rows of the block in LDS; per reflection one grid-wide exchange of
-//                  the column dot products x^T a (all of them at once, before the reflector is
-//                  known: v^T a = x^T a - alpha a_0 and v^T v = 2 (x^T x - alpha x_0)).
+//                  holds 256 rows of the block in LDS; per reflection one exchange of the
+//                  column dot products x^T a between the workgroups (all of them at once, before
+//                  the reflector is known: v^T a = x^T a - alpha a_0 and v^T v = 2 (x^T x -
+//                  alpha x_0)).
 //   right update   [A; Q][:, c:] -= ([A; Q][:, c:] V) T V^T   (A and Q stacked: one product)
 //   left update    A[c:, c:] -= V T^T (V^T A[c:, c:])
 // with FP64 MFMA products (k_dgemm; the long inner products are split over the K dimension
@@ -45,35 +46,31 @@ __device__ __forceinline__ double bld(const double *p) {
                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
-// Grid barrier number b: workgroup g raises arrive[g] to b (after its coherent stores have
-// completed), then one wavefront polls all entries until each has reached b.  Bounded: after
-// BP_SPIN_MAX polls, or once any workgroup has raised *err, the wait is abandoned (uniform
-// false) and the kernel winds down.
-__device__ __forceinline__ bool band_barrier(unsigned *arrive, int G, unsigned b, int *err, int *sh) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    if (lane == 0) __hip_atomic_store(arrive + blockIdx.x, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    for (int it = 0;; ++it) {
-      bool done = true;
-      for (int q = lane; q < G; q += 64)
-        done = done && __hip_atomic_load(arrive + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
-      if (__all(done)) break;
-      if (it > BP_SPIN_MAX || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        if (lane == 0) atomicOr(err, 1);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
+// Exchange slots.  Every value a workgroup publishes goes to a slot of its own (per reflection
+// step, workgroup and column), written once per panel with a 64-bit atomic store; a slot holds
+// the sentinel until then, so a reader waits on the value itself (no separate barrier): one
+// round trip once the writer has stored.  Two slot sets alternate between consecutive panels;
+// each panel refills the other set with the sentinel for the next one.  Waits are bounded:
+// after BP_SPIN_MAX polls, or once any workgroup has raised *err, the reader gives up.
+static constexpr unsigned long long BP_SENTINEL = 0x7ff4deadbeefcafeull;  // a NaN no sum produces
+
+__device__ __forceinline__ bool bwait(const double *p, double *out, const int *err) {
+  for (int it = 0;; ++it) {
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (u != BP_SENTINEL) {
+      *out = __longlong_as_double((long long)u);
+      return true;
     }
-    if (lane == 0) *sh = ok;
+    if (it > BP_SPIN_MAX || ((it & 63) == 63 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      return false;
+    __builtin_amdgcn_s_sleep(1);
   }
-  __syncthreads();
-  const bool ok = *sh != 0;
-  __syncthreads();
-  return ok;
+}
+
+__global__ void k_band_fill(unsigned long long *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = BP_SENTINEL;
 }
 
 // ---- [A; Q] = [J padded with I; I] -------------------------------------------------------
@@ -109,22 +106,23 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 
 // ---- panel reduction (cooperative) ---------------------------------------------------------
 // Workgroup g holds panel rows [256 g, 256 g + 256) (local to the panel: row r is row c + r of
-// A) in LDS; thread t works on column t % 64 and rows t / 64 + 8 i.  Barrier numbers b0 + 1 ..
-// b0 + 65 (the arrive array is cleared before the first panel of a reduction).  After a barrier
-// every thread fetches one exchanged partial (all 512 at once), then the sums run over LDS in
-// workgroup order.
+// A) in LDS; thread t works on column t % 64 and rows t / 64 + 8 i.  Per reflection step j each
+// workgroup publishes its column dot products (and workgroup 0 the panel's row j) into the
+// step's slots, then waits for all of them; the sums run over LDS in workgroup order.
 static constexpr int BP_NT = 512, BP_RG = BP_NT / BW;  // threads, row groups
+// slot set layout (doubles): xpart [64 steps][BP_MAXG][64], xtop [64 steps][64], gpart
+// [BP_MAXG][64][64], gflag [BP_MAXG] (raised once a workgroup's gpart is stored)
+static constexpr size_t BP_XPART = (size_t)BW * BP_MAXG * BW, BP_XTOP = (size_t)BW * BW,
+                        BP_GPART = (size_t)BP_MAXG * BW * BW,
+                        BP_SET = BP_XPART + BP_XTOP + BP_GPART + BP_MAXG;
 struct BandPanelArgs {
   double *AQ;           // [2 mp][mp]
   double *V;            // [w][64]: the Householder vectors (zero above the diagonal)
   double *T;            // [64][64]: the compact-WY factor (zero below the diagonal)
-  double *xpart;        // [2][G][64]: per-workgroup column dot products, two steps in flight
-  double *xtop;         // [2][64]: row j of the panel at step j
-  double *gpart;        // [G][64][64]: per-workgroup parts of V^T V
-  unsigned *arrive;     // [G]
+  double *slots;        // this panel's slot set (BP_SET doubles)
+  double *next;         // the other set, refilled with the sentinel for the next panel
   int *err;
   int mp, p;
-  unsigned b0;
 };
 
 __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
@@ -132,18 +130,23 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   __shared__ double red[BP_RG][BW];
   __shared__ double xch[BP_MAXG][BW];
   __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
-  __shared__ int sh;
+  __shared__ int bad;
   const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
   const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
   const int rbase = g * BP_ROWS;  // first panel row of this workgroup
+  double *xpart = a.slots, *xtop = a.slots + BP_XPART, *gpart = xtop + BP_XTOP, *gflag = gpart + BP_GPART;
+  {  // this workgroup's share of the next panel's slots
+    unsigned long long *nx = reinterpret_cast<unsigned long long *>(a.next);
+    const size_t per = (BP_SET + G - 1) / G, lo = per * g, hi = lo + per < BP_SET ? lo + per : BP_SET;
+    for (size_t i = lo + t; i < hi; i += BP_NT) nx[i] = BP_SENTINEL;
+  }
+  if (t == 0) bad = 0;
   for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
     const int sr = rg + BP_RG * i, r = rbase + sr;
     S[sr][col] = r < w ? a.AQ[(size_t)(c + r) * mp + pc] : 0.0;
   }
   __syncthreads();
-  unsigned bno = a.b0;
-  bool ok = true;
-  for (int j = 0; j < BW && ok; ++j) {
+  for (int j = 0; j < BW; ++j) {
     // column dot products of step j over this workgroup's rows r >= j: x^T a for every column
     double s = 0.0;
     for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
@@ -155,14 +158,18 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     if (t < BW) {
       double q = 0.0;
       for (int h = 0; h < BP_RG; ++h) q += red[h][t];
-      bst(&a.xpart[((size_t)(j & 1) * G + g) * BW + t], q);
-      if (g == 0) bst(&a.xtop[(j & 1) * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 256)
+      bst(&xpart[((size_t)j * BP_MAXG + g) * BW + t], q);
+      if (g == 0) bst(&xtop[(size_t)j * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 256)
     }
-    ok = band_barrier(a.arrive, G, ++bno, a.err, &sh);
-    if (!ok) break;
-    for (int h = rg; h < G; h += BP_RG) xch[h][col] = bld(&a.xpart[((size_t)(j & 1) * G + h) * BW + col]);
-    if (t < BW) tp[t] = bld(&a.xtop[(j & 1) * BW + t]);
+    bool ok = true;
+    for (int h = rg; h < G; h += BP_RG) ok = ok && bwait(&xpart[((size_t)j * BP_MAXG + h) * BW + col], &xch[h][col], a.err);
+    if (t < BW) ok = ok && bwait(&xtop[(size_t)j * BW + t], &tp[t], a.err);
+    if (!ok) {
+      bad = 1;
+      atomicOr(a.err, 1);
+    }
     __syncthreads();
+    if (bad) return;
     if (t < BW) {
       double q = 0.0;
       for (int h = 0; h < G; ++h) q += xch[h][t];
@@ -193,7 +200,6 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     if (g == 0 && t == 0) S[j][j] = beta > 0.0 ? v0 : 0.0;  // v_j's first entry
     __syncthreads();
   }
-  if (!ok) return;
   // V (zero above the diagonal, and the whole column when beta_j = 0) and the reduced panel:
   // R on and above the diagonal, zeros below
   for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
@@ -211,20 +217,31 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     const int u = e >> 6, v = e & 63;
     double q = 0.0;
     for (int sr = 0; sr < BP_ROWS; ++sr) q = fma(S[sr][u], S[sr][v], q);
-    bst(&a.gpart[(size_t)g * BW * BW + e], q);
+    bst(&gpart[(size_t)g * BW * BW + e], q);
   }
-  ok = band_barrier(a.arrive, G, ++bno, a.err, &sh);
-  if (!ok || g != 0) return;
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __syncthreads();
+  if (t == 0) bst(&gflag[g], 1.0);
+  if (g != 0) return;
   // T by the forward recurrence, in workgroup 0: Gm = V^T V summed over the workgroups in
   // order, then column j of T from columns 0 .. j-1
+  if (t < G) {
+    double y;
+    if (!bwait(&gflag[t], &y, a.err)) {
+      bad = 1;
+      atomicOr(a.err, 1);
+    }
+  }
+  __syncthreads();
+  if (bad) return;
   double(*Gm)[BW + 1] = S;  // rows 0..63 of the slab buffer
+  double(*Tm)[BW + 1] = S + BW;  // rows 64..127
   for (int e = t; e < BW * BW; e += BP_NT) {
     double q = 0.0;
-    for (int h = 0; h < G; ++h) q += bld(&a.gpart[(size_t)h * BW * BW + e]);
+    for (int h = 0; h < G; ++h) q += bld(&gpart[(size_t)h * BW * BW + e]);
     Gm[e >> 6][e & 63] = q;
+    Tm[e >> 6][e & 63] = 0.0;
   }
-  double(*Tm)[BW + 1] = S + BW;  // rows 64..127
-  for (int e = t; e < BW * BW; e += BP_NT) Tm[e >> 6][e & 63] = 0.0;
   __syncthreads();
   for (int j = 0; j < BW; ++j) {
     if (t < j) {
@@ -362,8 +379,6 @@ __global__ __launch_bounds__(256) void k_band_transpose(const double *__restrict
 }
 
 // ---- host side -------------------------------------------------------------------------------
-int band_panel_groups(int mp) { return (mp - BW + BP_ROWS - 1) / BP_ROWS; }
-
 static int dg_splits(int tiles, int K) {
   // enough workgroups to fill the device twice over, each with at least 256 of the K range
   int z = 1;
@@ -372,14 +387,11 @@ static int dg_splits(int tiles, int K) {
 }
 
 size_t band_work_doubles(int mp) {
-  const int G = band_panel_groups(mp);
   const size_t w2 = (size_t)2 * mp * BW * 16;  // W partials: up to 16 splits of [2 mp][64]
   const size_t y1 = (size_t)BW * mp * 16;      // Y partials
   return (size_t)mp * BW      // V
          + BW * BW             // T
-         + (size_t)2 * G * BW  // xpart
-         + 2 * BW              // xtop
-         + (size_t)G * BW * BW  // gpart
+         + 2 * BP_SET          // two slot sets
          + std::max(w2, y1)    // partial products
          + (size_t)2 * mp * BW  // W2
          + (size_t)BW * mp;     // Y2
@@ -395,22 +407,20 @@ static hipError_t dgemm(int M, int N, int K, int splits, const double *A, int ld
 }
 
 hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
-                              unsigned *arrive, int *err, hipStream_t st) {
-  const int G = band_panel_groups(mp);
-  double *V = work, *T = V + (size_t)mp * BW, *xpart = T + BW * BW, *xtop = xpart + (size_t)2 * G * BW;
-  double *gpart = xtop + 2 * BW, *part = gpart + (size_t)G * BW * BW;
+                              int *err, hipStream_t st) {
+  double *V = work, *T = V + (size_t)mp * BW, *slots = T + BW * BW, *part = slots + 2 * BP_SET;
   const size_t w2 = (size_t)2 * mp * BW * 16, y1 = (size_t)BW * mp * 16;
   double *W2 = part + std::max(w2, y1), *Y2 = W2 + (size_t)2 * mp * BW;
   hipLaunchKernelGGL(k_band_init, dim3((mp + 255) / 256, 2 * mp), dim3(256), 0, st, D, inst, AQ);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_zero_u32, dim3(1), dim3(256), 0, st, arrive, G);
+  hipLaunchKernelGGL(k_band_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<unsigned long long *>(slots), BP_SET);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int np = mp / BW;
   for (int p = 0; p + 1 < np; ++p) {
     const int c = (p + 1) * BW, w = mp - c;
     const int g = (w + BP_ROWS - 1) / BP_ROWS;
-    BandPanelArgs pa{AQ, V, T, xpart, xtop, gpart, arrive, err, mp, p, (unsigned)(p * (BW + 1))};
+    BandPanelArgs pa{AQ, V, T, slots + (size_t)(p & 1) * BP_SET, slots + (size_t)((p + 1) & 1) * BP_SET, err, mp, p};
     void *args[] = {(void *)&pa};
     if ((e = hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(BP_NT), args, 0, st)) != hipSuccess)
       return e;

@@ -136,12 +136,11 @@ template <typename T>
 hipError_t launch_hess_uinv(const InstDesc *D, const ItemMap &map, int items, int *flag,
                             hipStream_t st);
 // ---- the band route: J = Q H Q^T with H of lower bandwidth 64 (k_band.hip) ----
-int band_panel_groups(int mp);    // workgroups of the first panel reduction
 size_t band_work_doubles(int mp);  // workspace of launch_band_reduce
-// [A; Q] ([2 mp][mp]) <- [H; Q] from J of instance `inst`, Qt <- Q^T; arrive [band_panel_groups],
-// err set if a grid barrier had to be abandoned
+// [A; Q] ([2 mp][mp]) <- [H; Q] from J of instance `inst`, Qt <- Q^T; *err set if a wait
+// between the workgroups of a panel reduction had to be abandoned
 hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
-                              unsigned *arrive, int *err, hipStream_t st);
+                              int *err, hipStream_t st);
 // step j of the pivoted band LU: item = (instance, block) for the panel, (instance, block, tile)
 // with npan - j - 1 tiles per block for the rows; permutations in hpiv [nb][npan][128]
 template <typename T>

@@ -178,10 +178,9 @@ struct fde_bvm {
   HessWork hwk{};
   // ---- band route to the blocks (allocated when first factored that way): [H; Q] [2 mp][mp]
   // of J = Q H Q^T (H of lower bandwidth 64), Q^T [mp][mp], the row orders of the pivoted band
-  // LU [nb][npan][128], the reduction's workspace, grid-barrier counters and error flag
+  // LU [nb][npan][128], the reduction's workspace and error flag
   double *d_bAQ = nullptr, *d_bQt = nullptr, *d_bwork = nullptr;
   int *d_bpiv = nullptr, *d_berr = nullptr;
-  unsigned *d_barrive = nullptr;
   // ---- BCCB preconditioner tables (allocated when a BCCB preconditioner is factored)
   double2 *d_chirp = nullptr, *d_bh = nullptr, *d_lamx = nullptr;
   double lam0s = 0.0;
@@ -1444,14 +1443,13 @@ static fde_status hess_alloc(fde_bvm *h) {
 // (a panel launch over the blocks of all instances, then a launch over their row tiles).
 static fde_status band_alloc(fde_bvm *h) {
   if (h->d_bAQ) return FDE_OK;
-  const size_t mp = h->mp, nb = h->nb, G = band_panel_groups(h->mp);
+  const size_t mp = h->mp, nb = h->nb;
   STCHK(dalloc_t(h, &h->d_bAQ, 2 * mp * mp));
   STCHK(dalloc_t(h, &h->d_bQt, mp * mp));
   STCHK(dalloc_t(h, &h->d_bpiv, nb * mp * 2));
   STCHK(dalloc_t(h, &h->d_bwork, band_work_doubles(h->mp)));
-  STCHK(dalloc_t(h, &h->d_barrive, G + 64));
-  h->d_berr = (int *)(h->d_barrive + G + 32);
-  HIPCHK(hipMemsetAsync(h->d_barrive, 0, (G + 64) * sizeof(unsigned), h->stream));
+  STCHK(dalloc_t(h, &h->d_berr, 64));
+  HIPCHK(hipMemsetAsync(h->d_berr, 0, 64 * sizeof(int), h->stream));
   if (!h->d_Vh2) {
     STCHK(dalloc_t(h, &h->d_Vh2, nb * mp));
     HIPCHK(hipMemsetAsync(h->d_Vh2, 0, nb * mp * sizeof(double2), h->stream));
@@ -1471,7 +1469,7 @@ static fde_status band_factor(Plan *P) {
     // algorithmic flops of the reduction: 10/3 m^3 for H, 4/3 m^3 for Q (Householder)
     const double m = h->m;
     HIPCHK(run(L, "band_reduce", 14.0 / 3.0 * m * m * m, [&] {
-      return launch_band_reduce(P->d_desc, i, h->mp, h->d_bAQ, h->d_bQt, h->d_bwork, h->d_barrive, h->d_berr, st);
+      return launch_band_reduce(P->d_desc, i, h->mp, h->d_bAQ, h->d_bQt, h->d_bwork, h->d_berr, st);
     }));
   }
   std::vector<int> slots(count), it(count);

@@ -197,7 +197,8 @@ typedef enum {
   FDE_OPT_PRECOND = 5,
   FDE_OPT_SIDE = 6,
   FDE_OPT_BLOCKS = 7,
-  FDE_OPT_ORTHO = 8
+  FDE_OPT_ORTHO = 8,
+  FDE_OPT_BLOCKS_IN_USE = 9
 } fde_option;
 /* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
  * discards the current factorization):
@@ -229,7 +230,7 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
 /* FDE_OPT_BLOCKS selects how the blocks K_k = lambda_k I - tau mu_k J of S are factored and
  * solved (the operator S^{-1} is the same up to rounding; changing it discards the current
  * factorization):
- *   FDE_BLOCKS_LU          (default) a pivot-free LU of every block (s/2+1 dense LUs on MFMA);
+ *   FDE_BLOCKS_LU          a pivot-free LU of every block (s/2+1 dense LUs on MFMA);
  *                          the solves read the full L and U factors.
  *   FDE_BLOCKS_HESSENBERG  every block is a shift of J: one Householder reduction J = Q H Q^T
  *                          (H upper Hessenberg, Q orthogonal; FP64) and, per block, Gaussian
@@ -244,7 +245,16 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
  *                          tau mu_k H with partial pivoting among the 128 rows of each 64-column
  *                          panel (O(64 m^2)); the solves read U and the band of L.  Any m the
  *                          library takes; needs cooperative launches.  Not in the paper. */
-typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2 } fde_block_solver;
+/*   FDE_BLOCKS_AUTO        (default) FDE_BLOCKS_BAND when m >= FDE_BAND_MIN_M_FP64 (FP64 blocks)
+ *                          or m >= FDE_BAND_MIN_M_MIXED (FP32 blocks), else FDE_BLOCKS_LU (for a
+ *                          batch: the band route only if every instance qualifies).  Measured on
+ *                          MI355X at s = 256: FP64 factor + solve take the same time both ways at
+ *                          m = 1535 (39 ms) and the band route is 1.3x faster at m = 2047 and 2x
+ *                          at m = 3071; with FP32 blocks block LU stays faster up to m = 2047.
+ * FDE_OPT_BLOCKS_IN_USE (read-only) is the route of the current factorization. */
+typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2, FDE_BLOCKS_AUTO = 3 } fde_block_solver;
+#define FDE_BAND_MIN_M_FP64 1536
+#define FDE_BAND_MIN_M_MIXED 2560
 /* FDE_OPT_ORTHO selects the Arnoldi orthogonalisation (FP64 either way):
  *   FDE_ORTHO_MGS   (default) modified Gram-Schmidt, j + 2 dependent launches at step j.
  *   FDE_ORTHO_CGS2  classical Gram-Schmidt applied twice: three launches per step whatever j;

@@ -406,38 +406,63 @@ static hipError_t dgemm(int M, int N, int K, int splits, const double *A, int ld
   return hipGetLastError();
 }
 
-hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
-                              int *err, hipStream_t st) {
-  double *V = work, *T = V + (size_t)mp * BW, *slots = T + BW * BW, *part = slots + 2 * BP_SET;
+// The reduction in three parts, so that a caller can time the panels and the updates apart:
+// init ([A; Q] from J, slot set 0 filled), then per panel p = 0 .. mp/64 - 2 the panel and its
+// two-sided update, then Qt = Q^T.
+struct BandPtrs {
+  double *V, *T, *slots, *part, *W2, *Y2;
+};
+static BandPtrs band_ptrs(int mp, double *work) {
+  BandPtrs b;
+  b.V = work;
+  b.T = b.V + (size_t)mp * BW;
+  b.slots = b.T + BW * BW;
+  b.part = b.slots + 2 * BP_SET;
   const size_t w2 = (size_t)2 * mp * BW * 16, y1 = (size_t)BW * mp * 16;
-  double *W2 = part + std::max(w2, y1), *Y2 = W2 + (size_t)2 * mp * BW;
+  b.W2 = b.part + std::max(w2, y1);
+  b.Y2 = b.W2 + (size_t)2 * mp * BW;
+  return b;
+}
+
+hipError_t launch_band_init(const InstDesc *D, int inst, int mp, double *AQ, double *work, hipStream_t st) {
+  const BandPtrs b = band_ptrs(mp, work);
   hipLaunchKernelGGL(k_band_init, dim3((mp + 255) / 256, 2 * mp), dim3(256), 0, st, D, inst, AQ);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<unsigned long long *>(slots), BP_SET);
+  hipLaunchKernelGGL(k_band_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<unsigned long long *>(b.slots), BP_SET);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_panel(int mp, int p, double *AQ, double *work, int *err, hipStream_t st) {
+  const BandPtrs b = band_ptrs(mp, work);
+  const int c = (p + 1) * BW, w = mp - c;
+  const int g = (w + BP_ROWS - 1) / BP_ROWS;
+  BandPanelArgs pa{AQ, b.V, b.T, b.slots + (size_t)(p & 1) * BP_SET, b.slots + (size_t)((p + 1) & 1) * BP_SET,
+                   err, mp, p};
+  void *args[] = {(void *)&pa};
+  return hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(BP_NT), args, 0, st);
+}
+
+hipError_t launch_band_update(int mp, int p, double *AQ, double *work, hipStream_t st) {
+  const BandPtrs b = band_ptrs(mp, work);
+  const int c = (p + 1) * BW, w = mp - c;
+  hipError_t e;
+  // right update of [A; Q] (2 mp rows): W = [A; Q][:, c:] V, W2 = W T, [A; Q][:, c:] -= W2 V^T
+  const int zr = dg_splits(2 * mp / 64, w);
+  if ((e = dgemm<false, false, 0>(2 * mp, BW, w, zr, AQ + c, mp, b.V, BW, b.part, BW, 1.0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_w2, dim3(2 * mp / 4), dim3(256), 0, st, b.part, zr, 2 * mp, b.T, b.W2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int np = mp / BW;
-  for (int p = 0; p + 1 < np; ++p) {
-    const int c = (p + 1) * BW, w = mp - c;
-    const int g = (w + BP_ROWS - 1) / BP_ROWS;
-    BandPanelArgs pa{AQ, V, T, slots + (size_t)(p & 1) * BP_SET, slots + (size_t)((p + 1) & 1) * BP_SET, err, mp, p};
-    void *args[] = {(void *)&pa};
-    if ((e = hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(BP_NT), args, 0, st)) != hipSuccess)
-      return e;
-    // right update of [A; Q] (2 mp rows): W = [A; Q][:, c:] V, W2 = W T, [A; Q][:, c:] -= W2 V^T
-    const int zr = dg_splits(2 * mp / 64, w);
-    if ((e = dgemm<false, false, 0>(2 * mp, BW, w, zr, AQ + c, mp, V, BW, part, BW, 1.0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_w2, dim3(2 * mp / 4), dim3(256), 0, st, part, zr, 2 * mp, T, W2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = dgemm<false, true, 1>(2 * mp, w, BW, 1, W2, BW, V, BW, AQ + c, mp, -1.0, st)) != hipSuccess) return e;
-    // left update of A[c:, c:]: Y = V^T A[c:, c:], Y2 = T^T Y, A[c:, c:] -= V Y2
-    const int zl = dg_splits(w / 64, w);
-    double *Ac = AQ + (size_t)c * mp + c;
-    if ((e = dgemm<true, false, 0>(BW, w, w, zl, V, BW, Ac, mp, part, w, 1.0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_y2, dim3(w / 4), dim3(256), 0, st, part, zl, w, T, Y2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = dgemm<false, false, 1>(w, w, BW, 1, V, BW, Y2, w, Ac, mp, -1.0, st)) != hipSuccess) return e;
-  }
+  if ((e = dgemm<false, true, 1>(2 * mp, w, BW, 1, b.W2, BW, b.V, BW, AQ + c, mp, -1.0, st)) != hipSuccess) return e;
+  // left update of A[c:, c:]: Y = V^T A[c:, c:], Y2 = T^T Y, A[c:, c:] -= V Y2
+  const int zl = dg_splits(w / 64, w);
+  double *Ac = AQ + (size_t)c * mp + c;
+  if ((e = dgemm<true, false, 0>(BW, w, w, zl, b.V, BW, Ac, mp, b.part, w, 1.0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_y2, dim3(w / 4), dim3(256), 0, st, b.part, zl, w, b.T, b.Y2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return dgemm<false, false, 1>(w, w, BW, 1, b.V, BW, b.Y2, w, Ac, mp, -1.0, st);
+}
+
+hipError_t launch_band_finish(int mp, double *AQ, double *Qt, hipStream_t st) {
   hipLaunchKernelGGL(k_band_transpose, dim3(mp / 64, mp / 64), dim3(256), 0, st, AQ + (size_t)mp * mp, Qt, mp);
   return hipGetLastError();
 }

@@ -136,11 +136,14 @@ template <typename T>
 hipError_t launch_hess_uinv(const InstDesc *D, const ItemMap &map, int items, int *flag,
                             hipStream_t st);
 // ---- the band route: J = Q H Q^T with H of lower bandwidth 64 (k_band.hip) ----
-size_t band_work_doubles(int mp);  // workspace of launch_band_reduce
-// [A; Q] ([2 mp][mp]) <- [H; Q] from J of instance `inst`, Qt <- Q^T; *err set if a wait
-// between the workgroups of a panel reduction had to be abandoned
-hipError_t launch_band_reduce(const InstDesc *D, int inst, int mp, double *AQ, double *Qt, double *work,
-                              int *err, hipStream_t st);
+size_t band_work_doubles(int mp);  // workspace of the reduction
+// J = Q H Q^T of instance `inst` in [A; Q] ([2 mp][mp]): init ([J; I]), then for p = 0 .. mp/64-2
+// the panel (cooperative; *err set if a wait between its workgroups had to be abandoned) and its
+// two-sided update, then Qt = Q^T
+hipError_t launch_band_init(const InstDesc *D, int inst, int mp, double *AQ, double *work, hipStream_t st);
+hipError_t launch_band_panel(int mp, int p, double *AQ, double *work, int *err, hipStream_t st);
+hipError_t launch_band_update(int mp, int p, double *AQ, double *work, hipStream_t st);
+hipError_t launch_band_finish(int mp, double *AQ, double *Qt, hipStream_t st);
 // step j of the pivoted band LU: item = (instance, block) for the panel, (instance, block, tile)
 // with npan - j - 1 tiles per block for the rows; permutations in hpiv [nb][npan][128]
 template <typename T>

@@ -191,7 +191,7 @@ struct fde_bvm {
   int opt_precond = FDE_PC_STRANG;  // chosen kind; pc = the kind of the current factorization
   int pc = FDE_PC_STRANG;
   int opt_side = FDE_SIDE_RIGHT;
-  int opt_blocks = FDE_BLOCKS_LU;
+  int opt_blocks = FDE_BLOCKS_AUTO;
   int opt_ortho = FDE_ORTHO_MGS;
   // ---- profiling
   bool prof = false;
@@ -1147,8 +1147,9 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
       h->opt_ortho = value;
       return FDE_OK;
     case FDE_OPT_BLOCKS:
-      if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG && value != FDE_BLOCKS_BAND)
-        return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU, FDE_BLOCKS_HESSENBERG or FDE_BLOCKS_BAND");
+      if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG && value != FDE_BLOCKS_BAND &&
+          value != FDE_BLOCKS_AUTO)
+        return fail(FDE_EINVAL, "FDE_OPT_BLOCKS must be FDE_BLOCKS_LU, _HESSENBERG, _BAND or _AUTO");
       if (value != h->opt_blocks) h->prec = -1;  // factor again before the next solve
       h->opt_blocks = value;
       return FDE_OK;
@@ -1167,6 +1168,7 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
     case FDE_OPT_SIDE: *value = h->opt_side; return FDE_OK;
     case FDE_OPT_BLOCKS: *value = h->opt_blocks; return FDE_OK;
+    case FDE_OPT_BLOCKS_IN_USE: *value = h->blk_route; return FDE_OK;
     case FDE_OPT_ORTHO: *value = h->opt_ortho; return FDE_OK;
     case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
@@ -1466,11 +1468,20 @@ static fde_status band_factor(Plan *P) {
   for (int i = 0; i < count; ++i) {
     fde_bvm *h = P->hs[i];
     maxpan = std::max(maxpan, h->npan);
-    // algorithmic flops of the reduction: 10/3 m^3 for H, 4/3 m^3 for Q (Householder)
-    const double m = h->m;
-    HIPCHK(run(L, "band_reduce", 14.0 / 3.0 * m * m * m, [&] {
-      return launch_band_reduce(P->d_desc, i, h->mp, h->d_bAQ, h->d_bQt, h->d_bwork, h->d_berr, st);
-    }));
+    // algorithmic flops: the panel QR of a w x 64 block 2 * 64^2 (w - 64/3); the two-sided update
+    // with its product into Q 4 (2 mp) w 64 + 4 w^2 64 (right update of [A; Q], left update)
+    const int mp = h->mp;
+    HIPCHK(run(L, "band_init", 16.0 * mp * mp, [&] { return launch_band_init(P->d_desc, i, mp, h->d_bAQ, h->d_bwork, st); }));
+    for (int p = 0; p + 1 < h->npan; ++p) {
+      const double w = mp - 64.0 * (p + 1);
+      HIPCHK(run(L, "band_panel", 2.0 * 64.0 * 64.0 * (w - 64.0 / 3.0), [&] {
+        return launch_band_panel(mp, p, h->d_bAQ, h->d_bwork, h->d_berr, st);
+      }));
+      HIPCHK(run(L, "band_update", 4.0 * 2.0 * mp * w * 64.0 + 4.0 * w * w * 64.0, [&] {
+        return launch_band_update(mp, p, h->d_bAQ, h->d_bwork, st);
+      }));
+    }
+    HIPCHK(run(L, "band_finish", 16.0 * mp * mp, [&] { return launch_band_finish(mp, h->d_bAQ, h->d_bQt, st); }));
   }
   std::vector<int> slots(count), it(count);
   for (int i = 0; i < count; ++i) slots[i] = i;
@@ -1535,9 +1546,16 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
     }
     return FDE_OK;
   }
-  const int route = P->hs[0]->opt_blocks;
-  for (fde_bvm *h : P->hs) {
+  int route = P->hs[0]->opt_blocks;
+  for (fde_bvm *h : P->hs)
     if (h->opt_blocks != route) return fail(FDE_EINVAL, "all instances of a batch need the same block solver");
+  if (route == FDE_BLOCKS_AUTO) {  // the band route once every instance is large enough
+    const int mmin = prec == FDE_FP64 ? FDE_BAND_MIN_M_FP64 : FDE_BAND_MIN_M_MIXED;
+    bool band = true;
+    for (fde_bvm *h : P->hs) band = band && h->m >= mmin;
+    route = band ? FDE_BLOCKS_BAND : FDE_BLOCKS_LU;
+  }
+  for (fde_bvm *h : P->hs) {
     if (route == FDE_BLOCKS_HESSENBERG && h->m > hess_reduce_max_m())
       return fail(FDE_EUNSUPPORTED, "the Hessenberg route takes m <= %d (m = %d)", hess_reduce_max_m(), h->m);
   }

@@ -22,7 +22,8 @@ _PREC = {"fp64": N.FDE_FP64, "mixed": N.FDE_MIXED_C32, "c32": N.FDE_MIXED_C32}
 _PC = {"strang": N.FDE_PC_STRANG, "bccb": N.FDE_PC_BCCB, "bccb_shifted": N.FDE_PC_BCCB_SHIFTED,
        "none": N.FDE_PC_NONE}
 _SIDE = {"right": N.FDE_SIDE_RIGHT, "left": N.FDE_SIDE_LEFT}
-_BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG, "band": N.FDE_BLOCKS_BAND}
+_BLOCKS = {"lu": N.FDE_BLOCKS_LU, "hessenberg": N.FDE_BLOCKS_HESSENBERG, "band": N.FDE_BLOCKS_BAND,
+           "auto": N.FDE_BLOCKS_AUTO}
 
 
 _LIVE = weakref.WeakSet()
@@ -182,8 +183,8 @@ class BvmSolver:
     def factor(self, precision: str = "fp64", preconditioner: Optional[str] = None,
                blocks: Optional[str] = None):
         """Build the preconditioner: "strang" (block LUs), "bccb" or "bccb_shifted" (2-D DFT),
-        or "none".  blocks: "lu" or "hessenberg" (how the blocks of "strang" are factored);
-        None keeps the handle's setting."""
+        or "none".  blocks: "lu", "hessenberg", "band" or "auto" (how the blocks of "strang" are
+        factored); None keeps the handle's setting."""
         if blocks is not None:
             kind = _BLOCKS[blocks]
             if self.get_option(N.FDE_OPT_BLOCKS) != kind:

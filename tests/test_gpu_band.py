@@ -111,3 +111,24 @@ def test_band_route_switches_with_the_others_on_one_handle():
     assert _rel(sols["band"][0], sols["lu"][0]) <= 1e-9
     assert _rel(sols["hessenberg"][0], sols["lu"][0]) <= 1e-9
     S.close()
+
+
+def test_automatic_route_choice_by_size():
+    """FDE_BLOCKS_AUTO (the default): the band route from m = 1536 on for FP64 blocks and from
+    m = 2560 for FP32 blocks, block LU below; a batch takes the band route only if every
+    instance qualifies."""
+    small, big = W.tiny(200, 8, 1.5, 1, "gbdf3"), W.tiny(1600, 8, 1.5, 2, "gbdf3")
+    Ss, Sb = BvmSolver(small), BvmSolver(big)
+    assert Ss.get_option(N.FDE_OPT_BLOCKS) == N.FDE_BLOCKS_AUTO
+    Ss.factor("fp64")
+    Sb.factor("fp64")
+    assert Ss.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
+    assert Sb.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_BAND
+    u, info = Sb.solve(big.u0, big.f)
+    assert info["converged"] == 1 and O.true_relres(big, u) <= 1.5e-10
+    Sb.factor("mixed")
+    assert Sb.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
+    factor_batch([Ss, Sb], "fp64")
+    assert Sb.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
+    Ss.close()
+    Sb.close()

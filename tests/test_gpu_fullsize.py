@@ -3,9 +3,10 @@
 * 1023 x 512 GBDF3 (seed 2): the FP64 and the mixed-form solutions against the oracle's
   (textbook preconditioned GMRES to 1e-11 with LAPACK block solves, ~10-20 s), plus the
   true residual with the oracle's dense operator, and sampled factor blocks.
-* 4095 x 256 GBDF3 (seed 3), FP64 and mixed form: the solutions against the oracle's (about a
-  minute of host LAPACK work and 35 GB of host memory for its block factors), plus the true
-  residual with the oracle's dense operator and sampled factor blocks against the oracle's K_k
+* 4095 x 256 GBDF3 (seed 3), FP64 and mixed form, through the band route (the default at this
+  size) and the dense block LU: the solutions against the oracle's (about a minute of host
+  LAPACK work and 35 GB of host memory for its block factors), plus the true residual with the
+  oracle's dense operator and, for the block LU, sampled factor blocks against the oracle's K_k
   by products with random vectors.
 
 Solutions are compared norm-wise and entry by entry (the worst entry relative to the
@@ -16,6 +17,7 @@ import pytest
 import oracle as O
 import workloads as W
 from paper_1305_6653_amd import BvmSolver
+from paper_1305_6653_amd import _native as N
 
 pytestmark = pytest.mark.gpu
 
@@ -71,20 +73,28 @@ def c3_oracle():
 
 
 @pytest.mark.timeout(1200)
+@pytest.mark.parametrize("blocks", ["band", "lu"])
 @pytest.mark.parametrize("prec,tol,ftol", [("fp64", 1e-9, 1e-12), ("mixed", 1e-8, 1e-4)])
-def test_m4095_s256_matches_the_oracle(c3_oracle, prec, tol, ftol):
+def test_m4095_s256_matches_the_oracle(c3_oracle, prec, tol, ftol, blocks):
+    """Both block solvers at the benchmark's largest size: the band route (the default at this m)
+    and the dense block LU (whose factors are also checked against the oracle's K_k)."""
     p, ref = c3_oracle
     assert ref.converged
     S = BvmSolver(p)
-    S.factor(prec)
+    if blocks == "band":
+        S.factor(prec)  # the default route choice takes the band route at m = 4095
+        assert S.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_BAND
+    else:
+        S.factor(prec, blocks="lu")
     u, info = S.solve(p.u0, p.f, rtol=1e-10)
     assert info["converged"] == 1 and info["true_relres"] <= 1e-10
     assert _rel(u, ref.x) <= tol, (prec, _rel(u, ref.x))
     assert _elem(u, ref.x) <= tol, (prec, _elem(u, ref.x))
     assert O.true_relres(p, u) <= 1.5e-10
-    rng = np.random.default_rng(6)
-    nb = p.s // 2 + 1
-    for k in (0, 1, nb // 2, nb - 1):
-        e = _factor_product_error(S, p, k, rng)
-        assert e <= ftol, (prec, k, e)
+    if blocks == "lu":
+        rng = np.random.default_rng(6)
+        nb = p.s // 2 + 1
+        for k in (0, 1, nb // 2, nb - 1):
+            e = _factor_product_error(S, p, k, rng)
+            assert e <= ftol, (prec, k, e)
     S.close()

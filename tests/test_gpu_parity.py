@@ -303,7 +303,7 @@ def test_options_validate_and_read_back():
     p, S = _setup("gbdf3_m7_s8")
     defaults = {N.FDE_OPT_GRAPHS: 1, N.FDE_OPT_AUTOTUNE: 1, N.FDE_OPT_TRSV_W: 0,
                 N.FDE_OPT_PRECOND: N.FDE_PC_STRANG, N.FDE_OPT_SIDE: N.FDE_SIDE_RIGHT,
-                N.FDE_OPT_BLOCKS: N.FDE_BLOCKS_LU, N.FDE_OPT_ORTHO: N.FDE_ORTHO_MGS}
+                N.FDE_OPT_BLOCKS: N.FDE_BLOCKS_AUTO, N.FDE_OPT_ORTHO: N.FDE_ORTHO_MGS}
     for opt, v in defaults.items():
         assert S.get_option(opt) == v, opt
     for opt, bad in [(N.FDE_OPT_PRECOND, 7), (N.FDE_OPT_SIDE, 2), (N.FDE_OPT_BLOCKS, -1),

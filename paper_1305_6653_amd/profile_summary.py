@@ -220,7 +220,13 @@ def counters_main(a):
         print(a.title)
     for c in a.command or []:
         print(f"command: {c}")
-    print(f"{'kernel':44s} {'disp':>6s} " + " ".join(f"{c:>28s}" for c in names))
+    util = a.simds > 0 and "SQ_VALU_MFMA_BUSY_CYCLES" in names and "GRBM_GUI_ACTIVE" in names
+    extra = ["mfma_busy_frac", "mfma_flops/disp"] if util else []
+    if util:
+        print(f"mfma_busy_frac = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {a.xcds} x {a.simds} SIMDs) "
+              "(the busy cycles summed over every SIMD, the active cycles over the XCDs); "
+              "mfma_flops/disp = (SQ_INSTS_VALU_MFMA_MOPS_F64 + _F32) x 512")
+    print(f"{'kernel':44s} {'disp':>6s} " + " ".join(f"{c:>28s}" for c in names + extra))
     rows = []
     for n, lst in by.items():
         med = sorted(x.get(first, 0.0) for x in lst)[len(lst) // 2]
@@ -229,7 +235,12 @@ def counters_main(a):
         rows.append((n, len(act), avg))
     rows.sort(key=lambda r: -r[2].get(first, 0.0) * r[1])
     for n, k, avg in rows[:a.top]:
-        print(f"{n[:44]:44s} {k:6d} " + " ".join(f"{avg[c]:28.4g}" for c in names))
+        vals = [avg[c] for c in names]
+        if util:
+            act = avg["GRBM_GUI_ACTIVE"] / a.xcds * a.simds
+            vals.append(avg["SQ_VALU_MFMA_BUSY_CYCLES"] / act if act > 0 else 0.0)
+            vals.append(512.0 * (avg.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) + avg.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)))
+        print(f"{n[:44]:44s} {k:6d} " + " ".join(f"{v:28.4g}" for v in vals))
 
 
 def main():
@@ -257,6 +268,8 @@ def main():
     g.add_argument("--title", default="")
     g.add_argument("--command", action="append")
     g.add_argument("--top", type=int, default=25)
+    g.add_argument("--xcds", type=int, default=8, help="XCDs whose GRBM_GUI_ACTIVE counts are summed")
+    g.add_argument("--simds", type=int, default=0, help="SIMDs of the device (1024 on MI355X): adds the MFMA busy fraction")
     a = ap.parse_args()
     {"trace": trace_main, "pmc": pmc_main, "counters": counters_main}[a.mode](a)
 

@@ -48,36 +48,51 @@ PMC_KERNEL_GROUP = {
     "band_panel": "band", "band_update": "band", "band_init": "band", "band_finish": "band",
     "band_lu_panel": "factor", "band_lu_rows": "factor", "band_lsolve": "factor",
 }
-PMC_SOURCE_HASH = {"factor": "c53d9b1c3810c0bd", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb", "hessenberg": "cf0e655e99339546"}
-PMC_TRAFFIC = {
-    ("c2", "fp64", "assemble"): 1.0112e+09,
-    ("c2", "fp64", "bccb_solve"): 9.3250e+06,
-    ("c2", "fp64", "bvm_matvec"): 2.1818e+07,
-    ("c2", "fp64", "lu_diag"): 6.7648e+07,
-    ("c2", "fp64", "lu_panel"): 5.7406e+08,
-    ("c2", "fp64", "lu_update"): 1.8857e+09,
-    ("c2", "fp64", "mgs"): 1.5971e+07,
-    ("c2", "fp64", "normalize"): 8.5660e+06,
-    ("c2", "fp64", "time_irfft"): 8.6140e+06,
-    ("c2", "fp64", "time_rfft"): 8.9990e+06,
-    ("c2", "fp64", "trsv"): 4.4729e+09,
-    ("c2", "mixed", "assemble"): 5.0574e+08,
-    ("c2", "mixed", "lu_diag"): 3.3814e+07,
-    ("c2", "mixed", "lu_panel"): 2.9044e+08,
-    ("c2", "mixed", "lu_update"): 8.5514e+08,
-    ("c2", "mixed", "trsv"): 2.6343e+09,
-    ("c2h", "fp64", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "fp64", "hess_lu"): 2.2026e+09,
-    ("c2h", "fp64", "hess_reduce"): 6.8204e+09,
-    ("c2h", "fp64", "hess_uinv"): 4.2120e+08,
-    ("c2h", "fp64", "qgemm"): 5.2862e+07,
-    ("c2h", "fp64", "trsv"): 2.2364e+09,
-    ("c2h", "mixed", "hess_lsolve"): 1.3739e+07,
-    ("c2h", "mixed", "hess_lu"): 1.1253e+09,
-    ("c2h", "mixed", "hess_reduce"): 6.8204e+09,
-    ("c2h", "mixed", "hess_uinv"): 2.1905e+08,
-    ("c2h", "mixed", "qgemm"): 5.2862e+07,
-    ("c2h", "mixed", "trsv"): 1.3156e+09,
+# Per measured workload: the source hashes of every kernel group when its counters were taken,
+# and the bytes per launch.  Workload keys: the bench workload, plus a route letter for the
+# routes compared beside the headline ("c2h": Hessenberg route at 1023x512, "c3l": block-LU
+# route at 4095x256; "c3" itself is the band route, the default there).
+PMC_MEASURED = {
+    "c2": {"hash": {"factor": "c53d9b1c3810c0bd", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb"},
+           "bytes": {
+               ("fp64", "assemble"): 1.0112e+09, ("fp64", "bccb_solve"): 9.3250e+06,
+               ("fp64", "bvm_matvec"): 2.1818e+07, ("fp64", "lu_diag"): 6.7648e+07,
+               ("fp64", "lu_panel"): 5.7406e+08, ("fp64", "lu_update"): 1.8857e+09,
+               ("fp64", "mgs"): 1.5971e+07, ("fp64", "normalize"): 8.5660e+06,
+               ("fp64", "time_irfft"): 8.6140e+06, ("fp64", "time_rfft"): 8.9990e+06,
+               ("fp64", "trsv"): 4.4729e+09,
+               ("mixed", "assemble"): 5.0574e+08, ("mixed", "lu_diag"): 3.3814e+07,
+               ("mixed", "lu_panel"): 2.9044e+08, ("mixed", "lu_update"): 8.5514e+08,
+               ("mixed", "trsv"): 2.6343e+09}},
+    "c2h": {"hash": {"factor": "c53d9b1c3810c0bd", "hessenberg": "cf0e655e99339546"},
+            "bytes": {
+                ("fp64", "hess_lsolve"): 1.3739e+07, ("fp64", "hess_lu"): 2.2026e+09,
+                ("fp64", "hess_reduce"): 6.8204e+09, ("fp64", "hess_uinv"): 4.2120e+08,
+                ("fp64", "qgemm"): 5.2862e+07, ("fp64", "trsv"): 2.2364e+09,
+                ("mixed", "hess_lsolve"): 1.3739e+07, ("mixed", "hess_lu"): 1.1253e+09,
+                ("mixed", "hess_reduce"): 6.8204e+09, ("mixed", "hess_uinv"): 2.1905e+08,
+                ("mixed", "qgemm"): 5.2862e+07, ("mixed", "trsv"): 1.3156e+09}},
+    # profiles/hbm_traffic_m4095_s256_gbdf3.txt
+    "c3": {"hash": {"factor": "dafde4e25e27436c", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb",
+                    "hessenberg": "cf0e655e99339546", "band": "9c32f2edab4b14b6"},
+           "bytes": {
+               ("fp64", "trsv"): 1.7687e+10, ("fp64", "band_lu_rows"): 7.4667e+08,
+               ("fp64", "band_lu_panel"): 4.2582e+07, ("fp64", "band_lsolve"): 1.1412e+09,
+               ("fp64", "qgemm"): 3.6323e+08, ("fp64", "band_panel"): 9.092e+06,
+               ("fp64", "band_init"): 2.6942e+08, ("fp64", "mgs"): 3.1231e+07,
+               ("fp64", "bvm_matvec"): 7.0734e+07, ("fp64", "time_rfft"): 1.7179e+07,
+               ("fp64", "time_irfft"): 1.6987e+07, ("fp64", "normalize"): 1.6917e+07,
+               ("mixed", "trsv"): 9.3536e+09, ("mixed", "band_lu_rows"): 3.0336e+08,
+               ("mixed", "band_lsolve"): 5.7383e+08, ("mixed", "qgemm"): 3.6323e+08,
+               ("mixed", "band_panel"): 9.092e+06, ("mixed", "band_init"): 2.6942e+08}},
+    "c3l": {"hash": {"factor": "dafde4e25e27436c", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb"},
+            "bytes": {
+                ("fp64", "lu_update"): 2.2903e+10, ("fp64", "trsv"): 3.5386e+10,
+                ("fp64", "lu_panel"): 1.1004e+09, ("fp64", "lu_diag"): 3.4088e+07,
+                ("fp64", "assemble"): 2.1333e+09,
+                ("mixed", "lu_update"): 9.5115e+09, ("mixed", "trsv"): 1.8696e+10,
+                ("mixed", "lu_panel"): 6.3488e+08, ("mixed", "lu_diag"): 1.7035e+07,
+                ("mixed", "assemble"): 1.0670e+09}},
 }
 
 
@@ -91,10 +106,13 @@ def group_source_hash(group: str) -> str:
 
 
 def measured_traffic(workload_name, prec, kernel):
+    """HBM bytes per launch of the kernel, or None when it was not measured for this workload,
+    route and form, or its group's sources have changed since."""
+    rec = PMC_MEASURED.get(workload_name)
     group = PMC_KERNEL_GROUP.get(kernel)
-    if group is None or PMC_SOURCE_HASH.get(group) != group_source_hash(group):
+    if rec is None or group is None or rec["hash"].get(group) != group_source_hash(group):
         return None
-    return PMC_TRAFFIC.get((workload_name, prec, kernel))
+    return rec["bytes"].get((prec, kernel))
 
 
 _MFMA_PEAK = {}
@@ -119,7 +137,7 @@ FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "h
 def kernel_table(prof, steps, prec):
     """Per kernel and step: time, launches, average launch, and the algorithmic rate of its
     launches (bytes or flops recorded by the library per launch) as a fraction of the roofline
-    that bounds it (HBM 8 TB/s; FP64/FP32 MFMA for the LU GEMMs; FP64 vector for the others)."""
+    that bounds it (HBM 8 TB/s; FP64 or FP32 for the flop kernels, in the precision they run in)."""
     out = {}
     for k, v in prof.items():
         row = {"total_ms": round(v["total_ms"] / steps, 4), "count": v["count"] // steps,
@@ -127,8 +145,9 @@ def kernel_table(prof, steps, prec):
         if v.get("work") and v["total_ms"] > 0:
             rate = v["work"] / (v["total_ms"] * 1e-3)
             if k in FLOP_KERNELS:
-                peak = PEAK_FP32_TFLOPS if (prec == "mixed" and k in ("lu_panel", "lu_update", "band_lu_rows")) \
-                    else PEAK_FP64_TFLOPS
+                fp32 = k in ("lu_diag", "lu_panel", "lu_update", "band_lu_rows", "band_lu_panel", "hess_lu",
+                             "hess_uinv")
+                peak = PEAK_FP32_TFLOPS if (prec == "mixed" and fp32) else PEAK_FP64_TFLOPS
                 row["TFLOPs"] = round(rate / 1e12, 3)
                 row["frac"] = round(rate / 1e12 / peak, 4)
             else:
@@ -301,16 +320,21 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
     name, q = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = q["total_ms"] / q["count"]
     traffic = measured_traffic(workload_name, prec, name)
-    if name.startswith("hess_"):  # the Hessenberg reduction / shifted LUs: latency-bound flops
+    if name.startswith("hess_") or name in ("band_panel", "band_lu_panel"):
+        # the Hessenberg reduction, the shifted LUs and the band panels: flops on the vector ALUs
+        # in chains of dependent steps (latency-bound), priced against the vector peak of the
+        # precision they run in (the reductions are FP64 in either form)
         achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
+        fp32 = prec == "mixed" and name in ("hess_lu", "hess_uinv", "band_lu_panel")
+        peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
         return {"kernel": name, "bound": "alu", "achieved": round(achieved, 4),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                 "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
                 "work_per_launch": q["work"] / q["count"]}
-    if name.startswith("lu_") or name.startswith("band_"):
+    if name in FLOP_KERNELS:
         achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
         # the band reduction is FP64 in either form; the band LU runs in the factor precision
-        peak = PEAK_FP64_TFLOPS if (prec == "fp64" or name in ("band_panel", "band_update")) else PEAK_FP32_TFLOPS
+        peak = PEAK_FP64_TFLOPS if (prec == "fp64" or name == "band_update") else PEAK_FP32_TFLOPS
         out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],

@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfdebvm.so")
+# FDE_LIB_PATH selects another build of the same library (the host-sanitizer build of
+# `python -m paper_1305_6653_amd.build --sanitize`); by default the in-tree library.
+LIB_PATH = os.environ.get("FDE_LIB_PATH") or os.path.join(_HERE, "libfdebvm.so")
 
 FDE_OK, FDE_EINVAL, FDE_ENOMEM, FDE_ESINGULAR, FDE_ENOCONV, FDE_EDEVICE, FDE_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)

@@ -22,8 +22,21 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fdebvm.h"
 #include "kernels.hpp"
+
+// Named host-side ranges for timeline tools (roctx; rocprofv3 --marker-trace shows them).
+// Without a tool attached the calls return at once.  The factor and solve entry points wait
+// for their device work before returning, so their outer ranges span it; inner ranges mark
+// where the host issues each phase.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 using namespace fde;
 typedef std::complex<double> cd;
@@ -928,14 +941,19 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
     if (!(p->d_plus[i] + p->d_minus[i] > 0.0))
       return fail(FDE_EINVAL, "d+ + d- must be positive (node %d)", i + 1);
   }
+  // the kind as the int a C caller stored: a value outside the enumeration is rejected below,
+  // and reading it through the enumeration type would already be undefined in C++
+  static_assert(sizeof(fde_bvm_kind) == sizeof(int), "fde_bvm_kind is stored as an int");
+  int kind = 0;
+  std::memcpy(&kind, &p->kind, sizeof kind);
   HostFormula F;
-  if (p->kind == FDE_BVM_TRAPEZOIDAL) {
+  if (kind == FDE_BVM_TRAPEZOIDAL) {
     F = formula_trapezoidal();
-  } else if (p->kind == FDE_BVM_GBDF3) {
+  } else if (kind == FDE_BVM_GBDF3) {
     F = formula_gbdf3();
-  } else if (p->kind == FDE_BVM_GAM5) {
+  } else if (kind == FDE_BVM_GAM5) {
     F = formula_gam5();
-  } else if (p->kind == FDE_BVM_CUSTOM) {
+  } else if (kind == FDE_BVM_CUSTOM) {
     const fde_bvm_formula *c = p->custom;
     if (!c) return fail(FDE_EINVAL, "custom formula is NULL");
     if (c->nu1 < 1 || c->nu2 < 0 || c->nu1 + c->nu2 > 16)
@@ -959,7 +977,7 @@ extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
       F.bf.assign(c->beta_fin, c->beta_fin + (size_t)c->nu2 * mu1);
     }
   } else {
-    return fail(FDE_EINVAL, "unknown BVM kind %d", (int)p->kind);
+    return fail(FDE_EINVAL, "unknown BVM kind %d", kind);
   }
   STCHK(validate_formula(F));
   if (p->s < F.mu + 1) return fail(FDE_EINVAL, "s = %d must be at least mu+1 = %d", p->s, F.mu + 1);
@@ -1466,6 +1484,7 @@ static fde_status band_factor(Plan *P) {
   hipStream_t st = L->stream;
   int maxpan = 0;
   for (int i = 0; i < count; ++i) {
+    TraceRange tr("band reduction of J");
     fde_bvm *h = P->hs[i];
     maxpan = std::max(maxpan, h->npan);
     // algorithmic flops: the panel QR of a w x 64 block 2 * 64^2 (w - 64/3); the two-sided update
@@ -1494,6 +1513,7 @@ static fde_status band_factor(Plan *P) {
   }
   std::vector<ItemMap> dm;
   STCHK(upload_maps(P, hm, dm));
+  TraceRange tr("band LU of the shifted blocks");
   for (int j = 0; j < maxpan; ++j) {
     // algorithmic flops (complex multiply-add = 8 real flops): the 128 x 64 panel LU, and per
     // tile of the trailing width the two 64 x 64 x 64 products
@@ -1517,6 +1537,7 @@ static fde_status bccb_prepare(fde_bvm *h);
 
 static fde_status factor_plan(Plan *P, fde_precision prec) {
   if (prec != FDE_FP64 && prec != FDE_MIXED_C32) return fail(FDE_EINVAL, "unknown precision %d", (int)prec);
+  TraceRange tr_factor("fde_precond_factor");
   fde_bvm *L = P->lead;
   const int kind = P->hs[0]->opt_precond;
   for (fde_bvm *h : P->hs)
@@ -1588,12 +1609,16 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipMemsetAsync(P->d_flag, 0, sizeof(int), L->stream));
   HIPCHK(hipEventRecord(e0, L->stream));
-  if (route == FDE_BLOCKS_HESSENBERG)
+  if (route == FDE_BLOCKS_HESSENBERG) {
+    TraceRange tr("blocks: Hessenberg route");
     STCHK(prec == FDE_FP64 ? hess_factor<double>(P) : hess_factor<float>(P));
-  else if (route == FDE_BLOCKS_BAND)
+  } else if (route == FDE_BLOCKS_BAND) {
+    TraceRange tr("blocks: band route");
     STCHK(prec == FDE_FP64 ? band_factor<double>(P) : band_factor<float>(P));
-  else
+  } else {
+    TraceRange tr("blocks: block LU");
     STCHK(prec == FDE_FP64 ? factor_plan_impl<double>(P) : factor_plan_impl<float>(P));
+  }
   HIPCHK(hipEventRecord(e1, L->stream));
   int flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, L->stream));
@@ -2120,6 +2145,7 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     bool any = false;
     for (int i = 0; i < count; ++i) any = any || !ctl[i].done;
     if (!any) break;
+    TraceRange tr_cycle("gmres restart cycle");
     std::vector<int> its_cycle(count);
     for (int i = 0; i < count; ++i) its_cycle[i] = ctl[i].its;
     const int pred = c < (int)P->pred_steps.size() ? P->pred_steps[c] : 0;
@@ -2259,6 +2285,7 @@ static fde_status autotune_trsv(Plan *P, int prec) {
 static fde_status solve_plan(Plan *P, const double *const *u0, const double *const *f,
                              double *const *u, const double *const *x0, const fde_solve_opts &o,
                              fde_solve_info *info) {
+  TraceRange tr_solve("fde_bvm_solve");
   fde_bvm *L = P->lead;
   const int count = (int)P->hs.size();
   const int prec = P->hs[0]->prec;

@@ -54,9 +54,20 @@ def test_traffic_is_reported_only_for_the_sources_it_was_measured_on():
     for group in bench.PMC_GROUPS:
         assert len(bench.group_source_hash(group)) == 16
     assert bench.measured_traffic("c2", "fp64", "no_such_kernel") is None
-    key = ("c2", "fp64", "trsv")
-    if key in bench.PMC_TRAFFIC and bench.PMC_SOURCE_HASH["factor"] == bench.group_source_hash("factor"):
-        assert bench.measured_traffic(*key) == bench.PMC_TRAFFIC[key]
+    assert bench.measured_traffic("no_such_workload", "fp64", "trsv") is None
+    for wl, rec in bench.PMC_MEASURED.items():
+        for (prec, kernel), nbytes in rec["bytes"].items():
+            group = bench.PMC_KERNEL_GROUP[kernel]
+            current = rec["hash"].get(group) == bench.group_source_hash(group)
+            assert bench.measured_traffic(wl, prec, kernel) == (nbytes if current else None), (wl, kernel)
+    # a changed source of the group nulls the figure
+    saved = bench.group_source_hash
+    try:
+        bench.group_source_hash = lambda g: "0" * 16
+        assert all(bench.measured_traffic(wl, p, k) is None
+                   for wl, rec in bench.PMC_MEASURED.items() for (p, k) in rec["bytes"])
+    finally:
+        bench.group_source_hash = saved
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():

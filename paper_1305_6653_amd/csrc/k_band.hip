@@ -106,10 +106,14 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 
 // ---- panel reduction (cooperative) ---------------------------------------------------------
 // Workgroup g holds panel rows [256 g, 256 g + 256) (local to the panel: row r is row c + r of
-// A) in LDS; thread t works on column t % 64 and rows t / 64 + 8 i.  Per reflection step j each
+// A) in LDS; thread t works on column t % 64 and rows t / 64 + 16 i.  Per reflection step j each
 // workgroup publishes its column dot products (and workgroup 0 the panel's row j) into the
-// step's slots, then waits for all of them; the sums run over LDS in workgroup order.
-static constexpr int BP_NT = 512, BP_RG = BP_NT / BW;  // threads, row groups
+// step's slots, then waits for all of them; every thread sums the published values it needs in
+// workgroup order, so all threads of all workgroups derive bitwise-equal reflectors.  Three
+// barriers per step: after the local dot products, after the exchange, after the update.
+static constexpr int BP_NT = 1024, BP_RG = BP_NT / BW;  // threads, row groups
+static constexpr int BP_RPT = BP_ROWS / BP_RG;          // rows per thread
+static_assert(BP_MAXG <= BP_RG, "one exchange slot per row group");
 // slot set layout (doubles): xpart [64 steps][BP_MAXG][64], xtop [64 steps][64], gpart
 // [BP_MAXG][64][64], gflag [BP_MAXG] (raised once a workgroup's gpart is stored)
 static constexpr size_t BP_XPART = (size_t)BW * BP_MAXG * BW, BP_XTOP = (size_t)BW * BW,
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   __shared__ double S[BP_ROWS][BW + 1];
   __shared__ double red[BP_RG][BW];
   __shared__ double xch[BP_MAXG][BW];
-  __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
+  __shared__ double tp[BW], rd[BW], bt[BW];
   __shared__ int bad;
   const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
   const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
@@ -141,28 +145,33 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     for (size_t i = lo + t; i < hi; i += BP_NT) nx[i] = BP_SENTINEL;
   }
   if (t == 0) bad = 0;
-  for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+#pragma unroll
+  for (int i = 0; i < BP_RPT; ++i) {
     const int sr = rg + BP_RG * i, r = rbase + sr;
     S[sr][col] = r < w ? a.AQ[(size_t)(c + r) * mp + pc] : 0.0;
   }
   __syncthreads();
   for (int j = 0; j < BW; ++j) {
     // column dot products of step j over this workgroup's rows r >= j: x^T a for every column
-    double s = 0.0;
-    for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+    // (four interleaved partial sums, combined in a fixed order)
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < BP_RPT; ++i) {
       const int sr = rg + BP_RG * i;
-      if (rbase + sr >= j) s = fma(S[sr][j], S[sr][col], s);
+      const double x = rbase + sr >= j ? S[sr][j] : 0.0;
+      s4[i & 3] = fma(x, S[sr][col], s4[i & 3]);
     }
-    red[rg][col] = s;
+    red[rg][col] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     if (t < BW) {
       double q = 0.0;
+#pragma unroll
       for (int h = 0; h < BP_RG; ++h) q += red[h][t];
       bst(&xpart[((size_t)j * BP_MAXG + g) * BW + t], q);
       if (g == 0) bst(&xtop[(size_t)j * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 256)
     }
     bool ok = true;
-    for (int h = rg; h < G; h += BP_RG) ok = ok && bwait(&xpart[((size_t)j * BP_MAXG + h) * BW + col], &xch[h][col], a.err);
+    if (rg < G) ok = bwait(&xpart[((size_t)j * BP_MAXG + rg) * BW + col], &xch[rg][col], a.err);
     if (t < BW) ok = ok && bwait(&xtop[(size_t)j * BW + t], &tp[t], a.err);
     if (!ok) {
       bad = 1;
@@ -170,39 +179,41 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     }
     __syncthreads();
     if (bad) return;
-    if (t < BW) {
-      double q = 0.0;
-      for (int h = 0; h < G; ++h) q += xch[h][t];
-      sx[t] = q;
+    double sxx = 0.0, sxc = 0.0;
+    for (int h = 0; h < G; ++h) {
+      sxx += xch[h][j];
+      sxc += xch[h][col];
     }
-    __syncthreads();
-    const double sxx = sx[j], x0 = tp[j];
+    const double x0 = tp[j];
     const double nrm = sqrt(sxx);
     const double alpha = x0 >= 0.0 ? -nrm : nrm;
     const double vtv = 2.0 * (sxx - alpha * x0);  // (x0 - alpha)^2 + sum_{r > j} x_r^2
     const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
     const double v0 = x0 - alpha;
     if (col > j) {
-      const double f = beta * (sx[col] - alpha * tp[col]);  // beta v^T a
-      for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+      const double f = beta * (sxc - alpha * tp[col]);  // beta v^T a
+#pragma unroll
+      for (int i = 0; i < BP_RPT; ++i) {
         const int sr = rg + BP_RG * i, r = rbase + sr;
         if (r >= j) {
           const double v = r == j ? v0 : S[sr][j];
           S[sr][col] = fma(-f, v, S[sr][col]);
         }
       }
+    } else if (col == j && g == 0 && rg == j % BP_RG) {
+      // v_j's first entry (no thread reads S[j][j] during this step: the update uses v0)
+      S[j][j] = beta > 0.0 ? v0 : 0.0;
     }
     if (t == 0) {
       rd[j] = beta > 0.0 ? alpha : x0;  // R[j][j] (a zero column below j keeps x0)
       bt[j] = beta;
     }
     __syncthreads();
-    if (g == 0 && t == 0) S[j][j] = beta > 0.0 ? v0 : 0.0;  // v_j's first entry
-    __syncthreads();
   }
   // V (zero above the diagonal, and the whole column when beta_j = 0) and the reduced panel:
-  // R on and above the diagonal, zeros below
-  for (int i = 0; i < BP_ROWS / BP_RG; ++i) {
+  // R on and above the diagonal, zeros below.  Slab rows past the panel stay zero.
+#pragma unroll
+  for (int i = 0; i < BP_RPT; ++i) {
     const int sr = rg + BP_RG * i, r = rbase + sr;
     if (r >= w) continue;
     const double x = S[sr][col];
@@ -212,19 +223,23 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     S[sr][col] = vv;
   }
   __syncthreads();
-  // this workgroup's part of V^T V
-  for (int e = t; e < BW * BW; e += BP_NT) {
-    const int u = e >> 6, v = e & 63;
-    double q = 0.0;
-    for (int sr = 0; sr < BP_ROWS; ++sr) q = fma(S[sr][u], S[sr][v], q);
-    bst(&gpart[(size_t)g * BW * BW + e], q);
+  {  // this workgroup's part of V^T V on the matrix cores: wavefront q computes the 16 x 16 tile
+     // (q / 4, q % 4) over the 256 slab rows
+    const int q = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+    const int u0 = (q >> 2) * 16, w0 = (q & 3) * 16;
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < BP_ROWS; k0 += 4) acc = mfma16(S[k0 + lk][u0 + li], S[k0 + lk][w0 + li], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      bst(&gpart[(size_t)g * BW * BW + (size_t)(u0 + mfma_row<double>(lk, v)) * BW + w0 + li], acc[v]);
   }
   __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
   __syncthreads();
   if (t == 0) bst(&gflag[g], 1.0);
   if (g != 0) return;
-  // T by the forward recurrence, in workgroup 0: Gm = V^T V summed over the workgroups in
-  // order, then column j of T from columns 0 .. j-1
+  // T in workgroup 0 from Gm = V^T V (the workgroups' parts summed in order) by recursive
+  // doubling: for V = [V1 V2], T = [T1 T12; 0 T2] with T12 = -T1 (V1^T V2) T2, over blocks of
+  // 1, 2, ..., 32 columns (the product of the reflectors is I - V T V^T)
   if (t < G) {
     double y;
     if (!bwait(&gflag[t], &y, a.err)) {
@@ -234,22 +249,35 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   }
   __syncthreads();
   if (bad) return;
-  double(*Gm)[BW + 1] = S;  // rows 0..63 of the slab buffer
-  double(*Tm)[BW + 1] = S + BW;  // rows 64..127
+  double(*Gm)[BW + 1] = S;           // rows 0..63 of the slab buffer
+  double(*Tm)[BW + 1] = S + BW;      // rows 64..127
+  double(*Wm)[BW + 1] = S + 2 * BW;  // rows 128..191
   for (int e = t; e < BW * BW; e += BP_NT) {
+    double v[BP_MAXG];
+#pragma unroll
+    for (int h = 0; h < BP_MAXG; ++h) v[h] = h < G ? bld(&gpart[(size_t)h * BW * BW + e]) : 0.0;
     double q = 0.0;
-    for (int h = 0; h < G; ++h) q += bld(&gpart[(size_t)h * BW * BW + e]);
+#pragma unroll
+    for (int h = 0; h < BP_MAXG; ++h)
+      if (h < G) q += v[h];
     Gm[e >> 6][e & 63] = q;
-    Tm[e >> 6][e & 63] = 0.0;
+    Tm[e >> 6][e & 63] = (e >> 6) == (e & 63) ? bt[e & 63] : 0.0;
   }
   __syncthreads();
-  for (int j = 0; j < BW; ++j) {
-    if (t < j) {
+  for (int b = 1; b < BW; b *= 2) {
+    const int nout = (BW / (2 * b)) * b * b;
+    for (int e = t; e < nout; e += BP_NT) {  // W = (V1^T V2) T2 (T2 upper triangular)
+      const int o = 2 * b * (e / (b * b)), i = (e % (b * b)) / b, jj = e % b;
       double q = 0.0;
-      for (int l = t; l < j; ++l) q = fma(Tm[t][l], Gm[l][j], q);
-      Tm[t][j] = -bt[j] * q;
-    } else if (t == j) {
-      Tm[j][j] = bt[j];
+      for (int l = 0; l <= jj; ++l) q = fma(Gm[o + i][o + b + l], Tm[o + b + l][o + b + jj], q);
+      Wm[o + i][jj] = q;
+    }
+    __syncthreads();
+    for (int e = t; e < nout; e += BP_NT) {  // T12 = -T1 W (T1 upper triangular)
+      const int o = 2 * b * (e / (b * b)), i = (e % (b * b)) / b, jj = e % b;
+      double q = 0.0;
+      for (int l = i; l < b; ++l) q = fma(Tm[o + i][o + l], Wm[o + l][jj], q);
+      Tm[o + i][o + b + jj] = -q;
     }
     __syncthreads();
   }

@@ -131,7 +131,7 @@ def measured_mfma_peak(prec):
 
 
 FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "hess_uinv",
-                "band_panel", "band_update", "band_lu_panel", "band_lu_rows")
+                "band_panel", "band_update", "band_lu_panel", "band_lu_rows", "qgemm")
 
 
 def kernel_table(prof, steps, prec):
@@ -334,7 +334,7 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
     if name in FLOP_KERNELS:
         achieved = q["work"] / (q["total_ms"] * 1e-3) / 1e12
         # the band reduction is FP64 in either form; the band LU runs in the factor precision
-        peak = PEAK_FP64_TFLOPS if (prec == "fp64" or name == "band_update") else PEAK_FP32_TFLOPS
+        peak = PEAK_FP64_TFLOPS if (prec == "fp64" or name in ("band_update", "qgemm")) else PEAK_FP32_TFLOPS
         out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],

@@ -108,9 +108,9 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 // Workgroup g holds panel rows [256 g, 256 g + 256) (local to the panel: row r is row c + r of
 // A) in LDS; thread t works on column t % 64 and rows t / 64 + 16 i.  Per reflection step j each
 // workgroup publishes its column dot products (and workgroup 0 the panel's row j) into the
-// step's slots, then waits for all of them; every thread sums the published values it needs in
-// workgroup order, so all threads of all workgroups derive bitwise-equal reflectors.  Three
-// barriers per step: after the local dot products, after the exchange, after the update.
+// step's slots, then waits for all of them; wavefront 0 sums the published values in workgroup
+// order, so all workgroups derive bitwise-equal reflectors.  Four barriers per step: after the
+// local dot products, after the exchange, after the sums, after the update.
 static constexpr int BP_NT = 1024, BP_RG = BP_NT / BW;  // threads, row groups
 static constexpr int BP_RPT = BP_ROWS / BP_RG;          // rows per thread
 static_assert(BP_MAXG <= BP_RG, "one exchange slot per row group");
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   __shared__ double S[BP_ROWS][BW + 1];
   __shared__ double red[BP_RG][BW];
   __shared__ double xch[BP_MAXG][BW];
-  __shared__ double tp[BW], rd[BW], bt[BW];
+  __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
   __shared__ int bad;
   const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
   const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
@@ -179,12 +179,13 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
     }
     __syncthreads();
     if (bad) return;
-    double sxx = 0.0, sxc = 0.0;
-    for (int h = 0; h < G; ++h) {
-      sxx += xch[h][j];
-      sxc += xch[h][col];
+    if (t < BW) {
+      double q = 0.0;
+      for (int h = 0; h < G; ++h) q += xch[h][t];
+      sx[t] = q;
     }
-    const double x0 = tp[j];
+    __syncthreads();
+    const double sxx = sx[j], sxc = sx[col], x0 = tp[j];
     const double nrm = sqrt(sxx);
     const double alpha = x0 >= 0.0 ? -nrm : nrm;
     const double vtv = 2.0 * (sxx - alpha * x0);  // (x0 - alpha)^2 + sum_{r > j} x_r^2

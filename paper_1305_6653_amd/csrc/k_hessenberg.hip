@@ -556,113 +556,139 @@ hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, 
 // ------------------------------------------------------------------------------------
 // Y[k][j] = sum_{i<m} X[k][i] B[i][j] with B = Q (trans = 0) or Q^T (trans = 1), both stored
 // row-major with leading dimension mp; X, Y are [nb][mp] complex; Y[k][j] = 0 for j >= m.
-// Workgroup tile 32 (k) x 32 (j), split over K: wave w accumulates the whole tile (2 x 2 MFMA
-// 16x16 tiles, real and imaginary parts sharing the B operand) over the w-th quarter of K,
-// with the operands of four K-steps loaded ahead; the four partial tiles are summed through
-// LDS in wave order.  Item = (instance, row tile, column tile).
-static constexpr int QG_T = 32;
+// As a real product its rows are the real and imaginary parts of the bins 1 .. s/2 - 1 and the
+// real parts of bins 0 and s/2, paired in slot 0: the imaginary parts of those two bins never
+// reach the preconditioner's result (the inverse time FFT of a real vector discards them), so
+// they are not read and are written as 0.  That is s real rows.
+// Workgroup tile: 32 slots (64 real rows) x 64 columns over the whole K range.  Wavefronts 0-3
+// take the even 16-deep K slices and 4-7 the odd ones, each a 32 x 32 quarter of the tile
+// (2 x 2 FP64 MFMA 16x16x4 tiles), staged through LDS one slice ahead; the two halves are
+// summed at the end in a fixed order.  Consecutive workgroups run on different XCDs; the slot
+// tiles of one column tile go to the same XCD, so its L2 serves their common B columns.
+// Item = (instance, slot tile, column tile).
+static constexpr int QG_NT = 512, QG_KS = 16;
 
-__global__ __launch_bounds__(256) void k_qgemm(const InstDesc *__restrict__ Dd, ItemMap map,
-                                               int trans, int src2) {
-  __shared__ v4d part[3][8][64];
+__global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd, ItemMap map,
+                                                 int trans, int src2) {
+  __shared__ double As[2][2][QG_KS][64 + 1];  // [K half][buffer][k][real row]
+  __shared__ double Bs[2][2][QG_KS][64 + 1];  // [K half][buffer][k][column]
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int local = blockIdx.x - map.pre[q];
-  const int m = d.m, mp = d.mp, nb = d.nb;
-  const int ncol = mp / QG_T, nrow = (nb + QG_T - 1) / QG_T;
-  // consecutive workgroups go to different XCDs: give XCD x the column tiles ct = x mod 8, so
-  // each XCD's L2 holds an eighth of B (when the column tiles split evenly)
+  const int m = d.m, mp = d.mp, nb = d.nb, ns = nb - 1;
+  const int ncol = mp / 64, nrt = (ns + 31) / 32;
   int rt, ct;
   if (ncol % 8 == 0) {
-    const int x = local % 8, r = local / 8;
-    ct = x + 8 * (r / nrow);
-    rt = r % nrow;
+    ct = 8 * ((local / 8) / nrt) + local % 8;
+    rt = (local / 8) % nrt;
   } else {
     rt = local / ncol;
     ct = local % ncol;
   }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = rt * QG_T, c0 = ct * QG_T;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int kh = wv >> 2, wr = ((wv & 3) >> 1) * 32, wc = (wv & 1) * 32, ht = tid & 255;
   const double2 *X = src2 ? d.Vts : d.Vh;
   double2 *Y = src2 ? d.Vh : d.Vts;
   const double *B = trans ? d.hQt : d.hQ;
-  const int li = lane & 15, lk = lane >> 4;
-  const int ar0 = r0 + li, ar1 = r0 + 16 + li;  // A rows of this lane (two 16-row halves)
-  const int bc0 = c0 + li, bc1 = c0 + 16 + li;  // B columns of this lane
-  const bool a0ok = ar0 < nb, a1ok = ar1 < nb, b0ok = bc0 < m, b1ok = bc1 < m;
-  const double2 *X0 = X + (size_t)(a0ok ? ar0 : 0) * mp, *X1 = X + (size_t)(a1ok ? ar1 : 0) * mp;
-  v4d acc[8];
+  const int s0 = rt * 32, c0 = ct * 64;
+  // loaders (per K half): A slot ht / 8 at k pair 2 (ht % 8); B row ht / 16 at columns 4 (ht % 16)
+  const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 2, bk = ht >> 4, bc = (ht & 15) * 4;
+  const bool aok = aslot < ns;
+  const double2 *Xa = X + (size_t)(aok ? aslot : 0) * mp, *Xn = X + (size_t)ns * mp;
+  double2 ra[2], rb[2];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-  // this wave's K range; 16 K values per operand set, two sets in flight (loaded one set
-  // ahead of the MFMAs that use the other)
-  const int kq = ((m + 63) / 64) * 16;
-  const int kb = wv * kq, ke = kb + kq < m ? kb + kq : m;
-  double2 pa0[4], pa1[4], qa0[4], qa1[4];
-  double pb0[4], pb1[4], qb0[4], qb1[4];
-#define QG_LOAD(A0, A1, B0, B1, K0)                                               \
-  _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                             \
-    const int kk = (K0) + 4 * s4 + lk;                                           \
-    const bool kok = kk < ke;                                                    \
-    A0[s4] = (kok && a0ok) ? X0[kk] : make_double2(0.0, 0.0);                    \
-    A1[s4] = (kok && a1ok) ? X1[kk] : make_double2(0.0, 0.0);                    \
-    B0[s4] = (kok && b0ok) ? B[(size_t)kk * mp + bc0] : 0.0;                     \
-    B1[s4] = (kok && b1ok) ? B[(size_t)kk * mp + bc1] : 0.0;                     \
-  }
-#define QG_MMA(A0, A1, B0, B1)                                                    \
-  _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                             \
-    acc[0] = mfma16(A0[s4].x, B0[s4], acc[0]);                                   \
-    acc[1] = mfma16(A0[s4].y, B0[s4], acc[1]);                                   \
-    acc[2] = mfma16(A0[s4].x, B1[s4], acc[2]);                                   \
-    acc[3] = mfma16(A0[s4].y, B1[s4], acc[3]);                                   \
-    acc[4] = mfma16(A1[s4].x, B0[s4], acc[4]);                                   \
-    acc[5] = mfma16(A1[s4].y, B0[s4], acc[5]);                                   \
-    acc[6] = mfma16(A1[s4].x, B1[s4], acc[6]);                                   \
-    acc[7] = mfma16(A1[s4].y, B1[s4], acc[7]);                                   \
-  }
-  QG_LOAD(pa0, pa1, pb0, pb1, kb)
-  for (int k0 = kb; k0 < ke; k0 += 32) {
-    QG_LOAD(qa0, qa1, qb0, qb1, k0 + 16)
-    QG_MMA(pa0, pa1, pb0, pb1)
-    QG_LOAD(pa0, pa1, pb0, pb1, k0 + 32)
-    QG_MMA(qa0, qa1, qb0, qb1)
-  }
-#undef QG_LOAD
-#undef QG_MMA
-  if (wv > 0) {
+    for (int u = 0; u < 2; ++u) {
+      const int k = k0 + ak + u;
+      double2 v = make_double2(0.0, 0.0);
+      if (aok && k < m) {
+        v = Xa[k];
+        if (aslot == 0) v.y = Xn[k].x;  // slot 0: real parts of bins 0 and s/2
+      }
+      ra[u] = v;
+    }
+    const int k = k0 + bk;
+    const double2 *pb = reinterpret_cast<const double2 *>(B + (size_t)(k < m ? k : 0) * mp + c0 + bc);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) part[wv - 1][t][lane] = acc[t];
-  }
+    for (int u = 0; u < 2; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      As[kh][buf][ak + u][2 * as] = ra[u].x;
+      As[kh][buf][ak + u][2 * as + 1] = ra[u].y;
+    }
+    Bs[kh][buf][bk][bc] = rb[0].x;
+    Bs[kh][buf][bk][bc + 1] = rb[0].y;
+    Bs[kh][buf][bk][bc + 2] = rb[1].x;
+    Bs[kh][buf][bk][bc + 3] = rb[1].y;
+  };
+  v4d acc[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int npair = (m + 2 * QG_KS - 1) / (2 * QG_KS);  // slice pairs covering K = m
+  load(kh * QG_KS);
+  stage(0);
   __syncthreads();
-  if (wv == 0) {
+  for (int p = 0; p < npair; ++p) {
+    const int buf = p & 1;
+    if (p + 1 < npair) load((2 * (p + 1) + kh) * QG_KS);
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int kk = 0; kk < QG_KS; kk += 4) {
+      double av[2], bv[2];
 #pragma unroll
-      for (int w = 0; w < 3; ++w) acc[t] += part[w][t][lane];
-    // acc[2*(2h + c) + p]: row half h, column half c, real (p = 0) or imaginary part; element v
-    // of this lane is row lk + 4v, column li of the 16x16 tile (FP64 layout)
+      for (int r = 0; r < 2; ++r) av[r] = As[kh][buf][kk + lk][wr + 16 * r + li];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+      for (int c = 0; c < 2; ++c) bv[c] = Bs[kh][buf][kk + lk][wc + 16 * c + li];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[r][c] = mfma16(av[r], bv[c], acc[r][c]);
+    }
+    if (p + 1 < npair) stage(buf ^ 1);
+    __syncthreads();
+  }
+  // the odd-slice half hands its quarters to the even-slice half (As reused as 64 x 64)
+  double *part = &As[0][0][0][0];
+  if (kh == 1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 16 * h + mfma_row<double>(lk, v), col = c0 + 16 * c + li;
-          if (row < nb && col < mp) {
-            const v4d re = acc[2 * (2 * h + c)], im = acc[2 * (2 * h + c) + 1];
-            Y[(size_t)row * mp + col] = col < m ? make_double2(re[v], im[v]) : make_double2(0.0, 0.0);
-          }
-        }
+        for (int v = 0; v < 4; ++v)
+          part[(wr + 16 * r + mfma_row<double>(lk, v)) * 64 + wc + 16 * c + li] = acc[r][c][v];
   }
+  __syncthreads();
+  if (kh == 1) return;
+  double *Yd = reinterpret_cast<double *>(Y);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * r + mfma_row<double>(lk, v), col = c0 + wc + 16 * c + li;
+        const int slot = s0 + (row >> 1), im = row & 1;
+        if (slot >= ns) continue;
+        double val = acc[r][c][v] + part[row * 64 + wc + 16 * c + li];
+        if (col >= m) val = 0.0;
+        if (slot == 0)
+          Y[(size_t)(im ? ns : 0) * mp + col] = make_double2(val, 0.0);
+        else
+          Yd[((size_t)slot * mp + col) * 2 + im] = val;
+      }
 }
 
-int qgemm_items(int nb, int mp) { return ((nb + QG_T - 1) / QG_T) * (mp / QG_T); }
+int qgemm_items(int nb, int mp) { return ((nb - 1 + 31) / 32) * (mp / 64); }
 
 hipError_t launch_qgemm(const InstDesc *D, const ItemMap &map, int items, int trans, int src2,
                         hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qgemm, dim3(items), dim3(256), 0, st, D, map, trans, src2);
+  hipLaunchKernelGGL(k_qgemm, dim3(items), dim3(QG_NT), 0, st, D, map, trans, src2);
   return hipGetLastError();
 }
 

@@ -351,7 +351,7 @@ struct SolveMaps {
   int tfft_cols = 16;  // spatial columns per time-FFT workgroup
   int npan_u = 0;      // panels per block if every instance has the same count, else 0
   int prec = -1;
-  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_bytes = 0, band_l_bytes = 0;
+  double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_flops = 0, band_l_bytes = 0;
 };
 
 // The same maps with their items skipped for instances whose gate entry is zero.
@@ -1693,7 +1693,7 @@ static fde_status ensure_full_maps(Plan *P) {
     const double fac = h->blk_route != FDE_BLOCKS_LU ? 0.5 * h->m * (h->m + 1.0)
                                                              : (double)h->m * h->m;
     S.trsv_bytes += (double)h->nb * fac * esz + 32.0 * h->nb * h->m;
-    S.qg_bytes += 8.0 * h->m * h->m + 32.0 * h->nb * h->m;  // Q once, X in and Y out
+    S.qg_flops += 2.0 * (2.0 * (h->nb - 1)) * h->m * h->m;  // 2 (nb - 1) real rows times Q
     S.vec_bytes += 8.0 * h->n();
     S.tfft_bytes += 8.0 * h->n() + 16.0 * h->nb * h->m;
     S.bccb_bytes += 32.0 * h->nb * h->m;  // one complex read and write per (frequency, node)
@@ -1799,7 +1799,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
   }));
   if (S.route == FDE_BLOCKS_BAND) {
     // Q^T v_k (the frequency vectors are rows: the row v_k^T Q), the band L solve, U^{-1}, Q
-    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
+    HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
     HIPCHK(run(L, "band_lsolve", S.band_l_bytes, [&] {
       return S.prec == FDE_FP64 ? launch_band_lsolve<double>(P->d_desc, S.blk, S.n_blk, st)
                                 : launch_band_lsolve<float>(P->d_desc, S.blk, S.n_blk, st);
@@ -1812,7 +1812,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
                  : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
                                            &S.blk, S.n_blk, S.npan_u);
     }));
-    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
+    HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
       return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
     }));
@@ -1821,7 +1821,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
   if (S.route == FDE_BLOCKS_HESSENBERG) {
     // Q^T v_k, the row exchanges and eliminations, U^{-1}, then Q (the frequency vectors are
     // rows, so Q^T v_k is the row v_k^T Q)
-    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
+    HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 0, 0, st); }));
     HIPCHK(run(L, "hess_lsolve", S.bccb_bytes, [&] {
       return launch_hess_lsolve(P->d_desc, S.blk, S.n_blk, S.max_mp, st);
     }));
@@ -1833,7 +1833,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
                  : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
                                            &S.blk, S.n_blk, S.npan_u);
     }));
-    HIPCHK(run(L, "qgemm", S.qg_bytes, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
+    HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
       return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
     }));

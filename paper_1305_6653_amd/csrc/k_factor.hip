@@ -1316,14 +1316,15 @@ __device__ __forceinline__ void gemm64_win(const c_t<T> *__restrict__ A, int lda
       }
 }
 
-// Item = (instance, block, tile t < npan - j - 1): columns c0 = 64 (j + 1 + t) .. of the window.
+// Item = (instance, block, tile t0 <= t < min(t1, npan - j - 1)): columns c0 = 64 (j + 1 + t) ..
+// of the window.
 //   half 1 (launched first): block row j + 1 <- bottom - M21 top       (K block row j + 1)
 //   half 0:                  block row j     <- L11^{-1} top = U12      (K block row j, in place)
 // Half 1 reads block row j before half 0 replaces it; within half 0 each workgroup reads its
 // own tile completely before it stores it.
 template <typename T>
 __global__ __launch_bounds__(256, 3) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j,
-                                                         int half) {
+                                                         int half, int t0, int t1) {
   typedef c_t<T> C;
   __shared__ GemmLds<T> sm;
   const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
@@ -1331,8 +1332,9 @@ __global__ __launch_bounds__(256, 3) void k_band_lu_rows(const InstDesc *__restr
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
   const int mp = d.mp, npan = d.npan, nrem = npan - j - 1;
+  const int ntile = (t1 < nrem ? t1 : nrem) - t0;
   const int local = item - map.pre[q];
-  const int blk = local / nrem, tt = local % nrem;
+  const int blk = local / ntile, tt = t0 + local % ntile;
   const int r0 = j * PB, c0 = (j + 1 + tt) * PB, tid = threadIdx.x;
   C *K = (C *)d.K + (size_t)blk * mp * mp;
   BandWin<T> win;
@@ -1484,12 +1486,13 @@ hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items
 }
 
 template <typename T>
-hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st) {
+hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, int t0, int t1,
+                               hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 1);
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 1, t0, t1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 0);
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 0, t0, t1);
   return hipGetLastError();
 }
 
@@ -1559,7 +1562,7 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                                           hipStream_t);                                         \
   template hipError_t launch_band_lu_panel<T>(const InstDesc *, const ItemMap &, int, int, int *,  \
                                               hipStream_t);                                     \
-  template hipError_t launch_band_lu_rows<T>(const InstDesc *, const ItemMap &, int, int,          \
+  template hipError_t launch_band_lu_rows<T>(const InstDesc *, const ItemMap &, int, int, int, int, \
                                              hipStream_t);                                      \
   template hipError_t launch_band_lsolve<T>(const InstDesc *, const ItemMap &, int, hipStream_t);   \
   template int trsv_coop_capacity<T>();

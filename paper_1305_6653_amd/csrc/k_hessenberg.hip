@@ -561,12 +561,12 @@ hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, 
 // reach the preconditioner's result (the inverse time FFT of a real vector discards them), so
 // they are not read and are written as 0.  That is s real rows.
 // Workgroup tile: 32 slots (64 real rows) x 64 columns over the whole K range.  Wavefronts 0-3
-// take the even 16-deep K slices and 4-7 the odd ones, each a 32 x 32 quarter of the tile
+// take the even 32-deep K slices and 4-7 the odd ones, each a 32 x 32 quarter of the tile
 // (2 x 2 FP64 MFMA 16x16x4 tiles), staged through LDS one slice ahead; the two halves are
 // summed at the end in a fixed order.  Consecutive workgroups run on different XCDs; the slot
 // tiles of one column tile go to the same XCD, so its L2 serves their common B columns.
 // Item = (instance, slot tile, column tile).
-static constexpr int QG_NT = 512, QG_KS = 16;
+static constexpr int QG_NT = 512, QG_KS = 32;
 
 __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd, ItemMap map,
                                                  int trans, int src2) {
@@ -592,14 +592,14 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
   double2 *Y = src2 ? d.Vh : d.Vts;
   const double *B = trans ? d.hQt : d.hQ;
   const int s0 = rt * 32, c0 = ct * 64;
-  // loaders (per K half): A slot ht / 8 at k pair 2 (ht % 8); B row ht / 16 at columns 4 (ht % 16)
-  const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 2, bk = ht >> 4, bc = (ht & 15) * 4;
+  // loaders (per K half): A slot ht / 8 at k 4 (ht % 8) .. + 3; B row ht / 8 at columns 8 (ht % 8) .. + 7
+  const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 4, bk = ht >> 3, bc = (ht & 7) * 8;
   const bool aok = aslot < ns;
   const double2 *Xa = X + (size_t)(aok ? aslot : 0) * mp, *Xn = X + (size_t)ns * mp;
-  double2 ra[2], rb[2];
+  double2 ra[4], rb[4];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const int k = k0 + ak + u;
       double2 v = make_double2(0.0, 0.0);
       if (aok && k < m) {
@@ -611,18 +611,16 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
     const int k = k0 + bk;
     const double2 *pb = reinterpret_cast<const double2 *>(B + (size_t)(k < m ? k : 0) * mp + c0 + bc);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 4; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < 4; ++u) {
       As[kh][buf][ak + u][2 * as] = ra[u].x;
       As[kh][buf][ak + u][2 * as + 1] = ra[u].y;
+      Bs[kh][buf][bk][bc + 2 * u] = rb[u].x;
+      Bs[kh][buf][bk][bc + 2 * u + 1] = rb[u].y;
     }
-    Bs[kh][buf][bk][bc] = rb[0].x;
-    Bs[kh][buf][bk][bc + 1] = rb[0].y;
-    Bs[kh][buf][bk][bc + 2] = rb[1].x;
-    Bs[kh][buf][bk][bc + 3] = rb[1].y;
   };
   v4d acc[2][2];
 #pragma unroll

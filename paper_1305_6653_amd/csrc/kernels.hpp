@@ -145,12 +145,14 @@ hipError_t launch_band_panel(int mp, int p, double *AQ, double *work, int *err, 
 hipError_t launch_band_update(int mp, int p, double *AQ, double *work, hipStream_t st);
 hipError_t launch_band_finish(int mp, double *AQ, double *Qt, hipStream_t st);
 // step j of the pivoted band LU: item = (instance, block) for the panel, (instance, block, tile)
-// with npan - j - 1 tiles per block for the rows; permutations in hpiv [nb][npan][128]
+// for the rows, tiles t0 <= t < min(t1, npan - j - 1) of each block; permutations in hpiv
+// [nb][npan][128]
 template <typename T>
 hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items, int j, int *flag,
                                 hipStream_t st);
 template <typename T>
-hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, hipStream_t st);
+hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, int t0, int t1,
+                               hipStream_t st);
 // item = (instance, block): y <- L^{-1} P y on Vts in place
 template <typename T>
 hipError_t launch_band_lsolve(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);

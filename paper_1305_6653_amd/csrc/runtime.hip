@@ -164,6 +164,10 @@ struct fde_bvm {
   bool need_Ju0 = false;
   // ---- device
   hipStream_t stream = nullptr, own_stream = nullptr;
+  // second stream of the band LU's look-ahead (the next panel beside the current row updates),
+  // with the two events that order it against the first; created on first use
+  hipStream_t side_stream = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
   std::vector<void *> allocs;
   double *d_g = nullptr, *d_dp = nullptr, *d_dm = nullptr, *d_cG = nullptr;
   double2 *d_chat = nullptr, *d_twL = nullptr, *d_tws = nullptr, *d_lam = nullptr, *d_mu = nullptr;
@@ -921,6 +925,12 @@ static void destroy_handle(fde_bvm *h) {
     }
   for (auto e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  if (h->side_stream) {
+    (void)hipStreamSynchronize(h->side_stream);
+    (void)hipStreamDestroy(h->side_stream);
+  }
+  for (hipEvent_t &e : h->side_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -1502,33 +1512,60 @@ static fde_status band_factor(Plan *P) {
     }
     HIPCHK(run(L, "band_finish", 16.0 * mp * mp, [&] { return launch_band_finish(mp, h->d_bAQ, h->d_bQt, st); }));
   }
+  // Step j of the LU: panel j, then the row tiles of step j.  Look-ahead: the first row tile
+  // (block column j + 1, all the next panel reads) runs first on the main stream; panel j + 1
+  // then runs on the side stream while the other row tiles of step j run on the main stream
+  // (they touch block rows j and j + 1 at block columns >= j + 2 only); the main stream waits
+  // for the panel before step j + 1.
   std::vector<int> slots(count), it(count);
   for (int i = 0; i < count; ++i) slots[i] = i;
   std::vector<HostMap> hm;
   for (int j = 0; j < maxpan; ++j) {
     for (int i = 0; i < count; ++i) it[i] = j < P->hs[i]->npan ? P->hs[i]->nb : 0;
     hm.push_back(make_map(slots, it));  // panel j
-    for (int i = 0; i < count; ++i) it[i] = std::max(0, P->hs[i]->npan - j - 1) * P->hs[i]->nb;
-    hm.push_back(make_map(slots, it));  // row tiles j
+    for (int i = 0; i < count; ++i) it[i] = P->hs[i]->npan - j - 1 >= 1 ? P->hs[i]->nb : 0;
+    hm.push_back(make_map(slots, it));  // row tile 0 of step j
+    for (int i = 0; i < count; ++i) it[i] = std::max(0, P->hs[i]->npan - j - 2) * P->hs[i]->nb;
+    hm.push_back(make_map(slots, it));  // row tiles 1 .. of step j
   }
   std::vector<ItemMap> dm;
   STCHK(upload_maps(P, hm, dm));
-  TraceRange tr("band LU of the shifted blocks");
-  for (int j = 0; j < maxpan; ++j) {
-    // algorithmic flops (complex multiply-add = 8 real flops): the 128 x 64 panel LU, and per
-    // tile of the trailing width the two 64 x 64 x 64 products
-    double wp = 0.0, wr = 0.0;
+  if (!L->side_stream) {
+    HIPCHK(hipStreamCreateWithFlags(&L->side_stream, hipStreamNonBlocking));
+    for (hipEvent_t &e : L->side_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  hipStream_t ss = L->side_stream;
+  // algorithmic flops (complex multiply-add = 8 real flops): the 128 x 64 panel LU, and per
+  // tile of the trailing width the two 64 x 64 x 64 products
+  auto panel_work = [&](int j) {
+    double w = 0.0;
     for (fde_bvm *h : P->hs) {
       if (j >= h->npan) continue;
       const double nr = j + 1 < h->npan ? 128.0 : 64.0;
-      wp += h->nb * 8.0 * 64.0 * 64.0 * (nr - 64.0 / 3.0) / 2.0;
-      wr += h->nb * std::max(0, h->npan - j - 1) * 2.0 * 8.0 * 64.0 * 64.0 * 64.0;
+      w += h->nb * 8.0 * 64.0 * 64.0 * (nr - 64.0 / 3.0) / 2.0;
     }
-    const size_t ip = 2 * j, ir = 2 * j + 1;
-    if (hm[ip].items > 0)
-      HIPCHK(run(L, "band_lu_panel", wp, [&] { return launch_band_lu_panel<T>(P->d_desc, dm[ip], hm[ip].items, j, P->d_flag, st); }));
-    if (hm[ir].items > 0)
-      HIPCHK(run(L, "band_lu_rows", wr, [&] { return launch_band_lu_rows<T>(P->d_desc, dm[ir], hm[ir].items, j, st); }));
+    return w;
+  };
+  auto rows_work = [&](size_t mi) { return hm[mi].items * 2.0 * 8.0 * 64.0 * 64.0 * 64.0; };
+  TraceRange tr("band LU of the shifted blocks");
+  if (hm[0].items > 0)
+    HIPCHK(run(L, "band_lu_panel", panel_work(0), [&] { return launch_band_lu_panel<T>(P->d_desc, dm[0], hm[0].items, 0, P->d_flag, st); }));
+  for (int j = 0; j < maxpan; ++j) {
+    const size_t i0 = 3 * j + 1, i1 = 3 * j + 2, ip = 3 * (j + 1);
+    if (hm[i0].items > 0)
+      HIPCHK(run(L, "band_lu_rows", rows_work(i0), [&] { return launch_band_lu_rows<T>(P->d_desc, dm[i0], hm[i0].items, j, 0, 1, st); }));
+    const bool ahead = j + 1 < maxpan && hm[ip].items > 0;
+    if (ahead) {
+      HIPCHK(hipEventRecord(L->side_ev[0], st));
+      HIPCHK(hipStreamWaitEvent(ss, L->side_ev[0], 0));
+      HIPCHK(run(L, "band_lu_panel", panel_work(j + 1), [&] {
+        return launch_band_lu_panel<T>(P->d_desc, dm[ip], hm[ip].items, j + 1, P->d_flag, ss);
+      }, ss));
+      HIPCHK(hipEventRecord(L->side_ev[1], ss));
+    }
+    if (hm[i1].items > 0)
+      HIPCHK(run(L, "band_lu_rows", rows_work(i1), [&] { return launch_band_lu_rows<T>(P->d_desc, dm[i1], hm[i1].items, j, 1, 1 << 30, st); }));
+    if (ahead) HIPCHK(hipStreamWaitEvent(st, L->side_ev[1], 0));
   }
   return FDE_OK;
 }

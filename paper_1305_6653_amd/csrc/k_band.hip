@@ -13,9 +13,9 @@
 //   k_band_panel   the w x 64 block A[c:, 64p:c] is reduced to upper triangular form by 64
 //                  Householder reflections H_j = I - beta_j v_j v_j^T (the sign choice of the
 //                  textbook reflector, alpha = -sign(x_0) |x|), accumulated in compact WY form
-//                  H_0 ... H_63 = I - V T V^T (T upper triangular, by the forward recurrence
-//                  T[0:j, j] = -beta_j T[0:j, 0:j] V[:, 0:j]^T v_j).  Cooperative: workgroup g
-//                  holds 256 rows of the block in LDS; per reflection one exchange of the
+//                  H_0 ... H_63 = I - V T V^T (T upper triangular, from V^T V by recursive
+//                  doubling: T = [T1 -T1 V1^T V2 T2; 0 T2]).  Cooperative: workgroup g
+//                  holds 128 rows of the block in LDS; per reflection one exchange of the
 //                  column dot products x^T a between the workgroups (all of them at once, before
 //                  the reflector is known: v^T a = x^T a - alpha a_0 and v^T v = 2 (x^T x -
 //                  alpha x_0)).
@@ -33,8 +33,8 @@
 namespace fde {
 
 static constexpr int BW = 64;           // bandwidth = panel width
-static constexpr int BP_ROWS = 256;     // rows of the panel per workgroup
-static constexpr int BP_MAXG = 16;      // workgroups of a panel reduction (mp <= 4096)
+static constexpr int BP_ROWS = 128;     // rows of the panel per workgroup
+static constexpr int BP_MAXG = 32;      // workgroups of a panel reduction (mp <= 4096)
 static constexpr int BP_SPIN_MAX = 1 << 21;
 
 __device__ __forceinline__ void bst(double *p, double v) {
@@ -105,7 +105,7 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 }
 
 // ---- panel reduction (cooperative) ---------------------------------------------------------
-// Workgroup g holds panel rows [256 g, 256 g + 256) (local to the panel: row r is row c + r of
+// Workgroup g holds panel rows [128 g, 128 g + 128) (local to the panel: row r is row c + r of
 // A) in LDS; thread t works on column t % 64 and rows t / 64 + 16 i.  Per reflection step j each
 // workgroup publishes its column dot products (and workgroup 0 the panel's row j) into the
 // step's slots, then waits for all of them; wavefront 0 sums the published values in workgroup
@@ -113,7 +113,6 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
 // local dot products, after the exchange, after the sums, after the update.
 static constexpr int BP_NT = 1024, BP_RG = BP_NT / BW;  // threads, row groups
 static constexpr int BP_RPT = BP_ROWS / BP_RG;          // rows per thread
-static_assert(BP_MAXG <= BP_RG, "one exchange slot per row group");
 // slot set layout (doubles): xpart [64 steps][BP_MAXG][64], xtop [64 steps][64], gpart
 // [BP_MAXG][64][64], gflag [BP_MAXG] (raised once a workgroup's gpart is stored)
 static constexpr size_t BP_XPART = (size_t)BW * BP_MAXG * BW, BP_XTOP = (size_t)BW * BW,
@@ -134,6 +133,7 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   __shared__ double red[BP_RG][BW];
   __shared__ double xch[BP_MAXG][BW];
   __shared__ double sx[BW], tp[BW], rd[BW], bt[BW];
+  __shared__ double tw[BW][BW + 1];  // W of the T recursion
   __shared__ int bad;
   const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, col = t & 63, rg = t >> 6;
   const int mp = a.mp, c = (a.p + 1) * BW, w = mp - c, pc = a.p * BW + col;
@@ -168,10 +168,11 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
 #pragma unroll
       for (int h = 0; h < BP_RG; ++h) q += red[h][t];
       bst(&xpart[((size_t)j * BP_MAXG + g) * BW + t], q);
-      if (g == 0) bst(&xtop[(size_t)j * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 256)
+      if (g == 0) bst(&xtop[(size_t)j * BW + t], S[j][t]);  // panel row j lies in slab 0 (j < 128)
     }
     bool ok = true;
-    if (rg < G) ok = bwait(&xpart[((size_t)j * BP_MAXG + rg) * BW + col], &xch[rg][col], a.err);
+    for (int h = rg; h < G; h += BP_RG)
+      ok = ok && bwait(&xpart[((size_t)j * BP_MAXG + h) * BW + col], &xch[h][col], a.err);
     if (t < BW) ok = ok && bwait(&xtop[(size_t)j * BW + t], &tp[t], a.err);
     if (!ok) {
       bad = 1;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   }
   __syncthreads();
   {  // this workgroup's part of V^T V on the matrix cores: wavefront q computes the 16 x 16 tile
-     // (q / 4, q % 4) over the 256 slab rows
+     // (q / 4, q % 4) over the 128 slab rows
     const int q = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
     const int u0 = (q >> 2) * 16, w0 = (q & 3) * 16;
     v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
@@ -250,9 +251,9 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
   }
   __syncthreads();
   if (bad) return;
-  double(*Gm)[BW + 1] = S;           // rows 0..63 of the slab buffer
-  double(*Tm)[BW + 1] = S + BW;      // rows 64..127
-  double(*Wm)[BW + 1] = S + 2 * BW;  // rows 128..191
+  double(*Gm)[BW + 1] = S;       // rows 0..63 of the slab buffer
+  double(*Tm)[BW + 1] = S + BW;  // rows 64..127
+  double(*Wm)[BW + 1] = tw;
   for (int e = t; e < BW * BW; e += BP_NT) {
     double v[BP_MAXG];
 #pragma unroll

@@ -293,62 +293,81 @@ __global__ __launch_bounds__(BP_NT) void k_band_panel(BandPanelArgs a) {
 // op(A)(i, k) = TA ? A[k lda + i] : A[i lda + k];  op(B)(k, j) = TB ? B[j ldb + k] : B[k ldb + j].
 // M, N multiples of 64 and kc of 16.  64 x 64 tile per workgroup; wavefront w computes the 32 x 32
 // quarter (w / 2, w % 2) as 2 x 2 products of v_mfma_f64_16x16x4f64 from 16-deep K slices
-// staged in LDS.  Fixed summation order (deterministic).
+// staged in LDS, the next slice loaded into registers while the current one is multiplied;
+// in MODE 1 the tile of C is read before the K loop.  Fixed summation order (deterministic).
 static constexpr int DG_KS = 16;
 
 template <bool TA, bool TB, int MODE>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int kc, int K, const double *__restrict__ A,
                                                int lda, const double *__restrict__ B, int ldb,
                                                double *__restrict__ C, int ldc, double alpha) {
-  __shared__ double As[DG_KS][64 + 1];  // As[k][i]
-  __shared__ double Bs[DG_KS][64 + 1];  // Bs[k][j]
+  __shared__ double As[2][DG_KS][64 + 1];  // As[buf][k][i]
+  __shared__ double Bs[2][DG_KS][64 + 1];  // Bs[buf][k][j]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
   const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double cv[2][2][4];
+  if (MODE == 1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          cv[r][c][v] = C[(size_t)(row0 + wr + 16 * r + mfma_row<double>(lk, v)) * ldc + col0 + wc + 16 * c + li];
+  }
   v4d acc[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[r][c] = v4d{0.0, 0.0, 0.0, 0.0};
+  // loader roles: op(A)[row0 .. +64][k0 .. +16] and op(B)[k0 .. +16][col0 .. +64], 4 doubles each
+  const int a_i = TA ? (tid & 15) * 4 : tid >> 2, a_k = TA ? tid >> 4 : (tid & 3) * 4;
+  const int b_k = TB ? (tid & 3) * 4 : tid >> 4, b_j = TB ? tid >> 2 : (tid & 15) * 4;
+  const double *Ap = TA ? A + (size_t)a_k * lda + row0 + a_i : A + (size_t)(row0 + a_i) * lda + a_k;
+  const double *Bp = TB ? B + (size_t)(col0 + b_j) * ldb + b_k : B + (size_t)b_k * ldb + col0 + b_j;
+  const size_t a_step = TA ? (size_t)DG_KS * lda : DG_KS, b_step = TB ? DG_KS : (size_t)DG_KS * ldb;
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+    const double *pa = Ap + (size_t)(k0 / DG_KS) * a_step, *pb = Bp + (size_t)(k0 / DG_KS) * b_step;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ra[u] = pa[u];
+      rb[u] = pb[u];
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (TA) As[buf][a_k][a_i + u] = ra[u]; else As[buf][a_k + u][a_i] = ra[u];
+      if (TB) Bs[buf][b_k + u][b_j] = rb[u]; else Bs[buf][b_k][b_j + u] = rb[u];
+    }
+  };
+  if (kb < ke) {
+    load(kb);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += DG_KS) {
-    // stage op(A)[row0 .. +64][k0 .. +16] and op(B)[k0 .. +16][col0 .. +64], 4 doubles per thread each
-    if (!TA) {
-      const int i = tid >> 2, k4 = (tid & 3) * 4;
-      const double *p = A + (size_t)(row0 + i) * lda + k0 + k4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) As[k4 + u][i] = p[u];
-    } else {
-      const int k = tid >> 4, i4 = (tid & 15) * 4;
-      const double *p = A + (size_t)(k0 + k) * lda + row0 + i4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) As[k][i4 + u] = p[u];
-    }
-    if (!TB) {
-      const int k = tid >> 4, j4 = (tid & 15) * 4;
-      const double *p = B + (size_t)(k0 + k) * ldb + col0 + j4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[k][j4 + u] = p[u];
-    } else {
-      const int j = tid >> 2, k4 = (tid & 3) * 4;
-      const double *p = B + (size_t)(col0 + j) * ldb + k0 + k4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[k4 + u][j] = p[u];
-    }
-    __syncthreads();
+    const bool more = k0 + DG_KS < ke;
+    if (more) load(k0 + DG_KS);
 #pragma unroll
     for (int kk = 0; kk < DG_KS; kk += 4) {
       double av[2], bv[2];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) av[r] = As[kk + lk][wr + 16 * r + li];
+      for (int r = 0; r < 2; ++r) av[r] = As[buf][kk + lk][wr + 16 * r + li];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) bv[c] = Bs[kk + lk][wc + 16 * c + li];
+      for (int c = 0; c < 2; ++c) bv[c] = Bs[buf][kk + lk][wc + 16 * c + li];
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[r][c] = mfma16(av[r], bv[c], acc[r][c]);
     }
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
@@ -357,12 +376,10 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int kc, int K, cons
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = row0 + wr + 16 * r + mfma_row<double>(lk, v), j = col0 + wc + 16 * c + li;
-        if (MODE == 0) {
+        if (MODE == 0)
           C[(size_t)blockIdx.z * M * N + (size_t)i * N + j] = acc[r][c][v];
-        } else {
-          double *e = C + (size_t)i * ldc + j;
-          *e = fma(alpha, acc[r][c][v], *e);
-        }
+        else
+          C[(size_t)i * ldc + j] = fma(alpha, acc[r][c][v], cv[r][c][v]);
       }
 }
 

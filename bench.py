@@ -46,7 +46,7 @@ PMC_KERNEL_GROUP = {
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
     "band_panel": "band", "band_update": "band", "band_init": "band", "band_finish": "band",
-    "band_lu_panel": "factor", "band_lu_rows": "factor", "band_lsolve": "factor",
+    "band_lu_panel": "factor", "band_lu_rows": "factor", "band_lu_step": "factor", "band_lsolve": "factor",
 }
 # Per measured workload: the source hashes of every kernel group when its counters were taken,
 # and the bytes per launch.  Workload keys: the bench workload, plus a route letter for the
@@ -131,7 +131,7 @@ def measured_mfma_peak(prec):
 
 
 FLOP_KERNELS = ("lu_diag", "lu_panel", "lu_update", "hess_lu", "hess_reduce", "hess_uinv",
-                "band_panel", "band_update", "band_lu_panel", "band_lu_rows", "qgemm")
+                "band_panel", "band_update", "band_lu_panel", "band_lu_rows", "band_lu_step", "qgemm")
 
 
 def kernel_table(prof, steps, prec):
@@ -145,8 +145,8 @@ def kernel_table(prof, steps, prec):
         if v.get("work") and v["total_ms"] > 0:
             rate = v["work"] / (v["total_ms"] * 1e-3)
             if k in FLOP_KERNELS:
-                fp32 = k in ("lu_diag", "lu_panel", "lu_update", "band_lu_rows", "band_lu_panel", "hess_lu",
-                             "hess_uinv")
+                fp32 = k in ("lu_diag", "lu_panel", "lu_update", "band_lu_rows", "band_lu_panel", "band_lu_step",
+                             "hess_lu", "hess_uinv")
                 peak = PEAK_FP32_TFLOPS if (prec == "mixed" and fp32) else PEAK_FP64_TFLOPS
                 row["TFLOPs"] = round(rate / 1e12, 3)
                 row["frac"] = round(rate / 1e12 / peak, 4)
@@ -305,7 +305,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
               "time_irfft", "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot",
               "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve",
               "band_init", "band_panel", "band_update", "band_finish", "band_lu_panel", "band_lu_rows",
-              "band_lsolve"):
+              "band_lu_step", "band_lsolve"):
         q = S.profile_query(k)
         if q["count"]:
             prof[k] = q
@@ -339,7 +339,7 @@ def roofline(prof, prec, workload_name=None, read_peak=None):
                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                "avg_launch_ms": round(avg_ms, 4), "launches": q["count"],
                "work_per_launch": q["work"] / q["count"]}
-        if name in ("lu_update", "lu_panel", "band_lu_rows"):
+        if name in ("lu_update", "lu_panel", "band_lu_rows", "band_lu_step"):
             # the work is counted as 8 real flops per complex multiply-add; the 3M form of the
             # complex GEMM issues 3 real MFMA products per complex one, i.e. 6 of those 8 flops
             out["mfma_executed_frac"] = round(0.75 * achieved / peak, 4)

@@ -1106,20 +1106,30 @@ __device__ __forceinline__ c_t<T> band_entry(const double *__restrict__ H, int m
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map, int j,
-                                                       int *__restrict__ flag) {
+struct PanelLds {
+  c_t<T> a[2 * PB][PB + 1];
+  int perm[2 * PB];
+  T wmax[2];
+  int widx[2];
+  int spiv;
+  c_t<T> srec;
+};
+
+template <typename T>
+__device__ __forceinline__ void band_lu_panel_body(const InstDesc *__restrict__ Dd, const ItemMap &map, int item,
+                                                   int j, int *__restrict__ flag, PanelLds<T> &sp) {
   typedef c_t<T> C;
   constexpr int NT = 512;
-  __shared__ C a[2 * PB][PB + 1];
-  __shared__ int perm[2 * PB];
-  __shared__ T wmax[2];
-  __shared__ int widx[2];
-  __shared__ int spiv;
-  __shared__ C srec;
-  const int q = item_slot(map, blockIdx.x);
+  C(*a)[PB + 1] = sp.a;
+  int *perm = sp.perm;
+  T *wmax = sp.wmax;
+  int *widx = sp.widx;
+  int &spiv = sp.spiv;
+  C &srec = sp.srec;
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
-  const int blk = blockIdx.x - map.pre[q], tid = threadIdx.x;
+  const int blk = item - map.pre[q], tid = threadIdx.x;
   const int mp = d.mp, npan = d.npan, m = d.m, r0 = j * PB;
   const int nr = j + 1 < npan ? 2 * PB : PB;
   C *K = (C *)d.K + (size_t)blk * mp * mp;
@@ -1237,97 +1247,24 @@ struct BandWin {
   }
 };
 
-// (cre, cim) = (+/-) A W for A 64 x 64 (row stride lda, streamed in slices) and W the window's
-// reordered top rows 0..63, columns c0 .. c0 + 63, staged in slices as they are gathered; 3M
-// form and double buffering as gemm64_lds.  Every read completes before it returns.
-template <typename T, bool NEG>
-__device__ __forceinline__ void gemm64_win(const c_t<T> *__restrict__ A, int lda, const BandWin<T> &win, int c0,
-                                           GemmLds<T> &sm, acc_t<T> (&cre)[2][2], acc_t<T> (&cim)[2][2]) {
-  typedef c_t<T> C;
-  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  const int wave = tid >> 6, wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int ar = tid >> 2, ac = (tid & 3) * 2, br = tid >> 5, bc = (tid & 31) * 2;
-  const C *Ap = A + (size_t)ar * lda + ac;
-  acc_t<T> p1[2][2], p2[2][2], p3[2][2];
-  tile_zero<T>(p1, p2);
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
-  C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);
-  C rb0 = win.get(br, c0 + bc), rb1 = win.get(br, c0 + bc + 1);
-  sm.As[0][ar][ac] = ra0;
-  sm.As[0][ar][ac + 1] = ra1;
-  sm.Bs[0][br][bc] = rb0;
-  sm.Bs[0][br][bc + 1] = rb1;
-  __syncthreads();
-  constexpr int nsl = PB / US;
-#pragma unroll 1
-  for (int sl = 0; sl < nsl; ++sl) {
-    const int buf = sl & 1;
-    const bool more = sl + 1 < nsl;
-    if (more) {
-      const int k1 = (sl + 1) * US;
-      ra0 = ld_global<T>(Ap + k1);
-      ra1 = ld_global<T>(Ap + k1 + 1);
-      rb0 = win.get(k1 + br, c0 + bc);
-      rb1 = win.get(k1 + br, c0 + bc + 1);
-    }
-#pragma unroll
-    for (int kk = 0; kk < US; kk += 4) {
-      C a[2], b[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) a[r] = sm.As[buf][wr + r * 16 + li][kk + lk];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
-      T bs[2];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const T ar_ = NEG ? -a[r].x : a[r].x, ai_ = NEG ? -a[r].y : a[r].y;
-        const T as_ = ar_ + ai_;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          p1[r][c] = mfma16(ar_, b[c].x, p1[r][c]);
-          p2[r][c] = mfma16(ai_, b[c].y, p2[r][c]);
-          p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
-        }
-      }
-    }
-    if (more) {
-      sm.As[buf ^ 1][ar][ac] = ra0;
-      sm.As[buf ^ 1][ar][ac + 1] = ra1;
-      sm.Bs[buf ^ 1][br][bc] = rb0;
-      sm.Bs[buf ^ 1][br][bc + 1] = rb1;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cre[r][c][v] = p1[r][c][v] - p2[r][c][v];
-        cim[r][c][v] = p3[r][c][v] - p1[r][c][v] - p2[r][c][v];
-      }
-}
-
 // Item = (instance, block, tile t0 <= t < min(t1, npan - j - 1)): columns c0 = 64 (j + 1 + t) ..
-// of the window.
-//   half 1 (launched first): block row j + 1 <- bottom - M21 top       (K block row j + 1)
-//   half 0:                  block row j     <- L11^{-1} top = U12      (K block row j, in place)
-// Half 1 reads block row j before half 0 replaces it; within half 0 each workgroup reads its
-// own tile completely before it stores it.
+// of the window.  Both products of the step share the window's reordered top rows W, gathered
+// once into LDS slices: wavefronts 0-3 form block row j + 1 <- bottom - M21 W, wavefronts 4-7
+// block row j <- L11^{-1} W = U12 (each a 32 x 32 quarter of its 64 x 64 tile, 3M complex
+// MFMA products over 8-deep K slices, double-buffered).  The bottom rows are gathered and the
+// new block row j + 1 stored before a barrier after which block row j is overwritten, so every
+// read of the window precedes the stores that replace it.
 template <typename T>
-__global__ __launch_bounds__(256, 3) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j,
-                                                         int half, int t0, int t1) {
+struct RowsLds {
+  c_t<T> As[2][2][PB][US + 1];  // [product][buffer]: M21 (0), L11^{-1} (1) slices, 64 rows x US
+  c_t<T> Bs[2][US][PB + 1];     // W slices: US x 64 columns
+};
+
+template <typename T>
+__device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ Dd, const ItemMap &map, int bid,
+                                                  int nbid, int j, int t0, int t1, RowsLds<T> &sm) {
   typedef c_t<T> C;
-  __shared__ GemmLds<T> sm;
-  const int item = xcd_item(blockIdx.x, gridDim.x);  // the tiles of a block share an L2
+  const int item = xcd_item(bid, nbid);  // the tiles of a block share an L2
   const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
@@ -1349,26 +1286,122 @@ __global__ __launch_bounds__(256, 3) void k_band_lu_rows(const InstDesc *__restr
   win.r0 = r0;
   win.top_from_K = j > 0;
   const int lane = tid & 63, li = lane & 15, lk = lane >> 4, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  acc_t<T> cre[2][2], cim[2][2];
-  if (half == 0) {
-    const C *Dl = (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB;
-    gemm64_win<T, false>(Dl, PB, win, c0, sm, cre, cim);
-    tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
-    return;
+  const int prod = wave >> 2;  // 0: bottom (M21), 1: top (L11^{-1})
+  const int wr = ((wave & 3) >> 1) * 32, wc = (wave & 1) * 32;
+  // loaders: A slices, thread t < 256 M21 and t >= 256 L11^{-1}, row (t & 255) / 4, columns
+  // 2 ((t & 255) % 4) .. + 1; W slice, row t / 64, column t % 64
+  const int ht = tid & 255, ar = ht >> 2, ac = (ht & 3) * 2, ap = tid >> 8, br = tid >> 6, bc = tid & 63;
+  const C *Ap = ap == 0 ? K + (size_t)(r0 + PB + ar) * mp + r0 + ac
+                        : (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)ar * PB + ac;
+  C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);
+  C rb = win.get(br, c0 + bc);
+  sm.As[ap][0][ar][ac] = ra0;
+  sm.As[ap][0][ar][ac + 1] = ra1;
+  sm.Bs[0][br][bc] = rb;
+  __syncthreads();
+  acc_t<T> p1[2][2], p2[2][2], p3[2][2];
+  tile_zero<T>(p1, p2);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
+  constexpr int nsl = PB / US;
+#pragma unroll 1
+  for (int sl = 0; sl < nsl; ++sl) {
+    const int buf = sl & 1;
+    const bool more = sl + 1 < nsl;
+    if (more) {
+      const int k1 = (sl + 1) * US;
+      ra0 = ld_global<T>(Ap + k1);
+      ra1 = ld_global<T>(Ap + k1 + 1);
+      rb = win.get(k1 + br, c0 + bc);
+    }
+#pragma unroll
+    for (int kk = 0; kk < US; kk += 4) {
+      C a[2], b[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) a[r] = sm.As[prod][buf][wr + r * 16 + li][kk + lk];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
+      T bs[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const T as_ = a[r].x + a[r].y;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          p1[r][c] = mfma16(a[r].x, b[c].x, p1[r][c]);
+          p2[r][c] = mfma16(a[r].y, b[c].y, p2[r][c]);
+          p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
+        }
+      }
+    }
+    if (more) {
+      sm.As[ap][buf ^ 1][ar][ac] = ra0;
+      sm.As[ap][buf ^ 1][ar][ac + 1] = ra1;
+      sm.Bs[buf ^ 1][br][bc] = rb;
+    }
+    __syncthreads();
   }
-  gemm64_win<T, true>(K + (size_t)(r0 + PB) * mp + r0, mp, win, c0, sm, cre, cim);  // -M21 top
+  acc_t<T> cre[2][2], cim[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const C z = win.get(PB + wr + r * 16 + mfma_row<T>(lk, v), c0 + wc + c * 16 + li);
-        cre[r][c][v] += z.x;
-        cim[r][c][v] += z.y;
+        cre[r][c][v] = p1[r][c][v] - p2[r][c][v];
+        cim[r][c][v] = p3[r][c][v] - p1[r][c][v] - p2[r][c][v];
       }
-  tile_store<T>(K + (size_t)(r0 + PB + wr) * mp + c0 + wc, mp, cre, cim);
+  if (prod == 0) {  // block row j + 1 <- bottom - M21 W
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const C z = win.get(PB + wr + r * 16 + mfma_row<T>(lk, v), c0 + wc + c * 16 + li);
+          cre[r][c][v] = z.x - cre[r][c][v];
+          cim[r][c][v] = z.y - cim[r][c][v];
+        }
+    tile_store<T>(K + (size_t)(r0 + PB + wr) * mp + c0 + wc, mp, cre, cim);
+  }
+  __syncthreads();  // every read of the window (block row j included) is complete
+  if (prod == 1) tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map, int j,
+                                                       int *__restrict__ flag) {
+  __shared__ PanelLds<T> sp;
+  band_lu_panel_body<T>(Dd, map, blockIdx.x, j, flag, sp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j, int t0,
+                                                      int t1) {
+  __shared__ RowsLds<T> sm;
+  band_lu_rows_body<T>(Dd, map, blockIdx.x, gridDim.x, j, t0, t1, sm);
+}
+
+// Panel j + 1 and the row tiles t >= 1 of step j in one launch: the first npi workgroups take the
+// panel (dispatched first, so it never waits for CUs behind the row tiles), the others the
+// tiles.  The two touch disjoint parts of the factors (block column j + 1 against block columns
+// >= j + 2), and the panel reads only what the first row tile of step j wrote before.
+template <typename T>
+__global__ __launch_bounds__(512) void k_band_lu_step(const InstDesc *__restrict__ Dd, ItemMap pmap, int npi,
+                                                      ItemMap rmap, int j, int *__restrict__ flag) {
+  __shared__ union {
+    PanelLds<T> p;
+    RowsLds<T> r;
+  } lds;
+  if ((int)blockIdx.x < npi)
+    band_lu_panel_body<T>(Dd, pmap, blockIdx.x, j + 1, flag, lds.p);
+  else
+    band_lu_rows_body<T>(Dd, rmap, blockIdx.x - npi, gridDim.x - npi, j, 1, 1 << 30, lds.r);
 }
 
 // One workgroup per block: the window [top; bottom] of step j (the top carried from step j-1,
@@ -1489,10 +1522,15 @@ template <typename T>
 hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, int t0, int t1,
                                hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 1, t0, t1);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(256), 0, st, D, map, j, 0, t0, t1);
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(512), 0, st, D, map, j, t0, t1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_lu_step(const InstDesc *D, const ItemMap &pmap, int pitems, const ItemMap &rmap, int ritems,
+                               int j, int *flag, hipStream_t st) {
+  if (pitems + ritems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_lu_step<T>, dim3(pitems + ritems), dim3(512), 0, st, D, pmap, pitems, rmap, j, flag);
   return hipGetLastError();
 }
 
@@ -1564,6 +1602,8 @@ hipError_t launch_trsv_coop(const InstDesc *D, const ItemMap &map, int items,
                                               hipStream_t);                                     \
   template hipError_t launch_band_lu_rows<T>(const InstDesc *, const ItemMap &, int, int, int, int, \
                                              hipStream_t);                                      \
+  template hipError_t launch_band_lu_step<T>(const InstDesc *, const ItemMap &, int, const ItemMap &, int, \
+                                             int, int *, hipStream_t);                          \
   template hipError_t launch_band_lsolve<T>(const InstDesc *, const ItemMap &, int, hipStream_t);   \
   template int trsv_coop_capacity<T>();
 FDE_INST(double)

@@ -153,6 +153,10 @@ hipError_t launch_band_lu_panel(const InstDesc *D, const ItemMap &map, int items
 template <typename T>
 hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, int t0, int t1,
                                hipStream_t st);
+// panel j + 1 (pitems workgroups first) and the row tiles t >= 1 of step j in one launch
+template <typename T>
+hipError_t launch_band_lu_step(const InstDesc *D, const ItemMap &pmap, int pitems, const ItemMap &rmap, int ritems,
+                               int j, int *flag, hipStream_t st);
 // item = (instance, block): y <- L^{-1} P y on Vts in place
 template <typename T>
 hipError_t launch_band_lsolve(const InstDesc *D, const ItemMap &map, int items, hipStream_t st);

@@ -164,10 +164,6 @@ struct fde_bvm {
   bool need_Ju0 = false;
   // ---- device
   hipStream_t stream = nullptr, own_stream = nullptr;
-  // second stream of the band LU's look-ahead (the next panel beside the current row updates),
-  // with the two events that order it against the first; created on first use
-  hipStream_t side_stream = nullptr;
-  hipEvent_t side_ev[2] = {nullptr, nullptr};
   std::vector<void *> allocs;
   double *d_g = nullptr, *d_dp = nullptr, *d_dm = nullptr, *d_cG = nullptr;
   double2 *d_chat = nullptr, *d_twL = nullptr, *d_tws = nullptr, *d_lam = nullptr, *d_mu = nullptr;
@@ -925,12 +921,6 @@ static void destroy_handle(fde_bvm *h) {
     }
   for (auto e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
-  if (h->side_stream) {
-    (void)hipStreamSynchronize(h->side_stream);
-    (void)hipStreamDestroy(h->side_stream);
-  }
-  for (hipEvent_t &e : h->side_ev)
-    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -1513,10 +1503,9 @@ static fde_status band_factor(Plan *P) {
     HIPCHK(run(L, "band_finish", 16.0 * mp * mp, [&] { return launch_band_finish(mp, h->d_bAQ, h->d_bQt, st); }));
   }
   // Step j of the LU: panel j, then the row tiles of step j.  Look-ahead: the first row tile
-  // (block column j + 1, all the next panel reads) runs first on the main stream; panel j + 1
-  // then runs on the side stream while the other row tiles of step j run on the main stream
-  // (they touch block rows j and j + 1 at block columns >= j + 2 only); the main stream waits
-  // for the panel before step j + 1.
+  // (block column j + 1, all that panel j + 1 reads) runs first; panel j + 1 then runs in the
+  // same launch as the other row tiles of step j (which touch block rows j and j + 1 at block
+  // columns >= j + 2 only), its workgroups first.
   std::vector<int> slots(count), it(count);
   for (int i = 0; i < count; ++i) slots[i] = i;
   std::vector<HostMap> hm;
@@ -1530,11 +1519,6 @@ static fde_status band_factor(Plan *P) {
   }
   std::vector<ItemMap> dm;
   STCHK(upload_maps(P, hm, dm));
-  if (!L->side_stream) {
-    HIPCHK(hipStreamCreateWithFlags(&L->side_stream, hipStreamNonBlocking));
-    for (hipEvent_t &e : L->side_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  hipStream_t ss = L->side_stream;
   // algorithmic flops (complex multiply-add = 8 real flops): the 128 x 64 panel LU, and per
   // tile of the trailing width the two 64 x 64 x 64 products
   auto panel_work = [&](int j) {
@@ -1554,18 +1538,11 @@ static fde_status band_factor(Plan *P) {
     const size_t i0 = 3 * j + 1, i1 = 3 * j + 2, ip = 3 * (j + 1);
     if (hm[i0].items > 0)
       HIPCHK(run(L, "band_lu_rows", rows_work(i0), [&] { return launch_band_lu_rows<T>(P->d_desc, dm[i0], hm[i0].items, j, 0, 1, st); }));
-    const bool ahead = j + 1 < maxpan && hm[ip].items > 0;
-    if (ahead) {
-      HIPCHK(hipEventRecord(L->side_ev[0], st));
-      HIPCHK(hipStreamWaitEvent(ss, L->side_ev[0], 0));
-      HIPCHK(run(L, "band_lu_panel", panel_work(j + 1), [&] {
-        return launch_band_lu_panel<T>(P->d_desc, dm[ip], hm[ip].items, j + 1, P->d_flag, ss);
-      }, ss));
-      HIPCHK(hipEventRecord(L->side_ev[1], ss));
-    }
-    if (hm[i1].items > 0)
-      HIPCHK(run(L, "band_lu_rows", rows_work(i1), [&] { return launch_band_lu_rows<T>(P->d_desc, dm[i1], hm[i1].items, j, 1, 1 << 30, st); }));
-    if (ahead) HIPCHK(hipStreamWaitEvent(st, L->side_ev[1], 0));
+    const int pitems = j + 1 < maxpan ? hm[ip].items : 0;
+    if (pitems + hm[i1].items > 0)
+      HIPCHK(run(L, "band_lu_step", (pitems ? panel_work(j + 1) : 0.0) + rows_work(i1), [&] {
+        return launch_band_lu_step<T>(P->d_desc, dm[j + 1 < maxpan ? ip : i1], pitems, dm[i1], hm[i1].items, j, P->d_flag, st);
+      }));
   }
   return FDE_OK;
 }

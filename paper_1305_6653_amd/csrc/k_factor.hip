@@ -1115,11 +1115,10 @@ struct PanelLds {
   c_t<T> srec;
 };
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void band_lu_panel_body(const InstDesc *__restrict__ Dd, const ItemMap &map, int item,
                                                    int j, int *__restrict__ flag, PanelLds<T> &sp) {
   typedef c_t<T> C;
-  constexpr int NT = 512;
   C(*a)[PB + 1] = sp.a;
   int *perm = sp.perm;
   T *wmax = sp.wmax;
@@ -1249,11 +1248,13 @@ struct BandWin {
 
 // Item = (instance, block, tile t0 <= t < min(t1, npan - j - 1)): columns c0 = 64 (j + 1 + t) ..
 // of the window.  Both products of the step share the window's reordered top rows W, gathered
-// once into LDS slices: wavefronts 0-3 form block row j + 1 <- bottom - M21 W, wavefronts 4-7
-// block row j <- L11^{-1} W = U12 (each a 32 x 32 quarter of its 64 x 64 tile, 3M complex
-// MFMA products over 8-deep K slices, double-buffered).  The bottom rows are gathered and the
-// new block row j + 1 stored before a barrier after which block row j is overwritten, so every
-// read of the window precedes the stores that replace it.
+// once into LDS slices: wavefronts 0-7 form block row j + 1 <- bottom - M21 W, wavefronts 8-15
+// block row j <- L11^{-1} W = U12 (each a 32 x 16 part of its 64 x 64 tile, 3M complex MFMA
+// products over 8-deep K slices, double-buffered; 16 wavefronts per CU hide the slices'
+// latency).  The bottom rows are gathered and the new block row j + 1 stored before a barrier
+// after which block row j is overwritten, so every read of the window precedes the stores that
+// replace it.
+static constexpr int BR_NT = 1024;
 template <typename T>
 struct RowsLds {
   c_t<T> As[2][2][PB][US + 1];  // [product][buffer]: M21 (0), L11^{-1} (1) slices, 64 rows x US
@@ -1286,27 +1287,24 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
   win.r0 = r0;
   win.top_from_K = j > 0;
   const int lane = tid & 63, li = lane & 15, lk = lane >> 4, wave = tid >> 6;
-  const int prod = wave >> 2;  // 0: bottom (M21), 1: top (L11^{-1})
-  const int wr = ((wave & 3) >> 1) * 32, wc = (wave & 1) * 32;
-  // loaders: A slices, thread t < 256 M21 and t >= 256 L11^{-1}, row (t & 255) / 4, columns
-  // 2 ((t & 255) % 4) .. + 1; W slice, row t / 64, column t % 64
-  const int ht = tid & 255, ar = ht >> 2, ac = (ht & 3) * 2, ap = tid >> 8, br = tid >> 6, bc = tid & 63;
+  const int prod = wave >> 3;  // 0: bottom (M21), 1: top (L11^{-1})
+  const int pw = wave & 7, wr = (pw >> 2) * 32, wc = (pw & 3) * 16;
+  // loaders: A slices, thread t: product t / 512, row (t % 512) / 8, column t % 8; W slice
+  // (t < 512), row t / 64, column t % 64
+  const int ap = tid >> 9, ar = (tid & 511) >> 3, ac = tid & 7, br = (tid & 511) >> 6, bc = tid & 63;
+  const bool bl = tid < 512;
   const C *Ap = ap == 0 ? K + (size_t)(r0 + PB + ar) * mp + r0 + ac
                         : (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)ar * PB + ac;
-  C ra0 = ld_global<T>(Ap), ra1 = ld_global<T>(Ap + 1);
-  C rb = win.get(br, c0 + bc);
-  sm.As[ap][0][ar][ac] = ra0;
-  sm.As[ap][0][ar][ac + 1] = ra1;
-  sm.Bs[0][br][bc] = rb;
+  C ra = ld_global<T>(Ap);
+  C rb = bl ? win.get(br, c0 + bc) : mk<T>((T)0, (T)0);
+  sm.As[ap][0][ar][ac] = ra;
+  if (bl) sm.Bs[0][br][bc] = rb;
   __syncthreads();
-  acc_t<T> p1[2][2], p2[2][2], p3[2][2];
-  tile_zero<T>(p1, p2);
+  acc_t<T> p1[2], p2[2], p3[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) p3[r][c][v] = (T)0;
+    for (int v = 0; v < 4; ++v) p1[r][v] = p2[r][v] = p3[r][v] = (T)0;
   constexpr int nsl = PB / US;
 #pragma unroll 1
   for (int sl = 0; sl < nsl; ++sl) {
@@ -1314,75 +1312,67 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
     const bool more = sl + 1 < nsl;
     if (more) {
       const int k1 = (sl + 1) * US;
-      ra0 = ld_global<T>(Ap + k1);
-      ra1 = ld_global<T>(Ap + k1 + 1);
-      rb = win.get(k1 + br, c0 + bc);
+      ra = ld_global<T>(Ap + k1);
+      if (bl) rb = win.get(k1 + br, c0 + bc);
     }
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {
-      C a[2], b[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) a[r] = sm.As[prod][buf][wr + r * 16 + li][kk + lk];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = sm.Bs[buf][kk + lk][wc + c * 16 + li];
-      T bs[2];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) bs[c] = b[c].x + b[c].y;
+      const C b = sm.Bs[buf][kk + lk][wc + li];
+      const T bs = b.x + b.y;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        const T as_ = a[r].x + a[r].y;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          p1[r][c] = mfma16(a[r].x, b[c].x, p1[r][c]);
-          p2[r][c] = mfma16(a[r].y, b[c].y, p2[r][c]);
-          p3[r][c] = mfma16(as_, bs[c], p3[r][c]);
-        }
+        const C a = sm.As[prod][buf][wr + r * 16 + li][kk + lk];
+        p1[r] = mfma16(a.x, b.x, p1[r]);
+        p2[r] = mfma16(a.y, b.y, p2[r]);
+        p3[r] = mfma16(a.x + a.y, bs, p3[r]);
       }
     }
     if (more) {
-      sm.As[ap][buf ^ 1][ar][ac] = ra0;
-      sm.As[ap][buf ^ 1][ar][ac + 1] = ra1;
-      sm.Bs[buf ^ 1][br][bc] = rb;
+      sm.As[ap][buf ^ 1][ar][ac] = ra;
+      if (bl) sm.Bs[buf ^ 1][br][bc] = rb;
     }
     __syncthreads();
   }
-  acc_t<T> cre[2][2], cim[2][2];
+  T cre[2][4], cim[2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cre[r][c][v] = p1[r][c][v] - p2[r][c][v];
-        cim[r][c][v] = p3[r][c][v] - p1[r][c][v] - p2[r][c][v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      cre[r][v] = p1[r][v] - p2[r][v];
+      cim[r][v] = p3[r][v] - p1[r][v] - p2[r][v];
+    }
   if (prod == 0) {  // block row j + 1 <- bottom - M21 W
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const C z = win.get(PB + wr + r * 16 + mfma_row<T>(lk, v), c0 + wc + c * 16 + li);
-          cre[r][c][v] = z.x - cre[r][c][v];
-          cim[r][c][v] = z.y - cim[r][c][v];
-        }
-    tile_store<T>(K + (size_t)(r0 + PB + wr) * mp + c0 + wc, mp, cre, cim);
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + r * 16 + mfma_row<T>(lk, v);
+        const C z = win.get(PB + row, c0 + wc + li);
+        K[(size_t)(r0 + PB + row) * mp + c0 + wc + li] = mk<T>(z.x - cre[r][v], z.y - cim[r][v]);
+      }
   }
   __syncthreads();  // every read of the window (block row j included) is complete
-  if (prod == 1) tile_store<T>(K + (size_t)(r0 + wr) * mp + c0 + wc, mp, cre, cim);
+  if (prod == 1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + r * 16 + mfma_row<T>(lk, v);
+        K[(size_t)(r0 + row) * mp + c0 + wc + li] = mk<T>(cre[r][v], cim[r][v]);
+      }
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(512) void k_band_lu_panel(const InstDesc *__restrict__ Dd, ItemMap map, int j,
                                                        int *__restrict__ flag) {
   __shared__ PanelLds<T> sp;
-  band_lu_panel_body<T>(Dd, map, blockIdx.x, j, flag, sp);
+  band_lu_panel_body<T, 512>(Dd, map, blockIdx.x, j, flag, sp);
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j, int t0,
-                                                      int t1) {
+__global__ __launch_bounds__(BR_NT) void k_band_lu_rows(const InstDesc *__restrict__ Dd, ItemMap map, int j, int t0,
+                                                        int t1) {
   __shared__ RowsLds<T> sm;
   band_lu_rows_body<T>(Dd, map, blockIdx.x, gridDim.x, j, t0, t1, sm);
 }
@@ -1392,14 +1382,14 @@ __global__ __launch_bounds__(512) void k_band_lu_rows(const InstDesc *__restrict
 // tiles.  The two touch disjoint parts of the factors (block column j + 1 against block columns
 // >= j + 2), and the panel reads only what the first row tile of step j wrote before.
 template <typename T>
-__global__ __launch_bounds__(512) void k_band_lu_step(const InstDesc *__restrict__ Dd, ItemMap pmap, int npi,
-                                                      ItemMap rmap, int j, int *__restrict__ flag) {
+__global__ __launch_bounds__(BR_NT) void k_band_lu_step(const InstDesc *__restrict__ Dd, ItemMap pmap, int npi,
+                                                        ItemMap rmap, int j, int *__restrict__ flag) {
   __shared__ union {
     PanelLds<T> p;
     RowsLds<T> r;
   } lds;
   if ((int)blockIdx.x < npi)
-    band_lu_panel_body<T>(Dd, pmap, blockIdx.x, j + 1, flag, lds.p);
+    band_lu_panel_body<T, BR_NT>(Dd, pmap, blockIdx.x, j + 1, flag, lds.p);
   else
     band_lu_rows_body<T>(Dd, rmap, blockIdx.x - npi, gridDim.x - npi, j, 1, 1 << 30, lds.r);
 }
@@ -1522,7 +1512,7 @@ template <typename T>
 hipError_t launch_band_lu_rows(const InstDesc *D, const ItemMap &map, int items, int j, int t0, int t1,
                                hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(512), 0, st, D, map, j, t0, t1);
+  hipLaunchKernelGGL(k_band_lu_rows<T>, dim3(items), dim3(BR_NT), 0, st, D, map, j, t0, t1);
   return hipGetLastError();
 }
 
@@ -1530,7 +1520,7 @@ template <typename T>
 hipError_t launch_band_lu_step(const InstDesc *D, const ItemMap &pmap, int pitems, const ItemMap &rmap, int ritems,
                                int j, int *flag, hipStream_t st) {
   if (pitems + ritems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lu_step<T>, dim3(pitems + ritems), dim3(512), 0, st, D, pmap, pitems, rmap, j, flag);
+  hipLaunchKernelGGL(k_band_lu_step<T>, dim3(pitems + ritems), dim3(BR_NT), 0, st, D, pmap, pitems, rmap, j, flag);
   return hipGetLastError();
 }
 

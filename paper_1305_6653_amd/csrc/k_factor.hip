@@ -1396,10 +1396,10 @@ __global__ __launch_bounds__(BR_NT) void k_band_lu_step(const InstDesc *__restri
 
 // One workgroup per block: the window [top; bottom] of step j (the top carried from step j-1,
 // the bottom read from the vector), reordered; then top <- L11^{-1} top (final) and bottom <-
-// bottom - M21 top (the next step's top), both from the reordered top.  Thread t: row t / 4,
-// columns 16 (t % 4) .. + 16.
+// bottom - M21 top (the next step's top), both from the reordered top.  Thread t: row t / 8,
+// columns 8 (t % 8) .. + 8.
 template <typename T>
-__global__ __launch_bounds__(256) void k_band_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
+__global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
   typedef c_t<T> C;
   __shared__ double2 ys[2 * PB];  // the window before the exchanges
   __shared__ double2 y[2 * PB];   // after them
@@ -1412,30 +1412,37 @@ __global__ __launch_bounds__(256) void k_band_lsolve(const InstDesc *__restrict_
   const C *K = (const C *)d.K + (size_t)blk * mp * mp;
   const C *dinv = (const C *)d.dinv;
   const int *perm = d.hpiv + (size_t)blk * npan * 2 * PB;
-  const int i = tid >> 2, qq = tid & 3;
+  const int i = tid >> 3, qq = tid & 7;  // row i, columns 8 qq .. + 7
   if (tid < PB) ys[tid] = v[tid];
   for (int j = 0; j < npan; ++j) {
     const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
+    // this step's entries of L11^{-1} and M21 do not depend on the solve: loaded first, so
+    // their latency overlaps the window's exchanges
+    C li[8], mm[8];
+    const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) li[c] = Li[c];
+    if (nr == 2 * PB) {
+      const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 8;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) mm[c] = M21[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) mm[c] = mk<T>((T)0, (T)0);
+    }
     if (tid >= PB && tid < nr) ys[tid] = v[r0 + tid];
     __syncthreads();
     if (tid < nr) y[tid] = ys[perm[(size_t)j * 2 * PB + tid]];
     __syncthreads();
-    const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq * 16;
     double2 s = make_double2(0.0, 0.0), t = make_double2(0.0, 0.0);
-    if (nr == 2 * PB) {
-      const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 16;
-#pragma unroll 4
-      for (int c = 0; c < 16; ++c) {
-        const double2 yc = y[qq * 16 + c];
-        s = cfma(widen(Li[c]), yc, s);
-        t = cfma(widen(M21[c]), yc, t);
-      }
-    } else {
-#pragma unroll 4
-      for (int c = 0; c < 16; ++c) s = cfma(widen(Li[c]), y[qq * 16 + c], s);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double2 yc = y[qq * 8 + c];
+      s = cfma(widen(li[c]), yc, s);
+      t = cfma(widen(mm[c]), yc, t);
     }
 #pragma unroll
-    for (int o = 1; o <= 2; o <<= 1) {
+    for (int o = 1; o <= 4; o <<= 1) {
       s.x += __shfl_xor(s.x, o, 64);
       s.y += __shfl_xor(s.y, o, 64);
       t.x += __shfl_xor(t.x, o, 64);
@@ -1527,7 +1534,7 @@ hipError_t launch_band_lu_step(const InstDesc *D, const ItemMap &pmap, int pitem
 template <typename T>
 hipError_t launch_band_lsolve(const InstDesc *D, const ItemMap &map, int items, hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_lsolve<T>, dim3(items), dim3(256), 0, st, D, map);
+  hipLaunchKernelGGL(k_band_lsolve<T>, dim3(items), dim3(512), 0, st, D, map);
   return hipGetLastError();
 }
 

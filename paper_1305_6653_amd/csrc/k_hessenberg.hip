@@ -560,18 +560,20 @@ hipError_t launch_hess_lsolve(const InstDesc *D, const ItemMap &map, int items, 
 // real parts of bins 0 and s/2, paired in slot 0: the imaginary parts of those two bins never
 // reach the preconditioner's result (the inverse time FFT of a real vector discards them), so
 // they are not read and are written as 0.  That is s real rows.
-// Workgroup tile: 32 slots (64 real rows) x 64 columns over the whole K range.  Wavefronts 0-3
-// take the even 32-deep K slices and 4-7 the odd ones, each a 32 x 32 quarter of the tile
-// (2 x 2 FP64 MFMA 16x16x4 tiles), staged through LDS one slice ahead; the two halves are
-// summed at the end in a fixed order.  Consecutive workgroups run on different XCDs; the slot
-// tiles of one column tile go to the same XCD, so its L2 serves their common B columns.
-// Item = (instance, slot tile, column tile).
-static constexpr int QG_NT = 512, QG_KS = 32;
+// Workgroup tile: 32 slots (64 real rows) x 64 columns over the whole K range.  Four groups of
+// four wavefronts take interleaved 16-deep K slices (group g the slices g, g + 4, ...), each
+// wavefront a 32 x 32 quarter of the tile (2 x 2 FP64 MFMA 16x16x4 tiles), staged through LDS
+// one slice ahead; the groups' partial tiles are summed at the end in group order.  Sixteen
+// wavefronts per CU hide the slices' latency.  Consecutive workgroups run on different XCDs;
+// the slot tiles of one column tile go to the same XCD, so its L2 serves their common B
+// columns.  Item = (instance, slot tile, column tile).
+static constexpr int QG_NG = 4, QG_NT = 256 * QG_NG, QG_KS = 16, QG_LD = 64 + 1;
+static constexpr int QG_BUF = QG_KS * QG_LD;  // one staged slice of A or B
 
 __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd, ItemMap map,
                                                  int trans, int src2) {
-  __shared__ double As[2][2][QG_KS][64 + 1];  // [K half][buffer][k][real row]
-  __shared__ double Bs[2][2][QG_KS][64 + 1];  // [K half][buffer][k][column]
+  // [group][buffer] A slices (k x real row) then B slices (k x column); reused for the partials
+  __shared__ double sm[2 * QG_NG * 2 * QG_BUF];
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const InstDesc &d = Dd[map.ids[q]];
@@ -587,19 +589,20 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
     ct = local % ncol;
   }
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  const int kh = wv >> 2, wr = ((wv & 3) >> 1) * 32, wc = (wv & 1) * 32, ht = tid & 255;
+  const int kg = wv >> 2, wr = ((wv & 3) >> 1) * 32, wc = (wv & 1) * 32, ht = tid & 255;
   const double2 *X = src2 ? d.Vts : d.Vh;
   double2 *Y = src2 ? d.Vh : d.Vts;
   const double *B = trans ? d.hQt : d.hQ;
   const int s0 = rt * 32, c0 = ct * 64;
-  // loaders (per K half): A slot ht / 8 at k 4 (ht % 8) .. + 3; B row ht / 8 at columns 8 (ht % 8) .. + 7
-  const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 4, bk = ht >> 3, bc = (ht & 7) * 8;
+  double *Ag = sm + (size_t)kg * 2 * QG_BUF, *Bg = sm + (size_t)(QG_NG + kg) * 2 * QG_BUF;
+  // loaders (per group): A slot ht / 8 at k 2 (ht % 8) .. + 1; B row ht / 16 at columns 4 (ht % 16) .. + 3
+  const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 2, bk = ht >> 4, bc = (ht & 15) * 4;
   const bool aok = aslot < ns;
   const double2 *Xa = X + (size_t)(aok ? aslot : 0) * mp, *Xn = X + (size_t)ns * mp;
-  double2 ra[4], rb[4];
+  double2 ra[2], rb[2];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       const int k = k0 + ak + u;
       double2 v = make_double2(0.0, 0.0);
       if (aok && k < m) {
@@ -611,15 +614,16 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
     const int k = k0 + bk;
     const double2 *pb = reinterpret_cast<const double2 *>(B + (size_t)(k < m ? k : 0) * mp + c0 + bc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 2; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
   };
   auto stage = [&](int buf) {
+    double *A_ = Ag + buf * QG_BUF, *B_ = Bg + buf * QG_BUF;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      As[kh][buf][ak + u][2 * as] = ra[u].x;
-      As[kh][buf][ak + u][2 * as + 1] = ra[u].y;
-      Bs[kh][buf][bk][bc + 2 * u] = rb[u].x;
-      Bs[kh][buf][bk][bc + 2 * u + 1] = rb[u].y;
+    for (int u = 0; u < 2; ++u) {
+      A_[(ak + u) * QG_LD + 2 * as] = ra[u].x;
+      A_[(ak + u) * QG_LD + 2 * as + 1] = ra[u].y;
+      B_[bk * QG_LD + bc + 2 * u] = rb[u].x;
+      B_[bk * QG_LD + bc + 2 * u + 1] = rb[u].y;
     }
   };
   v4d acc[2][2];
@@ -627,31 +631,32 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[r][c] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int npair = (m + 2 * QG_KS - 1) / (2 * QG_KS);  // slice pairs covering K = m
-  load(kh * QG_KS);
+  const int nround = (m + QG_NG * QG_KS - 1) / (QG_NG * QG_KS);  // slice rounds covering K = m
+  load(kg * QG_KS);
   stage(0);
   __syncthreads();
-  for (int p = 0; p < npair; ++p) {
+  for (int p = 0; p < nround; ++p) {
     const int buf = p & 1;
-    if (p + 1 < npair) load((2 * (p + 1) + kh) * QG_KS);
+    if (p + 1 < nround) load(((p + 1) * QG_NG + kg) * QG_KS);
+    const double *A_ = Ag + buf * QG_BUF, *B_ = Bg + buf * QG_BUF;
 #pragma unroll
     for (int kk = 0; kk < QG_KS; kk += 4) {
       double av[2], bv[2];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) av[r] = As[kh][buf][kk + lk][wr + 16 * r + li];
+      for (int r = 0; r < 2; ++r) av[r] = A_[(kk + lk) * QG_LD + wr + 16 * r + li];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) bv[c] = Bs[kh][buf][kk + lk][wc + 16 * c + li];
+      for (int c = 0; c < 2; ++c) bv[c] = B_[(kk + lk) * QG_LD + wc + 16 * c + li];
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[r][c] = mfma16(av[r], bv[c], acc[r][c]);
     }
-    if (p + 1 < npair) stage(buf ^ 1);
+    if (p + 1 < nround) stage(buf ^ 1);
     __syncthreads();
   }
-  // the odd-slice half hands its quarters to the even-slice half (As reused as 64 x 64)
-  double *part = &As[0][0][0][0];
-  if (kh == 1) {
+  // groups 1 .. 3 hand their tiles to group 0 (the staging buffers reused as [3][64][64])
+  if (kg > 0) {
+    double *part = sm + (size_t)(kg - 1) * 64 * 64;
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -661,7 +666,7 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
           part[(wr + 16 * r + mfma_row<double>(lk, v)) * 64 + wc + 16 * c + li] = acc[r][c][v];
   }
   __syncthreads();
-  if (kh == 1) return;
+  if (kg > 0) return;
   double *Yd = reinterpret_cast<double *>(Y);
 #pragma unroll
   for (int r = 0; r < 2; ++r)
@@ -672,7 +677,9 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
         const int row = wr + 16 * r + mfma_row<double>(lk, v), col = c0 + wc + 16 * c + li;
         const int slot = s0 + (row >> 1), im = row & 1;
         if (slot >= ns) continue;
-        double val = acc[r][c][v] + part[row * 64 + wc + 16 * c + li];
+        double val = acc[r][c][v];
+#pragma unroll
+        for (int g = 0; g < QG_NG - 1; ++g) val += sm[(size_t)g * 64 * 64 + row * 64 + wc + 16 * c + li];
         if (col >= m) val = 0.0;
         if (slot == 0)
           Y[(size_t)(im ? ns : 0) * mp + col] = make_double2(val, 0.0);

@@ -248,13 +248,16 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
 /*   FDE_BLOCKS_AUTO        (default) FDE_BLOCKS_BAND when m >= FDE_BAND_MIN_M_FP64 (FP64 blocks)
  *                          or m >= FDE_BAND_MIN_M_MIXED (FP32 blocks), else FDE_BLOCKS_LU (for a
  *                          batch: the band route only if every instance qualifies).  Measured on
- *                          MI355X at s = 256: FP64 factor + solve take the same time both ways at
- *                          m = 1535 (39 ms) and the band route is 1.3x faster at m = 2047 and 2x
- *                          at m = 3071; with FP32 blocks block LU stays faster up to m = 2047.
+ *                          MI355X at s = 256 (factor + solve): in FP64 block LU is 7% faster at
+ *                          m = 1023 and the band route 12% faster at m = 1279, 1.7x at m = 2047
+ *                          and 2.5x at m = 3071; with FP32 blocks block LU is 4% faster at
+ *                          m = 1535 and the band route 1.2x faster at m = 2047.  Block LU's
+ *                          factorization grows with s and the band reduction does not, so for
+ *                          s = 512 the band route already wins at m = 1023 in FP64.
  * FDE_OPT_BLOCKS_IN_USE (read-only) is the route of the current factorization. */
 typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2, FDE_BLOCKS_AUTO = 3 } fde_block_solver;
-#define FDE_BAND_MIN_M_FP64 1536
-#define FDE_BAND_MIN_M_MIXED 2560
+#define FDE_BAND_MIN_M_FP64 1152
+#define FDE_BAND_MIN_M_MIXED 1792
 /* FDE_OPT_ORTHO selects the Arnoldi orthogonalisation (FP64 either way):
  *   FDE_ORTHO_MGS   (default) modified Gram-Schmidt, j + 2 dependent launches at step j.
  *   FDE_ORTHO_CGS2  classical Gram-Schmidt applied twice: three launches per step whatever j;

@@ -114,8 +114,8 @@ def test_band_route_switches_with_the_others_on_one_handle():
 
 
 def test_automatic_route_choice_by_size():
-    """FDE_BLOCKS_AUTO (the default): the band route from m = 1536 on for FP64 blocks and from
-    m = 2560 for FP32 blocks, block LU below; a batch takes the band route only if every
+    """FDE_BLOCKS_AUTO (the default): the band route from m = 1152 on for FP64 blocks and from
+    m = 1792 for FP32 blocks, block LU below; a batch takes the band route only if every
     instance qualifies."""
     small, big = W.tiny(200, 8, 1.5, 1, "gbdf3"), W.tiny(1600, 8, 1.5, 2, "gbdf3")
     Ss, Sb = BvmSolver(small), BvmSolver(big)

@@ -665,6 +665,9 @@ def main():
     ms_alt = (time.perf_counter() - t0) * 1e3 / args.steps
     result["changed_rhs"] = {"ms_per_step": round(ms_alt, 4), "value": round(1000.0 / ms_alt, 4),
                              "rhs": f"alternating {p.name} and {q.name}'s u0, f"}
+    route_names = {N.FDE_BLOCKS_LU: "lu", N.FDE_BLOCKS_HESSENBERG: "hessenberg", N.FDE_BLOCKS_BAND: "band"}
+    in_use = S.get_option(N.FDE_OPT_BLOCKS_IN_USE)  # the headline form's route (before the mixed form's)
+    result["config"]["blocks"] = route_names.get(in_use, in_use)
     if not args.no_mixed:
         ms2, _, infos2, prof2 = timed_steps(S, u0, f, out, "mixed", args.steps, args.warmup)
         u_mixed = DEV.get(out)
@@ -675,12 +678,10 @@ def main():
             "t_solve_ms": round(infos2[-1]["t_solve_ms"], 3),
             "rel_diff_vs_fp64": float(np.linalg.norm(u_mixed - u_main) / np.linalg.norm(u_main)),
             "speedup_vs_fp64": round(ms / ms2, 3),
+            "blocks": route_names.get(S.get_option(N.FDE_OPT_BLOCKS_IN_USE)),
             "kernels": kernel_table(prof2, args.steps, "mixed"),
             "roofline": roofline(prof2, "mixed", args.workload, read_peak),
         }
-    route_names = {N.FDE_BLOCKS_LU: "lu", N.FDE_BLOCKS_HESSENBERG: "hessenberg", N.FDE_BLOCKS_BAND: "band"}
-    in_use = S.get_option(N.FDE_OPT_BLOCKS_IN_USE)
-    result["config"]["blocks"] = route_names.get(in_use, in_use)
     if not args.no_hessenberg:
         # the same preconditioner S with its blocks solved by the other routes: dense block LU,
         # one Hessenberg form of J (m <= 1024), one band form of J

@@ -245,18 +245,21 @@ typedef enum { FDE_SIDE_RIGHT = 0, FDE_SIDE_LEFT = 1 } fde_precond_side;
  *                          tau mu_k H with partial pivoting among the 128 rows of each 64-column
  *                          panel (O(64 m^2)); the solves read U and the band of L.  Any m the
  *                          library takes; needs cooperative launches.  Not in the paper. */
-/*   FDE_BLOCKS_AUTO        (default) FDE_BLOCKS_BAND when m >= FDE_BAND_MIN_M_FP64 (FP64 blocks)
- *                          or m >= FDE_BAND_MIN_M_MIXED (FP32 blocks), else FDE_BLOCKS_LU (for a
+/*   FDE_BLOCKS_AUTO        (default) FDE_BLOCKS_BAND when m >= FDE_BAND_MIN_M_FP64 (FP64 blocks;
+ *                          FDE_BAND_MIN_M_FP64_LONG when s / 2 + 1 >= FDE_BAND_LONG_NB) or
+ *                          m >= FDE_BAND_MIN_M_MIXED (FP32 blocks), else FDE_BLOCKS_LU (for a
  *                          batch: the band route only if every instance qualifies).  Measured on
  *                          MI355X at s = 256 (factor + solve): in FP64 block LU is 7% faster at
  *                          m = 1023 and the band route 12% faster at m = 1279, 1.7x at m = 2047
  *                          and 2.5x at m = 3071; with FP32 blocks block LU is 4% faster at
  *                          m = 1535 and the band route 1.2x faster at m = 2047.  Block LU's
- *                          factorization grows with s and the band reduction does not, so for
- *                          s = 512 the band route already wins at m = 1023 in FP64.
+ *                          factorization grows with s and the band reduction does not: for
+ *                          s = 512 the band route is 10% faster at m = 1023 in FP64.
  * FDE_OPT_BLOCKS_IN_USE (read-only) is the route of the current factorization. */
 typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2, FDE_BLOCKS_AUTO = 3 } fde_block_solver;
 #define FDE_BAND_MIN_M_FP64 1152
+#define FDE_BAND_MIN_M_FP64_LONG 960
+#define FDE_BAND_LONG_NB 257
 #define FDE_BAND_MIN_M_MIXED 1792
 /* FDE_OPT_ORTHO selects the Arnoldi orthogonalisation (FP64 either way):
  *   FDE_ORTHO_MGS   (default) modified Gram-Schmidt, j + 2 dependent launches at step j.

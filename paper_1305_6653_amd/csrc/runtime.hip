@@ -1585,9 +1585,13 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   for (fde_bvm *h : P->hs)
     if (h->opt_blocks != route) return fail(FDE_EINVAL, "all instances of a batch need the same block solver");
   if (route == FDE_BLOCKS_AUTO) {  // the band route once every instance is large enough
-    const int mmin = prec == FDE_FP64 ? FDE_BAND_MIN_M_FP64 : FDE_BAND_MIN_M_MIXED;
     bool band = true;
-    for (fde_bvm *h : P->hs) band = band && h->m >= mmin;
+    for (fde_bvm *h : P->hs) {
+      const int mmin = prec != FDE_FP64              ? FDE_BAND_MIN_M_MIXED
+                       : h->nb >= FDE_BAND_LONG_NB ? FDE_BAND_MIN_M_FP64_LONG
+                                                   : FDE_BAND_MIN_M_FP64;
+      band = band && h->m >= mmin;
+    }
     route = band ? FDE_BLOCKS_BAND : FDE_BLOCKS_LU;
   }
   for (fde_bvm *h : P->hs) {

@@ -114,9 +114,9 @@ def test_band_route_switches_with_the_others_on_one_handle():
 
 
 def test_automatic_route_choice_by_size():
-    """FDE_BLOCKS_AUTO (the default): the band route from m = 1152 on for FP64 blocks and from
-    m = 1792 for FP32 blocks, block LU below; a batch takes the band route only if every
-    instance qualifies."""
+    """FDE_BLOCKS_AUTO (the default): the band route from m = 1152 on for FP64 blocks (from
+    m = 960 when s / 2 + 1 >= 257) and from m = 1792 for FP32 blocks, block LU below; a batch
+    takes the band route only if every instance qualifies."""
     small, big = W.tiny(200, 8, 1.5, 1, "gbdf3"), W.tiny(1600, 8, 1.5, 2, "gbdf3")
     Ss, Sb = BvmSolver(small), BvmSolver(big)
     assert Ss.get_option(N.FDE_OPT_BLOCKS) == N.FDE_BLOCKS_AUTO
@@ -132,3 +132,12 @@ def test_automatic_route_choice_by_size():
     assert Sb.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
     Ss.close()
     Sb.close()
+    # long time axis (s / 2 + 1 >= 257): the band route from m = 960 in FP64
+    mid_short, mid_long = W.tiny(1000, 256, 1.5, 3, "gbdf3"), W.tiny(1000, 512, 1.5, 3, "gbdf3")
+    for p, want in ((mid_short, N.FDE_BLOCKS_LU), (mid_long, N.FDE_BLOCKS_BAND)):
+        S = BvmSolver(p)
+        S.factor("fp64")
+        assert S.get_option(N.FDE_OPT_BLOCKS_IN_USE) == want, (p.s, want)
+        S.factor("mixed")
+        assert S.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
+        S.close()

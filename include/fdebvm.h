@@ -198,8 +198,18 @@ typedef enum {
   FDE_OPT_SIDE = 6,
   FDE_OPT_BLOCKS = 7,
   FDE_OPT_ORTHO = 8,
-  FDE_OPT_BLOCKS_IN_USE = 9
+  FDE_OPT_BLOCKS_IN_USE = 9,
+  FDE_OPT_X0_GATE = 10,
+  FDE_OPT_X0_KEPT = 11
 } fde_option;
+/* FDE_OPT_X0_GATE decides whether an initial guess is used, in millionths: after the scaling by
+ * gamma (see fde_solve_opts), a guess with ||b - gamma M x0|| > gate 1e-6 ||b|| is dropped and
+ * the instance starts from zero.  Default 10000 (1e-2): with the Strang preconditioner the
+ * iteration count is set by the few outlying eigenvalues of S^{-1} M (the rank of S^{-1} M - I
+ * is at most 2 m mu, Section 3.3), not by the starting residual, and guesses that reduce the
+ * residual less than about a hundredfold do not save iterations (they can cost one or two).
+ * 0 keeps every guess.  FDE_OPT_X0_KEPT (read-only): 1 if the handle's last solve used its
+ * guess, else 0. */
 /* FDE_OPT_PRECOND selects the preconditioner built by the next fde_precond_factor (changing it
  * discards the current factorization):
  *   FDE_PC_STRANG        S = s(A) (x) I - tau s(B) (x) J, eq. (1.11) (default): s/2+1 block LUs.

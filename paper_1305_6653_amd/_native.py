@@ -45,6 +45,7 @@ FDE_OPT_PRECOND, FDE_OPT_SIDE, FDE_OPT_BLOCKS, FDE_OPT_ORTHO = 5, 6, 7, 8
 FDE_ORTHO_MGS, FDE_ORTHO_CGS2 = 0, 1
 FDE_BLOCKS_LU, FDE_BLOCKS_HESSENBERG, FDE_BLOCKS_BAND, FDE_BLOCKS_AUTO = 0, 1, 2, 3
 FDE_OPT_BLOCKS_IN_USE = 9
+FDE_OPT_X0_GATE, FDE_OPT_X0_KEPT = 10, 11
 FDE_SIDE_RIGHT, FDE_SIDE_LEFT = 0, 1
 FDE_PC_STRANG, FDE_PC_BCCB, FDE_PC_BCCB_SHIFTED, FDE_PC_NONE = 0, 1, 2, 3
 

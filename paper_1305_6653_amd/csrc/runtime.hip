@@ -206,6 +206,8 @@ struct fde_bvm {
   int opt_side = FDE_SIDE_RIGHT;
   int opt_blocks = FDE_BLOCKS_AUTO;
   int opt_ortho = FDE_ORTHO_MGS;
+  int opt_x0_gate = 10000;  // millionths of ||b||
+  int x0_kept = 0;          // the last solve used its initial guess
   // ---- profiling
   bool prof = false;
   int prof_step_limit = 1 << 30;  // launches of cycle steps >= this were gated off: not counted
@@ -1164,6 +1166,10 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
         return fail(FDE_EINVAL, "FDE_OPT_ORTHO must be FDE_ORTHO_MGS or FDE_ORTHO_CGS2");
       h->opt_ortho = value;
       return FDE_OK;
+    case FDE_OPT_X0_GATE:
+      if (value < 0) return fail(FDE_EINVAL, "FDE_OPT_X0_GATE must be >= 0");
+      h->opt_x0_gate = value;
+      return FDE_OK;
     case FDE_OPT_BLOCKS:
       if (value != FDE_BLOCKS_LU && value != FDE_BLOCKS_HESSENBERG && value != FDE_BLOCKS_BAND &&
           value != FDE_BLOCKS_AUTO)
@@ -1189,6 +1195,8 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_BLOCKS_IN_USE: *value = h->blk_route; return FDE_OK;
     case FDE_OPT_ORTHO: *value = h->opt_ortho; return FDE_OK;
     case FDE_OPT_PRECOND: *value = h->opt_precond; return FDE_OK;
+    case FDE_OPT_X0_GATE: *value = h->opt_x0_gate; return FDE_OK;
+    case FDE_OPT_X0_KEPT: *value = h->x0_kept; return FDE_OK;
     default: return fail(FDE_EINVAL, "unknown option %d", option);
   }
 }
@@ -2019,7 +2027,8 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   }
   // An initial guess is first scaled by the gamma minimising ||b - gamma M x0|| (one step of
   // minimal residual along x0), so that ||r_0|| <= ||b||: a poor guess never starts worse
-  // than the zero start.
+  // than the zero start.  A guess that leaves ||b - gamma M x0|| above the gate (the lead
+  // handle's FDE_OPT_X0_GATE, millionths of ||b||) gets gamma = 0: the zero start.
   bool any_x0 = false;
   std::vector<int> &gh = P->gates_host;
   gh.assign(GATE_COUNT * count, 0);
@@ -2039,10 +2048,17 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
     STCHK(sync_and_flush(L));
     std::vector<double> ybuf((size_t)count * (R + 1), 0.0);
+    const double gate = L->opt_x0_gate * 1e-6;
     for (int i = 0; i < count; ++i) {
       if (!has_x0[i]) continue;
       const double bm = part_sum(P, parts, i, 0), mm = part_sum(P, parts, i, 1);
-      ybuf[(size_t)i * (R + 1)] = (mm > 0.0 && std::isfinite(bm / mm)) ? bm / mm : 0.0;
+      double g = (mm > 0.0 && std::isfinite(bm / mm)) ? bm / mm : 0.0;
+      const double bb = bnorm_true[i] * bnorm_true[i];
+      // ||b - g M x0||^2 = ||b||^2 - <b, M x0>^2 / ||M x0||^2
+      const double rr = bb > 0.0 && mm > 0.0 ? std::max(0.0, bb - bm * (bm / mm)) : bb;
+      if (L->opt_x0_gate > 0 && !(rr <= gate * gate * bb)) g = 0.0;
+      ybuf[(size_t)i * (R + 1)] = g;
+      P->hs[i]->x0_kept = g != 0.0 ? 1 : 0;
     }
     HIPCHK(hipMemcpy(P->d_y, ybuf.data(), ybuf.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(run(L, "scale_x", 2.0 * S.vec_bytes, [&] { return launch_scale_x(P->d_desc, Sx0.kry, S.n_kry, stream); }));
@@ -2328,7 +2344,10 @@ static fde_status solve_plan(Plan *P, const double *const *u0, const double *con
   }
   std::vector<InstState> st(count);
   std::vector<char> has_x0(count, 0);
-  for (int i = 0; i < count; ++i) has_x0[i] = (x0 && x0[i]) ? 1 : 0;
+  for (int i = 0; i < count; ++i) {
+    has_x0[i] = (x0 && x0[i]) ? 1 : 0;
+    P->hs[i]->x0_kept = 0;
+  }
   fde_status gs = gmres_plan(P, o, has_x0, st);
   if (gs != FDE_OK && gs != FDE_ENOCONV) return gs;
   const std::string msg = g_err;

@@ -7,6 +7,7 @@ the data beyond moving it.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 
 import numpy as np
 
@@ -59,7 +60,6 @@ class DeviceArray:
             self._ptr = None
 
     def __del__(self):
-        import sys
         if sys.is_finalizing():
             return
         try:

@@ -55,6 +55,7 @@ def main():
     del data
     seeds = list(range(1_000_000, 1_000_000 + a.heldout))
     res = WS.evaluate(net, seeds, W.warmstart_instance, batch=a.batch, target=a.target)
+    res_all = WS.evaluate(net, seeds, W.warmstart_instance, batch=a.batch, target=a.target, gate=0)
     n = len(seeds)
     summary = {
         "workload": "m=255, s=128, GBDF3, u0=0, random alpha/d+-/f (seeds 0..%d train, 1e6.. held out)" % (a.train - 1),
@@ -63,6 +64,9 @@ def main():
         "epochs": a.epochs, "train_seconds": round(t_train, 2), "loss_history": [float(x) for x in hist],
         "iters_zero_mean": float(np.mean(res["iters_zero"])), "iters_warm_mean": float(np.mean(res["iters_warm"])),
         "iters_zero_max": int(np.max(res["iters_zero"])), "iters_warm_max": int(np.max(res["iters_warm"])),
+        "x0_gate": "library default (1e-2 of ||b||)", "x0_kept_fraction": float(np.mean(res["x0_kept"])),
+        "iters_warm_mean_every_guess_kept": float(np.mean(res_all["iters_warm"])),
+        "ms_per_instance_warm_incl_nn_every_guess_kept": res_all["ms_warm"] / n,
         "x0_rel_err_mean": float(np.mean(res["rel_err_x0"])), "x0_rel_err_median": float(np.median(res["rel_err_x0"])),
         "ms_per_instance_zero": res["ms_zero"] / n, "ms_per_instance_warm_incl_nn": res["ms_warm"] / n,
         "ms_per_instance_nn": res["ms_nn"] / n,

@@ -9,6 +9,7 @@ FP64 residual, so the warm start changes cost, never the answer.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import time
 from typing import Optional, Sequence
 
@@ -40,7 +41,6 @@ class WarmStartNet:
             self._h = None
 
     def __del__(self):
-        import sys
         if sys.is_finalizing():
             return
         try:
@@ -219,10 +219,12 @@ def train(net: WarmStartNet, data: dict, epochs: int = 20, batch: int = 64, lr: 
 
 
 def evaluate(net: WarmStartNet, seeds: Sequence[int], make_problem, batch: int = 64,
-             precision: str = "fp64", target: str = "solution"):
+             precision: str = "fp64", target: str = "solution", gate: Optional[int] = None):
     """GMRES iterations and solve time to rel-res 1e-10 with zero start and with the network's
     guess (inference time included), per instance, on the same batched solver.  With target
-    "lowrank" the guess is c ~ (S - M) u and the solve starts from S^{-1}(b + c)."""
+    "lowrank" the guess is c ~ (S - M) u and the solve starts from S^{-1}(b + c).  gate: the
+    solver's FDE_OPT_X0_GATE for the warm-started solves (None: the library default; 0 keeps
+    every guess); x0_kept records which guesses passed it."""
     import torch
     dev = torch.device("cuda:0")
     n = len(seeds)
@@ -230,10 +232,13 @@ def evaluate(net: WarmStartNet, seeds: Sequence[int], make_problem, batch: int =
     X = torch.zeros((min(batch, n), 256, net.cin), dtype=torch.float32, device=dev)
     rms = torch.zeros(min(batch, n), dtype=torch.float32, device=dev)
     res = {"iters_zero": [], "iters_warm": [], "ms_zero": 0.0, "ms_warm": 0.0, "ms_nn": 0.0,
-           "rel_err_x0": [], "relres_warm": [], "relres_zero": []}
+           "rel_err_x0": [], "relres_warm": [], "relres_zero": [], "x0_kept": []}
     for b0 in range(0, n, batch):
         ps = [make_problem(sd) for sd in seeds[b0:b0 + batch]]
         Ss = pool.load(ps)
+        if gate is not None:
+            for S in Ss:
+                S.set_option(N.FDE_OPT_X0_GATE, gate)
         factor_batch(Ss, precision)
         u0s = [_device(p.u0, torch, dev) for p in ps]
         fs = [_device(p.f, torch, dev) for p in ps]
@@ -263,6 +268,7 @@ def evaluate(net: WarmStartNet, seeds: Sequence[int], make_problem, batch: int =
             res["iters_warm"].append(inf1[i]["iters"])
             res["relres_zero"].append(inf0[i]["true_relres"])
             res["relres_warm"].append(inf1[i]["true_relres"])
+            res["x0_kept"].append(Ss[i].get_option(N.FDE_OPT_X0_KEPT))
             ref = outs0[i]
             if target == "lowrank":
                 ref = Ss[i].lowrank_correction(ref)

@@ -161,6 +161,34 @@ def test_deterministic_and_warm_start():
     assert i3["iters"] == 0 and _rel(u3, u1) <= 1e-12 and i3["true_relres"] <= 1e-10
 
 
+def test_initial_guess_gate():
+    """FDE_OPT_X0_GATE: a guess whose gamma-scaled residual exceeds the gate (default 1e-2 of
+    ||b||) is dropped, and the solve is then the zero-start solve bit for bit; with the gate off
+    (0) the same guess is used; a close guess passes the default gate and saves iterations."""
+    p, S = _setup("gbdf3_m200_s32")
+    S.factor("fp64")
+    assert S.get_option(N.FDE_OPT_X0_GATE) == 10000
+    u0, i0 = S.solve(p.u0, p.f)
+    assert S.get_option(N.FDE_OPT_X0_KEPT) == 0
+    xs = np.arange(1, p.m + 1) / (p.m + 1)
+    smooth = np.outer(np.ones(p.s), np.sin(np.pi * xs) + 0.3 * np.sin(3 * np.pi * xs))
+    rough = u0 + 0.05 * np.linalg.norm(u0) / np.linalg.norm(smooth) * smooth
+    u1, i1 = S.solve(p.u0, p.f, x0=rough)
+    assert S.get_option(N.FDE_OPT_X0_KEPT) == 0
+    assert np.array_equal(u1, u0) and i1["iters"] == i0["iters"]
+    S.set_option(N.FDE_OPT_X0_GATE, 0)
+    u2, i2 = S.solve(p.u0, p.f, x0=rough)
+    assert S.get_option(N.FDE_OPT_X0_KEPT) == 1 and i2["true_relres"] <= 1e-10
+    assert _rel(u2, u0) <= 1e-9
+    S.set_option(N.FDE_OPT_X0_GATE, 10000)
+    close = u0 + 1e-9 * np.linalg.norm(u0) / np.linalg.norm(smooth) * smooth
+    u3, i3 = S.solve(p.u0, p.f, x0=close)
+    assert S.get_option(N.FDE_OPT_X0_KEPT) == 1 and i3["iters"] < i0["iters"]
+    assert i3["true_relres"] <= 1e-10 and _rel(u3, u0) <= 1e-9
+    with pytest.raises(FdeError):
+        S.set_option(N.FDE_OPT_X0_GATE, -1)
+
+
 def test_lowrank_start_with_exact_correction_needs_no_iteration():
     """x0_kind = LOWRANK: with the exact c = (S - M) u the start S^{-1}(b + c) is u itself."""
     p, S = _setup("gbdf3_m200_s32")

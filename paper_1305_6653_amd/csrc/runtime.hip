@@ -927,6 +927,7 @@ static void destroy_handle(fde_bvm *h) {
 }
 
 extern "C" fde_status fde_bvm_setup(const fde_problem *p, fde_bvm **out) {
+  TraceRange tr_setup("fde_bvm_setup");
   if (!out) return fail(FDE_EINVAL, "out is NULL");
   *out = nullptr;
   if (!p) return fail(FDE_EINVAL, "problem is NULL");

@@ -1251,14 +1251,15 @@ struct BandWin {
 // once into LDS slices: wavefronts 0-7 form block row j + 1 <- bottom - M21 W, wavefronts 8-15
 // block row j <- L11^{-1} W = U12 (each a 32 x 16 part of its 64 x 64 tile, 3M complex MFMA
 // products over 8-deep K slices, double-buffered; 16 wavefronts per CU hide the slices'
-// latency).  The bottom rows are gathered and the new block row j + 1 stored before a barrier
-// after which block row j is overwritten, so every read of the window precedes the stores that
-// replace it.
+// latency).  The window's bottom rows are gathered into LDS with the first slices, so their
+// latency overlaps the products; the new block row j + 1 is stored before a barrier after which
+// block row j is overwritten, so every read of the window precedes the stores that replace it.
 static constexpr int BR_NT = 1024;
 template <typename T>
 struct RowsLds {
   c_t<T> As[2][2][PB][US + 1];  // [product][buffer]: M21 (0), L11^{-1} (1) slices, 64 rows x US
   c_t<T> Bs[2][US][PB + 1];     // W slices: US x 64 columns
+  c_t<T> Wb[PB][PB + 1];        // the window's reordered bottom rows, columns c0 .. c0 + 63
 };
 
 template <typename T>
@@ -1297,8 +1298,13 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
                         : (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)ar * PB + ac;
   C ra = ld_global<T>(Ap);
   C rb = bl ? win.get(br, c0 + bc) : mk<T>((T)0, (T)0);
+  C wb[PB * PB / BR_NT];  // bottom rows: thread t takes rows t / 64 + 16 i, column t % 64
+#pragma unroll
+  for (int i = 0; i < PB * PB / BR_NT; ++i) wb[i] = win.get(PB + (tid >> 6) + 16 * i, c0 + (tid & 63));
   sm.As[ap][0][ar][ac] = ra;
   if (bl) sm.Bs[0][br][bc] = rb;
+#pragma unroll
+  for (int i = 0; i < PB * PB / BR_NT; ++i) sm.Wb[(tid >> 6) + 16 * i][tid & 63] = wb[i];
   __syncthreads();
   acc_t<T> p1[2], p2[2], p3[2];
 #pragma unroll
@@ -1347,7 +1353,7 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = wr + r * 16 + mfma_row<T>(lk, v);
-        const C z = win.get(PB + row, c0 + wc + li);
+        const C z = sm.Wb[row][wc + li];
         K[(size_t)(r0 + PB + row) * mp + c0 + wc + li] = mk<T>(z.x - cre[r][v], z.y - cim[r][v]);
       }
   }

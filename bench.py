@@ -41,7 +41,7 @@ PMC_KERNEL_GROUP = {
     "trsv": "factor", "hess_uinv": "factor",
     "bvm_matvec": "spacetime", "time_rfft": "spacetime", "time_irfft": "spacetime",
     "bccb_solve": "spacetime", "rhs": "spacetime",
-    "mgs": "krylov", "cgs": "krylov", "normalize": "krylov", "residual": "krylov",
+    "mgs": "krylov", "cgs": "krylov", "arnoldi": "krylov", "normalize": "krylov", "residual": "krylov",
     "update_x": "krylov", "dot": "krylov",
     "hess_reduce": "hessenberg", "hess_lu": "hessenberg", "qgemm": "hessenberg",
     "hess_lsolve": "hessenberg",
@@ -304,7 +304,7 @@ def timed_steps(S, u0, f, out, prec, steps, warmup, pc=None):
     ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "bccb_solve", "time_rfft",
-              "time_irfft", "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot",
+              "time_irfft", "bvm_matvec", "mgs", "cgs", "arnoldi", "normalize", "residual", "update_x", "rhs", "dot",
               "hess_reduce", "hess_formq", "hess_lu", "hess_uinv", "qgemm", "hess_lsolve",
               "band_init", "band_panel", "band_update", "band_finish", "band_lu_panel", "band_lu_rows",
               "band_lu_step", "band_lsolve"):
@@ -496,7 +496,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     prof = {}
     for k in ("assemble", "lu_diag", "lu_panel", "lu_update", "trsv", "time_rfft", "time_irfft",
-              "bvm_matvec", "mgs", "cgs", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
+              "bvm_matvec", "mgs", "cgs", "arnoldi", "normalize", "residual", "update_x", "rhs", "dot", "toeplitz"):
         q = lead.profile_query(k)
         if q["count"]:
             prof[k] = q

@@ -179,12 +179,16 @@ fde_status fde_get_dims(const fde_bvm *h, int *dims);
  * replayed; if recording fails they are launched directly, with identical results.
  *   FDE_OPT_GRAPHS        1 (default): replay recorded sequences; 0: launch directly.
  *   FDE_OPT_AUTOTUNE      1 (default): on the first solve of a shape (the sizes of all
- *                         instances of the call and the precision), time the cooperative
- *                         block solve for every candidate number of workgroups per block and
- *                         keep the fastest for the life of the process.
+ *                         instances of the call and the precision), time the block solve in
+ *                         its ordinary one-workgroup-per-block launch and in the cooperative
+ *                         launch for every candidate number of workgroups per block, and keep
+ *                         the fastest for the life of the process.  Every launch form gives
+ *                         the same bits.
  *   FDE_OPT_TRSV_W        0 (default): autotuned or the largest co-resident value;
- *                         k > 0: at most k workgroups per block (clamped to what fits).
- *   FDE_OPT_TRSV_W_IN_USE read-only: workgroups per block of the handle's last plan.
+ *                         k > 0: cooperative, at most k workgroups per block (clamped to what
+ *                         fits); -1: the ordinary launch, one workgroup per block, no flags.
+ *   FDE_OPT_TRSV_W_IN_USE read-only: workgroups per block of the handle's last plan's
+ *                         cooperative block solve, 0 for the ordinary launch.
  *   FDE_OPT_GRAPHS_IN_USE read-only: 1 if the handle's solves replay recorded sequences.
  * Options of the first handle of a batch call apply to the call.  Setting an option
  * synchronises the handle's stream.  Unknown options return FDE_EINVAL. */

@@ -692,74 +692,11 @@ __global__ __launch_bounds__(256, 3) void k_lu_update(const InstDesc *__restrict
 }
 
 // ------------------------------------------------------------------------------------
-// Block solves K_k w = v in place on Vh[k] (FP64 vectors, factors of type T).
-// One workgroup per block: per 64-row panel an off-diagonal GEMV streamed from HBM,
-// then the 64x64 inverse of the diagonal triangle.
-static constexpr int TS_NT = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(TS_NT) void k_trsv(const InstDesc *__restrict__ Dd, ItemMap map) {
-  extern __shared__ double2 sh[];
-  const int q = item_slot(map, blockIdx.x);
-  if (item_gated(map, q)) return;
-  const InstDesc &d = Dd[map.ids[q]];
-  const int mp = d.mp, npan = d.npan;
-  // the item map counts nb * W items per instance; one workgroup per block does the solve
-  const int local = blockIdx.x - map.pre[q];
-  if (local % d.W != 0) return;
-  const int blk = local / d.W;
-  double2 *y = sh;
-  double2 *tmp = sh + mp;
-  const c_t<T> *dinv = (const c_t<T> *)d.dinv;
-  const c_t<T> *A = (const c_t<T> *)d.K + (size_t)blk * mp * mp;
-  double2 *v = d.Vts + (size_t)blk * mp;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int NW = TS_NT / 64;
-  for (int i = threadIdx.x; i < mp; i += TS_NT) y[i] = v[i];
-  __syncthreads();
-  for (int P = 0; P < npan; ++P) {
-    const int p0 = P * PB;
-    for (int rr = wave; rr < PB; rr += NW) {
-      const c_t<T> *row = A + (size_t)(p0 + rr) * mp;
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 8
-      for (int c = lane; c < p0; c += 64) acc = cfma(widen(row[c]), y[c], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) tmp[rr] = csub(y[p0 + rr], acc);
-    }
-    __syncthreads();
-    const c_t<T> *Li = dinv + ((size_t)(blk * npan + P) * 2 + 0) * PB * PB;
-    for (int rr = wave; rr < PB; rr += NW) {
-      double2 acc = cfma(widen(Li[rr * PB + lane]), tmp[lane], make_double2(0.0, 0.0));
-      acc = wave_sum(acc);
-      if (lane == 0) y[p0 + rr] = acc;
-    }
-    __syncthreads();
-  }
-  for (int P = npan - 1; P >= 0; --P) {
-    const int p0 = P * PB;
-    for (int rr = wave; rr < PB; rr += NW) {
-      const c_t<T> *row = A + (size_t)(p0 + rr) * mp;
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 8
-      for (int c = p0 + PB + lane; c < mp; c += 64) acc = cfma(widen(row[c]), y[c], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) tmp[rr] = csub(y[p0 + rr], acc);
-    }
-    __syncthreads();
-    const c_t<T> *Ui = dinv + ((size_t)(blk * npan + P) * 2 + 1) * PB * PB;
-    for (int rr = wave; rr < PB; rr += NW) {
-      double2 acc = cfma(widen(Ui[rr * PB + lane]), tmp[lane], make_double2(0.0, 0.0));
-      acc = wave_sum(acc);
-      if (lane == 0) y[p0 + rr] = acc;
-    }
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < mp; i += TS_NT) v[i] = y[i];
-}
-
-// ------------------------------------------------------------------------------------
-// Block solves with several workgroups per block (cooperative launch, all workgroups
+// Block solves K_k w = v in place on Vts[k] (FP64 vectors, factors of type T): per 64-row
+// panel an off-diagonal GEMV streamed from HBM, then the 64x64 inverse of the diagonal
+// triangle (dinv).
+//
+// Several workgroups per block (cooperative launch, all workgroups
 // co-resident).  Item (k, w), w < W, owns the 64-row panels P = w, w+W, ... of block k in
 // both sweeps.  Panel P of the forward sweep needs y_Q for every Q < P: the owner streams
 // L[P][Q] as soon as y_Q is published (flag[k][Q][0] == epoch), so the bulk of the bytes
@@ -928,8 +865,10 @@ __device__ __forceinline__ bool ts_wait(const unsigned long long *flag, unsigned
 // are published, subtract, multiply by the diagonal inverse, publish.  need_fwd (backward
 // sweep, panels handed out dynamically): the forward result of this panel may come from
 // another workgroup, so its flag is awaited before it is read.  Returns false if a wait was
-// abandoned.  Every thread of the workgroup calls it.
-template <typename T>
+// abandoned.  Every thread of the workgroup calls it.  SOLO: the workgroup owns the whole
+// block, so every piece it reads was stored by itself before a barrier: no flag is read or
+// raised (the arithmetic is the same, so the result is the same to the bit).
+template <typename T, bool SOLO = false>
 __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int sweep,
                                            bool need_fwd, unsigned long long epoch, int *err,
                                            int *ready_slot, int &calls, double2 *tmp) {
@@ -954,6 +893,17 @@ __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int 
   double2 acc[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) acc[g] = make_double2(0.0, 0.0);
+  // SOLO: the diagonal inverse depends on nothing, so its loads are issued first and fly
+  // while the panel's right-hand side is formed
+  int glo = 0, ghi = 3;
+  if constexpr (sizeof(T) == 8) tri_groups(sweep, __builtin_amdgcn_readfirstlane(r16), glo, ghi);
+  c_t<T> ad[4][4];
+  if (SOLO) {
+    if constexpr (sizeof(T) == 8)
+      chunk_load_groups<T>(Di + (size_t)r16 * PB, PB, ad, glo, ghi);
+    else
+      chunk_load<T>(Di + (size_t)r16 * PB, PB, ad);
+  }
   const int nq = sweep == 0 ? P : npan - 1 - P;
   int have = 0;  // chunks t < have are known to be published
   for (int t = 0; t < nq; ++t) {
@@ -963,7 +913,7 @@ __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int 
     constexpr bool early = sizeof(T) == 4;
     c_t<T> a[4][4];
     if (early) chunk_load<T>(A + (size_t)(p0 + r16) * mp + (size_t)Q * PB, mp, a);
-    if (t >= have) {
+    if (!SOLO && t >= have) {
       have = ts_ready(fl, sweep, npan, t, nq, epoch, err, &ready_slot[calls++ & 1]);
       if (have < 0) return false;
     }
@@ -979,7 +929,7 @@ __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int 
     }
     chunk_fma<T>(a, x, acc);
   }
-  if (need_fwd && !ts_wait(&fl[P * 2 + 0], epoch, err, &ready_slot[calls++ & 1])) return false;
+  if (!SOLO && need_fwd && !ts_wait(&fl[P * 2 + 0], epoch, err, &ready_slot[calls++ & 1])) return false;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     acc[g] = sum16(acc[g]);
@@ -996,12 +946,12 @@ __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int 
   for (int g = 0; g < 4; ++g) b[g] = make_double2(0.0, 0.0);
 #pragma unroll
   for (int u = 0; u < TL; ++u) b[0].x = fma(touch[u], 0.0, b[0].x);
-  {
+  if (SOLO) {
+    chunk_fma<T>(ad, x, b);
+  } else {
     // FP64: only the column groups of the triangular inverse that meet this wave's rows are
     // read (5/8 of the tile on average).  (FP32 reads the whole tile: with its touched lines in
     // L2 the conditional loads cost more than they save.)
-    int glo = 0, ghi = 3;
-    if constexpr (sizeof(T) == 8) tri_groups(sweep, __builtin_amdgcn_readfirstlane(r16), glo, ghi);
     c_t<T> a[4][4];
     if constexpr (sizeof(T) == 8)
       chunk_load_groups<T>(Di + (size_t)r16 * PB, PB, a, glo, ghi);
@@ -1014,8 +964,35 @@ __device__ __forceinline__ bool trsv_panel(const InstDesc &d, int k, int P, int 
     b[g] = sum16(b[g]);
     if (cs == 0) st_coh(&v[p0 + r16 + 4 * g + rs], b[g]);
   }
-  ts_publish(&fl[P * 2 + sweep], epoch);
+  if (SOLO) {
+    __builtin_amdgcn_s_waitcnt(0);  // the next panel reads these entries
+    __syncthreads();
+  } else {
+    ts_publish(&fl[P * 2 + sweep], epoch);
+  }
   return true;
+}
+
+// One workgroup per block, no flags (an ordinary launch): the panels of both sweeps (the U
+// sweep only for first_sweep = 1) in order, by the cooperative kernel's panel code, so the
+// result equals its result for any W.  The item map counts nb W items per instance; the
+// workgroup of item k W solves block k, the others return.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_trsv(const InstDesc *__restrict__ Dd, ItemMap map,
+                                              int first_sweep) {
+  __shared__ double2 tmp[PB];
+  __shared__ int ready_slot[2];
+  int calls = 0;
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const InstDesc &d = Dd[map.ids[q]];
+  const int local = blockIdx.x - map.pre[q];
+  if (local % d.W != 0) return;
+  const int k = local / d.W, npan = d.npan;
+  for (int sweep = first_sweep; sweep < 2; ++sweep)
+    for (int t = 0; t < npan; ++t)
+      trsv_panel<T, true>(d, k, sweep == 0 ? t : npan - 1 - t, sweep, false, 0ull, nullptr, ready_slot,
+                          calls, tmp);
 }
 
 // Two ways of handing out the panels.  Static (npan_u = 0): item (k, w), w < W, owns the panels
@@ -1500,16 +1477,10 @@ hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, in
 }
 
 template <typename T>
-hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max_mp,
+hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int first_sweep,
                        hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  const size_t lds = sizeof(double2) * (max_mp + PB);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_trsv<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_trsv<T>, dim3(items), dim3(TS_NT), lds, st, D, map);
+  hipLaunchKernelGGL(k_trsv<T>, dim3(items), dim3(256), 0, st, D, map, first_sweep);
   return hipGetLastError();
 }
 

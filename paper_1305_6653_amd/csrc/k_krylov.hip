@@ -17,13 +17,20 @@
 // completed.
 #include "batch.hpp"
 #include "common.hpp"
+#include "gmres_step.hpp"
 #include "kernels.hpp"
 
 namespace fde {
 
 static constexpr int KR_NT = 256;
+// Vectors of up to KR_ONE_MAX entries form one chunk (one workgroup per reduction), which
+// lets a whole Arnoldi step run in one launch (k_arnoldi1).
+static constexpr size_t KR_ONE_MAX = 8192;
+
+size_t krylov_one_max() { return KR_ONE_MAX; }
 
 int krylov_blocks(size_t n) {
+  if (n <= KR_ONE_MAX) return 1;
   size_t b = (n + 1023) / 1024;
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
@@ -259,6 +266,214 @@ __global__ __launch_bounds__(KR_NT) void k_mgs_step(const InstDesc *__restrict__
   }
   acc = block_sum<KR_NT>(acc, red);
   if (threadIdx.x == 0) pout[c.b] = acc;
+}
+
+// Arnoldi step j of instances whose vectors are one chunk (nblk = 1): the modified
+// Gram-Schmidt projections on v_0 .. v_j, the norm of the remainder, v_{j+1} and the Givens
+// update of the control record, in one launch of one workgroup per instance instead of the
+// j + 4 launches of the chain (k_mgs_step i = 0 .. j+1, k_normalize, k_gm_givens).  Each
+// thread takes the elements it takes in the chain (e = t + KR_NT u) in the same order; w stays
+// in registers between projections, and each basis vector is read once (v_{i-1} is kept from
+// the projection before).  The reductions are the chain's: block_sum, then the one-chunk
+// partial sum 0 + p (sum_partials over a single partial), so the H column, w, v_{j+1} and the
+// control record equal the chain's to the bit.  U = elements per thread (n <= KR_NT U).
+template <int U>
+__global__ __launch_bounds__(KR_NT) void k_arnoldi1(const InstDesc *__restrict__ D, ItemMap map,
+                                                    int j, GmresCtl *__restrict__ ctl,
+                                                    GmresWork *__restrict__ work,
+                                                    int *__restrict__ gates, int count, int R) {
+  __shared__ double red[KR_NT / 64];
+  const int q = item_slot(map, blockIdx.x);
+  if (item_gated(map, q)) return;
+  const int inst = map.ids[q];
+  const InstDesc &d = D[inst];
+  const size_t n = (size_t)d.s * d.m;
+  const int t = threadIdx.x;
+  double w[U], cv[U], pv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const size_t e = (size_t)t + (size_t)u * KR_NT;
+    w[u] = e < n ? d.w[e] : 0.0;
+    cv[u] = e < n ? d.V[e] : 0.0;
+    pv[u] = 0.0;
+  }
+  double h = 0.0;
+  for (int i = 0; i <= j + 1; ++i) {
+    // i <= j: w -= h_{i-1} v_{i-1} (i > 0), partial <v_i, w>;  i = j + 1: the last
+    // subtraction and <w, w>
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if ((size_t)t + (size_t)u * KR_NT < n) {
+        const double x = i > 0 ? fma(-h, pv[u], w[u]) : w[u];
+        acc = fma(i <= j ? cv[u] : x, x, acc);
+        w[u] = x;
+      }
+    }
+    if (i <= j) {  // the next pass needs v_i and v_{i+1}; the loads fly during the reduction
+      const double *vn = d.V + (size_t)(i + 1) * n;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t e = (size_t)t + (size_t)u * KR_NT;
+        pv[u] = cv[u];
+        cv[u] = (i + 1 <= j && e < n) ? vn[e] : 0.0;
+      }
+    }
+    acc = block_sum<KR_NT>(acc, red);
+    h = 0.0 + acc;
+    if (t == 0 && i <= j) d.H[i] = h;
+  }
+  const double nrm = sqrt(h);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double *vj1 = d.V + (size_t)(j + 1) * n;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const size_t e = (size_t)t + (size_t)u * KR_NT;
+    if (e < n) {
+      d.w[e] = w[u];
+      vj1[e] = w[u] * inv;
+    }
+  }
+  if (t == 0) {
+    d.H[j + 1] = nrm;
+    gm_givens_one(d, ctl[inst], work[inst], gates, count, inst, j, R);
+  }
+}
+
+hipError_t launch_arnoldi1(const InstDesc *D, const ItemMap &map, int items, size_t max_n, int j,
+                           GmresCtl *ctl, GmresWork *work, int *gates, int count, int R,
+                           hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  if (max_n <= (size_t)KR_NT * 16) {
+    hipLaunchKernelGGL(k_arnoldi1<16>, dim3(items), dim3(KR_NT), 0, st, D, map, j, ctl, work, gates, count, R);
+  } else if (max_n <= KR_ONE_MAX) {
+    static_assert(KR_ONE_MAX == (size_t)KR_NT * 32, "one-chunk limit");
+    hipLaunchKernelGGL(k_arnoldi1<32>, dim3(items), dim3(KR_NT), 0, st, D, map, j, ctl, work, gates, count, R);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The restart step's tail for one-chunk instances: v_0 = (b - tmp) / ||b - tmp|| with the norm
+// into nrm[0] (k_residual, then k_normalize) for live instances, then the restart decision
+// (k_gm_restart) for every instance, in one launch; the same bits as those three launches.
+// Item = instance (the Krylov map without its gate).
+template <int U>
+__global__ __launch_bounds__(KR_NT) void k_restart1(const InstDesc *__restrict__ D, ItemMap map,
+                                                    GmresCtl *__restrict__ ctl,
+                                                    GmresWork *__restrict__ work,
+                                                    int *__restrict__ gates, int count) {
+  __shared__ double red[KR_NT / 64];
+  const int inst = map.ids[item_slot(map, blockIdx.x)];
+  const InstDesc &d = D[inst];
+  const int t = threadIdx.x;
+  if (gates[GATE_LIVE * count + inst]) {
+    const size_t n = (size_t)d.s * d.m;
+    double r[U];
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t e = (size_t)t + (size_t)u * KR_NT;
+      r[u] = 0.0;
+      if (e < n) {
+        r[u] = d.b[e] - d.tmp[e];
+        acc = fma(r[u], r[u], acc);
+      }
+    }
+    acc = block_sum<KR_NT>(acc, red);
+    const double nrm = sqrt(0.0 + acc);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t e = (size_t)t + (size_t)u * KR_NT;
+      if (e < n) d.V[e] = r[u] * inv;
+    }
+    if (t == 0) d.nrm[0] = nrm;
+  }
+  if (t == 0) gm_restart_one(d, ctl[inst], work[inst], gates, count, inst);
+}
+
+// The end of a cycle for one-chunk instances: y = H^{-1} g (k_gm_backsolve) for every
+// instance, then x += sum_{j<k} y_j Q_j (k_update_x) for live instances, in one launch; the
+// same bits.  Item = instance (the Krylov map without its gate).
+template <int U>
+__global__ __launch_bounds__(KR_NT) void k_finish1(const InstDesc *__restrict__ D, ItemMap map,
+                                                   GmresCtl *__restrict__ ctl,
+                                                   const GmresWork *__restrict__ work,
+                                                   const int *__restrict__ gates, int count,
+                                                   int basis_sel) {
+  __shared__ double ys[GM_RMAX + 1];
+  __shared__ double Hs[GM_RMAX][GM_RMAX + 1], gs[GM_RMAX];
+  const int inst = map.ids[item_slot(map, blockIdx.x)];
+  const InstDesc &d = D[inst];
+  const int t = threadIdx.x;
+  // the k x k triangle of H and g staged in LDS by every thread (independent loads), so the
+  // back substitution (one thread) runs on LDS instead of a chain of dependent global loads
+  const int kk = ctl[inst].k;
+  for (int e = t; e < kk * kk; e += KR_NT) {
+    const int r = e / kk, q = e % kk;
+    if (q >= r) Hs[r][q] = work[inst].H[r][q];
+  }
+  for (int r = t; r < kk; r += KR_NT) gs[r] = work[inst].g[r];
+  __syncthreads();
+  if (t == 0) {
+    gm_backsolve_lds(ctl[inst], Hs, gs, ys);
+    for (int q = 0; q <= kk; ++q) d.y[q] = ys[q];
+  }
+  __syncthreads();
+  if (!gates[GATE_LIVE * count + inst]) return;
+  const size_t n = (size_t)d.s * d.m;
+  const int k = (int)ys[0];
+  const double *Q = basis_sel == VS_V ? d.V : d.Z;
+  double acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const size_t e = (size_t)t + (size_t)u * KR_NT;
+    acc[u] = e < n ? d.x[e] : 0.0;
+  }
+  for (int j = 0; j < k; ++j) {
+    const double yj = ys[1 + j];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t e = (size_t)t + (size_t)u * KR_NT;
+      if (e < n) acc[u] = fma(yj, Q[(size_t)j * n + e], acc[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const size_t e = (size_t)t + (size_t)u * KR_NT;
+    if (e < n) d.x[e] = acc[u];
+  }
+}
+
+hipError_t launch_restart1(const InstDesc *D, const ItemMap &map, int items, size_t max_n,
+                           GmresCtl *ctl, GmresWork *work, int *gates, int count, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  ItemMap all = map;
+  all.gate = nullptr;
+  if (max_n <= (size_t)KR_NT * 16)
+    hipLaunchKernelGGL(k_restart1<16>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count);
+  else if (max_n <= KR_ONE_MAX)
+    hipLaunchKernelGGL(k_restart1<32>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_finish1(const InstDesc *D, const ItemMap &map, int items, size_t max_n,
+                          GmresCtl *ctl, const GmresWork *work, const int *gates, int count,
+                          int basis_sel, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  ItemMap all = map;
+  all.gate = nullptr;
+  if (max_n <= (size_t)KR_NT * 16)
+    hipLaunchKernelGGL(k_finish1<16>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
+  else if (max_n <= KR_ONE_MAX)
+    hipLaunchKernelGGL(k_finish1<32>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // nrm = sqrt(sum of part[psel]); dst = src / nrm (0 if nrm == 0).  The norm is stored in

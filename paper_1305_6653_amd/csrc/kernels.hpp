@@ -54,9 +54,12 @@ hipError_t launch_lu_panel(const InstDesc *D, const ItemMap &map, int items, int
 template <typename T>
 hipError_t launch_lu_update(const InstDesc *D, const ItemMap &map, int items, int p, int mode,
                             hipStream_t st);
-// one workgroup per block: items = nb per instance
+// one workgroup per block, an ordinary launch with no flags: items = nb W per instance (the
+// item k W solves block k); the same panel arithmetic as launch_trsv_coop, so the same bits.
+// first_sweep = 1 runs the U sweep only.
 template <typename T>
-hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int max_mp, hipStream_t st);
+hipError_t launch_trsv(const InstDesc *D, const ItemMap &map, int items, int first_sweep,
+                       hipStream_t st);
 // several workgroups per block (descriptor field W), cooperative launch: items = nb W per
 // instance; flags in the descriptors hold the epoch of the last published panel; the epoch of
 // this launch is read from *epoch (device memory, written by the preceding time FFT); *err is
@@ -75,6 +78,23 @@ int trsv_coop_capacity();
 
 // ---- Krylov BLAS-1 (FP64, deterministic reductions), items = nblk per instance ----
 int krylov_blocks(size_t n);
+// largest vector length that krylov_blocks makes one chunk
+size_t krylov_one_max();
+// Arnoldi step j in one launch when every instance's vectors are one chunk (n <= max_n <=
+// krylov_one_max()): the MGS projections, the norm, v_{j+1} and the Givens update of the
+// control record (the work of launch_mgs_step i = 0..j+1, launch_normalize and
+// launch_gm_givens), with the same bits.  items = 1 per instance (the Krylov map).
+hipError_t launch_arnoldi1(const InstDesc *D, const ItemMap &map, int items, size_t max_n, int j,
+                           GmresCtl *ctl, GmresWork *work, int *gates, int count, int R,
+                           hipStream_t st);
+// The same for the restart step's tail (residual, its norm, v_0, the restart decision) and
+// for the end of a cycle (back substitution, x += Q y), one-chunk instances only; items = 1
+// per instance (the Krylov map; its gate is ignored: the kernels read the live gate).
+hipError_t launch_restart1(const InstDesc *D, const ItemMap &map, int items, size_t max_n,
+                           GmresCtl *ctl, GmresWork *work, int *gates, int count, hipStream_t st);
+hipError_t launch_finish1(const InstDesc *D, const ItemMap &map, int items, size_t max_n,
+                          GmresCtl *ctl, const GmresWork *work, const int *gates, int count,
+                          int basis_sel, hipStream_t st);
 // Modified Gram-Schmidt step i of Arnoldi column j (i = 0..j+1, one launch each): h_{i-1} from
 // the partials of launch i-1, w -= h_{i-1} v_{i-1}, partial <v_i, w> (<w, w> for i = j+1).
 hipError_t launch_mgs_step(const InstDesc *D, const ItemMap &map, int items, int i, int j,

@@ -353,6 +353,8 @@ struct SolveMaps {
   int tfft_cols = 16;  // spatial columns per time-FFT workgroup
   int npan_u = 0;      // panels per block if every instance has the same count, else 0
   int prec = -1;
+  int trsv_solo = 0;   // block solve by one workgroup per block, an ordinary launch (k_trsv)
+  size_t kry_one_n = 0;  // largest vector if every instance's vectors are one chunk, else 0
   double trsv_bytes = 0, vec_bytes = 0, tfft_bytes = 0, bccb_bytes = 0, qg_flops = 0, band_l_bytes = 0;
 };
 
@@ -385,9 +387,15 @@ struct Plan {
   unsigned long long *d_epoch = nullptr;  // epoch of this plan's current block solve
   std::vector<GmresCtl> ctl_host;
   std::vector<int> gates_host;
+  // pinned host staging: the control records and the block-solve error flag read back once
+  // per cycle, the control records and gates uploaded once per solve (pin_* byte offsets)
+  void *pin = nullptr;
+  size_t pin_err = 0, pin_ctl_up = 0, pin_gates_up = 0;
+  double *pin_parts = nullptr;  // the reduction partials read back for the norms of b
   // solve maps over all instances, in their own allocation (recorded graphs refer to them)
   SolveMaps full;
   bool full_ok = false;
+  bool trsv_solo = false;  // the block solve's launch form (see trsv_solo_choice)
   int *d_fullmaps = nullptr;
   size_t fullmaps_ints = 0;
   std::vector<int> fullmaps_host;
@@ -430,6 +438,8 @@ static void plan_free(Plan *P) {
   if (graphs_recorded(P)) (void)hipStreamSynchronize(P->lead->stream);
   graphs_invalidate(P);
   for (void *p : P->allocs) (void)hipFree(p);
+  if (P->pin) (void)hipHostFree(P->pin);
+  if (P->pin_parts) (void)hipHostFree(P->pin_parts);
   delete P;
 }
 
@@ -607,18 +617,20 @@ static int trsv_wmax(const Plan *P, const fde_bvm *h, int prec) {
   return (int)std::max(1L, std::min<long>(h->npan, w));
 }
 
+// The value -1 (option or autotuner) selects the ordinary one-workgroup-per-block launch.
+static int trsv_choice(const Plan *P, int prec, int wmax) {
+  if (P->lead->opt_trsv_w != 0) return P->lead->opt_trsv_w;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tuned_w.find(plan_shape_key(P, prec));
+  return it != g_tuned_w.end() ? it->second : wmax;
+}
+
 static int trsv_workgroups(const Plan *P, const fde_bvm *h, int prec) {
   const int wmax = trsv_wmax(P, h, prec);
-  int w = wmax;
-  if (P->lead->opt_trsv_w > 0) {
-    w = P->lead->opt_trsv_w;
-  } else {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tuned_w.find(plan_shape_key(P, prec));
-    if (it != g_tuned_w.end()) w = it->second;
-  }
-  return std::max(1, std::min(wmax, w));
+  return std::max(1, std::min(wmax, trsv_choice(P, prec, wmax)));
 }
+
+static bool trsv_solo_choice(const Plan *P, int prec) { return trsv_choice(P, prec, 1) == -1; }
 
 static fde_status plan_prepare(Plan *P, int R, int prec) {
   const int count = (int)P->hs.size();
@@ -640,6 +652,9 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     void *p = nullptr;
     STCHK(plan_alloc(P, &p, parts * sizeof(double)));
     P->d_part = (double *)p;
+    if (P->pin_parts) (void)hipHostFree(P->pin_parts);
+    P->pin_parts = nullptr;
+    HIPCHK(hipHostMalloc((void **)&P->pin_parts, parts * sizeof(double), hipHostMallocDefault));
     STCHK(plan_alloc(P, &p, (size_t)count * (R + 2) * sizeof(double)));
     P->d_H = (double *)p;
     STCHK(plan_alloc(P, &p, (size_t)count * (R + 1) * sizeof(double)));
@@ -655,6 +670,9 @@ static fde_status plan_prepare(Plan *P, int R, int prec) {
     P->desc_dirty = true;
   }
   P->desc.resize(count);
+  const bool solo = trsv_solo_choice(P, prec);
+  if (solo != P->trsv_solo) P->full_ok = false;  // the launch sequence changes: new graphs
+  P->trsv_solo = solo;
   for (int i = 0; i < count; ++i) {
     fde_bvm *h = P->hs[i];
     InstDesc d = make_desc(h);
@@ -718,6 +736,14 @@ static fde_status plan_create(const std::vector<fde_bvm *> &hs, Plan **out) {
   }
   P->ctl_host.assign(count, GmresCtl{});
   P->gates_host.assign(GATE_COUNT * count, 0);
+  P->pin_err = ctl_bytes;
+  P->pin_ctl_up = ctl_bytes + 256;
+  P->pin_gates_up = 2 * ctl_bytes + 256;
+  if (hipHostMalloc(&P->pin, 2 * ctl_bytes + 256 + gate_bytes, hipHostMallocDefault) != hipSuccess) {
+    P->pin = nullptr;
+    plan_free(P);
+    return fail(FDE_EDEVICE, "pinned host buffer allocation failed");
+  }
   P->desc.resize(hs.size());
   std::memset(P->desc.data(), 0, sizeof(InstDesc) * hs.size());
   *out = P;
@@ -1147,7 +1173,7 @@ extern "C" fde_status fde_bvm_set_option(fde_bvm *h, int option, int value) {
       h->opt_autotune = value ? 1 : 0;
       return FDE_OK;
     case FDE_OPT_TRSV_W:
-      if (value < 0 || value > 1024) return fail(FDE_EINVAL, "FDE_OPT_TRSV_W must be in 0..1024");
+      if (value < -1 || value > 1024) return fail(FDE_EINVAL, "FDE_OPT_TRSV_W must be in -1..1024");
       h->opt_trsv_w = value;
       return FDE_OK;
     case FDE_OPT_PRECOND:
@@ -1189,7 +1215,9 @@ extern "C" fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value) {
     case FDE_OPT_GRAPHS: *value = h->opt_graphs; return FDE_OK;
     case FDE_OPT_AUTOTUNE: *value = h->opt_autotune; return FDE_OK;
     case FDE_OPT_TRSV_W: *value = h->opt_trsv_w; return FDE_OK;
-    case FDE_OPT_TRSV_W_IN_USE: *value = h->self->desc.empty() ? 0 : h->self->desc[0].W; return FDE_OK;
+    case FDE_OPT_TRSV_W_IN_USE:
+      *value = h->self->desc.empty() || h->self->trsv_solo ? 0 : h->self->desc[0].W;
+      return FDE_OK;
     case FDE_OPT_GRAPHS_IN_USE: *value = graphs_recorded(h->self) ? 1 : 0; return FDE_OK;
     case FDE_OPT_SIDE: *value = h->opt_side; return FDE_OK;
     case FDE_OPT_BLOCKS: *value = h->opt_blocks; return FDE_OK;
@@ -1631,7 +1659,8 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
       if (h->self) h->self->desc_dirty = true;
     }
   }
-  P->desc_dirty = true;
+  // plan_prepare uploads the descriptors only if one of them changed (a refactorisation of
+  // the same shape keeps them, and needs no host round trip here)
   STCHK(plan_prepare(P, std::max(P->R, 1), prec));
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipMemsetAsync(P->d_flag, 0, sizeof(int), L->stream));
@@ -1777,6 +1806,11 @@ static fde_status ensure_full_maps(Plan *P) {
   S.n_rhs = hm[4].items;
   S.n_ju0 = hm[5].items;
   S.prec = prec;
+  S.trsv_solo = P->trsv_solo ? 1 : 0;
+  S.kry_one_n = 0;
+  for (fde_bvm *h : P->hs) S.kry_one_n = std::max(S.kry_one_n, h->n());
+  for (fde_bvm *h : P->hs)
+    if (h->nblk != 1) S.kry_one_n = 0;
   S.npan_u = P->hs[0]->npan;
   for (fde_bvm *h : P->hs)
     if (h->npan != S.npan_u) S.npan_u = 0;
@@ -1793,9 +1827,27 @@ static fde_status op_matvec(Plan *P, const SolveMaps &S, int src, int sj, int ds
   return FDE_OK;
 }
 
-// The cooperative block solve is used unless the device refuses cooperative launches
-// (then one workgroup per block, k_trsv); decided once per process, never while recording.
+// Cooperative block solves are used unless the device refuses cooperative launches (then the
+// ordinary launch, k_trsv); decided once per process, never while recording.
 static bool g_coop_ok = true;
+
+// The block solve (both sweeps, or the U sweep only for first_sweep = 1) in the plan's launch
+// form; a device that refuses the cooperative launch gets the ordinary one.
+static hipError_t block_solve(Plan *P, const SolveMaps &S, int first_sweep, hipStream_t st) {
+  if (!S.trsv_solo && g_coop_ok) {
+    const hipError_t e =
+        S.prec == FDE_FP64
+            ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, first_sweep,
+                                       &S.blk, S.n_blk, S.npan_u)
+            : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, first_sweep,
+                                      &S.blk, S.n_blk, S.npan_u);
+    if (e == hipSuccess || g_capture) return e;  // a refusal while recording ends the recording
+    (void)hipGetLastError();
+    g_coop_ok = false;
+  }
+  return S.prec == FDE_FP64 ? launch_trsv<double>(P->d_desc, S.trsv, S.n_trsv, first_sweep, st)
+                            : launch_trsv<float>(P->d_desc, S.trsv, S.n_trsv, first_sweep, st);
+}
 
 static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int dst, int dj) {
   fde_bvm *L = P->lead;
@@ -1831,14 +1883,7 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
       return S.prec == FDE_FP64 ? launch_band_lsolve<double>(P->d_desc, S.blk, S.n_blk, st)
                                 : launch_band_lsolve<float>(P->d_desc, S.blk, S.n_blk, st);
     }));
-    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
-      if (!g_coop_ok) return hipErrorNotSupported;
-      return S.prec == FDE_FP64
-                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
-                                            &S.blk, S.n_blk, S.npan_u)
-                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
-                                           &S.blk, S.n_blk, S.npan_u);
-    }));
+    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] { return block_solve(P, S, 1, st); }));
     HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
       return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
@@ -1852,36 +1897,14 @@ static fde_status op_precond(Plan *P, const SolveMaps &S, int src, int sj, int d
     HIPCHK(run(L, "hess_lsolve", S.bccb_bytes, [&] {
       return launch_hess_lsolve(P->d_desc, S.blk, S.n_blk, S.max_mp, st);
     }));
-    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
-      if (!g_coop_ok) return hipErrorNotSupported;
-      return S.prec == FDE_FP64
-                 ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
-                                            &S.blk, S.n_blk, S.npan_u)
-                 : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 1,
-                                           &S.blk, S.n_blk, S.npan_u);
-    }));
+    HIPCHK(run(L, "trsv", S.trsv_bytes, [&] { return block_solve(P, S, 1, st); }));
     HIPCHK(run(L, "qgemm", S.qg_flops, [&] { return launch_qgemm(P->d_desc, S.qg, S.n_qg, 1, 1, st); }));
     HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
       return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
     }));
     return FDE_OK;
   }
-  HIPCHK(run(L, "trsv", S.trsv_bytes, [&] {
-    hipError_t e = hipErrorNotSupported;
-    if (g_coop_ok) {
-      e = S.prec == FDE_FP64
-              ? launch_trsv_coop<double>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 0,
-                                         &S.blk, S.n_blk, S.npan_u)
-              : launch_trsv_coop<float>(P->d_desc, S.trsv, S.n_trsv, P->d_epoch, P->d_err, st, 0,
-                                        &S.blk, S.n_blk, S.npan_u);
-      if (e == hipSuccess || g_capture) return e;  // a refusal while recording ends the recording
-      (void)hipGetLastError();
-      g_coop_ok = false;
-    }
-    // one workgroup per block; the map counts nb W items per instance, the extra ones return
-    return S.prec == FDE_FP64 ? launch_trsv<double>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st)
-                              : launch_trsv<float>(P->d_desc, S.trsv, S.n_trsv, S.max_mp, st);
-  }));
+  HIPCHK(run(L, "trsv", S.trsv_bytes, [&] { return block_solve(P, S, 0, st); }));
   HIPCHK(run(L, "time_irfft", S.tfft_bytes, [&] {
     return launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, dst, dj, st);
   }));
@@ -2004,8 +2027,14 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // also holds its Gram-Schmidt partials after part1)
   const size_t nparts = P->part_off.back() + 2 * (size_t)P->hs.back()->nblk;
   std::vector<double> parts(nparts);
-  HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
-  STCHK(sync_and_flush(L));
+  // the partials through pinned staging (a read into pageable memory would stage and block)
+  auto fetch_parts = [&]() -> fde_status {
+    HIPCHK(hipMemcpyAsync(P->pin_parts, P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
+    STCHK(sync_and_flush(L));
+    std::memcpy(parts.data(), P->pin_parts, nparts * sizeof(double));
+    return FDE_OK;
+  };
+  STCHK(fetch_parts());
   std::vector<double> bnorm(count);
   for (int i = 0; i < count; ++i) {
     bnorm[i] = std::sqrt(part_sum(P, parts, i, 0));
@@ -2018,8 +2047,7 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   if (left) {
     STCHK(op_precond(P, S, VS_B, 0, VS_TMP, 0));
     HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, S.kry, S.n_kry, VS_TMP, VS_TMP, 0, stream); }));
-    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
-    STCHK(sync_and_flush(L));
+    STCHK(fetch_parts());
     STCHK(check_trsv_err(P));
     for (int i = 0; i < count; ++i) {
       bnorm[i] = bnorm_true[i] == 0.0 ? 0.0 : std::sqrt(part_sum(P, parts, i, 0));
@@ -2046,8 +2074,7 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     STCHK(op_matvec(P, Sx0, VS_X, 0, VS_TMP, 0));
     HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, Sx0.kry, S.n_kry, VS_B, VS_TMP, 0, stream); }));
     HIPCHK(run(L, "dot", S.vec_bytes, [&] { return launch_dot_partial(P->d_desc, Sx0.kry, S.n_kry, VS_TMP, VS_TMP, 1, stream); }));
-    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
-    STCHK(sync_and_flush(L));
+    STCHK(fetch_parts());
     std::vector<double> ybuf((size_t)count * (R + 1), 0.0);
     const double gate = L->opt_x0_gate * 1e-6;
     for (int i = 0; i < count; ++i) {
@@ -2079,8 +2106,14 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     gh[GATE_LIVE * count + i] = c.done ? 0 : 1;
     gh[GATE_ACTIVE * count + i] = 0;
   }
-  HIPCHK(hipMemcpyAsync(P->d_ctl, ctl.data(), count * sizeof(GmresCtl), hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(P->d_gates, gh.data(), gh.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+  {  // from pinned staging (an upload from pageable memory would block the host)
+    GmresCtl *cu = (GmresCtl *)((char *)P->pin + P->pin_ctl_up);
+    int *gu = (int *)((char *)P->pin + P->pin_gates_up);
+    std::memcpy(cu, ctl.data(), count * sizeof(GmresCtl));
+    std::memcpy(gu, gh.data(), gh.size() * sizeof(int));
+    HIPCHK(hipMemcpyAsync(P->d_ctl, cu, count * sizeof(GmresCtl), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(P->d_gates, gu, gh.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+  }
 
   // Timing events are not recorded into graphs: a profiled solve launches directly.
   const bool use_graph = L->opt_graphs != 0 && !P->graph_off && !L->prof;
@@ -2098,6 +2131,13 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // control record's restart test.
   auto restart_step = [&]() -> fde_status {
     STCHK(op_matvec(P, Slive, VS_X, 0, VS_TMP, 0));
+    if (S.kry_one_n > 0 && !left) {  // one chunk per instance: residual, norm, v_0, decision
+      HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] {
+        return launch_restart1(P->d_desc, S.kry, S.n_kry, S.kry_one_n, P->d_ctl, P->d_work, P->d_gates,
+                               count, stream);
+      }));
+      return FDE_OK;
+    }
     HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, Slive.kry, S.n_kry, stream); }));
     if (left) {
       STCHK(op_precond(P, Slive, VS_V, 0, VS_V, 0));
@@ -2119,6 +2159,14 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
       } else {
         STCHK(op_precond(P, Sact, VS_V, j, VS_Z, j));
         STCHK(op_matvec(P, Sact, VS_Z, j, VS_W, 0));
+      }
+      if (ortho == FDE_ORTHO_MGS && S.kry_one_n > 0) {
+        // one chunk per instance: the projections, the norm and the Givens update in one launch
+        HIPCHK(run(L, "arnoldi", (j + 4.0) * S.vec_bytes, [&] {
+          return launch_arnoldi1(P->d_desc, Sact.kry, S.n_kry, S.kry_one_n, j, P->d_ctl, P->d_work,
+                                 P->d_gates, count, R, stream);
+        }));
+        continue;
       }
       if (ortho == FDE_ORTHO_CGS2) {
         // classical Gram-Schmidt twice: V^T w, w -= V h, V^T w, w -= V h', column h + h'
@@ -2143,6 +2191,13 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     return FDE_OK;
   };
   auto finish_and_restart = [&]() -> fde_status {
+    if (S.kry_one_n > 0) {  // one chunk per instance: back substitution and x += Q y together
+      HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] {
+        return launch_finish1(P->d_desc, S.kry, S.n_kry, S.kry_one_n, P->d_ctl, P->d_work, P->d_gates,
+                              count, left ? VS_V : VS_Z, stream);
+      }));
+      return restart_step();
+    }
     HIPCHK(launch_gm_backsolve(P->d_desc, P->d_ctl, P->d_work, count, stream));
     HIPCHK(run(L, "update_x", 3.0 * S.vec_bytes, [&] {
       return launch_update_x(P->d_desc, Slive.kry, S.n_kry, left ? VS_V : VS_Z, stream);
@@ -2153,9 +2208,14 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // snapshot its0) were gated off for every instance; the profile does not count them.
   std::vector<int> its0(count, 0);
   int j0 = 0;
+  GmresCtl *ctl_pin = (GmresCtl *)P->pin;
+  int *err_pin = (int *)((char *)P->pin + P->pin_err);
+  *err_pin = 0;
   auto read_ctl = [&]() -> fde_status {
-    HIPCHK(hipMemcpyAsync(ctl.data(), P->d_ctl, count * sizeof(GmresCtl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(ctl_pin, P->d_ctl, count * sizeof(GmresCtl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(err_pin, P->d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
+    std::memcpy(ctl.data(), ctl_pin, count * sizeof(GmresCtl));
     int taken = 0;
     for (int i = 0; i < count; ++i) taken = std::max(taken, ctl[i].its - its0[i]);
     L->prof_step_limit = j0 + taken;
@@ -2175,7 +2235,10 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   constexpr int kStretch = 4;
   std::vector<int> taken_per_cycle;
   STCHK(segment(P->seg_restart, restart_step));
-  STCHK(read_ctl());
+  // From a zero start the first restart step can end only the instances the host already
+  // marked done (b = 0) or that fail (then their gated steps launch nothing), so the host
+  // goes straight on to the cycle and reads the records after its first stretch.
+  if (any_x0 || o.maxit <= 0) STCHK(read_ctl());
   for (int c = 0;; ++c) {
     bool any = false;
     for (int i = 0; i < count; ++i) any = any || !ctl[i].done;
@@ -2207,8 +2270,7 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   if (left) {  // the control records hold preconditioned residuals: report the true one
     STCHK(op_matvec(P, S, VS_X, 0, VS_TMP, 0));
     HIPCHK(run(L, "residual", 3.0 * S.vec_bytes, [&] { return launch_residual(P->d_desc, S.kry, S.n_kry, stream); }));
-    HIPCHK(hipMemcpyAsync(parts.data(), P->d_part, nparts * sizeof(double), hipMemcpyDeviceToHost, stream));
-    STCHK(sync_and_flush(L));
+    STCHK(fetch_parts());
     for (int i = 0; i < count; ++i)
       ctl[i].truer = bnorm_true[i] > 0.0 ? std::sqrt(part_sum(P, parts, i, 0)) / bnorm_true[i] : 0.0;
   }
@@ -2220,7 +2282,10 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     st[i].conv = ctl[i].conv != 0;
     st[i].fail = ctl[i].fail != 0;
   }
-  STCHK(check_trsv_err(P));
+  if (*err_pin) {  // read with the last control records (no block solve ran after them)
+    (void)hipMemset(P->d_err, 0, sizeof(int));
+    return fail(FDE_EDEVICE, "block solve abandoned a dependency wait");
+  }
   for (int i = 0; i < count; ++i)
     if (st[i].fail) return fail(FDE_ENOCONV, "instance %d produced a non-finite residual", i);
   return FDE_OK;
@@ -2255,14 +2320,16 @@ static fde_status copy_out(fde_bvm *h, double *dst, const double *src, size_t co
 }
 
 // ---- autotuner of the block-solve launch shape ------------------------------------------
-// On the first solve of a plan shape (instance sizes + precision) the cooperative block
-// solve is timed for each candidate W (workgroups per block) within the co-residency limit,
+// On the first solve of a plan shape (instance sizes + precision) the block solve is timed in
+// each launch form: the ordinary one-workgroup-per-block launch (recorded as W = -1) and the
+// cooperative one for each candidate W (workgroups per block) within the co-residency limit,
 // on the factored blocks (the values in the work vectors do not matter for the timing); the
-// fastest is kept for the life of the process.  Skipped when W is forced by an option, when
-// autotuning is off, or when cooperative launches are unavailable.
+// fastest is kept for the life of the process.  Every form gives the same bits.  Skipped when
+// the form is forced by an option, when autotuning is off, or when cooperative launches are
+// unavailable.
 static fde_status autotune_trsv(Plan *P, int prec) {
   fde_bvm *L = P->lead;
-  if (!L->opt_autotune || L->opt_trsv_w > 0 || !g_coop_ok || L->pc != FDE_PC_STRANG) return FDE_OK;
+  if (!L->opt_autotune || L->opt_trsv_w != 0 || !g_coop_ok || L->pc != FDE_PC_STRANG) return FDE_OK;
   const std::string key = plan_shape_key(P, prec);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -2270,7 +2337,7 @@ static fde_status autotune_trsv(Plan *P, int prec) {
   }
   int wtop = 1;
   for (fde_bvm *h : P->hs) wtop = std::max(wtop, trsv_wmax(P, h, prec));
-  std::vector<int> cands;
+  std::vector<int> cands = {-1};  // -1: the ordinary one-workgroup-per-block launch
   for (int w = 1; w <= wtop; w = w < 4 ? w + 1 : w + w / 2) cands.push_back(w);
   if (cands.back() != wtop) cands.push_back(wtop);
   const bool prof = L->prof;

@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the configuration bench.py times.
 
-* 1023 x 512 GBDF3 (seed 2): the FP64 and the mixed-form solutions against the oracle's
-  (textbook preconditioned GMRES to 1e-11 with LAPACK block solves, ~10-20 s), plus the
-  true residual with the oracle's dense operator, and sampled factor blocks.
+* 1023 x 512 GBDF3 (seed 2): the FP64 and the mixed-form solutions, by the default route and
+  by the dense block LU, against the oracle's (textbook preconditioned GMRES to 1e-11 with
+  LAPACK block solves, ~10-20 s), plus the true residual with the oracle's dense operator, and
+  sampled block-LU factor blocks.
 * 4095 x 256 GBDF3 (seed 3), FP64 and mixed form, through the band route (the default at this
   size) and the dense block LU: the solutions against the oracle's (about a minute of host
   LAPACK work and 35 GB of host memory for its block factors), plus the true residual with the
@@ -53,12 +54,16 @@ def test_m1023_s512_fp64_and_mixed_match_the_oracle():
     rng = np.random.default_rng(5)
     nb = p.s // 2 + 1
     for prec, tol, ftol in (("fp64", 1e-9, 1e-12), ("mixed", 1e-8, 1e-5)):
-        S.factor(prec)
-        u, info = S.solve(p.u0, p.f, rtol=1e-10)
-        assert info["converged"] == 1 and info["true_relres"] <= 1e-10
-        assert _rel(u, ref.x) <= tol, (prec, _rel(u, ref.x))
-        assert _elem(u, ref.x) <= tol, (prec, _elem(u, ref.x))
-        assert O.true_relres(p, u) <= 1.5e-10
+        # the default route (the band route for FP64 at this size: s / 2 + 1 >= 257), then the
+        # dense block LU, whose factor blocks are L U = K_k
+        for blocks in ("auto", "lu"):
+            S.factor(prec, blocks=blocks)
+            u, info = S.solve(p.u0, p.f, rtol=1e-10)
+            assert info["converged"] == 1 and info["true_relres"] <= 1e-10
+            assert _rel(u, ref.x) <= tol, (prec, blocks, _rel(u, ref.x))
+            assert _elem(u, ref.x) <= tol, (prec, blocks, _elem(u, ref.x))
+            assert O.true_relres(p, u) <= 1.5e-10
+        assert S.get_option(N.FDE_OPT_BLOCKS_IN_USE) == N.FDE_BLOCKS_LU
         for k in (0, 1, nb // 2, nb - 1):
             e = _factor_product_error(S, p, k, rng)
             assert e <= ftol, (prec, k, e)

@@ -68,21 +68,26 @@ def test_autotuned_and_forced_launch_shapes_give_identical_results():
     u1, i1 = S.solve(p.u0, p.f)
     assert "f64:200x32=" in autotune_report()
     w_auto = S.get_option(N.FDE_OPT_TRSV_W_IN_USE)
-    assert 1 <= w_auto <= 4                 # mp = 256: four 64-row panels per block
+    assert 0 <= w_auto <= 4                 # mp = 256: four 64-row panels per block (0: ordinary launch)
     outs = []
-    for w in (1, 2, 4):
+    for w in (-1, 1, 2, 4):
         S.set_option(N.FDE_OPT_TRSV_W, w)
         u, info = S.solve(p.u0, p.f)
-        assert S.get_option(N.FDE_OPT_TRSV_W_IN_USE) == w
+        assert S.get_option(N.FDE_OPT_TRSV_W_IN_USE) == max(w, 0)
         outs.append(u)
         assert info["iters"] == i1["iters"]
     for u in outs:
         assert np.array_equal(u, u1)
 
 
+@pytest.mark.parametrize("s", [32, 64])
 @pytest.mark.parametrize("graphs", [1, 0])
-def test_profile_counts_the_steps_that_ran(graphs):
-    p = W.tiny(200, 32, 1.7, 4, "gbdf3")
+def test_profile_counts_the_steps_that_ran(graphs, s):
+    """m = 200: with s = 32 (n = 6400) the vectors are one chunk and each Arnoldi step is one
+    fused launch (as is each restart step's residual, norm and decision); with s = 64
+    (n = 12800) the step is the MGS launch chain (j + 2 launches), the normalisation and the
+    Givens update."""
+    p = W.tiny(200, s, 1.7, 4, "gbdf3")
     S = BvmSolver(p)
     S.set_option(N.FDE_OPT_GRAPHS, graphs)
     S.factor("fp64")
@@ -91,7 +96,16 @@ def test_profile_counts_the_steps_that_ran(graphs):
     u, info = S.solve(p.u0, p.f)
     q = S.profile_query("trsv")
     assert q["count"] == info["iters"] and q["total_ms"] > 0.0
-    assert S.profile_query("mgs")["count"] == sum(j + 2 for j in range(info["iters"]))
+    restarts = S.profile_query("residual")["count"]
+    assert restarts == info["restarts"] + 1
+    if s == 32:
+        assert S.profile_query("arnoldi")["count"] == info["iters"]
+        assert S.profile_query("mgs")["count"] == 0
+        assert S.profile_query("normalize")["count"] == 0
+    else:
+        assert S.profile_query("arnoldi")["count"] == 0
+        assert S.profile_query("mgs")["count"] == sum(j + 2 for j in range(info["iters"]))
+        assert S.profile_query("normalize")["count"] == restarts + info["iters"]
     S.profile(False)
 
 

@@ -94,6 +94,7 @@ struct GmresCtl {
   double est;       // Givens estimate of the relative residual
   int maxit, its, k, restarts;
   int conv, done, fail, active;  // active: taking part in the current cycle (mirrors the gate)
+  int badrhs, pad;               // badrhs: ||b|| is not finite (set by k_gm_init)
 };
 
 struct GmresWork {

@@ -73,12 +73,14 @@ __device__ __forceinline__ void gm_backsolve_lds(GmresCtl &c, const double (*Hs)
 
 // Givens update after Arnoldi step j: the previous rotations applied to the new Hessenberg
 // column h_{0..j+1, j} (written by the orthogonalisation), the rotation that zeroes
-// H[j+1][j], the residual estimate |g[j+1]| / ||b|| and the end-of-cycle decision.
-__device__ __forceinline__ void gm_givens_one(const InstDesc &d, GmresCtl &c, GmresWork &w,
-                                              int *__restrict__ gates, int count, int i, int j,
-                                              int R) {
+// H[j+1][j], the residual estimate |g[j+1]| / ||b|| and the end-of-cycle decision.  The column
+// hc, the previous rotations csp/snp and g[j] come in as arguments (global memory, or copies
+// in LDS), the results go to w.
+__device__ __forceinline__ void gm_givens_core(const double *hc, const double *csp, const double *snp,
+                                               double gj, GmresCtl &c, GmresWork &w,
+                                               int *__restrict__ gates, int count, int i, int j,
+                                               int R) {
   int *live = gates + GATE_LIVE * count, *act = gates + GATE_ACTIVE * count;
-  const double *hc = d.H;  // h_{0..j+1, j} from the Arnoldi launches
   c.its += 1;
   // the column and the previous rotations are loaded together into registers (unrolled with
   // constant indices), then rotated through a carried value: no memory round trip per rotation
@@ -87,8 +89,8 @@ __device__ __forceinline__ void gm_givens_one(const InstDesc &d, GmresCtl &c, Gm
   for (int r = 0; r <= GM_RMAX; ++r) h[r] = r <= j + 1 ? hc[r] : 0.0;
 #pragma unroll
   for (int r = 0; r < GM_RMAX; ++r) {
-    cs[r] = r < j ? w.cs[r] : 0.0;
-    sn[r] = r < j ? w.sn[r] : 0.0;
+    cs[r] = r < j ? csp[r] : 0.0;
+    sn[r] = r < j ? snp[r] : 0.0;
   }
   double a = h[0], b = h[1];  // rows j and j+1 of the column once rotation j-1 is applied
 #pragma unroll
@@ -101,14 +103,16 @@ __device__ __forceinline__ void gm_givens_one(const InstDesc &d, GmresCtl &c, Gm
     if (r == j) b = h[r + 1];
   }
   const double dd = hypot(a, b);
-  w.cs[j] = dd > 0.0 ? a / dd : 1.0;
-  w.sn[j] = dd > 0.0 ? b / dd : 0.0;
+  const double cj = dd > 0.0 ? a / dd : 1.0, sj = dd > 0.0 ? b / dd : 0.0;
+  w.cs[j] = cj;
+  w.sn[j] = sj;
   w.H[j][j] = dd;
   w.H[j + 1][j] = 0.0;
-  w.g[j + 1] = -w.sn[j] * w.g[j];
-  w.g[j] = w.cs[j] * w.g[j];
+  const double g1 = -sj * gj;
+  w.g[j + 1] = g1;
+  w.g[j] = cj * gj;
   c.k = j + 1;
-  c.est = fabs(w.g[j + 1]) / c.bnorm;
+  c.est = fabs(g1) / c.bnorm;
   if (!isfinite(c.est)) {  // the cycle is discarded; the solve reports the failure
     c.fail = 1;
     c.done = 1;
@@ -118,10 +122,17 @@ __device__ __forceinline__ void gm_givens_one(const InstDesc &d, GmresCtl &c, Gm
     live[i] = 0;
     return;
   }
-  if (fabs(w.g[j + 1]) <= c.tol * c.bnorm || c.its >= c.maxit || j + 1 >= R) {
+  if (fabs(g1) <= c.tol * c.bnorm || c.its >= c.maxit || j + 1 >= R) {
     act[i] = 0;
     c.active = 0;
   }
+}
+
+// The same with every input read from global memory (the Givens launch).
+__device__ __forceinline__ void gm_givens_one(const InstDesc &d, GmresCtl &c, GmresWork &w,
+                                              int *__restrict__ gates, int count, int i, int j,
+                                              int R) {
+  gm_givens_core(d.H, w.cs, w.sn, w.g[j], c, w, gates, count, i, j, R);
 }
 
 }  // namespace fde

@@ -45,6 +45,43 @@ __global__ __launch_bounds__(GM_NT) void k_gm_backsolve(const InstDesc *__restri
   gm_backsolve_one(D[i], ctl[i], work[i]);
 }
 
+// Control records and gates of a zero-start solve, on the device: ||b|| from the partials of
+// the preceding dot launch (summed in index order, as the host does), tolerance and iteration
+// limit; b = 0 ends the instance at once (x is already zero); a non-finite ||b|| ends it with
+// badrhs set, for the host to report.
+__global__ __launch_bounds__(GM_NT) void k_gm_init(const InstDesc *__restrict__ D,
+                                                   GmresCtl *__restrict__ ctl,
+                                                   int *__restrict__ gates, int count, double tol,
+                                                   int maxit) {
+  const int i = blockIdx.x * GM_NT + threadIdx.x;
+  if (i >= count) return;
+  const InstDesc &d = D[i];
+  double t = 0.0;
+  for (int q = 0; q < d.nblk; ++q) t += d.part0[q];
+  GmresCtl c{};
+  c.bnorm = sqrt(t);
+  c.tol = tol;
+  c.maxit = maxit;
+  if (!isfinite(c.bnorm)) {
+    c.badrhs = 1;
+    c.done = 1;
+  } else if (c.bnorm == 0.0) {
+    c.done = c.conv = 1;
+  }
+  ctl[i] = c;
+  gates[GATE_LIVE * count + i] = c.done ? 0 : 1;
+  gates[GATE_ACTIVE * count + i] = 0;
+  gates[GATE_X0 * count + i] = 0;
+}
+
+hipError_t launch_gm_init(const InstDesc *D, GmresCtl *ctl, int *gates, int count, double tol,
+                          int maxit, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gm_init, dim3((count + GM_NT - 1) / GM_NT), dim3(GM_NT), 0, st, D, ctl, gates,
+                     count, tol, maxit);
+  return hipGetLastError();
+}
+
 static inline dim3 gm_grid(int count) { return dim3((count + GM_NT - 1) / GM_NT); }
 
 hipError_t launch_gm_restart(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int *gates,

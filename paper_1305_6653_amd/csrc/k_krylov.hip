@@ -283,12 +283,20 @@ __global__ __launch_bounds__(KR_NT) void k_arnoldi1(const InstDesc *__restrict__
                                                     GmresWork *__restrict__ work,
                                                     int *__restrict__ gates, int count, int R) {
   __shared__ double red[KR_NT / 64];
+  __shared__ double hcol[GM_RMAX + 2], csl[GM_RMAX], snl[GM_RMAX], gjs;
   const int q = item_slot(map, blockIdx.x);
   if (item_gated(map, q)) return;
   const int inst = map.ids[q];
   const InstDesc &d = D[inst];
   const size_t n = (size_t)d.s * d.m;
   const int t = threadIdx.x;
+  // the Givens update's other inputs (previous rotations, g[j]) copied into LDS now, while the
+  // projections run (the first reduction's barriers publish them)
+  for (int r = t; r < j; r += KR_NT) {
+    csl[r] = work[inst].cs[r];
+    snl[r] = work[inst].sn[r];
+  }
+  if (t == 0) gjs = work[inst].g[j];
   double w[U], cv[U], pv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -321,7 +329,10 @@ __global__ __launch_bounds__(KR_NT) void k_arnoldi1(const InstDesc *__restrict__
     }
     acc = block_sum<KR_NT>(acc, red);
     h = 0.0 + acc;
-    if (t == 0 && i <= j) d.H[i] = h;
+    if (t == 0 && i <= j) {
+      d.H[i] = h;
+      hcol[i] = h;
+    }
   }
   const double nrm = sqrt(h);
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
@@ -336,7 +347,8 @@ __global__ __launch_bounds__(KR_NT) void k_arnoldi1(const InstDesc *__restrict__
   }
   if (t == 0) {
     d.H[j + 1] = nrm;
-    gm_givens_one(d, ctl[inst], work[inst], gates, count, inst, j, R);
+    hcol[j + 1] = nrm;
+    gm_givens_core(hcol, csl, snl, gjs, ctl[inst], work[inst], gates, count, inst, j, R);
   }
 }
 
@@ -396,9 +408,13 @@ __global__ __launch_bounds__(KR_NT) void k_restart1(const InstDesc *__restrict__
 
 // The end of a cycle for one-chunk instances: y = H^{-1} g (k_gm_backsolve) for every
 // instance, then x += sum_{j<k} y_j Q_j (k_update_x) for live instances, in one launch; the
-// same bits.  Item = instance (the Krylov map without its gate).
+// same bits (no reduction: each element's sum is formed in j order whatever the thread
+// mapping, so FN_NT threads share the elements).  x and Q_0 are loaded while H is staged and
+// the back substitution runs.  Item = instance (the Krylov map without its gate).
+static constexpr int FN_NT = 1024;
+
 template <int U>
-__global__ __launch_bounds__(KR_NT) void k_finish1(const InstDesc *__restrict__ D, ItemMap map,
+__global__ __launch_bounds__(FN_NT) void k_finish1(const InstDesc *__restrict__ D, ItemMap map,
                                                    GmresCtl *__restrict__ ctl,
                                                    const GmresWork *__restrict__ work,
                                                    const int *__restrict__ gates, int count,
@@ -408,14 +424,23 @@ __global__ __launch_bounds__(KR_NT) void k_finish1(const InstDesc *__restrict__ 
   const int inst = map.ids[item_slot(map, blockIdx.x)];
   const InstDesc &d = D[inst];
   const int t = threadIdx.x;
+  const size_t n = (size_t)d.s * d.m;
+  const double *Q = basis_sel == VS_V ? d.V : d.Z;
   // the k x k triangle of H and g staged in LDS by every thread (independent loads), so the
   // back substitution (one thread) runs on LDS instead of a chain of dependent global loads
   const int kk = ctl[inst].k;
-  for (int e = t; e < kk * kk; e += KR_NT) {
+  double acc[U], q0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const size_t e = (size_t)t + (size_t)u * FN_NT;
+    acc[u] = e < n ? d.x[e] : 0.0;
+    q0[u] = (kk > 0 && e < n) ? Q[e] : 0.0;
+  }
+  for (int e = t; e < kk * kk; e += FN_NT) {
     const int r = e / kk, q = e % kk;
     if (q >= r) Hs[r][q] = work[inst].H[r][q];
   }
-  for (int r = t; r < kk; r += KR_NT) gs[r] = work[inst].g[r];
+  for (int r = t; r < kk; r += FN_NT) gs[r] = work[inst].g[r];
   __syncthreads();
   if (t == 0) {
     gm_backsolve_lds(ctl[inst], Hs, gs, ys);
@@ -423,26 +448,19 @@ __global__ __launch_bounds__(KR_NT) void k_finish1(const InstDesc *__restrict__ 
   }
   __syncthreads();
   if (!gates[GATE_LIVE * count + inst]) return;
-  const size_t n = (size_t)d.s * d.m;
   const int k = (int)ys[0];
-  const double *Q = basis_sel == VS_V ? d.V : d.Z;
-  double acc[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const size_t e = (size_t)t + (size_t)u * KR_NT;
-    acc[u] = e < n ? d.x[e] : 0.0;
-  }
   for (int j = 0; j < k; ++j) {
     const double yj = ys[1 + j];
+    const double *Qj = Q + (size_t)j * n;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const size_t e = (size_t)t + (size_t)u * KR_NT;
-      if (e < n) acc[u] = fma(yj, Q[(size_t)j * n + e], acc[u]);
+      const size_t e = (size_t)t + (size_t)u * FN_NT;
+      if (e < n) acc[u] = fma(yj, j == 0 ? q0[u] : Qj[e], acc[u]);
     }
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const size_t e = (size_t)t + (size_t)u * KR_NT;
+    const size_t e = (size_t)t + (size_t)u * FN_NT;
     if (e < n) d.x[e] = acc[u];
   }
 }
@@ -467,10 +485,10 @@ hipError_t launch_finish1(const InstDesc *D, const ItemMap &map, int items, size
   if (items <= 0) return hipSuccess;
   ItemMap all = map;
   all.gate = nullptr;
-  if (max_n <= (size_t)KR_NT * 16)
-    hipLaunchKernelGGL(k_finish1<16>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
+  if (max_n <= (size_t)FN_NT * 4)
+    hipLaunchKernelGGL(k_finish1<4>, dim3(items), dim3(FN_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
   else if (max_n <= KR_ONE_MAX)
-    hipLaunchKernelGGL(k_finish1<32>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
+    hipLaunchKernelGGL(k_finish1<8>, dim3(items), dim3(FN_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -123,6 +123,9 @@ hipError_t launch_copy(const InstDesc *D, const ItemMap &map, int items, int src
 // ---- restarted GMRES control on the device (one thread per instance of the plan) ----
 // restart: beta = nrm[0] of every live instance -> converged / out of iterations / new cycle;
 // sets gate[GATE_LIVE] and gate[GATE_ACTIVE].
+// control records and gates of a zero-start solve from the partials of <b, b> in part0
+hipError_t launch_gm_init(const InstDesc *D, GmresCtl *ctl, int *gates, int count, double tol,
+                          int maxit, hipStream_t st);
 hipError_t launch_gm_restart(const InstDesc *D, GmresCtl *ctl, GmresWork *work, int *gates,
                              int count, hipStream_t st);
 // Arnoldi step j done: rotate the new Hessenberg column, update the residual estimate and

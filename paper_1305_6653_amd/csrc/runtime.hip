@@ -388,7 +388,8 @@ struct Plan {
   std::vector<GmresCtl> ctl_host;
   std::vector<int> gates_host;
   // pinned host staging: the control records and the block-solve error flag read back once
-  // per cycle, the control records and gates uploaded once per solve (pin_* byte offsets)
+  // per cycle (the factorization's pivot flag in the int after that flag), the control
+  // records and gates uploaded once per solve (pin_* byte offsets)
   void *pin = nullptr;
   size_t pin_err = 0, pin_ctl_up = 0, pin_gates_up = 0;
   double *pin_parts = nullptr;  // the reduction partials read back for the norms of b
@@ -1676,8 +1677,8 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
     STCHK(prec == FDE_FP64 ? factor_plan_impl<double>(P) : factor_plan_impl<float>(P));
   }
   HIPCHK(hipEventRecord(e1, L->stream));
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, L->stream));
+  int *flag_pin = (int *)((char *)P->pin + P->pin_err) + 1;  // pinned: no staging copy
+  HIPCHK(hipMemcpyAsync(flag_pin, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, L->stream));
   std::vector<int> herr(P->hs.size(), 0);
   if (route == FDE_BLOCKS_HESSENBERG)
     for (size_t i = 0; i < P->hs.size(); ++i)
@@ -1695,7 +1696,7 @@ static fde_status factor_plan(Plan *P, fde_precision prec) {
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   L->evpool.push_back(e0);
   L->evpool.push_back(e1);
-  if (flag) return fail(FDE_ESINGULAR, "zero or non-finite pivot in a preconditioner block");
+  if (*flag_pin) return fail(FDE_ESINGULAR, "zero or non-finite pivot in a preconditioner block");
   for (fde_bvm *h : P->hs) {
     h->prec = prec;
     h->t_factor_ms = ms;
@@ -2034,15 +2035,23 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     std::memcpy(parts.data(), P->pin_parts, nparts * sizeof(double));
     return FDE_OK;
   };
-  STCHK(fetch_parts());
-  std::vector<double> bnorm(count);
-  for (int i = 0; i < count; ++i) {
-    bnorm[i] = std::sqrt(part_sum(P, parts, i, 0));
-    if (!std::isfinite(bnorm[i])) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
-  }
   // Left preconditioning measures residuals after the preconditioner: the reference norm of
   // the stopping test is ||P^{-1} b||.  (With no preconditioner both sides are the same.)
   const bool left = L->opt_side == FDE_SIDE_LEFT && S.pc != FDE_PC_NONE;
+  bool any_x0 = false;
+  for (int i = 0; i < count; ++i) any_x0 = any_x0 || has_x0[i];
+  // A zero start with right preconditioning needs nothing from the host before the first
+  // cycle: the control records are set up on the device (k_gm_init) and the host first reads
+  // them after the first stretch of Arnoldi steps.
+  const bool dev_init = !left && !any_x0;
+  std::vector<double> bnorm(count, 0.0);
+  if (!dev_init) {
+    STCHK(fetch_parts());
+    for (int i = 0; i < count; ++i) {
+      bnorm[i] = std::sqrt(part_sum(P, parts, i, 0));
+      if (!std::isfinite(bnorm[i])) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
+    }
+  }
   const std::vector<double> bnorm_true = bnorm;
   if (left) {
     STCHK(op_precond(P, S, VS_B, 0, VS_TMP, 0));
@@ -2058,13 +2067,9 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // minimal residual along x0), so that ||r_0|| <= ||b||: a poor guess never starts worse
   // than the zero start.  A guess that leaves ||b - gamma M x0|| above the gate (the lead
   // handle's FDE_OPT_X0_GATE, millionths of ||b||) gets gamma = 0: the zero start.
-  bool any_x0 = false;
   std::vector<int> &gh = P->gates_host;
   gh.assign(GATE_COUNT * count, 0);
-  for (int i = 0; i < count; ++i) {
-    gh[GATE_X0 * count + i] = has_x0[i] ? 1 : 0;
-    any_x0 = any_x0 || has_x0[i];
-  }
+  for (int i = 0; i < count; ++i) gh[GATE_X0 * count + i] = has_x0[i] ? 1 : 0;
   if (any_x0) {
     HIPCHK(hipMemcpyAsync(P->d_gates, gh.data(), gh.size() * sizeof(int), hipMemcpyHostToDevice, stream));
     if (o.x0_kind == FDE_X0_LOWRANK) {  // x holds c: start from S^{-1}(b + c)
@@ -2094,7 +2099,8 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
   // control records and gates
   std::vector<GmresCtl> &ctl = P->ctl_host;
   ctl.assign(count, GmresCtl{});
-  for (int i = 0; i < count; ++i) {
+  if (dev_init) HIPCHK(launch_gm_init(P->d_desc, P->d_ctl, P->d_gates, count, o.rtol, o.maxit, stream));
+  for (int i = 0; !dev_init && i < count; ++i) {
     GmresCtl &c = ctl[i];
     c.bnorm = bnorm[i];
     c.tol = o.rtol;
@@ -2106,7 +2112,7 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     gh[GATE_LIVE * count + i] = c.done ? 0 : 1;
     gh[GATE_ACTIVE * count + i] = 0;
   }
-  {  // from pinned staging (an upload from pageable memory would block the host)
+  if (!dev_init) {  // from pinned staging (an upload from pageable memory would block the host)
     GmresCtl *cu = (GmresCtl *)((char *)P->pin + P->pin_ctl_up);
     int *gu = (int *)((char *)P->pin + P->pin_gates_up);
     std::memcpy(cu, ctl.data(), count * sizeof(GmresCtl));
@@ -2216,6 +2222,8 @@ static fde_status gmres_plan(Plan *P, const fde_solve_opts &o, const std::vector
     HIPCHK(hipMemcpyAsync(err_pin, P->d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     std::memcpy(ctl.data(), ctl_pin, count * sizeof(GmresCtl));
+    for (int i = 0; i < count; ++i)
+      if (ctl[i].badrhs) return fail(FDE_EINVAL, "right-hand side %d is not finite", i);
     int taken = 0;
     for (int i = 0; i < count; ++i) taken = std::max(taken, ctl[i].its - its0[i]);
     L->prof_step_limit = j0 + taken;
@@ -2321,12 +2329,12 @@ static fde_status copy_out(fde_bvm *h, double *dst, const double *src, size_t co
 
 // ---- autotuner of the block-solve launch shape ------------------------------------------
 // On the first solve of a plan shape (instance sizes + precision) the block solve is timed in
-// each launch form: the ordinary one-workgroup-per-block launch (recorded as W = -1) and the
-// cooperative one for each candidate W (workgroups per block) within the co-residency limit,
-// on the factored blocks (the values in the work vectors do not matter for the timing); the
-// fastest is kept for the life of the process.  Every form gives the same bits.  Skipped when
-// the form is forced by an option, when autotuning is off, or when cooperative launches are
-// unavailable.
+// each launch form: the ordinary one-workgroup-per-block launch (recorded as W = -1; blocks of
+// up to four panels) and the cooperative one for each candidate W (workgroups per block)
+// within the co-residency limit, on the factored blocks (the values in the work vectors do
+// not matter for the timing); the fastest is kept for the life of the process.  Every form
+// gives the same bits.  Skipped when the form is forced by an option, when autotuning is off,
+// or when cooperative launches are unavailable.
 static fde_status autotune_trsv(Plan *P, int prec) {
   fde_bvm *L = P->lead;
   if (!L->opt_autotune || L->opt_trsv_w != 0 || !g_coop_ok || L->pc != FDE_PC_STRANG) return FDE_OK;
@@ -2337,7 +2345,13 @@ static fde_status autotune_trsv(Plan *P, int prec) {
   }
   int wtop = 1;
   for (fde_bvm *h : P->hs) wtop = std::max(wtop, trsv_wmax(P, h, prec));
-  std::vector<int> cands = {-1};  // -1: the ordinary one-workgroup-per-block launch
+  // -1: the ordinary one-workgroup-per-block launch, a candidate for blocks of at most
+  // four panels (one workgroup streams a whole factor: beyond that it cannot win, and timing
+  // it would cost more than the solves it could speed up)
+  int npan_max = 0;
+  for (fde_bvm *h : P->hs) npan_max = std::max(npan_max, h->npan);
+  std::vector<int> cands;
+  if (npan_max <= 4) cands.push_back(-1);
   for (int w = 1; w <= wtop; w = w < 4 ? w + 1 : w + w / 2) cands.push_back(w);
   if (cands.back() != wtop) cands.push_back(wtop);
   const bool prof = L->prof;

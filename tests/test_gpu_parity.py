@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from paper_1305_6653_amd import BvmSolver, FdeError
+from paper_1305_6653_amd import BvmSolver, FdeError, factor_batch, solve_batch
 from paper_1305_6653_amd import _native as N
 
 pytestmark = pytest.mark.gpu
@@ -278,6 +278,31 @@ def test_non_finite_input_is_rejected(where):
     with pytest.raises(FdeError) as e:
         S.solve(u0, f)
     assert e.value.status == N.FDE_EINVAL
+    # the handle is still good: a finite right-hand side solves as on a fresh handle
+    u, info = S.solve(p.u0, p.f)
+    S2 = BvmSolver(p)
+    S2.factor("fp64")
+    u2, info2 = S2.solve(p.u0, p.f)
+    assert info["converged"] == 1 and np.array_equal(u, u2) and info["iters"] == info2["iters"]
+    S2.close()
+
+
+def test_non_finite_instance_in_a_batch_is_rejected():
+    """One instance of a batch with a NaN in f: the batch call returns FDE_EINVAL; the other
+    instances then solve as before."""
+    ps = [CASES["gbdf3_m7_s8"](), CASES["gbdf3_m200_s32"]()]
+    Ss = [BvmSolver(q) for q in ps]
+    factor_batch(Ss, "fp64")
+    f_bad = ps[1].f.copy()
+    f_bad[2, 5] = np.nan
+    with pytest.raises(FdeError) as e:
+        solve_batch(Ss, [q.u0 for q in ps], [ps[0].f, f_bad])
+    assert e.value.status == N.FDE_EINVAL
+    outs, infos = solve_batch(Ss, [q.u0 for q in ps], [q.f for q in ps])
+    for q, u, info in zip(ps, outs, infos):
+        assert info["converged"] == 1 and O.true_relres(q, u) <= 1.5e-10
+    for S in Ss:
+        S.close()
 
 
 def test_custom_formula_equals_the_built_in_one():

@@ -181,9 +181,10 @@ fde_status fde_get_dims(const fde_bvm *h, int *dims);
  *   FDE_OPT_AUTOTUNE      1 (default): on the first solve of a shape (the sizes of all
  *                         instances of the call and the precision), time the block solve in
  *                         its ordinary one-workgroup-per-block launch and in the cooperative
- *                         launch for every candidate number of workgroups per block, and keep
- *                         the fastest for the life of the process.  Every launch form gives
- *                         the same bits.
+ *                         launch for every candidate number of workgroups per block, and the
+ *                         time FFTs for 4, 8 and 16 spatial columns per workgroup, and keep the
+ *                         fastest for the life of the process.  Every launch form gives the
+ *                         same bits.
  *   FDE_OPT_TRSV_W        0 (default): autotuned or the largest co-resident value;
  *                         k > 0: cooperative, at most k workgroups per block (clamped to what
  *                         fits); -1: the ordinary launch, one workgroup per block, no flags.
@@ -282,8 +283,9 @@ typedef enum { FDE_BLOCKS_LU = 0, FDE_BLOCKS_HESSENBERG = 1, FDE_BLOCKS_BAND = 2
 typedef enum { FDE_ORTHO_MGS = 0, FDE_ORTHO_CGS2 = 1 } fde_ortho;
 fde_status fde_bvm_set_option(fde_bvm *h, int option, int value);
 fde_status fde_bvm_get_option(fde_bvm *h, int option, int *value);
-/* Autotuned choices of this process as "shape=W;..." into buf (NUL-terminated);
- * FDE_EINVAL if len is too small. */
+/* Autotuned choices of this process into buf (NUL-terminated), ';'-separated: "shape=W" for
+ * the block solve (W = -1: the ordinary one-workgroup-per-block launch) and "shape/tfft=c" for
+ * the time FFTs' spatial columns per workgroup (4, 8 or 16); FDE_EINVAL if len is too small. */
 fde_status fde_autotune_report(char *buf, int len);
 /* Measurement aid: the best of `reps` timed passes of a plain streaming-read kernel over a
  * `bytes`-byte device buffer (allocated and freed by the call), in GB/s: the read bandwidth

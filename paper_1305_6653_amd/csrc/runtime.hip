@@ -582,6 +582,7 @@ static fde_status ensure_krylov(fde_bvm *h, int R) {
 // (sizes of all instances and the precision), or the largest value that fits.
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tuned_w;
+static std::map<std::string, int> g_tuned_cols;  // time-FFT spatial columns per workgroup
 
 static std::string plan_shape_key(const Plan *P, int prec) {
   std::string k = prec == FDE_FP64 ? "f64" : "c32";
@@ -596,12 +597,17 @@ static std::string plan_shape_key(const Plan *P, int prec) {
 }
 
 // Autotuned choices so far, "shape=W" separated by ';' (for reports).
+// The time-FFT column groups appear as "shape/tfft=cols".
 static std::string tuned_summary() {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   std::string out;
   for (auto &kv : g_tuned_w) {
     if (!out.empty()) out += ";";
     out += kv.first + "=" + std::to_string(kv.second);
+  }
+  for (auto &kv : g_tuned_cols) {
+    if (!out.empty()) out += ";";
+    out += kv.first + "/tfft=" + std::to_string(kv.second);
   }
   return out;
 }
@@ -1731,6 +1737,9 @@ static fde_status ensure_full_maps(Plan *P) {
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     S.tfft_cols = time_fft_cols_per_item(total_mp, std::max(cus, 1));
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned_cols.find(plan_shape_key(P, prec));
+    if (it != g_tuned_cols.end()) S.tfft_cols = it->second;
   }
   for (int q = 0; q < count; ++q) {
     fde_bvm *h = P->hs[q];
@@ -2398,6 +2407,64 @@ static fde_status autotune_trsv(Plan *P, int prec) {
   return s != FDE_OK ? s : s2;
 }
 
+// The time FFTs' column groups (4, 8 or 16 spatial columns per workgroup; every choice gives
+// the same bits, each column's transform being the same), timed on the first solve of a plan
+// shape like the block solve: the forward and inverse transform pair, fastest of three
+// repetitions after a warm-up, kept for the process.  The heuristic choice
+// (time_fft_cols_per_item) stands when autotuning is off.
+static fde_status autotune_tfft(Plan *P, int prec) {
+  fde_bvm *L = P->lead;
+  if (!L->opt_autotune || L->pc == FDE_PC_NONE) return FDE_OK;
+  const std::string key = plan_shape_key(P, prec);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_tuned_cols.count(key)) return FDE_OK;
+  }
+  const bool prof = L->prof;
+  L->prof = false;
+  auto set_cols = [&](int c) -> fde_status {
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tuned_cols[key] = c;
+    }
+    P->full_ok = false;  // new item counts: new maps (and graphs)
+    return ensure_full_maps(P);
+  };
+  hipEvent_t e0 = get_event(L), e1 = get_event(L);
+  int best_c = 16;
+  float best = 1e30f;
+  fde_status s = FDE_OK;
+  for (int c : {4, 8, 16}) {
+    if ((s = set_cols(c)) != FDE_OK) break;
+    const SolveMaps &S = P->full;
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 4 && s == FDE_OK; ++rep) {
+      (void)hipEventRecord(e0, L->stream);
+      hipError_t e = launch_time_rfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, VS_TMP, 0, L->stream);
+      if (e == hipSuccess)
+        e = launch_time_irfft(P->d_desc, S.tfft, S.n_tfft, S.max_log2s, S.tfft_cols, VS_TMP, 0, L->stream);
+      (void)hipEventRecord(e1, L->stream);
+      if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(FDE_EDEVICE, "autotuner timing of the time FFTs failed");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tmin = std::min(tmin, ms);
+    }
+    if (s != FDE_OK) break;
+    if (tmin < best) {
+      best = tmin;
+      best_c = c;
+    }
+  }
+  L->evpool.push_back(e0);
+  L->evpool.push_back(e1);
+  L->prof = prof;
+  const fde_status s2 = set_cols(best_c);
+  return s != FDE_OK ? s : s2;
+}
+
 static fde_status solve_plan(Plan *P, const double *const *u0, const double *const *f,
                              double *const *u, const double *const *x0, const fde_solve_opts &o,
                              fde_solve_info *info) {
@@ -2415,6 +2482,7 @@ static fde_status solve_plan(Plan *P, const double *const *u0, const double *con
   }
   STCHK(plan_prepare(P, o.restart, prec));
   STCHK(autotune_trsv(P, prec));
+  STCHK(autotune_tfft(P, prec));
   hipEvent_t e0 = get_event(L), e1 = get_event(L);
   HIPCHK(hipEventRecord(e0, L->stream));
   for (int i = 0; i < count; ++i) {

@@ -320,8 +320,8 @@ class BvmSolver:
 
 
 def autotune_report() -> str:
-    """The autotuner's choices so far, "shape=W;..."."""
-    buf = C.create_string_buffer(4096)
+    """The autotuner's choices so far, "shape=W;...;shape/tfft=cols;..."."""
+    buf = C.create_string_buffer(1 << 20)
     N.check(N.lib().fde_autotune_report(buf, len(buf)))
     return buf.value.decode()
 

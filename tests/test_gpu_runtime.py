@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from paper_1305_6653_amd import BvmSolver, autotune_report, solve_batch
+from paper_1305_6653_amd import BvmSolver, autotune_report, factor_batch, solve_batch
 from paper_1305_6653_amd import _native as N
 
 pytestmark = pytest.mark.gpu
@@ -78,6 +78,28 @@ def test_autotuned_and_forced_launch_shapes_give_identical_results():
         assert info["iters"] == i1["iters"]
     for u in outs:
         assert np.array_equal(u, u1)
+
+
+def test_autotuned_time_fft_column_groups_give_identical_results():
+    """The autotuner also picks the time FFTs' spatial columns per workgroup (4, 8 or 16;
+    reported as "shape/tfft=cols").  Every choice gives the same bits: a batch of the same
+    instance twice is a different shape, tuned (and column-grouped) on its own, and returns the
+    single solve's bits for both."""
+    p = W.tiny(255, 64, 1.4, 9, "gbdf3")
+    S = BvmSolver(p)
+    S.factor("fp64")
+    u1, i1 = S.solve(p.u0, p.f)
+    rep = dict(e.split("=") for e in autotune_report().split(";") if e)
+    assert int(rep["f64:255x64/tfft"]) in (4, 8, 16)
+    Sb = [BvmSolver(p), BvmSolver(p)]
+    factor_batch(Sb, "fp64")
+    outs, infos = solve_batch(Sb, [p.u0, p.u0], [p.f, p.f])
+    rep = dict(e.split("=") for e in autotune_report().split(";") if e)
+    assert int(rep["f64:255x64:255x64/tfft"]) in (4, 8, 16)
+    for u, info in zip(outs, infos):
+        assert np.array_equal(u, u1) and info["iters"] == i1["iters"]
+    for T in [S] + Sb:
+        T.close()
 
 
 @pytest.mark.parametrize("s", [32, 64])

@@ -73,28 +73,27 @@ PMC_MEASURED = {
                 ("mixed", "hess_reduce"): 6.8204e+09, ("mixed", "hess_uinv"): 2.1905e+08,
                 ("mixed", "qgemm"): 5.2862e+07, ("mixed", "trsv"): 1.3156e+09}},
     # profiles/hbm_traffic_m4095_s256_gbdf3.txt
-    "c3": {"hash": {"factor": "4ec781ac2c13f106", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb",
-                    "hessenberg": "6ede7fd550e117dd", "band": "c925d7c2942c8c2b"},
+    "c3": {"hash": {"factor": "635bc6d6f79ab3d4", "spacetime": "d66c00e29b9c7eba", "krylov": "75c896fa8d00a98a",
+                    "hessenberg": "ab6671406771da5c", "band": "8b6961dd5424920e"},
            "bytes": {
-               ("fp64", "trsv"): 1.7687e+10, ("fp64", "band_lu_step"): 9.8421e+08,
-               ("fp64", "band_lu_rows"): 4.2581e+07, ("fp64", "band_lu_panel"): 3.4651e+07,
-               ("fp64", "band_lsolve"): 1.0949e+09, ("fp64", "qgemm"): 2.2480e+08,
-               ("fp64", "band_panel"): 1.4625e+07, ("fp64", "band_init"): 2.6942e+08,
-               ("fp64", "mgs"): 3.1256e+07, ("fp64", "bvm_matvec"): 7.0790e+07,
-               ("fp64", "time_rfft"): 1.7179e+07, ("fp64", "time_irfft"): 1.6988e+07,
-               ("fp64", "normalize"): 1.6918e+07,
-               ("mixed", "trsv"): 9.3537e+09, ("mixed", "band_lu_step"): 5.2376e+08,
-               ("mixed", "band_lu_rows"): 2.1510e+07, ("mixed", "band_lu_panel"): 1.7744e+07,
-               ("mixed", "band_lsolve"): 5.5797e+08, ("mixed", "qgemm"): 2.2480e+08,
-               ("mixed", "band_panel"): 1.4625e+07, ("mixed", "band_init"): 2.6942e+08}},
-    "c3l": {"hash": {"factor": "4ec781ac2c13f106", "spacetime": "41b6c6d79eb78c42", "krylov": "a336f5b3ef0ee3cb"},
-            "bytes": {
-                ("fp64", "lu_update"): 2.2900e+10, ("fp64", "trsv"): 3.5386e+10,
-                ("fp64", "lu_panel"): 1.1004e+09, ("fp64", "lu_diag"): 3.4090e+07,
-                ("fp64", "assemble"): 2.1339e+09,
-                ("mixed", "lu_update"): 9.5163e+09, ("mixed", "trsv"): 1.8712e+10,
-                ("mixed", "lu_panel"): 6.3441e+08, ("mixed", "lu_diag"): 1.7037e+07,
-                ("mixed", "assemble"): 1.0673e+09}},
+               ("fp64", "trsv"): 1.7687e+10, ("fp64", "band_lu_step"): 9.7484e+08,
+               ("fp64", "band_lu_rows"): 4.2568e+07, ("fp64", "band_lu_panel"): 3.4665e+07,
+               ("fp64", "band_lsolve"): 1.0948e+09, ("fp64", "qgemm"): 2.2571e+08,
+               ("fp64", "band_panel"): 1.4623e+07, ("fp64", "band_init"): 2.6942e+08,
+               ("fp64", "mgs"): 3.1258e+07, ("fp64", "bvm_matvec"): 7.0803e+07,
+               ("fp64", "time_rfft"): 1.7046e+07, ("fp64", "time_irfft"): 1.6858e+07,
+               ("fp64", "normalize"): 1.6916e+07, ("mixed", "trsv"): 9.3470e+09,
+               ("mixed", "band_lu_step"): 5.0594e+08, ("mixed", "band_lu_rows"): 2.1495e+07,
+               ("mixed", "band_lu_panel"): 1.7741e+07, ("mixed", "band_lsolve"): 5.5797e+08,
+               ("mixed", "qgemm"): 2.2571e+08, ("mixed", "band_panel"): 1.4623e+07,
+               ("mixed", "band_init"): 2.6942e+08}},
+    "c3l": {"hash": {"factor": "635bc6d6f79ab3d4", "spacetime": "d66c00e29b9c7eba", "krylov": "75c896fa8d00a98a"},
+           "bytes": {
+               ("fp64", "lu_update"): 2.2901e+10, ("fp64", "trsv"): 3.5387e+10,
+               ("fp64", "lu_panel"): 1.1004e+09, ("fp64", "lu_diag"): 3.4090e+07,
+               ("fp64", "assemble"): 2.1339e+09, ("mixed", "lu_update"): 9.5146e+09,
+               ("mixed", "trsv"): 1.8711e+10, ("mixed", "lu_panel"): 6.3422e+08,
+               ("mixed", "lu_diag"): 1.7037e+07, ("mixed", "assemble"): 1.0673e+09}},
 }
 
 

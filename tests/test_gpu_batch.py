@@ -23,6 +23,39 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_restarted_small_instances_fused_and_chained_agree(prec):
+    """Small instances (vectors of <= 8192 entries) run an Arnoldi step, the restart tail and the
+    end of a cycle as one launch each when solved alone; beside a larger instance in a batch they
+    take the launch chains.  With restarts every 4 steps (several cycles, so every fused kernel
+    runs many times) the batch results equal the single solves bit for bit, and a zero
+    right-hand side gives u = 0 with no iteration either way."""
+    ps = [W.tiny(63, 16, 1.5, 1, "gbdf3"), W.tiny(100, 64, 1.7, 5, "gbdf3"), W.tiny(200, 64, 1.8, 4, "gbdf3")]
+    zero = W.tiny(63, 16, 1.5, 1, "gbdf3")
+    zero.u0 = np.zeros_like(zero.u0)
+    zero.f = np.zeros_like(zero.f)
+    ps.append(zero)
+    assert ps[2].m * ps[2].s > 8192 and all(p.m * p.s <= 8192 for p in ps[:2])
+    batch = [BvmSolver(p) for p in ps]
+    factor_batch(batch, prec)
+    outs, infos = solve_batch(batch, [p.u0 for p in ps], [p.f for p in ps], restart=4)
+    for p, u, info in zip(ps, outs, infos):
+        assert info["converged"] == 1
+        S = BvmSolver(p)
+        S.factor(prec)
+        u1, i1 = S.solve(p.u0, p.f, restart=4)
+        assert np.array_equal(u, u1) and info["iters"] == i1["iters"], p.name
+        assert info["restarts"] == i1["restarts"]
+        if p is zero:
+            assert info["iters"] == 0 and not np.any(u)
+        else:
+            assert O.true_relres(p, u) <= 1.5e-10
+        S.close()
+    assert max(i["restarts"] for i in infos) >= 3
+    for S in batch:
+        S.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-8)])
 def test_batch_bitwise_equals_single_and_oracle(prec, tol):
     ps = _mixed_bag()

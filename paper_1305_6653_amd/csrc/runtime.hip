@@ -2756,9 +2756,12 @@ extern "C" fde_status fde_apply_precond_noalloc(fde_bvm *h, const double *v, dou
   const ItemMap trsv{hd->ids, hd->pre_trsv, 1, nullptr};
   const ItemMap blk{hd->ids, hd->pre_blk, 1, nullptr};
   HIPCHK(launch_time_rfft(D, tfft, n_tfft, h->log2s, cols, VS_SIO, 0, st, &hd->ctr, hd->epoch));
-  HIPCHK(h->prec == FDE_FP64
-             ? launch_trsv_coop<double>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan)
-             : launch_trsv_coop<float>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan));
+  if (h->self->trsv_solo)  // the handle's plan takes the ordinary one-workgroup launch (same bits)
+    HIPCHK(h->prec == FDE_FP64 ? launch_trsv<double>(D, trsv, n_trsv, 0, st) : launch_trsv<float>(D, trsv, n_trsv, 0, st));
+  else
+    HIPCHK(h->prec == FDE_FP64
+               ? launch_trsv_coop<double>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan)
+               : launch_trsv_coop<float>(D, trsv, n_trsv, hd->epoch, &hd->err, st, 0, &blk, n_blk, h->npan));
   HIPCHK(launch_time_irfft(D, tfft, n_tfft, h->log2s, cols, VS_TMP, 0, st));
   int err = 0;
   HIPCHK(hipMemcpyAsync(&err, &hd->err, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -18,13 +18,17 @@ def _noalloc(S, v, z):
     return N.lib().fde_apply_precond_noalloc(S.handle, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr()))
 
 
+@pytest.mark.parametrize("trsv_w", [0, -1])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_noalloc_apply_equals_the_handle_apply(prec):
+def test_noalloc_apply_equals_the_handle_apply(prec, trsv_w):
+    """trsv_w = -1: the handle's block solve is the ordinary one-workgroup launch, which the
+    allocation-free apply then takes too."""
     import torch
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(11)
     for p in (W.tiny(1000, 64, 1.6, 1, "gbdf3"), W.tiny(130, 16, 1.3, 2, "trapezoidal")):
         S = BvmSolver(p)
+        S.set_option(N.FDE_OPT_TRSV_W, trsv_w)
         S.factor(prec)
         v = torch.from_numpy(rng.standard_normal((p.s, p.m))).to(dev)
         ref = S.precond(v)

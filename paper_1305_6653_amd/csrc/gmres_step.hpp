@@ -1,6 +1,8 @@
 // The per-instance control steps of restarted GMRES (Saad's GMRES, right preconditioning,
 // flexible form), each run by one thread per instance: from the small launches of k_gmres.hip
-// and from the fused one-chunk kernels of k_krylov.hip, so both give the same bits.
+// and from the fused one-chunk kernels of k_krylov.hip, so both give the same bits.  Every
+// multiply-add is an explicit fma (or an explicitly rounded product), so that the compiler
+// has no contraction to choose differently in the kernels these are inlined into.
 #pragma once
 #include "batch.hpp"
 
@@ -49,7 +51,7 @@ __device__ __forceinline__ void gm_backsolve_one(const InstDesc &d, GmresCtl &c,
   y[0] = (double)k;
   for (int r = k - 1; r >= 0; --r) {
     double t = w.g[r];
-    for (int q = r + 1; q < k; ++q) t -= w.H[r][q] * y[1 + q];
+    for (int q = r + 1; q < k; ++q) t = fma(-w.H[r][q], y[1 + q], t);
     y[1 + r] = t / w.H[r][r];
   }
   if (k > 0) c.restarts += 1;
@@ -64,7 +66,7 @@ __device__ __forceinline__ void gm_backsolve_lds(GmresCtl &c, const double (*Hs)
   ys[0] = (double)k;
   for (int r = k - 1; r >= 0; --r) {
     double t = gs[r];
-    for (int q = r + 1; q < k; ++q) t -= Hs[r][q] * ys[1 + q];
+    for (int q = r + 1; q < k; ++q) t = fma(-Hs[r][q], ys[1 + q], t);
     ys[1 + r] = t / Hs[r][r];
   }
   if (k > 0) c.restarts += 1;
@@ -97,8 +99,8 @@ __device__ __forceinline__ void gm_givens_core(const double *hc, const double *c
   for (int r = 0; r < GM_RMAX; ++r) {
     if (r < j) {
       const double hb = h[r + 1];
-      w.H[r][j] = cs[r] * a + sn[r] * hb;
-      a = -sn[r] * a + cs[r] * hb;
+      w.H[r][j] = fma(cs[r], a, sn[r] * hb);
+      a = fma(-sn[r], a, cs[r] * hb);
     }
     if (r == j) b = h[r + 1];
   }

@@ -24,8 +24,10 @@ namespace fde {
 
 static constexpr int KR_NT = 256;
 // Vectors of up to KR_ONE_MAX entries form one chunk (one workgroup per reduction), which
-// lets a whole Arnoldi step run in one launch (k_arnoldi1).
-static constexpr size_t KR_ONE_MAX = 8192;
+// lets a whole Arnoldi step run in one launch (k_arnoldi1).  Larger vectors keep chunks of
+// 1024 entries: one workgroup streaming a longer vector through a chain launch (a batch that
+// mixes sizes) would become the launch's tail.
+static constexpr size_t KR_ONE_MAX = 4096;
 
 size_t krylov_one_max() { return KR_ONE_MAX; }
 
@@ -356,14 +358,9 @@ hipError_t launch_arnoldi1(const InstDesc *D, const ItemMap &map, int items, siz
                            GmresCtl *ctl, GmresWork *work, int *gates, int count, int R,
                            hipStream_t st) {
   if (items <= 0) return hipSuccess;
-  if (max_n <= (size_t)KR_NT * 16) {
-    hipLaunchKernelGGL(k_arnoldi1<16>, dim3(items), dim3(KR_NT), 0, st, D, map, j, ctl, work, gates, count, R);
-  } else if (max_n <= KR_ONE_MAX) {
-    static_assert(KR_ONE_MAX == (size_t)KR_NT * 32, "one-chunk limit");
-    hipLaunchKernelGGL(k_arnoldi1<32>, dim3(items), dim3(KR_NT), 0, st, D, map, j, ctl, work, gates, count, R);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  static_assert(KR_ONE_MAX == (size_t)KR_NT * 16, "one-chunk limit");
+  if (max_n > KR_ONE_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_arnoldi1<16>, dim3(items), dim3(KR_NT), 0, st, D, map, j, ctl, work, gates, count, R);
   return hipGetLastError();
 }
 
@@ -470,12 +467,8 @@ hipError_t launch_restart1(const InstDesc *D, const ItemMap &map, int items, siz
   if (items <= 0) return hipSuccess;
   ItemMap all = map;
   all.gate = nullptr;
-  if (max_n <= (size_t)KR_NT * 16)
-    hipLaunchKernelGGL(k_restart1<16>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count);
-  else if (max_n <= KR_ONE_MAX)
-    hipLaunchKernelGGL(k_restart1<32>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count);
-  else
-    return hipErrorInvalidValue;
+  if (max_n > KR_ONE_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_restart1<16>, dim3(items), dim3(KR_NT), 0, st, D, all, ctl, work, gates, count);
   return hipGetLastError();
 }
 
@@ -485,12 +478,9 @@ hipError_t launch_finish1(const InstDesc *D, const ItemMap &map, int items, size
   if (items <= 0) return hipSuccess;
   ItemMap all = map;
   all.gate = nullptr;
-  if (max_n <= (size_t)FN_NT * 4)
-    hipLaunchKernelGGL(k_finish1<4>, dim3(items), dim3(FN_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
-  else if (max_n <= KR_ONE_MAX)
-    hipLaunchKernelGGL(k_finish1<8>, dim3(items), dim3(FN_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
-  else
-    return hipErrorInvalidValue;
+  static_assert(KR_ONE_MAX == (size_t)FN_NT * 4, "one-chunk limit");
+  if (max_n > KR_ONE_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish1<4>, dim3(items), dim3(FN_NT), 0, st, D, all, ctl, work, gates, count, basis_sel);
   return hipGetLastError();
 }
 

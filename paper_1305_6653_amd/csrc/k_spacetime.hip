@@ -36,30 +36,53 @@ __global__ __launch_bounds__(ST_NT) void k_symbol(const double *__restrict__ cG,
 // mode 3 ((S - M) z): W[n] = (u_S - u) - tau J (v_S - v); nonzero only on the nu + (mu-nu)
 //                boundary rows where the circulant and the BVM matrices differ.
 // J v = scale/L * (d+ Re + d- Im) of IFFT(chat*V + i conj(chat)*V) = L (G v + i G^T v).
-__device__ __forceinline__ void band_combo(const InstDesc &d, const double *Z, int n, int mode, int i,
-                                           double &u, double &v) {
+// The combinations u, v above for the KU elements i = tid + NT k (k < KU) of a thread: the
+// loads of one coefficient step are issued together and u, v stay in registers (elements
+// i >= m come out as zeros and are not used).
+template <int KU, int NT>
+__device__ __forceinline__ void band_combo_k(const InstDesc &d, const double *__restrict__ Z, int n, int mode,
+                                             int tid, double (&u)[KU], double (&v)[KU]) {
   const int m = d.m, s = d.s, mu1 = d.mu1;
-  u = 0.0;
-  v = 0.0;
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    u[k] = 0.0;
+    v[k] = 0.0;
+  }
   if (mode == 1) {
-    v = Z[(size_t)n * m + i];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int i = tid + NT * k;
+      v[k] = i < m ? Z[(size_t)n * m + i] : 0.0;
+    }
     return;
   }
+  auto step = [&](int col, double a, double b) {
+    double z[KU];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int i = tid + NT * k;
+      z[k] = i < m ? Z[(size_t)col * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      u[k] = fma(a, z[k], u[k]);
+      v[k] = fma(b, z[k], v[k]);
+    }
+  };
   if (mode != 2) {  // BVM rows (subtracted in mode 3)
     const int c0 = d.band_c[n] - 1;
     const double *ra = d.band_a + (size_t)n * mu1;
     const double *rb = d.band_b + (size_t)n * mu1;
     for (int t = 0; t < mu1; ++t) {
       const int col = c0 + t;
-      if (col >= 0 && col < s) {
-        const double z = Z[(size_t)col * m + i];
-        u = fma(ra[t], z, u);
-        v = fma(rb[t], z, v);
-      }
+      if (col >= 0 && col < s) step(col, ra[t], rb[t]);
     }
     if (mode == 3) {
-      u = -u;
-      v = -v;
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        u[k] = -u[k];
+        v[k] = -v[k];
+      }
     }
   }
   if (mode >= 2) {  // circulant rows: main formula (stored in s-form row nu-1) wrapped mod s
@@ -68,51 +91,68 @@ __device__ __forceinline__ void band_combo(const InstDesc &d, const double *Z, i
     for (int t = 0; t < mu1; ++t) {
       int col = (n - d.nu + t) % s;
       if (col < 0) col += s;
-      const double z = Z[(size_t)col * m + i];
-      u = fma(ra[t], z, u);
-      v = fma(rb[t], z, v);
+      step(col, ra[t], rb[t]);
     }
   }
 }
 
-__global__ __launch_bounds__(ST_NT) void k_bvm_matvec(const InstDesc *__restrict__ D, ItemMap map,
+// NT threads (1024 for transforms of 4096 points and more, whose LDS allows one workgroup per
+// CU: more wavefronts to hide the LDS passes; 256 below), KU = elements per thread
+// (m <= NT KU).  Rows are numbered contiguously per XCD (xcd_item), so the neighbouring time
+// rows that share band columns read them through one L2; the band combination is formed once
+// (u stays in registers for the output) and d+, d- are loaded before the transforms.  Each
+// element sees the same operations whatever NT, so the result does not depend on it.
+template <int KU, int NT>
+__global__ __launch_bounds__(NT) void k_bvm_matvec(const InstDesc *__restrict__ D, ItemMap map,
                                                       int src_sel, int src_j, int dst_sel,
                                                       int dst_j, int mode) {
   extern __shared__ double2 buf[];
-  const int q = item_slot(map, blockIdx.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = item_slot(map, item);
   if (item_gated(map, q)) return;
   const InstDesc &d = D[map.ids[q]];
-  const int n = blockIdx.x - map.pre[q];
-  const int m = d.m, L = 1 << d.log2L;
+  const int n = item - map.pre[q];
+  const int m = d.m, L = 1 << d.log2L, tid = threadIdx.x;
   const double *Z = vsel(d, src_sel, src_j);
   double *W = vsel(d, dst_sel, dst_j);
   if (mode == 3 && n >= d.nu && n < d.s - (d.mu1 - 1 - d.nu)) {
     // interior row: S and M apply the same main formula without wrap-around, so the
     // difference is exactly zero (uniform per workgroup, before any barrier)
-    for (int i = threadIdx.x; i < m; i += ST_NT) W[(size_t)n * m + i] = 0.0;
+    for (int i = tid; i < m; i += NT) W[(size_t)n * m + i] = 0.0;
     return;
   }
-  for (int i = threadIdx.x; i < L; i += ST_NT) {
-    double u, v = 0.0;
-    if (i < m) band_combo(d, Z, n, mode, i, u, v);
-    buf[i] = make_double2(v, 0.0);
+  double u[KU], v[KU], dpv[KU], dmv[KU];
+  band_combo_k<KU, NT>(d, Z, n, mode, tid, u, v);
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int i = tid + NT * k;
+    dpv[k] = i < m ? d.dp[i] : 0.0;
+    dmv[k] = i < m ? d.dm[i] : 0.0;
+  }
+  for (int i = tid; i < L; i += NT) buf[i] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {  // the same thread wrote the zero first
+    const int i = tid + NT * k;
+    if (i < m) buf[i] = make_double2(v[k], 0.0);
   }
   __syncthreads();
-  fft_dif<ST_NT>(buf, d.log2L, 1, d.twL);
-  for (int k = threadIdx.x; k < L; k += ST_NT) {
+  fft_dif<NT>(buf, d.log2L, 1, d.twL);
+  for (int k = tid; k < L; k += NT) {
     const double2 x = buf[k], c = d.chat[k];
     const double2 P = cmul(c, x);
     const double2 Qv = cmulc(x, c);
     buf[k] = make_double2(P.x - Qv.y, P.y + Qv.x);
   }
   __syncthreads();
-  fft_dit_inv<ST_NT>(buf, d.log2L, 1, d.twL);
+  fft_dit_inv<NT>(buf, d.log2L, 1, d.twL);
   const double coef = (mode == 1 ? 1.0 : -d.tau) * d.scale / (double)L;
-  for (int i = threadIdx.x; i < m; i += ST_NT) {
-    double u, v;
-    band_combo(d, Z, n, mode, i, u, v);
-    const double2 y = buf[i];
-    W[(size_t)n * m + i] = fma(coef, fma(d.dp[i], y.x, d.dm[i] * y.y), u);
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int i = tid + NT * k;
+    if (i < m) {
+      const double2 y = buf[i];
+      W[(size_t)n * m + i] = fma(coef, fma(dpv[k], y.x, dmv[k] * y.y), u[k]);
+    }
   }
 }
 
@@ -302,16 +342,31 @@ hipError_t launch_symbol(const double *cG, double2 *chat_br, int log2L, const do
   return hipGetLastError();
 }
 
+template <int KU, int NT>
+static hipError_t bvm_matvec_ku(const InstDesc *D, const ItemMap &map, int items, size_t lds, int src_sel,
+                                int src_j, int dst_sel, int dst_j, int mode, hipStream_t st) {
+  hipError_t e = set_lds((const void *)k_bvm_matvec<KU, NT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_bvm_matvec<KU, NT>), dim3(items), dim3(NT), lds, st, D, map, src_sel, src_j, dst_sel,
+                     dst_j, mode);
+  return hipGetLastError();
+}
+
 hipError_t launch_bvm_matvec(const InstDesc *D, const ItemMap &map, int items, int max_log2L,
                              int src_sel, int src_j, int dst_sel, int dst_j, int mode,
                              hipStream_t st) {
   if (items <= 0) return hipSuccess;
   const size_t lds = sizeof(double2) << max_log2L;
-  hipError_t e = set_lds((const void *)k_bvm_matvec, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bvm_matvec, dim3(items), dim3(ST_NT), lds, st, D, map, src_sel, src_j,
-                     dst_sel, dst_j, mode);
-  return hipGetLastError();
+  // every instance has m <= L / 2 <= NT KU
+  switch (max_log2L) {
+    case 13: return bvm_matvec_ku<4, 1024>(D, map, items, lds, src_sel, src_j, dst_sel, dst_j, mode, st);
+    case 12: return bvm_matvec_ku<2, 1024>(D, map, items, lds, src_sel, src_j, dst_sel, dst_j, mode, st);
+    case 11: return bvm_matvec_ku<4, ST_NT>(D, map, items, lds, src_sel, src_j, dst_sel, dst_j, mode, st);
+    case 10: return bvm_matvec_ku<2, ST_NT>(D, map, items, lds, src_sel, src_j, dst_sel, dst_j, mode, st);
+    default:
+      if (max_log2L < 10) return bvm_matvec_ku<1, ST_NT>(D, map, items, lds, src_sel, src_j, dst_sel, dst_j, mode, st);
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_rhs(const InstDesc *D, const ItemMap &map, int items, int use_ju0,

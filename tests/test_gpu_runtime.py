@@ -80,6 +80,24 @@ def test_autotuned_and_forced_launch_shapes_give_identical_results():
         assert np.array_equal(u, u1)
 
 
+@pytest.mark.parametrize("blocks", ["band", "hessenberg"])
+def test_u_sweep_launch_forms_give_identical_results(blocks):
+    """The band and Hessenberg routes run only the U sweep of the block solve; its ordinary
+    one-workgroup launch (W = -1) and the cooperative one (W = 1, 2) give the same bits."""
+    p = W.tiny(200, 32, 1.7, 4, "gbdf3")
+    outs = []
+    for w in (-1, 1, 2):
+        S = BvmSolver(p)
+        S.set_option(N.FDE_OPT_TRSV_W, w)
+        S.factor("fp64", blocks=blocks)
+        u, info = S.solve(p.u0, p.f)
+        assert info["converged"] == 1 and S.get_option(N.FDE_OPT_TRSV_W_IN_USE) == max(w, 0)
+        outs.append((u, info["iters"]))
+        S.close()
+    for u, it in outs[1:]:
+        assert np.array_equal(u, outs[0][0]) and it == outs[0][1]
+
+
 def test_autotuned_time_fft_column_groups_give_identical_results():
     """The autotuner also picks the time FFTs' spatial columns per workgroup (4, 8 or 16;
     reported as "shape/tfft=cols").  Every choice gives the same bits: a batch of the same

@@ -1211,7 +1211,7 @@ template <typename T>
 struct BandWin {
   const c_t<T> *Ktop;  // K block row j (row stride mp)
   const double *H;
-  const int *perm;
+  const int *perm;  // the window's row order, staged in LDS
   double2 lam, mu;
   double tau;
   int mp, m, r0;
@@ -1227,8 +1227,7 @@ struct BandWin {
 // of the window.  Both products of the step share the window's reordered top rows W, gathered
 // once into LDS slices: wavefronts 0-7 form block row j + 1 <- bottom - M21 W, wavefronts 8-15
 // block row j <- L11^{-1} W = U12 (each a 32 x 16 part of its 64 x 64 tile, 3M complex MFMA
-// products over 8-deep K slices, double-buffered; 16 wavefronts per CU hide the slices'
-// latency).  The window's bottom rows are gathered into LDS with the first slices, so their
+// products over 8-deep K slices, double-buffered in LDS, their loads issued two slices ahead).  The window's bottom rows are gathered into LDS with the first slices, so their
 // latency overlaps the products; the new block row j + 1 is stored before a barrier after which
 // block row j is overwritten, so every read of the window precedes the stores that replace it.
 static constexpr int BR_NT = 1024;
@@ -1237,6 +1236,7 @@ struct RowsLds {
   c_t<T> As[2][2][PB][US + 1];  // [product][buffer]: M21 (0), L11^{-1} (1) slices, 64 rows x US
   c_t<T> Bs[2][US][PB + 1];     // W slices: US x 64 columns
   c_t<T> Wb[PB][PB + 1];        // the window's reordered bottom rows, columns c0 .. c0 + 63
+  int perm[2 * PB];             // the window's row order (row i came from row perm[i])
 };
 
 template <typename T>
@@ -1256,7 +1256,7 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
   BandWin<T> win;
   win.Ktop = K + (size_t)r0 * mp;
   win.H = d.hH;
-  win.perm = d.hpiv + ((size_t)blk * npan + j) * 2 * PB;
+  win.perm = sm.perm;
   win.lam = d.lam[blk];
   win.mu = d.mu[blk];
   win.tau = d.tau;
@@ -1273,13 +1273,23 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
   const bool bl = tid < 512;
   const C *Ap = ap == 0 ? K + (size_t)(r0 + PB + ar) * mp + r0 + ac
                         : (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)ar * PB + ac;
-  C ra = ld_global<T>(Ap);
-  C rb = bl ? win.get(br, c0 + bc) : mk<T>((T)0, (T)0);
+  // slices in flight two ahead: the loads of slice sl + 2 are issued before slice sl is multiplied
+  // and stored to LDS only after slice sl + 1 is, so each has two slices' products to arrive
+  constexpr int nsl = PB / US;
+  static_assert(nsl >= 2, "two slices are loaded before the loop");
+  C qa[3], qb[3];
+  qa[0] = ld_global<T>(Ap);
+  qa[1] = ld_global<T>(Ap + US);
+  // the window's row order into LDS first: every gather below then takes one global round trip
+  if (tid < 2 * PB) sm.perm[tid] = d.hpiv[((size_t)blk * npan + j) * 2 * PB + tid];
+  __syncthreads();
+  qb[0] = bl ? win.get(br, c0 + bc) : mk<T>((T)0, (T)0);
+  qb[1] = bl ? win.get(US + br, c0 + bc) : mk<T>((T)0, (T)0);
   C wb[PB * PB / BR_NT];  // bottom rows: thread t takes rows t / 64 + 16 i, column t % 64
 #pragma unroll
   for (int i = 0; i < PB * PB / BR_NT; ++i) wb[i] = win.get(PB + (tid >> 6) + 16 * i, c0 + (tid & 63));
-  sm.As[ap][0][ar][ac] = ra;
-  if (bl) sm.Bs[0][br][bc] = rb;
+  sm.As[ap][0][ar][ac] = qa[0];
+  if (bl) sm.Bs[0][br][bc] = qb[0];
 #pragma unroll
   for (int i = 0; i < PB * PB / BR_NT; ++i) sm.Wb[(tid >> 6) + 16 * i][tid & 63] = wb[i];
   __syncthreads();
@@ -1288,15 +1298,13 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int v = 0; v < 4; ++v) p1[r][v] = p2[r][v] = p3[r][v] = (T)0;
-  constexpr int nsl = PB / US;
-#pragma unroll 1
+#pragma unroll
   for (int sl = 0; sl < nsl; ++sl) {
     const int buf = sl & 1;
-    const bool more = sl + 1 < nsl;
-    if (more) {
-      const int k1 = (sl + 1) * US;
-      ra = ld_global<T>(Ap + k1);
-      if (bl) rb = win.get(k1 + br, c0 + bc);
+    if (sl + 2 < nsl) {
+      const int k2 = (sl + 2) * US;
+      qa[(sl + 2) % 3] = ld_global<T>(Ap + k2);
+      if (bl) qb[(sl + 2) % 3] = win.get(k2 + br, c0 + bc);
     }
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {
@@ -1310,9 +1318,9 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
         p3[r] = mfma16(a.x + a.y, bs, p3[r]);
       }
     }
-    if (more) {
-      sm.As[ap][buf ^ 1][ar][ac] = ra;
-      if (bl) sm.Bs[buf ^ 1][br][bc] = rb;
+    if (sl + 1 < nsl) {
+      sm.As[ap][buf ^ 1][ar][ac] = qa[(sl + 1) % 3];
+      if (bl) sm.Bs[buf ^ 1][br][bc] = qb[(sl + 1) % 3];
     }
     __syncthreads();
   }
@@ -1380,7 +1388,18 @@ __global__ __launch_bounds__(BR_NT) void k_band_lu_step(const InstDesc *__restri
 // One workgroup per block: the window [top; bottom] of step j (the top carried from step j-1,
 // the bottom read from the vector), reordered; then top <- L11^{-1} top (final) and bottom <-
 // bottom - M21 top (the next step's top), both from the reordered top.  Thread t: row t / 8,
-// columns 8 (t % 8) .. + 8.
+// columns t % 8 + 8 c (c = 0 .. 7: each load instruction of a wavefront reads eight whole
+// 128-byte lines, one per row, not 64 lines 16 bytes at a time).  What a step reads from memory does not depend on the solve (its
+// entries of L11^{-1} and M21, its row order, the window's bottom rows of the vector, which only
+// step j + 1 overwrites), so step j + 1's loads are issued before step j runs, into the other of
+// two register sets: the steps then wait on barriers only, not on memory latency.
+template <typename T>
+struct LsolveRegs {
+  c_t<T> li[8], mm[8];
+  double2 vb;
+  int pr;
+};
+
 template <typename T>
 __global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict__ Dd, ItemMap map) {
   typedef c_t<T> C;
@@ -1395,34 +1414,35 @@ __global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict_
   const C *K = (const C *)d.K + (size_t)blk * mp * mp;
   const C *dinv = (const C *)d.dinv;
   const int *perm = d.hpiv + (size_t)blk * npan * 2 * PB;
-  const int i = tid >> 3, qq = tid & 7;  // row i, columns 8 qq .. + 7
-  if (tid < PB) ys[tid] = v[tid];
-  for (int j = 0; j < npan; ++j) {
+  const int i = tid >> 3, qq = tid & 7;  // row i, columns qq + 8 c
+  auto load = [&](int j, LsolveRegs<T> &R) {
     const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
-    // this step's entries of L11^{-1} and M21 do not depend on the solve: loaded first, so
-    // their latency overlaps the window's exchanges
-    C li[8], mm[8];
-    const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq * 8;
+    const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) li[c] = Li[c];
+    for (int c = 0; c < 8; ++c) R.li[c] = Li[8 * c];
     if (nr == 2 * PB) {
-      const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq * 8;
+      const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) mm[c] = M21[c];
+      for (int c = 0; c < 8; ++c) R.mm[c] = M21[8 * c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) mm[c] = mk<T>((T)0, (T)0);
+      for (int c = 0; c < 8; ++c) R.mm[c] = mk<T>((T)0, (T)0);
     }
-    if (tid >= PB && tid < nr) ys[tid] = v[r0 + tid];
+    if (tid < nr) R.pr = perm[(size_t)j * 2 * PB + tid];
+    if (tid >= PB && tid < nr) R.vb = v[r0 + tid];
+  };
+  auto step = [&](int j, const LsolveRegs<T> &R) {
+    const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
+    if (tid >= PB && tid < nr) ys[tid] = R.vb;
     __syncthreads();
-    if (tid < nr) y[tid] = ys[perm[(size_t)j * 2 * PB + tid]];
+    if (tid < nr) y[tid] = ys[R.pr];
     __syncthreads();
     double2 s = make_double2(0.0, 0.0), t = make_double2(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const double2 yc = y[qq * 8 + c];
-      s = cfma(widen(li[c]), yc, s);
-      t = cfma(widen(mm[c]), yc, t);
+      const double2 yc = y[qq + 8 * c];
+      s = cfma(widen(R.li[c]), yc, s);
+      t = cfma(widen(R.mm[c]), yc, t);
     }
 #pragma unroll
     for (int o = 1; o <= 4; o <<= 1) {
@@ -1436,6 +1456,16 @@ __global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict_
       if (nr == 2 * PB) ys[i] = csub(y[PB + i], t);
     }
     __syncthreads();
+  };
+  LsolveRegs<T> ra, rb;
+  if (tid < PB) ys[tid] = v[tid];
+  load(0, ra);
+  for (int j = 0; j < npan; j += 2) {
+    if (j + 1 < npan) load(j + 1, rb);
+    step(j, ra);
+    if (j + 1 == npan) break;
+    if (j + 2 < npan) load(j + 2, ra);
+    step(j + 1, rb);
   }
 }
 

@@ -18,6 +18,7 @@ CASES = {
     "gbdf3_m1_s4": lambda: W.tiny(1, 4, 1.3, 2, "gbdf3"),
     "gbdf3_m63_s16": lambda: W.tiny(63, 16, 1.7, 3, "gbdf3"),         # one panel: no reduction
     "trap_m130_s16": lambda: W.tiny(130, 16, 1.2, 5, "trapezoidal"),  # three panels, ragged
+    "gbdf3_m128_s16": lambda: W.tiny(128, 16, 1.4, 6, "gbdf3"),        # m = mp: H's last entry is read
     "gbdf3_m200_s32": lambda: W.tiny(200, 32, 1.7, 4, "gbdf3"),
     "gam5_m96_s64": lambda: W.example41(1.5, 96, 64),
     "gbdf3_m255_s128": lambda: W.warmstart_instance(7),
@@ -49,7 +50,7 @@ def test_band_reduction_properties(name):
 
 
 @pytest.mark.parametrize("prec,eps", [("fp64", 2.0 ** -53), ("mixed", 2.0 ** -24)])
-@pytest.mark.parametrize("name", ["gbdf3_m1_s4", "gbdf3_m63_s16", "trap_m130_s16", "gbdf3_m200_s32"])
+@pytest.mark.parametrize("name", ["gbdf3_m1_s4", "gbdf3_m63_s16", "trap_m130_s16", "gbdf3_m128_s16", "gbdf3_m200_s32"])
 def test_band_preconditioner_apply(name, prec, eps):
     """Forward error of S^{-1} v within 100 eps max_k cond(K_k) of the oracle's (the reduction
     adds an orthogonal similarity, the pivoting only bounded growth)."""

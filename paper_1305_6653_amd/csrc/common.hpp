@@ -18,6 +18,41 @@ template <typename T> using acc_t = typename ctype<T>::acc;
 
 template <typename T> __device__ __forceinline__ c_t<T> mk(T re, T im) { c_t<T> r; r.x = re; r.y = im; return r; }
 
+// Loads through a global-address-space pointer.  A pointer read from memory (a descriptor's
+// arrays) is generic, and a load through it is a flat load, which counts in lgkmcnt as well as
+// vmcnt: the next wait for an LDS access would wait for it too, so a load issued ahead of LDS work
+// would not stay in flight.  These are global loads (and stores), counted in vmcnt only.
+template <typename V> __device__ __forceinline__ V gld(const V *p) {
+  typedef __attribute__((address_space(1))) const V gV;
+  return *(gV *)p;
+}
+template <typename V> __device__ __forceinline__ void gst(V *p, V v) {
+  typedef __attribute__((address_space(1))) V gV;
+  *(gV *)p = v;
+}
+// the HIP vector types copy through a generic this pointer: load and store them as native vectors
+#define FDE_GLD_VEC(V, E)                                                   \
+  template <> __device__ __forceinline__ V gld<V>(const V *p) {            \
+    typedef E nv __attribute__((ext_vector_type(2)));                      \
+    typedef __attribute__((address_space(1))) const nv gnv;                \
+    const nv v = *(gnv *)p;                                                \
+    V r;                                                                   \
+    r.x = v.x;                                                             \
+    r.y = v.y;                                                             \
+    return r;                                                              \
+  }                                                                        \
+  template <> __device__ __forceinline__ void gst<V>(V * p, V v) {         \
+    typedef E nv __attribute__((ext_vector_type(2)));                      \
+    typedef __attribute__((address_space(1))) nv gnv;                      \
+    nv w;                                                                  \
+    w.x = v.x;                                                             \
+    w.y = v.y;                                                             \
+    *(gnv *)p = w;                                                         \
+  }
+FDE_GLD_VEC(double2, double)
+FDE_GLD_VEC(float2, float)
+#undef FDE_GLD_VEC
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {

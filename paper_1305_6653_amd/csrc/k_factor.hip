@@ -1419,17 +1419,17 @@ __global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict_
     const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
     const C *Li = dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)i * PB + qq;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) R.li[c] = Li[8 * c];
+    for (int c = 0; c < 8; ++c) R.li[c] = gld(Li + 8 * c);
     if (nr == 2 * PB) {
       const C *M21 = K + (size_t)(r0 + PB + i) * mp + r0 + qq;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) R.mm[c] = M21[8 * c];
+      for (int c = 0; c < 8; ++c) R.mm[c] = gld(M21 + 8 * c);
     } else {
 #pragma unroll
       for (int c = 0; c < 8; ++c) R.mm[c] = mk<T>((T)0, (T)0);
     }
-    if (tid < nr) R.pr = perm[(size_t)j * 2 * PB + tid];
-    if (tid >= PB && tid < nr) R.vb = v[r0 + tid];
+    if (tid < nr) R.pr = gld(perm + (size_t)j * 2 * PB + tid);
+    if (tid >= PB && tid < nr) R.vb = gld(v + r0 + tid);
   };
   auto step = [&](int j, const LsolveRegs<T> &R) {
     const int r0 = j * PB, nr = j + 1 < npan ? 2 * PB : PB;
@@ -1452,7 +1452,7 @@ __global__ __launch_bounds__(512) void k_band_lsolve(const InstDesc *__restrict_
       t.y += __shfl_xor(t.y, o, 64);
     }
     if (qq == 0) {
-      v[r0 + i] = s;
+      gst(v + r0 + i, s);
       if (nr == 2 * PB) ys[i] = csub(y[PB + i], t);
     }
     __syncthreads();

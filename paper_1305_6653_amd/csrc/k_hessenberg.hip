@@ -599,31 +599,38 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
   const int as = ht >> 3, aslot = s0 + as, ak = (ht & 7) * 2, bk = ht >> 4, bc = (ht & 15) * 4;
   const bool aok = aslot < ns;
   const double2 *Xa = X + (size_t)(aok ? aslot : 0) * mp, *Xn = X + (size_t)ns * mp;
-  double2 ra[2], rb[2];
+  // The global loads of a slice go to registers of their own (from in-range addresses only) and
+  // the zeros and the slot-0 pairing are applied when the slice is staged, after the products:
+  // nothing waits for the loads before then.
+  double2 xa[2], xb[2];
+  double xs[2];
+  int kpend = 0;
   auto load = [&](int k0) {
+    kpend = k0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int k = k0 + ak + u;
-      double2 v = make_double2(0.0, 0.0);
-      if (aok && k < m) {
-        v = Xa[k];
-        if (aslot == 0) v.y = Xn[k].x;  // slot 0: real parts of bins 0 and s/2
-      }
-      ra[u] = v;
+      const bool in = aok && k < m;
+      xa[u] = gld(Xa + (in ? k : 0));
+      // slot 0 pairs the real parts of bins 0 and s/2; loaded by every thread (no branch, so no
+      // wait at its join), an L2 hit but for the first
+      xs[u] = gld(&Xn[in ? k : 0].x);
     }
     const int k = k0 + bk;
     const double2 *pb = reinterpret_cast<const double2 *>(B + (size_t)(k < m ? k : 0) * mp + c0 + bc);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) rb[u] = k < m ? pb[u] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 2; ++u) xb[u] = gld(pb + u);
   };
   auto stage = [&](int buf) {
     double *A_ = Ag + buf * QG_BUF, *B_ = Bg + buf * QG_BUF;
+    const bool bin = kpend + bk < m;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      A_[(ak + u) * QG_LD + 2 * as] = ra[u].x;
-      A_[(ak + u) * QG_LD + 2 * as + 1] = ra[u].y;
-      B_[bk * QG_LD + bc + 2 * u] = rb[u].x;
-      B_[bk * QG_LD + bc + 2 * u + 1] = rb[u].y;
+      const bool in = aok && kpend + ak + u < m;
+      A_[(ak + u) * QG_LD + 2 * as] = in ? xa[u].x : 0.0;
+      A_[(ak + u) * QG_LD + 2 * as + 1] = in ? (aslot == 0 ? xs[u] : xa[u].y) : 0.0;
+      B_[bk * QG_LD + bc + 2 * u] = bin ? xb[u].x : 0.0;
+      B_[bk * QG_LD + bc + 2 * u + 1] = bin ? xb[u].y : 0.0;
     }
   };
   v4d acc[2][2];
@@ -638,6 +645,7 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
   for (int p = 0; p < nround; ++p) {
     const int buf = p & 1;
     if (p + 1 < nround) load(((p + 1) * QG_NG + kg) * QG_KS);
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products
     const double *A_ = Ag + buf * QG_BUF, *B_ = Bg + buf * QG_BUF;
 #pragma unroll
     for (int kk = 0; kk < QG_KS; kk += 4) {
@@ -651,6 +659,7 @@ __global__ __launch_bounds__(QG_NT) void k_qgemm(const InstDesc *__restrict__ Dd
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[r][c] = mfma16(av[r], bv[c], acc[r][c]);
     }
+    __builtin_amdgcn_sched_barrier(0);  // and the staging, which waits for them, after
     if (p + 1 < nround) stage(buf ^ 1);
     __syncthreads();
   }

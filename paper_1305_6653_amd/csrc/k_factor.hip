@@ -1273,18 +1273,20 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
   const bool bl = tid < 512;
   const C *Ap = ap == 0 ? K + (size_t)(r0 + PB + ar) * mp + r0 + ac
                         : (const C *)d.dinv + ((size_t)(blk * npan + j) * 2 + 0) * PB * PB + (size_t)ar * PB + ac;
-  // slices in flight two ahead: the loads of slice sl + 2 are issued before slice sl is multiplied
-  // and stored to LDS only after slice sl + 1 is, so each has two slices' products to arrive
-  constexpr int nsl = PB / US;
-  static_assert(nsl >= 2, "two slices are loaded before the loop");
-  C qa[3], qb[3];
-  qa[0] = ld_global<T>(Ap);
-  qa[1] = ld_global<T>(Ap + US);
+  // Slices in flight D ahead: the loads of slice sl + D are issued before slice sl is multiplied
+  // and stored to LDS after it, so each has D slices' products to arrive; register slot s % (D + 1)
+  // holds slice s.  FP64: D = 2.  FP32: D = 1, which keeps the kernel at 64 VGPRs with fewer
+  // spills (two workgroups per CU).
+  constexpr int nsl = PB / US, D = sizeof(T) == 8 ? 2 : 1, R = D + 1;
+  static_assert(nsl >= D, "D slices are loaded before the loop");
+  C qa[R], qb[R];
+#pragma unroll
+  for (int d = 0; d < D; ++d) qa[d] = ld_global<T>(Ap + d * US);
   // the window's row order into LDS first: every gather below then takes one global round trip
   if (tid < 2 * PB) sm.perm[tid] = d.hpiv[((size_t)blk * npan + j) * 2 * PB + tid];
   __syncthreads();
-  qb[0] = bl ? win.get(br, c0 + bc) : mk<T>((T)0, (T)0);
-  qb[1] = bl ? win.get(US + br, c0 + bc) : mk<T>((T)0, (T)0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) qb[d] = bl ? win.get(d * US + br, c0 + bc) : mk<T>((T)0, (T)0);
   C wb[PB * PB / BR_NT];  // bottom rows: thread t takes rows t / 64 + 16 i, column t % 64
 #pragma unroll
   for (int i = 0; i < PB * PB / BR_NT; ++i) wb[i] = win.get(PB + (tid >> 6) + 16 * i, c0 + (tid & 63));
@@ -1301,10 +1303,10 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
 #pragma unroll
   for (int sl = 0; sl < nsl; ++sl) {
     const int buf = sl & 1;
-    if (sl + 2 < nsl) {
-      const int k2 = (sl + 2) * US;
-      qa[(sl + 2) % 3] = ld_global<T>(Ap + k2);
-      if (bl) qb[(sl + 2) % 3] = win.get(k2 + br, c0 + bc);
+    if (sl + D < nsl) {
+      const int k2 = (sl + D) * US;
+      qa[(sl + D) % R] = ld_global<T>(Ap + k2);
+      if (bl) qb[(sl + D) % R] = win.get(k2 + br, c0 + bc);
     }
 #pragma unroll
     for (int kk = 0; kk < US; kk += 4) {
@@ -1319,8 +1321,8 @@ __device__ __forceinline__ void band_lu_rows_body(const InstDesc *__restrict__ D
       }
     }
     if (sl + 1 < nsl) {
-      sm.As[ap][buf ^ 1][ar][ac] = qa[(sl + 1) % 3];
-      if (bl) sm.Bs[buf ^ 1][br][bc] = qb[(sl + 1) % 3];
+      sm.As[ap][buf ^ 1][ar][ac] = qa[(sl + 1) % R];
+      if (bl) sm.Bs[buf ^ 1][br][bc] = qb[(sl + 1) % R];
     }
     __syncthreads();
   }

@@ -104,7 +104,7 @@ __global__ void k_band_zero_u32(unsigned *p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// ---- panel reduction (cooperative) ---------------------------------------------------------
+// ---- panel reduction (workgroups cooperating through exchange slots) --------------------------
 // Workgroup g holds panel rows [128 g, 128 g + 128) (local to the panel: row r is row c + r of
 // A) in LDS; thread t works on column t % 64 and rows t / 64 + 16 i.  Per reflection step j each
 // workgroup publishes its column dot products (and workgroup 0 the panel's row j) into the
@@ -436,12 +436,12 @@ static int dg_splits(int tiles, int K) {
 size_t band_work_doubles(int mp) {
   const size_t w2 = (size_t)2 * mp * BW * 16;  // W partials: up to 16 splits of [2 mp][64]
   const size_t y1 = (size_t)BW * mp * 16;      // Y partials
-  return (size_t)mp * BW      // V
-         + BW * BW             // T
-         + 2 * BP_SET          // two slot sets
-         + std::max(w2, y1)    // partial products
-         + (size_t)2 * mp * BW  // W2
-         + (size_t)BW * mp;     // Y2
+  return 2 * ((size_t)mp * BW + BW * BW)      // V and T, one pair per panel parity
+         + 2 * BP_SET                          // two slot sets
+         + std::max(w2, y1)                    // partial products
+         + (size_t)2 * mp * BW                 // W2
+         + (size_t)BW * mp                     // Y2
+         + (size_t)16 * BW * BW + BW * BW;     // Y partials and Y2 of the next panel's columns
 }
 
 template <bool TA, bool TB, int MODE>
@@ -453,26 +453,30 @@ static hipError_t dgemm(int M, int N, int K, int splits, const double *A, int ld
   return hipGetLastError();
 }
 
-// The reduction in three parts, so that a caller can time the panels and the updates apart:
-// init ([A; Q] from J, slot set 0 filled), then per panel p = 0 .. mp/64 - 2 the panel and its
-// two-sided update, then Qt = Q^T.
+// The reduction in parts, so that a caller can time the panels and the updates apart and run
+// the next panel beside the current update: init ([A; Q] from J, slot set 0 filled), then per
+// panel p = 0 .. mp/64 - 2 the panel and its two-sided update, then Qt = Q^T.  Panel p writes
+// V and T of parity p & 1, so panel p + 1 may run while the update of panel p still reads its own.
 struct BandPtrs {
-  double *V, *T, *slots, *part, *W2, *Y2;
+  double *V, *T, *slots, *part, *W2, *Y2, *partn, *Y2n;
 };
-static BandPtrs band_ptrs(int mp, double *work) {
+static BandPtrs band_ptrs(int mp, double *work, int p) {
   BandPtrs b;
-  b.V = work;
+  const size_t vt = (size_t)mp * BW + BW * BW;
+  b.V = work + (size_t)(p & 1) * vt;
   b.T = b.V + (size_t)mp * BW;
-  b.slots = b.T + BW * BW;
+  b.slots = work + 2 * vt;
   b.part = b.slots + 2 * BP_SET;
   const size_t w2 = (size_t)2 * mp * BW * 16, y1 = (size_t)BW * mp * 16;
   b.W2 = b.part + std::max(w2, y1);
   b.Y2 = b.W2 + (size_t)2 * mp * BW;
+  b.partn = b.Y2 + (size_t)BW * mp;
+  b.Y2n = b.partn + (size_t)16 * BW * BW;
   return b;
 }
 
 hipError_t launch_band_init(const InstDesc *D, int inst, int mp, double *AQ, double *work, hipStream_t st) {
-  const BandPtrs b = band_ptrs(mp, work);
+  const BandPtrs b = band_ptrs(mp, work, 0);
   hipLaunchKernelGGL(k_band_init, dim3((mp + 255) / 256, 2 * mp), dim3(256), 0, st, D, inst, AQ);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -481,32 +485,50 @@ hipError_t launch_band_init(const InstDesc *D, int inst, int mp, double *AQ, dou
 }
 
 hipError_t launch_band_panel(int mp, int p, double *AQ, double *work, int *err, hipStream_t st) {
-  const BandPtrs b = band_ptrs(mp, work);
+  const BandPtrs b = band_ptrs(mp, work, p);
   const int c = (p + 1) * BW, w = mp - c;
   const int g = (w + BP_ROWS - 1) / BP_ROWS;
   BandPanelArgs pa{AQ, b.V, b.T, b.slots + (size_t)(p & 1) * BP_SET, b.slots + (size_t)((p + 1) & 1) * BP_SET,
                    err, mp, p};
-  void *args[] = {(void *)&pa};
-  return hipLaunchCooperativeKernel((const void *)k_band_panel, dim3(g), dim3(BP_NT), args, 0, st);
+  // An ordinary launch, so that it may run beside the previous panel's far update on another
+  // stream: its at most 32 workgroups become co-resident as that update's short workgroups
+  // retire, and every wait between them is bounded (BP_SPIN_MAX).
+  hipLaunchKernelGGL(k_band_panel, dim3(g), dim3(BP_NT), 0, st, pa);
+  return hipGetLastError();
 }
 
-hipError_t launch_band_update(int mp, int p, double *AQ, double *work, hipStream_t st) {
-  const BandPtrs b = band_ptrs(mp, work);
+// The two-sided update of panel p in two parts.  near: W = [A; Q][:, c:] V and W2 = W T (all of
+// the trailing width), then the next panel's 64 columns c .. c + 63 in full: [A; Q][:, c:c+64]
+// -= W2 V[0:64]^T, Y = V^T A[c:, c:c+64], Y2 = T^T Y, A[c:, c:c+64] -= V Y2.  far: the same for
+// the columns from c + 64 on (nothing when w = 64).  The far part touches none of the next panel's
+// columns and reads only this panel's V, T and W2, so it may run beside panel p + 1.
+hipError_t launch_band_update(int mp, int p, bool far, double *AQ, double *work, hipStream_t st) {
+  const BandPtrs b = band_ptrs(mp, work, p);
   const int c = (p + 1) * BW, w = mp - c;
-  hipError_t e;
-  // right update of [A; Q] (2 mp rows): W = [A; Q][:, c:] V, W2 = W T, [A; Q][:, c:] -= W2 V^T
-  const int zr = dg_splits(2 * mp / 64, w);
-  if ((e = dgemm<false, false, 0>(2 * mp, BW, w, zr, AQ + c, mp, b.V, BW, b.part, BW, 1.0, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_w2, dim3(2 * mp / 4), dim3(256), 0, st, b.part, zr, 2 * mp, b.T, b.W2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = dgemm<false, true, 1>(2 * mp, w, BW, 1, b.W2, BW, b.V, BW, AQ + c, mp, -1.0, st)) != hipSuccess) return e;
-  // left update of A[c:, c:]: Y = V^T A[c:, c:], Y2 = T^T Y, A[c:, c:] -= V Y2
-  const int zl = dg_splits(w / 64, w);
   double *Ac = AQ + (size_t)c * mp + c;
-  if ((e = dgemm<true, false, 0>(BW, w, w, zl, b.V, BW, Ac, mp, b.part, w, 1.0, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_y2, dim3(w / 4), dim3(256), 0, st, b.part, zl, w, b.T, b.Y2);
+  hipError_t e;
+  if (!far) {
+    const int zr = dg_splits(2 * mp / 64, w);
+    if ((e = dgemm<false, false, 0>(2 * mp, BW, w, zr, AQ + c, mp, b.V, BW, b.part, BW, 1.0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_w2, dim3(2 * mp / 4), dim3(256), 0, st, b.part, zr, 2 * mp, b.T, b.W2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = dgemm<false, true, 1>(2 * mp, BW, BW, 1, b.W2, BW, b.V, BW, AQ + c, mp, -1.0, st)) != hipSuccess) return e;
+    const int zn = dg_splits(1, w);
+    if ((e = dgemm<true, false, 0>(BW, BW, w, zn, b.V, BW, Ac, mp, b.partn, BW, 1.0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_y2, dim3(BW / 4), dim3(256), 0, st, b.partn, zn, BW, b.T, b.Y2n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return dgemm<false, false, 1>(w, BW, BW, 1, b.V, BW, b.Y2n, BW, Ac, mp, -1.0, st);
+  }
+  const int wf = w - BW;  // the columns from c + 64 on
+  if (wf <= 0) return hipSuccess;
+  if ((e = dgemm<false, true, 1>(2 * mp, wf, BW, 1, b.W2, BW, b.V + (size_t)BW * BW, BW, AQ + c + BW, mp, -1.0,
+                                 st)) != hipSuccess)
+    return e;
+  const int zl = dg_splits(wf / 64, w);
+  if ((e = dgemm<true, false, 0>(BW, wf, w, zl, b.V, BW, Ac + BW, mp, b.part, wf, 1.0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_y2, dim3(wf / 4), dim3(256), 0, st, b.part, zl, wf, b.T, b.Y2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return dgemm<false, false, 1>(w, w, BW, 1, b.V, BW, b.Y2, w, Ac, mp, -1.0, st);
+  return dgemm<false, false, 1>(w, wf, BW, 1, b.V, BW, b.Y2, wf, Ac + BW, mp, -1.0, st);
 }
 
 hipError_t launch_band_finish(int mp, double *AQ, double *Qt, hipStream_t st) {

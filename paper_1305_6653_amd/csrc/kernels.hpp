@@ -165,7 +165,9 @@ size_t band_work_doubles(int mp);  // workspace of the reduction
 // two-sided update, then Qt = Q^T
 hipError_t launch_band_init(const InstDesc *D, int inst, int mp, double *AQ, double *work, hipStream_t st);
 hipError_t launch_band_panel(int mp, int p, double *AQ, double *work, int *err, hipStream_t st);
-hipError_t launch_band_update(int mp, int p, double *AQ, double *work, hipStream_t st);
+// far = false: the update's products over the whole trailing width and the next panel's columns;
+// far = true: the rest of the columns (may run beside launch_band_panel(p + 1))
+hipError_t launch_band_update(int mp, int p, bool far, double *AQ, double *work, hipStream_t st);
 hipError_t launch_band_finish(int mp, double *AQ, double *Qt, hipStream_t st);
 // step j of the pivoted band LU: item = (instance, block) for the panel, (instance, block, tile)
 // for the rows, tiles t0 <= t < min(t1, npan - j - 1) of each block; permutations in hpiv

@@ -164,6 +164,10 @@ struct fde_bvm {
   bool need_Ju0 = false;
   // ---- device
   hipStream_t stream = nullptr, own_stream = nullptr;
+  // band route: a second stream for the reduction's next panel, which runs beside the rest of
+  // the current panel's update, and the two events that order it
+  hipStream_t side_stream = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
   std::vector<void *> allocs;
   double *d_g = nullptr, *d_dp = nullptr, *d_dm = nullptr, *d_cG = nullptr;
   double2 *d_chat = nullptr, *d_twL = nullptr, *d_tws = nullptr, *d_lam = nullptr, *d_mu = nullptr;
@@ -955,6 +959,9 @@ static void destroy_handle(fde_bvm *h) {
       (void)hipEventDestroy(p.b);
     }
   for (auto e : h->evpool) (void)hipEventDestroy(e);
+  for (auto e : h->side_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
 }
@@ -1514,6 +1521,10 @@ static fde_status band_alloc(fde_bvm *h) {
   STCHK(dalloc_t(h, &h->d_bwork, band_work_doubles(h->mp)));
   STCHK(dalloc_t(h, &h->d_berr, 64));
   HIPCHK(hipMemsetAsync(h->d_berr, 0, 64 * sizeof(int), h->stream));
+  if (!h->side_stream) {
+    HIPCHK(hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking));
+    for (auto &e : h->side_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   if (!h->d_Vh2) {
     STCHK(dalloc_t(h, &h->d_Vh2, nb * mp));
     HIPCHK(hipMemsetAsync(h->d_Vh2, 0, nb * mp * sizeof(double2), h->stream));
@@ -1535,14 +1546,34 @@ static fde_status band_factor(Plan *P) {
     // with its product into Q 4 (2 mp) w 64 + 4 w^2 64 (right update of [A; Q], left update)
     const int mp = h->mp;
     HIPCHK(run(L, "band_init", 16.0 * mp * mp, [&] { return launch_band_init(P->d_desc, i, mp, h->d_bAQ, h->d_bwork, st); }));
-    for (int p = 0; p + 1 < h->npan; ++p) {
+    // Panels 0 .. np - 1.  Look-ahead: the update of panel p first finishes the next panel's 64
+    // columns (near), then panel p + 1 runs on the side stream while the rest of the update
+    // (far, the columns after those) runs on the main one; the main stream waits for the panel
+    // before the next update.
+    const int np = h->npan - 1;
+    hipStream_t side = L->side_stream;
+    auto panel_work = [&](int p) { return 2.0 * 64.0 * 64.0 * (mp - 64.0 * (p + 1) - 64.0 / 3.0); };
+    if (np > 0)
+      HIPCHK(run(L, "band_panel", panel_work(0), [&] {
+        return launch_band_panel(mp, 0, h->d_bAQ, h->d_bwork, h->d_berr, st);
+      }));
+    for (int p = 0; p < np; ++p) {
       const double w = mp - 64.0 * (p + 1);
-      HIPCHK(run(L, "band_panel", 2.0 * 64.0 * 64.0 * (w - 64.0 / 3.0), [&] {
-        return launch_band_panel(mp, p, h->d_bAQ, h->d_bwork, h->d_berr, st);
-      }));
-      HIPCHK(run(L, "band_update", 4.0 * 2.0 * mp * w * 64.0 + 4.0 * w * w * 64.0, [&] {
-        return launch_band_update(mp, p, h->d_bAQ, h->d_bwork, st);
-      }));
+      const double all = 4.0 * 2.0 * mp * w * 64.0 + 4.0 * w * w * 64.0;
+      const double near = 2.0 * 2.0 * mp * w * 64.0 + 2.0 * 2.0 * mp * 64.0 * 64.0 + 4.0 * w * 64.0 * 64.0;
+      HIPCHK(run(L, "band_update", near, [&] { return launch_band_update(mp, p, false, h->d_bAQ, h->d_bwork, st); }));
+      const bool next = p + 1 < np;
+      if (next) {
+        HIPCHK(hipEventRecord(L->side_ev[0], st));
+        HIPCHK(hipStreamWaitEvent(side, L->side_ev[0], 0));
+        HIPCHK(run(L, "band_panel", panel_work(p + 1), [&] {
+          return launch_band_panel(mp, p + 1, h->d_bAQ, h->d_bwork, h->d_berr, side);
+        }, side));
+        HIPCHK(hipEventRecord(L->side_ev[1], side));
+      }
+      if (w > 64.0)
+        HIPCHK(run(L, "band_update", all - near, [&] { return launch_band_update(mp, p, true, h->d_bAQ, h->d_bwork, st); }));
+      if (next) HIPCHK(hipStreamWaitEvent(st, L->side_ev[1], 0));
     }
     HIPCHK(run(L, "band_finish", 16.0 * mp * mp, [&] { return launch_band_finish(mp, h->d_bAQ, h->d_bQt, st); }));
   }

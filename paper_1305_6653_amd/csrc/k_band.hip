@@ -427,9 +427,9 @@ __global__ __launch_bounds__(256) void k_band_transpose(const double *__restrict
 
 // ---- host side -------------------------------------------------------------------------------
 static int dg_splits(int tiles, int K) {
-  // enough workgroups to fill the device twice over, each with at least 256 of the K range
+  // enough workgroups to fill the device four times over, each with at least 128 of the K range
   int z = 1;
-  while (tiles * z < 512 && K / (2 * z) >= 256) z *= 2;
+  while (tiles * z < 1024 && K / (2 * z) >= 128 && z < 16) z *= 2;
   return z;
 }
 

@@ -74,25 +74,25 @@ PMC_MEASURED = {
                 ("mixed", "qgemm"): 5.2862e+07, ("mixed", "trsv"): 1.3156e+09}},
     # profiles/hbm_traffic_m4095_s256_gbdf3.txt
     "c3": {"hash": {"factor": "da95ccf4032e6e85", "spacetime": "7d1eafc888daca2c", "krylov": "5584998f77183f5e",
-                    "hessenberg": "6ab681476fb4a268", "band": "ecc4b37cf03e3eb9"},
+                    "hessenberg": "6ab681476fb4a268", "band": "6851e166aa9f8d8b"},
            "bytes": {
-               ("fp64", "trsv"): 1.7687e+10, ("fp64", "band_lu_step"): 9.8120e+08,
+               ("fp64", "trsv"): 1.7687e+10, ("fp64", "band_lu_step"): 9.8122e+08,
                ("fp64", "band_lu_rows"): 4.2619e+07, ("fp64", "band_lu_panel"): 3.4665e+07,
                ("fp64", "band_lsolve"): 1.0948e+09, ("fp64", "qgemm"): 2.1053e+08,
-               ("fp64", "band_panel"): 1.4643e+07, ("fp64", "band_init"): 2.6942e+08,
+               ("fp64", "band_panel"): 1.4629e+07, ("fp64", "band_init"): 2.6943e+08,
                ("fp64", "mgs"): 3.1258e+07, ("fp64", "bvm_matvec"): 1.9734e+07,
-               ("fp64", "time_rfft"): 1.7031e+07, ("fp64", "time_irfft"): 1.6834e+07,
-               ("fp64", "normalize"): 1.6917e+07, ("mixed", "trsv"): 9.3537e+09,
-               ("mixed", "band_lu_step"): 6.9871e+08, ("mixed", "band_lu_rows"): 2.1533e+07,
+               ("fp64", "time_rfft"): 1.7079e+07, ("fp64", "time_irfft"): 1.6881e+07,
+               ("fp64", "normalize"): 1.6917e+07, ("mixed", "trsv"): 9.3656e+09,
+               ("mixed", "band_lu_step"): 6.9877e+08, ("mixed", "band_lu_rows"): 2.1533e+07,
                ("mixed", "band_lu_panel"): 1.7741e+07, ("mixed", "band_lsolve"): 5.5800e+08,
-               ("mixed", "qgemm"): 2.1053e+08, ("mixed", "band_panel"): 1.4643e+07,
-               ("mixed", "band_init"): 2.6942e+08}},
+               ("mixed", "qgemm"): 2.1053e+08, ("mixed", "band_panel"): 1.4629e+07,
+               ("mixed", "band_init"): 2.6943e+08}},
     "c3l": {"hash": {"factor": "da95ccf4032e6e85", "spacetime": "7d1eafc888daca2c", "krylov": "5584998f77183f5e"},
            "bytes": {
-               ("fp64", "lu_update"): 2.2902e+10, ("fp64", "trsv"): 3.5387e+10,
+               ("fp64", "lu_update"): 2.2898e+10, ("fp64", "trsv"): 3.5387e+10,
                ("fp64", "lu_panel"): 1.1004e+09, ("fp64", "lu_diag"): 3.4090e+07,
-               ("fp64", "assemble"): 2.1340e+09, ("mixed", "lu_update"): 9.5183e+09,
-               ("mixed", "trsv"): 1.8696e+10, ("mixed", "lu_panel"): 6.3422e+08,
+               ("fp64", "assemble"): 2.1333e+09, ("mixed", "lu_update"): 9.5230e+09,
+               ("mixed", "trsv"): 1.8712e+10, ("mixed", "lu_panel"): 6.3364e+08,
                ("mixed", "lu_diag"): 1.7037e+07, ("mixed", "assemble"): 1.0673e+09}},
 }
 
